@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the treecode Green-function convolution on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload atom|cube]
+
+A step is one pass of the whole path on the workload: tree build and batches,
+upward pass, interaction lists and schedule, far and near fields, combine, for
+every convolution the workload holds. The default workload is the single-atom
+adaptive mesh (Be-like Z = 4 in [-20, 20]^3, 1,007,616 Fejer points): a Yukawa
+convolution (kappa = sqrt(0.4)) of psi_1s + psi_2s and a Coulomb (Hartree)
+convolution of rho = 2 psi_1s^2 + 2 psi_2s^2, both singularity-subtracted, with
+theta = 0.8, degree 8, N_L = 500. Inputs are resident in HBM before timing.
+
+Printed: one JSON line with the throughput (batch-cluster kernel evaluations
+per second, far + near, over the whole step), the accuracy against the GPU
+direct sum on sampled targets, the roofline position of the dominant kernel
+(the interaction kernel, timed with HIP events on its own stream) and the CPU
+oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Green-convolution time & interactions/s at 1e-6 rel err; batched/mixed vs plain"
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
+
+# Algorithmic FP64 flops per kernel evaluation (FMA = 2): squared distance (8
+# for particle sources; 3 for proxy sources, whose tensor grid gives d^2 with one
+# subtraction and one multiply-add per pair), reciprocal square root (seed plus
+# refinement, 9), exp by Cody-Waite reduction and a degree-11 polynomial (31),
+# the products forming the kernel value, and two multiply-adds (4).
+FLOPS = {
+    ("yukawa_ss", "far"): 3 + 9 + 1 + 1 + 31 + 1 + 4,
+    ("yukawa_ss", "near"): 8 + 9 + 1 + 1 + 31 + 1 + 4,
+    ("coulomb_ss", "far"): 3 + 9 + 1 + 31 + 1 + 2 + 2,
+    ("coulomb_ss", "near"): 8 + 9 + 1 + 31 + 1 + 2 + 2,
+}
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from workloads.configs import DOMAIN, atom_mesh, uniform_cube
+    if name == "atom":
+        d = atom_mesh()
+        convs = [("yukawa_ss", d["psi"], float(d["kappa"])), ("coulomb_ss", d["rho"], 0.0)]
+        return dict(name="atom_mesh_Z4", x=d["x"], y=d["y"], z=d["z"], w=d["w"], convs=convs,
+                    theta=0.8, degree=8, leaf=500,
+                    box=(*DOMAIN[0], *DOMAIN[1]))
+    x, y, z, f, w = uniform_cube(32768, seed=1)
+    return dict(name="uniform_cube_32768", x=x, y=y, z=z, w=w, convs=[("yukawa_ss", f, 1.0)],
+                theta=0.7, degree=6, leaf=500, box=None)
+
+
+def cpu_baseline(wl, seconds: float):
+    """The oracle's direct sum on sampled targets (all sources), both kernels."""
+    from oracle.direct import default_threads, direct_sum
+    from workloads.configs import sample_targets
+    threads = min(16, default_threads())
+    n = wl["x"].size
+
+    def run(k):
+        idx = sample_targets(n, k, seed=4)
+        t0 = time.perf_counter()
+        for kernel, f, kappa in wl["convs"]:
+            direct_sum(kernel, wl["x"], wl["y"], wl["z"], f, wl["w"], wl["x"][idx], wl["y"][idx],
+                       wl["z"][idx], f[idx], kappa=kappa if kappa else 1.0, threads=threads)
+        return time.perf_counter() - t0
+
+    probe = max(threads, 16)
+    dt = run(probe)
+    k = int(min(n, max(probe, probe * seconds / max(dt, 1e-6))))
+    dt = run(k)
+    pairs = k * n * len(wl["convs"])
+    return {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"direct sum at {k} seeded targets x {n} sources for "
+                      f"{len(wl['convs'])} kernel(s), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="atom", choices=["atom", "cube"])
+    ap.add_argument("--samples", type=int, default=2000, help="targets for the accuracy check")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures a single GPU; runs on more than one GPU are not part of this "
+              "build (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2003_01833_amd as tagi
+    from workloads.configs import sample_targets
+
+    torch.cuda.set_device(0)
+    _log(f"bench: building workload {args.workload}")
+    wl = make_workload(args.workload)
+    n = wl["x"].size
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    x, y, z, w = dev(wl["x"]), dev(wl["y"]), dev(wl["z"]), dev(wl["w"])
+    fields = [(k, dev(f), kap) for k, f, kap in wl["convs"]]
+    outs = [torch.empty((1, n), dtype=torch.float64, device="cuda") for _ in fields]
+    theta, degree, leaf = wl["theta"], wl["degree"], wl["leaf"]
+    torch.cuda.synchronize()
+
+    records = []
+
+    def step():
+        t = tagi.Tree(x, y, z, leaf, wl["box"])
+        t.set_timing(True)
+        for (kernel, f, kap), out in zip(fields, outs):
+            t.upward(f, w, degree)
+            t.convolve(kernel, kap if kap else 1.0, theta, degree, alpha=1.0, out=out)
+        records.append((t.timing(), t.stats()))
+        t.close()
+
+    for i in range(args.warmup):
+        step()
+        _log(f"bench: warmup step {i + 1}/{args.warmup} done")
+    records.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    _log(f"bench: {args.steps} timed steps in {elapsed:.3f} s")
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    st = records[-1][1]
+    inter_per_conv = st["far_interactions"] + st["near_interactions"]
+    interactions = inter_per_conv * len(fields)
+    value = interactions / (ms_per_step / 1e3)
+    phases = {k: float(np.mean([r[0][k] for r in records])) for k in
+              ("build_ms", "upward_ms", "lists_ms", "interact_ms", "combine_ms")}
+    flops = sum(st["far_interactions"] * FLOPS[(k, "far")] + st["near_interactions"] * FLOPS[(k, "near")]
+                for k, _, _ in fields)
+    interact_s = phases["interact_ms"] / 1e3
+    achieved = flops / interact_s / 1e12
+    launches = records[-1][0]["interact_launches"]
+
+    # accuracy of the last step's outputs against the GPU direct sum at sampled targets
+    idx = torch.from_numpy(sample_targets(n, min(args.samples, n), seed=4)).cuda()
+    acc = {}
+    for (kernel, f, kap), out in zip(fields, outs):
+        ref = tagi.direct(kernel, x, y, z, f, w, x[idx].contiguous(), y[idx].contiguous(),
+                          z[idx].contiguous(), f[idx].contiguous(), kappa=kap if kap else 1.0)
+        u = out[0, idx]
+        acc[kernel] = {"rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
+                       "rel_max": float((u - ref).abs().max() / ref.abs().max())}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log("bench: timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "n_points": n, "theta": theta, "degree": degree,
+                   "leaf_size": leaf, "convolutions": [k for k, _, _ in fields],
+                   "n_leaves": st["n_leaves"], "far_pairs": st["n_far_pairs"],
+                   "near_pairs": st["n_near_pairs"],
+                   "interactions_per_step": interactions},
+        "roofline": {"bound": "alu", "kernel": "k_interact", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "launches_per_step": launches,
+                     "avg_launch_ms": phases["interact_ms"] / max(launches, 1)},
+        "cpu_baseline": cpu,
+        "phases_ms": phases,
+        "accuracy_vs_direct": acc,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,241 @@
+/*
+ * tagi.h -- C ABI of the MI355X (gfx950) barycentric Lagrange treecode for the
+ * Green-function convolution sums of treecode-accelerated Green Iteration
+ * (Vaughn, Wilson, Krasny et al., arXiv 2003.01833).
+ *
+ * The library evaluates, for points r_i with values f_i and quadrature weights w_i,
+ *
+ *     u_i = sum_{j : |r_i - r_j| > 0} G(r_i, r_j) f_j w_j                (Section 6, Eq. direct-sum)
+ *
+ * with the Yukawa kernel G = exp(-k r)/r or the Coulomb kernel G = 1/r, and with
+ * the singularity-subtracted forms of Section 4.3:
+ *
+ *   TAGI_YUKAWA_SS  (Eq. yukawa-conv-ss and the analytic term 4 pi f / k^2):
+ *       u_i = sum_j (f_j - f_i) exp(-k d_ij)/d_ij w_j + 4 pi f_i / k^2
+ *   TAGI_COULOMB_SS (Eqs. coulomb-conv-ss and correction_term, Gaussian width a):
+ *       u_i = sum_j (f_j - f_i exp(-d_ij^2/a^2))/d_ij w_j + 2 pi a^2 f_i
+ *
+ * either exactly (tagi_direct) or by the barycentric Lagrange treecode of
+ * Section 6 (tagi_tree_build + tagi_upward + tagi_convolve: Algorithm 3, lines
+ * 1, 2 and 3). The kernels are not normalised: the Green-iteration prefactor
+ * -1/(2 pi) and f = V_eff psi are the caller's.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays are FP64 (or int32 where stated), contiguous, and live in DEVICE
+ *   memory of the current HIP device unless stated "host". The caller owns them.
+ *   Multi-field arrays are row-major: f[n_orb][n] means orbital o's values are
+ *   f + o * n.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream). Calls enqueue
+ *   work on it; tagi_tree_build and the first tagi_convolve for a given (theta,
+ *   degree) also synchronise it (they read sizes back to the host). Inputs must
+ *   stay valid until the stream has passed the call; the tree copies what it
+ *   keeps (sorted coordinates, weights, values), so after the call has completed
+ *   the caller may overwrite its inputs.
+ * - Every function returns TAGI_OK (0) or a negative status; nothing aborts or
+ *   throws across the ABI. tagi_last_error() returns a thread-local message for
+ *   the last failure on the calling thread. Arguments are validated before any
+ *   work is enqueued.
+ * - A tree handle may be used by one host thread at a time.
+ * - Pairs at distance exactly zero contribute nothing (the "i != j" of Eq.
+ *   direct-sum, generalised to any pair of coincident points).
+ */
+#ifndef TAGI_H
+#define TAGI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tagi_tree tagi_tree;
+
+enum tagi_status {
+  TAGI_OK = 0,
+  TAGI_E_ARG = -1,         /* invalid argument (null pointer, size, range) */
+  TAGI_E_STATE = -2,       /* call out of order (convolve before upward, degree mismatch) */
+  TAGI_E_OOM = -3,         /* device allocation failed */
+  TAGI_E_HIP = -4,         /* a HIP runtime call failed; message in tagi_last_error() */
+  TAGI_E_UNSUPPORTED = -5  /* valid request this build does not implement */
+};
+
+enum tagi_kernel {
+  TAGI_YUKAWA_SS = 0,  /* exp(-k r)/r with singularity subtraction (Section 4.3) */
+  TAGI_COULOMB_SS = 1, /* 1/r with Gaussian singularity subtraction (Section 4.3) */
+  TAGI_YUKAWA = 2,     /* exp(-k r)/r, singular pair skipped (Eq. direct-sum) */
+  TAGI_COULOMB = 3     /* 1/r, singular pair skipped (Eq. direct-sum) */
+};
+
+enum tagi_precision {
+  TAGI_FP64 = 0,  /* every step in FP64 */
+  TAGI_MIXED = 1  /* far-field (batch-proxy) kernel sums in FP32 per batch-cluster tile,
+                     added into FP64; near field, proxy charges, combine stay FP64 */
+};
+
+typedef struct {
+  int64_t n_points;      /* sources (= targets) */
+  int32_t n_nodes;       /* clusters, root included */
+  int32_t n_leaves;      /* leaves = target batches (Section 6.1, N_B = N_L) */
+  int32_t max_level;     /* deepest level (root = 0) */
+  int32_t leaf_size;     /* N_L */
+  int32_t degree;        /* degree of the last tagi_upward (0 if none) */
+  int32_t n_orb;         /* orbitals of the last tagi_upward */
+  int32_t n_approx;      /* clusters holding proxy charges ((n+1)^3 < N_S) */
+  double theta;          /* theta of the cached interaction lists (-1 if none) */
+  int64_t n_far_pairs;   /* batch-cluster pairs evaluated by the approximation */
+  int64_t n_near_pairs;  /* batch-cluster pairs evaluated directly */
+  int64_t far_interactions;  /* sum over far pairs of |B| (n+1)^3, one orbital */
+  int64_t near_interactions; /* sum over near pairs of |B| N_S, one orbital */
+  int64_t n_work_items;  /* compute work items of the cached schedule */
+} tagi_stats;
+
+/*
+ * Algorithm 3, line 1 (Section 6.1): build the tree of source clusters and the
+ * target batches.
+ *   x, y, z    device [n] source coordinates.
+ *   box        host double[6] = {lo_x, lo_y, lo_z, hi_x, hi_y, hi_z}: the domain
+ *              box that the root cluster encloses, or NULL for the sources'
+ *              bounding box. All sources must lie inside it.
+ *   leaf_size  N_L >= 1: a cluster with more than N_L sources is divided.
+ * Division (Section 6.1): a cluster is bisected at the midpoint of its box (the
+ * root: of `box`; others: of their shrunk box) in every dimension whose extent
+ * is at least 1/sqrt(2) of the largest extent, so into 8, 4 or 2 children;
+ * every cluster is shrunk to the bounding box of its sources. The sources are
+ * reordered so that every cluster is a contiguous range; batches are the leaves.
+ * Synchronises `stream`. On success *out owns all device memory of the tree.
+ * Errors: TAGI_E_ARG (null pointers, n < 1, n >= 2^31, leaf_size < 1, a source
+ * outside `box` or not finite), TAGI_E_OOM, TAGI_E_HIP.
+ */
+int tagi_tree_build(const double* x, const double* y, const double* z, int64_t n,
+                    const double* box, int leaf_size, void* stream, tagi_tree** out);
+
+/*
+ * Algorithm 3, line 2 (Section 6.2, Eq. particle-cluster-approx-rearranged):
+ * proxy charges of every cluster with more than (degree+1)^3 sources,
+ *     q^_k = sum_{j in C} L_k1(x_j) L_k2(y_j) L_k3(z_j) q_j,
+ * on the tensor grid of Chebyshev points of the second kind mapped to the
+ * cluster's box, with the barycentric Lagrange basis (Eqs. Lagrange_polynomials,
+ * barycentric_weights). Two charge sets per cluster: q_j = f_j w_j per orbital
+ * and q_j = w_j (the latter carries the singularity subtraction through the far
+ * field). Also stores the tree-ordered f and w for the near field.
+ *   f       device [n_orb][n] values in the caller's point order.
+ *   w       device [n] quadrature weights in the caller's point order.
+ *   n_orb   1 <= n_orb <= 64.
+ *   degree  interpolation degree n, 1 <= n <= 16.
+ * Errors: TAGI_E_ARG, TAGI_E_OOM, TAGI_E_HIP.
+ */
+int tagi_upward(tagi_tree* tree, const double* f, const double* w, int n_orb, int degree,
+                void* stream);
+
+/*
+ * Algorithm 3, line 3 (Section 6.3): for every target batch, ComputePotential
+ * from the root with the MAC of Eq. MAC, (r_B + r_C) < theta R and
+ * (n+1)^3 < N_S (r = half the diagonal of a shrunk box, R = distance between box
+ * midpoints); accepted pairs use the proxy charges, rejected leaves and
+ * size-rejected clusters are summed directly (Eq. direct-sum_2). Then the
+ * analytic subtraction term is added and the result is written in the caller's
+ * point order. All n_orb orbitals of the last tagi_upward are evaluated in one
+ * launch sequence (orbital o with kappa[o]).
+ *   targets    must be NULL: the targets are the sources (batches = leaves).
+ *   kernel     enum tagi_kernel.
+ *   kappa      HOST [n_orb] Yukawa decay rates, finite and > 0 (ignored for
+ *              Coulomb kernels; may then be NULL).
+ *   alpha      Gaussian width of TAGI_COULOMB_SS (> 0; the paper uses 1).
+ *   theta      MAC parameter, 0 <= theta < 1 (0 gives the direct sum).
+ *   degree     must equal the degree of the last tagi_upward.
+ *   precision  enum tagi_precision.
+ *   out        device [n_orb][n], caller's point order.
+ * The interaction lists and the work schedule are cached per (theta, degree);
+ * rebuilding them synchronises the stream.
+ * Errors: TAGI_E_ARG, TAGI_E_STATE (no upward yet, degree mismatch),
+ * TAGI_E_UNSUPPORTED (targets != NULL), TAGI_E_OOM, TAGI_E_HIP.
+ */
+int tagi_convolve(tagi_tree* tree, const void* targets, int kernel, const double* kappa,
+                  double alpha, double theta, int degree, int precision, double* out,
+                  void* stream);
+
+/*
+ * Direct evaluation of Eq. direct-sum (with the Section 4.3 subtraction for the
+ * *_SS kernels) at nt targets over ns sources, FP64.
+ *   sx, sy, sz, sf, sw  device [ns] source coordinates, values, weights.
+ *   tx, ty, tz          device [nt] target coordinates.
+ *   tf                  device [nt] target values (required for *_SS kernels,
+ *                       ignored otherwise; may be NULL then).
+ *   out                 device [nt].
+ * Errors: TAGI_E_ARG (null pointers, sizes < 1 or >= 2^31, kappa <= 0 for
+ * Yukawa, alpha <= 0 for TAGI_COULOMB_SS), TAGI_E_OOM, TAGI_E_HIP.
+ */
+int tagi_direct(const double* sx, const double* sy, const double* sz, const double* sf,
+                const double* sw, int64_t ns, const double* tx, const double* ty,
+                const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
+                double alpha, double* out, void* stream);
+
+/* Sizes and interaction counts of the tree and its cached lists (host struct). */
+int tagi_tree_stats(const tagi_tree* tree, tagi_stats* out);
+
+/*
+ * Copies the tree to HOST buffers for inspection (any pointer may be NULL):
+ *   perm   int32 [n]       tree position -> caller index
+ *   begin, end, parent, level, n_child  int32 [n_nodes]
+ *   lo, hi double [n_nodes][3] shrunk boxes
+ * Synchronises `stream`. Errors: TAGI_E_ARG, TAGI_E_HIP.
+ */
+int tagi_tree_export(const tagi_tree* tree, int32_t* perm, int32_t* begin, int32_t* end,
+                     int32_t* parent, int32_t* level, int32_t* n_child, double* lo, double* hi,
+                     void* stream);
+
+/*
+ * Copies the cached interaction lists of (theta, degree) to HOST buffers, built
+ * first if needed: per batch b (leaf order), far clusters
+ * far_id[far_off[b] .. far_off[b+1]) and near clusters likewise, in the order
+ * ComputePotential visits them. Pass NULL id arrays to query the sizes, which are
+ * written to *n_far and *n_near (host int64). Offsets are int64 [n_leaves+1].
+ * Errors: TAGI_E_ARG, TAGI_E_STATE, TAGI_E_OOM, TAGI_E_HIP.
+ */
+int tagi_lists_export(tagi_tree* tree, double theta, int degree, int64_t* far_off,
+                      int32_t* far_id, int64_t* near_off, int32_t* near_id, int64_t* n_far,
+                      int64_t* n_near, void* stream);
+
+/*
+ * Copies the proxy data of the last tagi_upward to HOST buffers (NULL skips):
+ *   cluster  int32 [n_approx]                     node id of each approximable cluster
+ *   nodes    double [n_approx][3][degree+1]       Chebyshev points per dimension
+ *   qhat     double [n_orb][n_approx][(degree+1)^3] proxy charges of f w (k1 slowest)
+ *   what     double [n_approx][(degree+1)^3]      proxy charges of w
+ * Errors: TAGI_E_ARG, TAGI_E_STATE, TAGI_E_HIP.
+ */
+int tagi_upward_export(const tagi_tree* tree, int32_t* cluster, double* nodes, double* qhat,
+                       double* what, void* stream);
+
+/* Per-phase device time of the calls made on a tree while timing is enabled,
+ * measured with HIP events recorded on the calls' stream around each phase's
+ * kernels (host-side work between kernels is not included). */
+typedef struct {
+  double build_ms;        /* tagi_tree_build (device work and host orchestration) */
+  double upward_ms;       /* tagi_upward: gather + proxy charges */
+  double lists_ms;        /* interaction lists and schedule (only when rebuilt) */
+  double interact_ms;     /* batch-cluster interaction kernel (far + near fields) */
+  double combine_ms;      /* partial-sum reduction, subtraction term, unpermute */
+  int64_t interact_launches;
+} tagi_timing;
+
+/* Enables (1) or disables (0) phase timing on the tree; enabling resets the sums. */
+int tagi_tree_set_timing(tagi_tree* tree, int enable);
+
+/* Sums of the phase times since timing was enabled. Synchronises on the recorded
+ * events. Errors: TAGI_E_ARG, TAGI_E_HIP. */
+int tagi_tree_timing(tagi_tree* tree, tagi_timing* out);
+
+/* Frees every device buffer of the tree (synchronises the device first). NULL is a no-op. */
+int tagi_tree_destroy(tagi_tree* tree);
+
+/* Thread-local message describing the last failure on this thread ("" if none). */
+const char* tagi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TAGI_H */

@@ -1,0 +1,246 @@
+"""Thin ctypes binding over libtagi.so (include/tagi.h).
+
+Argument marshalling only: every step of the computation runs in the library's
+HIP kernels. Arrays are torch tensors on the current HIP device (float64,
+contiguous); the stream is torch's current stream. The library must have been
+built (``python -m paper_2003_01833_amd.build``); importing this module on a
+machine without it raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtagi.so")
+
+YUKAWA_SS, COULOMB_SS, YUKAWA, COULOMB = 0, 1, 2, 3
+KERNELS = {"yukawa_ss": YUKAWA_SS, "coulomb_ss": COULOMB_SS, "yukawa": YUKAWA, "coulomb": COULOMB}
+FP64, MIXED = 0, 1
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+STATUS = {0: "TAGI_OK", -1: "TAGI_E_ARG", -2: "TAGI_E_STATE", -3: "TAGI_E_OOM",
+          -4: "TAGI_E_HIP", -5: "TAGI_E_UNSUPPORTED"}
+
+EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct", "tagi_tree_stats",
+            "tagi_tree_export", "tagi_lists_export", "tagi_upward_export", "tagi_tree_set_timing",
+            "tagi_tree_timing", "tagi_tree_destroy", "tagi_last_error"]
+
+
+class TagiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_nodes", ctypes.c_int32),
+                ("n_leaves", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("n_orb", ctypes.c_int32), ("n_approx", ctypes.c_int32),
+                ("theta", ctypes.c_double), ("n_far_pairs", ctypes.c_int64),
+                ("n_near_pairs", ctypes.c_int64), ("far_interactions", ctypes.c_int64),
+                ("near_interactions", ctypes.c_int64), ("n_work_items", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("build_ms", ctypes.c_double), ("upward_ms", ctypes.c_double),
+                ("lists_ms", ctypes.c_double), ("interact_ms", ctypes.c_double),
+                ("combine_ms", ctypes.c_double), ("interact_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2003_01833_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.tagi_tree_build.argtypes = [vp, vp, vp, i64, vp, i32, vp, ctypes.POINTER(vp)]
+    lib.tagi_upward.argtypes = [vp, vp, vp, i32, i32, vp]
+    lib.tagi_convolve.argtypes = [vp, vp, i32, vp, dbl, dbl, i32, i32, vp, vp]
+    lib.tagi_direct.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, i64, i32, dbl, dbl, vp, vp]
+    lib.tagi_tree_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.tagi_tree_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.tagi_lists_export.argtypes = [vp, dbl, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.tagi_upward_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tagi_tree_destroy.argtypes = [vp]
+    lib.tagi_tree_set_timing.argtypes = [vp, i32]
+    lib.tagi_tree_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+    lib.tagi_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "tagi_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise TagiError(rc, load_library().tagi_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t: torch.Tensor | None, name: str, n: int | None = None):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 tensor on the GPU")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def direct(kernel: str, sx, sy, sz, sf, sw, tx=None, ty=None, tz=None, tf=None,
+           kappa: float = 1.0, alpha: float = 1.0, out: torch.Tensor | None = None):
+    """tagi_direct: u at the targets (default: the sources) by the direct sum."""
+    lib = load_library()
+    if tx is None:
+        tx, ty, tz, tf = sx, sy, sz, sf
+    ns, nt = sx.numel(), tx.numel()
+    if out is None:
+        out = torch.empty(nt, dtype=torch.float64, device=tx.device)
+    _check(lib.tagi_direct(_dptr(sx, "sx", ns), _dptr(sy, "sy", ns), _dptr(sz, "sz", ns),
+                           _dptr(sf, "sf", ns), _dptr(sw, "sw", ns), ns,
+                           _dptr(tx, "tx", nt), _dptr(ty, "ty", nt), _dptr(tz, "tz", nt),
+                           _dptr(tf, "tf", nt), nt, KERNELS[kernel], float(kappa), float(alpha),
+                           _dptr(out, "out", nt), _stream()))
+    return out
+
+
+class Tree:
+    """Owns a tagi_tree handle (Algorithm 3, line 1)."""
+
+    def __init__(self, x: torch.Tensor, y: torch.Tensor, z: torch.Tensor, leaf_size: int,
+                 box=None):
+        lib = load_library()
+        self.n = x.numel()
+        h = ctypes.c_void_p()
+        bx = None
+        if box is not None:
+            self._box = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(6))
+            bx = _hptr(self._box)
+        _check(lib.tagi_tree_build(_dptr(x, "x", self.n), _dptr(y, "y", self.n),
+                                   _dptr(z, "z", self.n), self.n, bx, int(leaf_size), _stream(),
+                                   ctypes.byref(h)))
+        self._h = h
+        self.n_orb = 0
+        self.degree = 0
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().tagi_tree_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upward(self, f: torch.Tensor, w: torch.Tensor, degree: int):
+        """Algorithm 3, line 2: proxy charges; f is (n,) or (n_orb, n)."""
+        n_orb = 1 if f.dim() == 1 else f.shape[0]
+        _check(load_library().tagi_upward(self._h, _dptr(f, "f", n_orb * self.n),
+                                          _dptr(w, "w", self.n), n_orb, int(degree), _stream()))
+        self.n_orb, self.degree = n_orb, int(degree)
+
+    def convolve(self, kernel: str, kappa, theta: float, degree: int | None = None,
+                 alpha: float = 1.0, precision: str = "fp64", out: torch.Tensor | None = None):
+        """Algorithm 3, line 3 plus the subtraction term; returns (n_orb, n) in caller order."""
+        degree = self.degree if degree is None else degree
+        kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64),
+                                                   (max(self.n_orb, 1),)))
+        self._kap = kap
+        if out is None:
+            out = torch.empty((max(self.n_orb, 1), self.n), dtype=torch.float64, device="cuda")
+        _check(load_library().tagi_convolve(self._h, None, KERNELS[kernel], _hptr(kap),
+                                            float(alpha), float(theta), int(degree),
+                                            PRECISIONS[precision],
+                                            _dptr(out, "out", max(self.n_orb, 1) * self.n),
+                                            _stream()))
+        return out
+
+    def set_timing(self, enable: bool = True):
+        _check(load_library().tagi_tree_set_timing(self._h, int(bool(enable))))
+
+    def timing(self) -> dict:
+        tm = Timing()
+        _check(load_library().tagi_tree_timing(self._h, ctypes.byref(tm)))
+        return tm.as_dict()
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load_library().tagi_tree_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def export(self) -> dict:
+        st = self.stats()
+        nn = st["n_nodes"]
+        perm = np.empty(self.n, np.int32)
+        arrs = {k: np.empty(nn, np.int32) for k in ("begin", "end", "parent", "level", "n_child")}
+        lo = np.empty((nn, 3))
+        hi = np.empty((nn, 3))
+        _check(load_library().tagi_tree_export(self._h, _hptr(perm), _hptr(arrs["begin"]),
+                                               _hptr(arrs["end"]), _hptr(arrs["parent"]),
+                                               _hptr(arrs["level"]), _hptr(arrs["n_child"]),
+                                               _hptr(lo), _hptr(hi), _stream()))
+        return dict(perm=perm, lo=lo, hi=hi, **arrs)
+
+    def lists(self, theta: float, degree: int) -> dict:
+        lib = load_library()
+        nf, nn = ctypes.c_int64(), ctypes.c_int64()
+        nl = self.stats()["n_leaves"]
+        foff = np.empty(nl + 1, np.int64)
+        noff = np.empty(nl + 1, np.int64)
+        _check(lib.tagi_lists_export(self._h, float(theta), int(degree), _hptr(foff), None,
+                                     _hptr(noff), None, ctypes.byref(nf), ctypes.byref(nn),
+                                     _stream()))
+        fid = np.empty(max(nf.value, 1), np.int32)
+        nid = np.empty(max(nn.value, 1), np.int32)
+        _check(lib.tagi_lists_export(self._h, float(theta), int(degree), None, _hptr(fid), None,
+                                     _hptr(nid), None, None, _stream()))
+        return dict(far_off=foff, far_id=fid[:nf.value], near_off=noff, near_id=nid[:nn.value])
+
+    def proxies(self) -> dict:
+        st = self.stats()
+        na, p1 = st["n_approx"], st["degree"] + 1
+        cl = np.empty(max(na, 1), np.int32)
+        nodes = np.empty((max(na, 1), 3, p1))
+        qh = np.empty((st["n_orb"], max(na, 1), p1 ** 3))
+        wh = np.empty((max(na, 1), p1 ** 3))
+        _check(load_library().tagi_upward_export(self._h, _hptr(cl), _hptr(nodes), _hptr(qh),
+                                                 _hptr(wh), _stream()))
+        return dict(cluster=cl[:na], nodes=nodes[:na], qhat=qh[:, :na], what=wh[:na])
+
+
+def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_size: int,
+             alpha: float = 1.0, box=None, precision: str = "fp64"):
+    """Whole path: tree, upward pass, lists and convolution (one call each)."""
+    t = Tree(x, y, z, leaf_size, box)
+    try:
+        t.upward(f, w, degree)
+        return t.convolve(kernel, kappa, theta, degree, alpha=alpha, precision=precision)
+    finally:
+        torch.cuda.synchronize()
+        t.close()

@@ -1,0 +1,339 @@
+// The C ABI declared in include/tagi.h: argument validation, error state, and
+// dispatch to the tree, upward, list and interaction stages.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace tagi {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int DBuf::ensure(size_t bytes) {
+  if (bytes <= cap && p) return TAGI_OK;
+  if (p) {
+    (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? TAGI_E_OOM : TAGI_E_HIP;
+  }
+  cap = bytes;
+  return TAGI_OK;
+}
+
+void DBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+}  // namespace tagi
+
+using namespace tagi;
+
+#define REQUIRE(cond, ...)         \
+  do {                             \
+    if (!(cond)) {                 \
+      set_error(__VA_ARGS__);      \
+      return TAGI_E_ARG;           \
+    }                              \
+  } while (0)
+
+static bool valid_kernel(int k) { return k >= TAGI_YUKAWA_SS && k <= TAGI_COULOMB; }
+static bool is_yukawa(int k) { return k == TAGI_YUKAWA_SS || k == TAGI_YUKAWA; }
+
+#pragma GCC visibility push(default)
+extern "C" {
+
+const char* tagi_last_error(void) { return g_err; }
+
+int tagi_tree_build(const double* x, const double* y, const double* z, int64_t n,
+                    const double* box, int leaf_size, void* stream, tagi_tree** out) {
+  g_err[0] = 0;
+  REQUIRE(out, "tagi_tree_build: out is NULL");
+  *out = nullptr;
+  REQUIRE(x && y && z, "tagi_tree_build: null coordinate array");
+  REQUIRE(n >= 1 && n < (int64_t)INT32_MAX, "tagi_tree_build: n = %lld out of range [1, 2^31)",
+          (long long)n);
+  REQUIRE(leaf_size >= 1, "tagi_tree_build: leaf_size = %d must be >= 1", leaf_size);
+  if (box) {
+    for (int k = 0; k < 3; ++k)
+      REQUIRE(std::isfinite(box[k]) && std::isfinite(box[3 + k]) && box[k] <= box[3 + k],
+              "tagi_tree_build: box dimension %d is empty or not finite", k);
+  }
+  tagi_tree* t = new (std::nothrow) tagi_tree();
+  if (!t) {
+    set_error("tagi_tree_build: host allocation failed");
+    return TAGI_E_OOM;
+  }
+  (void)hipGetDevice(&t->device);
+  t->n = n;
+  t->leaf_size = leaf_size;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int st = build_tree(t, x, y, z, box, (hipStream_t)stream);
+  t->build_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st != TAGI_OK) {
+    char keep[1024];
+    std::memcpy(keep, g_err, sizeof(keep));
+    tagi_tree_destroy(t);
+    std::memcpy(g_err, keep, sizeof(keep));
+    return st;
+  }
+  *out = t;
+  return TAGI_OK;
+}
+
+int tagi_upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree,
+                void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_upward: tree is NULL");
+  REQUIRE(f && w, "tagi_upward: null f or w");
+  REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb, "tagi_upward: n_orb = %d out of range [1, %d]", n_orb,
+          kMaxOrb);
+  REQUIRE(degree >= 1 && degree <= kMaxDegree, "tagi_upward: degree = %d out of range [1, %d]",
+          degree, kMaxDegree);
+  return upward(t, f, w, n_orb, degree, (hipStream_t)stream);
+}
+
+int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* kappa,
+                  double alpha, double theta, int degree, int precision, double* out,
+                  void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_convolve: tree is NULL");
+  REQUIRE(out, "tagi_convolve: out is NULL");
+  REQUIRE(valid_kernel(kernel), "tagi_convolve: unknown kernel %d", kernel);
+  REQUIRE(precision == TAGI_FP64 || precision == TAGI_MIXED,
+          "tagi_convolve: unknown precision %d", precision);
+  REQUIRE(theta >= 0.0 && theta < 1.0, "tagi_convolve: theta = %g out of range [0, 1)", theta);
+  REQUIRE(degree >= 1 && degree <= kMaxDegree, "tagi_convolve: degree = %d out of range", degree);
+  if (targets) {
+    set_error("tagi_convolve: separate target sets are not supported (targets must be NULL)");
+    return TAGI_E_UNSUPPORTED;
+  }
+  if (t->degree == 0) {
+    set_error("tagi_convolve: tagi_upward has not run on this tree");
+    return TAGI_E_STATE;
+  }
+  if (t->degree != degree) {
+    set_error("tagi_convolve: degree %d differs from the upward pass degree %d", degree, t->degree);
+    return TAGI_E_STATE;
+  }
+  if (is_yukawa(kernel)) {
+    REQUIRE(kappa, "tagi_convolve: kappa is NULL for a Yukawa kernel");
+    for (int o = 0; o < t->n_orb; ++o)
+      REQUIRE(std::isfinite(kappa[o]) && kappa[o] > 0.0,
+              "tagi_convolve: kappa[%d] = %g must be finite and > 0", o, kappa[o]);
+  }
+  if (kernel == TAGI_COULOMB_SS)
+    REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_convolve: alpha = %g must be > 0", alpha);
+  if (precision == TAGI_MIXED) {
+    set_error("tagi_convolve: TAGI_MIXED is not available in this build");
+    return TAGI_E_UNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int ob = orbital_block(kernel, t->n_orb);
+  const bool rebuild = !(t->list_theta == theta && t->list_degree == degree) ||
+                       !(t->items_orb_block == ob && t->items_n_orb == t->n_orb && t->n_items > 0);
+  if (rebuild) {
+    phase_begin(t, kPhaseLists, s);
+    int st = ensure_lists(t, theta, degree, s);
+    if (st == TAGI_OK) st = ensure_schedule(t, ob, s);
+    phase_end(t, kPhaseLists, s);
+    if (st != TAGI_OK) return st;
+  }
+  return convolve(t, kernel, kappa, alpha, precision, out, s);
+}
+
+int tagi_direct(const double* sx, const double* sy, const double* sz, const double* sf,
+                const double* sw, int64_t ns, const double* tx, const double* ty,
+                const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
+                double alpha, double* out, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(valid_kernel(kernel), "tagi_direct: unknown kernel %d", kernel);
+  REQUIRE(sx && sy && sz && sf && sw, "tagi_direct: null source array");
+  REQUIRE(tx && ty && tz && out, "tagi_direct: null target or output array");
+  REQUIRE(ns >= 1 && ns < (int64_t)INT32_MAX, "tagi_direct: ns = %lld out of range", (long long)ns);
+  REQUIRE(nt >= 1 && nt < (int64_t)INT32_MAX, "tagi_direct: nt = %lld out of range", (long long)nt);
+  const bool ss = kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS;
+  REQUIRE(!ss || tf, "tagi_direct: target values tf are required for subtracted kernels");
+  if (is_yukawa(kernel))
+    REQUIRE(std::isfinite(kappa) && kappa > 0.0, "tagi_direct: kappa = %g must be > 0", kappa);
+  if (kernel == TAGI_COULOMB_SS)
+    REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_direct: alpha = %g must be > 0", alpha);
+  return direct(sx, sy, sz, sf, sw, ns, tx, ty, tz, tf, nt, kernel, kappa, alpha, out,
+                (hipStream_t)stream);
+}
+
+int tagi_tree_stats(const tagi_tree* t, tagi_stats* o) {
+  g_err[0] = 0;
+  REQUIRE(t && o, "tagi_tree_stats: null argument");
+  std::memset(o, 0, sizeof(*o));
+  o->n_points = t->n;
+  o->n_nodes = (int32_t)t->nodes.size();
+  o->n_leaves = (int32_t)t->leaves.size();
+  o->max_level = t->max_level;
+  o->leaf_size = t->leaf_size;
+  o->degree = t->degree;
+  o->n_orb = t->n_orb;
+  o->n_approx = t->n_approx;
+  o->theta = t->list_degree >= 0 ? t->list_theta : -1.0;
+  o->n_far_pairs = t->list_degree >= 0 ? t->n_far : 0;
+  o->n_near_pairs = t->list_degree >= 0 ? t->n_near : 0;
+  o->far_interactions = t->list_degree >= 0 ? t->far_inter : 0;
+  o->near_interactions = t->list_degree >= 0 ? t->near_inter : 0;
+  o->n_work_items = t->n_items;
+  return TAGI_OK;
+}
+
+int tagi_tree_export(const tagi_tree* t, int32_t* perm, int32_t* begin, int32_t* end,
+                     int32_t* parent, int32_t* level, int32_t* n_child, double* lo, double* hi,
+                     void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_tree_export: tree is NULL");
+  if (perm) {
+    TAGI_HIP(hipMemcpyAsync(perm, t->perm.p, t->n * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            (hipStream_t)stream));
+    TAGI_HIP(hipStreamSynchronize((hipStream_t)stream));
+  }
+  for (size_t c = 0; c < t->nodes.size(); ++c) {
+    const HostNode& q = t->nodes[c];
+    if (begin) begin[c] = q.begin;
+    if (end) end[c] = q.end;
+    if (parent) parent[c] = q.parent;
+    if (level) level[c] = q.level;
+    if (n_child) n_child[c] = q.n_child;
+    for (int k = 0; k < 3; ++k) {
+      if (lo) lo[c * 3 + k] = q.lo[k];
+      if (hi) hi[c * 3 + k] = q.hi[k];
+    }
+  }
+  return TAGI_OK;
+}
+
+int tagi_lists_export(tagi_tree* t, double theta, int degree, int64_t* far_off, int32_t* far_id,
+                      int64_t* near_off, int32_t* near_id, int64_t* n_far, int64_t* n_near,
+                      void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_lists_export: tree is NULL");
+  REQUIRE(theta >= 0.0 && theta < 1.0, "tagi_lists_export: theta out of range");
+  REQUIRE(degree >= 1 && degree <= kMaxDegree, "tagi_lists_export: degree out of range");
+  hipStream_t s = (hipStream_t)stream;
+  int st = ensure_lists(t, theta, degree, s);
+  if (st != TAGI_OK) return st;
+  const size_t nl1 = t->leaves.size() + 1;
+  if (n_far) *n_far = t->n_far;
+  if (n_near) *n_near = t->n_near;
+  if (far_off) std::memcpy(far_off, t->h_far_off.data(), nl1 * sizeof(int64_t));
+  if (near_off) std::memcpy(near_off, t->h_near_off.data(), nl1 * sizeof(int64_t));
+  if (far_id && t->n_far)
+    TAGI_HIP(hipMemcpyAsync(far_id, t->far_id.p, t->n_far * 4, hipMemcpyDeviceToHost, s));
+  if (near_id && t->n_near)
+    TAGI_HIP(hipMemcpyAsync(near_id, t->near_id.p, t->n_near * 4, hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  return TAGI_OK;
+}
+
+int tagi_upward_export(const tagi_tree* t, int32_t* cluster, double* nodes, double* qhat,
+                       double* what, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_upward_export: tree is NULL");
+  if (t->degree == 0) {
+    set_error("tagi_upward_export: tagi_upward has not run on this tree");
+    return TAGI_E_STATE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const size_t na = t->n_approx, np1 = t->degree + 1, K = np1 * np1 * np1;
+  if (cluster && na) std::memcpy(cluster, t->approx_nodes.data(), na * 4);
+  if (nodes && na)
+    TAGI_HIP(hipMemcpyAsync(nodes, t->pnodes.p, na * 3 * np1 * 8, hipMemcpyDeviceToHost, s));
+  if (qhat && na)
+    TAGI_HIP(hipMemcpyAsync(qhat, t->qhat.p, (size_t)t->n_orb * na * K * 8, hipMemcpyDeviceToHost, s));
+  if (what && na)
+    TAGI_HIP(hipMemcpyAsync(what, t->what.p, na * K * 8, hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  return TAGI_OK;
+}
+
+static void drop_events(tagi_tree* t) {
+  for (auto& v : t->events) {
+    for (auto& e : v) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    v.clear();
+  }
+}
+
+int tagi_tree_set_timing(tagi_tree* t, int enable) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_tree_set_timing: tree is NULL");
+  (void)hipDeviceSynchronize();
+  drop_events(t);
+  for (double& v : t->phase_ms) v = 0.0;
+  t->interact_launches = 0;
+  t->timing = enable != 0;
+  return TAGI_OK;
+}
+
+int tagi_tree_timing(tagi_tree* t, tagi_timing* o) {
+  g_err[0] = 0;
+  REQUIRE(t && o, "tagi_tree_timing: null argument");
+  for (int ph = 0; ph < 4; ++ph) {
+    for (auto& e : t->events[ph]) {
+      TAGI_HIP(hipEventSynchronize(e.second));
+      float ms = 0.f;
+      TAGI_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+      t->phase_ms[ph] += ms;
+    }
+  }
+  drop_events(t);
+  o->build_ms = t->build_ms;
+  o->upward_ms = t->phase_ms[kPhaseUpward];
+  o->lists_ms = t->phase_ms[kPhaseLists];
+  o->interact_ms = t->phase_ms[kPhaseInteract];
+  o->combine_ms = t->phase_ms[kPhaseCombine];
+  o->interact_launches = t->interact_launches;
+  return TAGI_OK;
+}
+
+int tagi_tree_destroy(tagi_tree* t) {
+  if (!t) return TAGI_OK;
+  (void)hipDeviceSynchronize();
+  drop_events(t);
+  DBuf* bufs[] = {&t->perm, &t->xs, &t->ys, &t->zs, &t->leaf_of_pos, &t->nd_begin, &t->nd_end,
+                  &t->nd_first_child, &t->nd_n_child, &t->nd_geom, &t->nd_box, &t->leaf_node,
+                  &t->slot_of_node, &t->approx_node, &t->pnodes, &t->qhat, &t->what,
+                  &t->pnodes32, &t->ws, &t->fs, &t->qs, &t->up_items, &t->up_partial,
+                  &t->far_off, &t->near_off, &t->far_id, &t->near_id, &t->chunks, &t->items,
+                  &t->group_first_item, &t->batch_group_base, &t->batch_chunks, &t->partial,
+                  &t->kappa_dev};
+  for (DBuf* b : bufs) b->release();
+  delete t;
+  return TAGI_OK;
+}
+
+}  // extern "C"
+#pragma GCC visibility pop

@@ -1,0 +1,160 @@
+// Internal declarations shared by the HIP translation units of libtagi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tagi.h"
+
+namespace tagi {
+
+// ---------------------------------------------------------------------------
+// error state
+
+void set_error(const char* fmt, ...);
+
+#define TAGI_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::tagi::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                        __FILE__, __LINE__);                                        \
+      return e_ == hipErrorOutOfMemory ? TAGI_E_OOM : TAGI_E_HIP;                   \
+    }                                                                               \
+  } while (0)
+
+#define TAGI_TRY(expr)      \
+  do {                      \
+    int s_ = (expr);        \
+    if (s_ != TAGI_OK) return s_; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// grow-only device buffer
+
+struct DBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int ensure(size_t bytes);   // reallocates (contents lost) when too small
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// tree handle
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxDegree = 16;
+constexpr int kMaxOrb = 64;
+
+struct HostNode {
+  int32_t begin, end, parent, level, first_child, n_child;
+  double lo[3], hi[3];
+};
+
+}  // namespace tagi
+
+struct tagi_tree {
+  int device = 0;
+  int64_t n = 0;
+  int leaf_size = 0;
+  // host copy of the nodes (level order) and leaves
+  std::vector<tagi::HostNode> nodes;
+  std::vector<int32_t> leaves;   // node ids of the leaves, in node order
+  int max_level = 0;
+
+  // device: tree-ordered sources
+  tagi::DBuf perm;                  // int32 [n]
+  tagi::DBuf xs, ys, zs;            // double [n]
+  tagi::DBuf leaf_of_pos;           // int32 [n] batch index of each tree position
+  // device: nodes
+  tagi::DBuf nd_begin, nd_end, nd_first_child, nd_n_child;  // int32 [n_nodes]
+  tagi::DBuf nd_geom;               // double [n_nodes][4] centre xyz, radius
+  tagi::DBuf nd_box;                // double [n_nodes][6] lo xyz, hi xyz
+  tagi::DBuf leaf_node;             // int32 [n_leaves]
+
+  // upward state
+  int degree = 0;
+  int n_orb = 0;
+  int n_approx = 0;
+  std::vector<int32_t> approx_nodes;  // host: node id per slot
+  std::vector<int32_t> h_slot_of;     // host staging kept alive across async uploads
+  std::vector<int32_t> h_up_items;
+  std::vector<int32_t> h_slot_first;
+  tagi::DBuf slot_of_node;          // int32 [n_nodes], -1 if none
+  tagi::DBuf approx_node;           // int32 [n_approx]
+  tagi::DBuf pnodes;                // double [n_approx][3][degree+1]
+  tagi::DBuf qhat;                  // double [n_orb][n_approx][(degree+1)^3]
+  tagi::DBuf what;                  // double [n_approx][(degree+1)^3]
+  tagi::DBuf pnodes32;              // float [n_approx][3][degree+1], centred on the cluster
+  tagi::DBuf ws;                    // double [n] tree-ordered weights
+  tagi::DBuf fs;                    // double [n_orb][n] tree-ordered values
+  tagi::DBuf qs;                    // double [n_orb][n] f*w tree-ordered
+  tagi::DBuf up_items, up_partial;  // upward work items and partial charges
+
+  // cached interaction lists and compute schedule
+  double list_theta = -1.0;
+  int list_degree = -1;
+  int64_t n_far = 0, n_near = 0;
+  int64_t far_inter = 0, near_inter = 0;
+  tagi::DBuf far_off, near_off;     // int64 [n_leaves+1]
+  tagi::DBuf far_id, near_id;       // int32
+  std::vector<int64_t> h_far_off, h_near_off;
+  // schedule: chunks of (kind, begin, end) per batch, items, group table
+  int64_t n_items = 0;
+  int items_orb_block = 0;
+  int items_n_orb = 0;
+  tagi::DBuf chunks;                // int4 {kind, e0, e1, cost}
+  tagi::DBuf items;                 // int4 {batch, group, oblock, chunk}
+  tagi::DBuf group_first_item;      // int32 per (batch, group)
+  tagi::DBuf batch_group_base;      // int32 [n_leaves] first (batch, group) index
+  tagi::DBuf batch_chunks;          // int2 [n_leaves] {first chunk, n chunks}
+  tagi::DBuf partial;               // double partial sums per item
+  tagi::DBuf kappa_dev;             // double [n_orb]
+
+  // phase timing (HIP events on the calls' stream)
+  bool timing = false;
+  double build_ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events[4];  // upward, lists, interact, combine
+  double phase_ms[4] = {0, 0, 0, 0};
+  int64_t interact_launches = 0;
+};
+
+namespace tagi {
+
+enum Phase { kPhaseUpward = 0, kPhaseLists = 1, kPhaseInteract = 2, kPhaseCombine = 3 };
+
+inline void phase_begin(tagi_tree* t, int ph, hipStream_t s) {
+  if (!t->timing) return;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return;
+  }
+  (void)hipEventRecord(a, s);
+  t->events[ph].push_back({a, b});
+}
+
+inline void phase_end(tagi_tree* t, int ph, hipStream_t s) {
+  if (!t->timing || t->events[ph].empty()) return;
+  (void)hipEventRecord(t->events[ph].back().second, s);
+}
+
+int build_tree(tagi_tree* t, const double* x, const double* y, const double* z,
+               const double* box, hipStream_t s);
+int upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree, hipStream_t s);
+int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s);
+int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s);
+int orbital_block(int kernel, int n_orb);
+int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
+             double* out, hipStream_t s);
+int direct(const double* sx, const double* sy, const double* sz, const double* sf,
+           const double* sw, int64_t ns, const double* tx, const double* ty, const double* tz,
+           const double* tf, int64_t nt, int kernel, double kappa, double alpha, double* out,
+           hipStream_t s);
+
+}  // namespace tagi

@@ -1,0 +1,285 @@
+// Algorithm 3, line 3 (Section 6.3): the interaction lists of every target batch,
+// precomputed as the paper's GPU implementation does, and the compute schedule.
+//
+// One thread per batch runs ComputePotential(B, root) with an explicit stack
+// (children pushed in reverse so they are visited in order, which reproduces the
+// recursive visiting order). MAC (Eq. MAC): a pair is approximated iff
+// (r_B + r_C) < theta R and (n+1)^3 < N_S; if the distance test fails, a leaf is
+// summed directly and a non-leaf is opened; if only the size test fails, the
+// whole cluster is summed directly. A count pass and a fill pass write CSR
+// lists (far = approximated, near = direct).
+//
+// Schedule: each batch's far list and near list are cut into chunks of bounded
+// cost (|B| (n+1)^3 per far pair, |B| N_S per near pair); a work item is
+// (batch, 64-target group, orbital block, chunk) and is processed by one wave.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace tagi {
+namespace {
+
+constexpr int kStack = 512;
+
+__device__ __forceinline__ bool distance_ok(const double* __restrict__ geom, int B, int C,
+                                            double theta) {
+#pragma clang fp contract(off)
+  const double dx = geom[B * 4 + 0] - geom[C * 4 + 0];
+  const double dy = geom[B * 4 + 1] - geom[C * 4 + 1];
+  const double dz = geom[B * 4 + 2] - geom[C * 4 + 2];
+  const double R = sqrt(dx * dx + dy * dy + dz * dz);
+  return (geom[B * 4 + 3] + geom[C * 4 + 3]) < theta * R;
+}
+
+// fill == 0: write counts (far pairs, near pairs, near sources) per batch;
+// fill == 1: write the ids at the given offsets.
+__global__ void k_lists(int n_leaves, const int32_t* __restrict__ leaf_node,
+                        const double* __restrict__ geom, const int32_t* __restrict__ nbeg,
+                        const int32_t* __restrict__ nend, const int32_t* __restrict__ first_child,
+                        const int32_t* __restrict__ n_child, double theta, int K, int fill,
+                        int64_t* __restrict__ far_cnt, int64_t* __restrict__ near_cnt,
+                        int64_t* __restrict__ near_src, const int64_t* __restrict__ far_off,
+                        const int64_t* __restrict__ near_off, int32_t* __restrict__ far_id,
+                        int32_t* __restrict__ near_id, int32_t* __restrict__ overflow) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_leaves) return;
+  const int B = leaf_node[b];
+  int stack[kStack];
+  int sp = 0;
+  stack[sp++] = 0;
+  int64_t nf = 0, nn = 0, ns = 0;
+  int64_t fo = fill ? far_off[b] : 0, no = fill ? near_off[b] : 0;
+  while (sp > 0) {
+    const int C = stack[--sp];
+    const int cnt = nend[C] - nbeg[C];
+    const bool dist = distance_ok(geom, B, C, theta);
+    const bool size = K < cnt;
+    int kind;  // 0 far, 1 near, 2 open
+    if (dist && size)
+      kind = 0;
+    else if (!dist)
+      kind = n_child[C] == 0 ? 1 : 2;
+    else
+      kind = 1;
+    if (kind == 0) {
+      if (fill) far_id[fo + nf] = C;
+      ++nf;
+    } else if (kind == 1) {
+      if (fill) near_id[no + nn] = C;
+      ++nn;
+      ns += cnt;
+    } else {
+      const int fc = first_child[C], nc = n_child[C];
+      if (sp + nc > kStack) {
+        atomicExch(overflow, 1);
+        return;
+      }
+      for (int k = nc - 1; k >= 0; --k) stack[sp++] = fc + k;
+    }
+  }
+  if (!fill) {
+    far_cnt[b] = nf;
+    near_cnt[b] = nn;
+    near_src[b] = ns;
+  }
+}
+
+// chunks: per batch, cut the far and near lists into pieces of cost <= cap
+struct Chunk {
+  int32_t kind, e0, e1, cost;
+};
+
+__global__ void k_chunks(int n_leaves, const int32_t* __restrict__ nbeg,
+                         const int32_t* __restrict__ nend, const int64_t* __restrict__ far_off,
+                         const int64_t* __restrict__ near_off, const int32_t* __restrict__ near_id,
+                         int K, int64_t cap, int fill, int32_t* __restrict__ n_chunks,
+                         const int32_t* __restrict__ chunk_off, Chunk* __restrict__ chunks) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_leaves) return;
+  int nc = 0;
+  int32_t co = fill ? chunk_off[b] : 0;
+  for (int kind = 0; kind < 2; ++kind) {
+    const int64_t e0 = kind == 0 ? far_off[b] : near_off[b];
+    const int64_t e1 = kind == 0 ? far_off[b + 1] : near_off[b + 1];
+    int64_t start = e0, cost = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+      const int64_t c = kind == 0 ? K : (int64_t)(nend[near_id[e]] - nbeg[near_id[e]]);
+      if (cost > 0 && cost + c > cap) {
+        if (fill) chunks[co + nc] = Chunk{kind, (int32_t)start, (int32_t)e, (int32_t)min(cost, (int64_t)INT32_MAX)};
+        ++nc;
+        start = e;
+        cost = 0;
+      }
+      cost += c;
+    }
+    if (e1 > start) {
+      if (fill) chunks[co + nc] = Chunk{kind, (int32_t)start, (int32_t)e1, (int32_t)min(cost, (int64_t)INT32_MAX)};
+      ++nc;
+    }
+  }
+  if (!fill) n_chunks[b] = nc;
+}
+
+}  // namespace
+
+int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
+  if (t->list_theta == theta && t->list_degree == degree) return TAGI_OK;
+  t->list_theta = -1.0;
+  t->list_degree = -1;
+  t->items_orb_block = 0;
+  t->n_items = 0;
+  const int nl = (int)t->leaves.size();
+  const int np1 = degree + 1;
+  const int K = np1 * np1 * np1;
+  DBuf cnt;
+  TAGI_TRY(cnt.ensure((size_t)nl * 3 * sizeof(int64_t) + sizeof(int32_t)));
+  int64_t* d_far_cnt = cnt.as<int64_t>();
+  int64_t* d_near_cnt = d_far_cnt + nl;
+  int64_t* d_near_src = d_near_cnt + nl;
+  int32_t* d_over = reinterpret_cast<int32_t*>(d_near_src + nl);
+  TAGI_HIP(hipMemsetAsync(d_over, 0, sizeof(int32_t), s));
+  const int blk = 128, grid = (nl + blk - 1) / blk;
+  hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, t->leaf_node.as<int32_t>(),
+                     t->nd_geom.as<double>(), t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(),
+                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K, 0,
+                     d_far_cnt, d_near_cnt, d_near_src, nullptr, nullptr, nullptr, nullptr,
+                     d_over);
+  TAGI_HIP(hipGetLastError());
+  std::vector<int64_t> h(3 * (size_t)nl);
+  int32_t over = 0;
+  TAGI_HIP(hipMemcpyAsync(h.data(), d_far_cnt, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipMemcpyAsync(&over, d_over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  if (over) {
+    cnt.release();
+    set_error("interaction-list traversal stack overflow (tree deeper than supported)");
+    return TAGI_E_UNSUPPORTED;
+  }
+  t->h_far_off.assign(nl + 1, 0);
+  t->h_near_off.assign(nl + 1, 0);
+  t->far_inter = t->near_inter = 0;
+  for (int b = 0; b < nl; ++b) {
+    t->h_far_off[b + 1] = t->h_far_off[b] + h[b];
+    t->h_near_off[b + 1] = t->h_near_off[b] + h[nl + b];
+    const HostNode& q = t->nodes[t->leaves[b]];
+    const int64_t nb = q.end - q.begin;
+    t->far_inter += nb * h[b] * K;
+    t->near_inter += nb * h[2 * (size_t)nl + b];
+  }
+  t->n_far = t->h_far_off[nl];
+  t->n_near = t->h_near_off[nl];
+  if (t->n_far >= INT32_MAX || t->n_near >= INT32_MAX) {
+    cnt.release();
+    set_error("interaction lists exceed 2^31 entries");
+    return TAGI_E_UNSUPPORTED;
+  }
+  TAGI_TRY(t->far_off.ensure((nl + 1) * sizeof(int64_t)));
+  TAGI_TRY(t->near_off.ensure((nl + 1) * sizeof(int64_t)));
+  TAGI_TRY(t->far_id.ensure(std::max<int64_t>(t->n_far, 1) * 4));
+  TAGI_TRY(t->near_id.ensure(std::max<int64_t>(t->n_near, 1) * 4));
+  TAGI_HIP(hipMemcpyAsync(t->far_off.p, t->h_far_off.data(), (nl + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+  TAGI_HIP(hipMemcpyAsync(t->near_off.p, t->h_near_off.data(), (nl + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, t->leaf_node.as<int32_t>(),
+                     t->nd_geom.as<double>(), t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(),
+                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K, 1,
+                     nullptr, nullptr, nullptr, t->far_off.as<int64_t>(),
+                     t->near_off.as<int64_t>(), t->far_id.as<int32_t>(),
+                     t->near_id.as<int32_t>(), d_over);
+  TAGI_HIP(hipGetLastError());
+  TAGI_HIP(hipStreamSynchronize(s));
+  cnt.release();
+  t->list_theta = theta;
+  t->list_degree = degree;
+  return TAGI_OK;
+}
+
+int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
+  if (t->items_orb_block == orb_block && t->items_n_orb == t->n_orb && t->n_items > 0)
+    return TAGI_OK;
+  t->items_orb_block = 0;
+  t->n_items = 0;
+  const int nl = (int)t->leaves.size();
+  const int np1 = t->list_degree + 1;
+  const int K = np1 * np1 * np1;
+  // cost cap per chunk (kernel evaluations per target lane): small enough to give
+  // every SIMD several items, large enough to amortise the per-item overhead
+  const int64_t total = (t->n_far * (int64_t)K) + t->near_inter / std::max<int64_t>(1, t->n / nl);
+  int64_t cap = std::max<int64_t>(total / 16384, 16 * (int64_t)K);
+  cap = std::max<int64_t>(cap, 4096);
+  DBuf nch;
+  TAGI_TRY(nch.ensure((size_t)(nl + 1) * 2 * sizeof(int32_t)));
+  int32_t* d_nch = nch.as<int32_t>();
+  int32_t* d_choff = d_nch + nl + 1;
+  const int blk = 128, grid = (nl + blk - 1) / blk;
+  hipLaunchKernelGGL(k_chunks, dim3(grid), dim3(blk), 0, s, nl, t->nd_begin.as<int32_t>(),
+                     t->nd_end.as<int32_t>(), t->far_off.as<int64_t>(), t->near_off.as<int64_t>(),
+                     t->near_id.as<int32_t>(), K, cap, 0, d_nch, nullptr, nullptr);
+  TAGI_HIP(hipGetLastError());
+  std::vector<int32_t> hn(nl);
+  TAGI_HIP(hipMemcpyAsync(hn.data(), d_nch, nl * 4, hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> choff(nl + 1, 0);
+  for (int b = 0; b < nl; ++b) choff[b + 1] = choff[b] + hn[b];
+  const int64_t n_chunks = choff[nl];
+  TAGI_TRY(t->chunks.ensure(std::max<int64_t>(n_chunks, 1) * sizeof(Chunk)));
+  TAGI_HIP(hipMemcpyAsync(d_choff, choff.data(), nl * 4, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_chunks, dim3(grid), dim3(blk), 0, s, nl, t->nd_begin.as<int32_t>(),
+                     t->nd_end.as<int32_t>(), t->far_off.as<int64_t>(), t->near_off.as<int64_t>(),
+                     t->near_id.as<int32_t>(), K, cap, 1, d_nch, d_choff, t->chunks.as<Chunk>());
+  TAGI_HIP(hipGetLastError());
+  // items in (batch, group, orbital block, chunk) order
+  const int n_ob = (t->n_orb + orb_block - 1) / orb_block;
+  std::vector<int32_t> items;
+  std::vector<int32_t> group_first;
+  std::vector<int32_t> group_base(nl);
+  std::vector<int32_t> bch(2 * (size_t)nl);
+  for (int b = 0; b < nl; ++b) {
+    const HostNode& q = t->nodes[t->leaves[b]];
+    const int ng = (q.end - q.begin + kWave - 1) / kWave;
+    group_base[b] = (int32_t)group_first.size();
+    bch[2 * b] = choff[b];
+    bch[2 * b + 1] = hn[b];
+    for (int g = 0; g < ng; ++g) {
+      group_first.push_back((int32_t)(items.size() / 4));
+      for (int ob = 0; ob < n_ob; ++ob)
+        for (int c = 0; c < hn[b]; ++c) {
+          items.push_back(b);
+          items.push_back(g);
+          items.push_back(ob);
+          items.push_back(choff[b] + c);
+        }
+    }
+  }
+  t->n_items = (int64_t)items.size() / 4;
+  if (t->n_items >= INT32_MAX) {
+    nch.release();
+    set_error("compute schedule exceeds 2^31 work items");
+    return TAGI_E_UNSUPPORTED;
+  }
+  TAGI_TRY(t->items.ensure(std::max<size_t>(items.size(), 4) * 4));
+  TAGI_TRY(t->group_first_item.ensure(std::max<size_t>(group_first.size(), 1) * 4));
+  TAGI_TRY(t->batch_group_base.ensure((size_t)nl * 4));
+  TAGI_TRY(t->batch_chunks.ensure((size_t)nl * 8));
+  if (!items.empty())
+    TAGI_HIP(hipMemcpyAsync(t->items.p, items.data(), items.size() * 4, hipMemcpyHostToDevice, s));
+  if (!group_first.empty())
+    TAGI_HIP(hipMemcpyAsync(t->group_first_item.p, group_first.data(), group_first.size() * 4,
+                            hipMemcpyHostToDevice, s));
+  TAGI_HIP(hipMemcpyAsync(t->batch_group_base.p, group_base.data(), (size_t)nl * 4,
+                          hipMemcpyHostToDevice, s));
+  TAGI_HIP(hipMemcpyAsync(t->batch_chunks.p, bch.data(), (size_t)nl * 8, hipMemcpyHostToDevice, s));
+  TAGI_TRY(t->partial.ensure(std::max<int64_t>(t->n_items, 1) * orb_block * 2 * kWave * sizeof(double)));
+  TAGI_HIP(hipStreamSynchronize(s));
+  nch.release();
+  t->items_orb_block = orb_block;
+  t->items_n_orb = t->n_orb;
+  return TAGI_OK;
+}
+
+}  // namespace tagi

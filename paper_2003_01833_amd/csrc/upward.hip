@@ -1,0 +1,296 @@
+// Algorithm 3, line 2 (Section 6.2): proxy charges of every source cluster that
+// can be approximated ((n+1)^3 < N_S, Eq. MAC), by Eq.
+// particle-cluster-approx-rearranged:
+//
+//     q^_{k1 k2 k3} = sum_{j in C} L_k1(x_j) L_k2(y_j) L_k3(z_j) q_j
+//
+// with Chebyshev points of the second kind s_k = c + h cos(pi k / n) mapped to the
+// cluster's shrunk box (end points placed exactly on the faces) and the
+// barycentric basis L_k(t) = (b_k/(t - s_k)) / sum_m b_m/(t - s_m),
+// b_k = (-1)^k delta_k (Eqs. Lagrange_polynomials, barycentric_weights). A source
+// that coincides with a node takes the Kronecker basis there; a zero-extent
+// dimension puts all mass on node 0.
+//
+// Charge sets: q_j = f_j w_j for every orbital, plus q_j = w_j (orbital
+// independent), which carries the singularity subtraction through the far field.
+//
+// GPU mapping: a work item is (cluster, range of at most kItemPts sources,
+// block of charge sets). The block stages the basis values of 64 sources at a
+// time in LDS; each thread owns up to R coefficients and MB charge sets in
+// registers; the charges q_j are wave-uniform and come through scalar loads.
+// Items of one cluster write partial sums that a second kernel adds in a fixed
+// order, so the result does not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace tagi {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kStage = 64;         // sources whose basis values sit in LDS at once
+constexpr int kItemPts = 8192;     // sources per work item
+
+struct UpItem {
+  int32_t slot, p0, p1, part;  // part: index of this item's partial block
+};
+
+__global__ void k_gather(const int32_t* __restrict__ perm, const double* __restrict__ f,
+                         const double* __restrict__ w, int64_t n, int n_orb,
+                         double* __restrict__ fs, double* __restrict__ qs,
+                         double* __restrict__ ws) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t src = perm[i];
+  const double wi = w[src];
+  ws[i] = wi;
+  for (int o = 0; o < n_orb; ++o) {
+    const double fi = f[(int64_t)o * n + src];
+    fs[(int64_t)o * n + i] = fi;
+    qs[(int64_t)o * n + i] = fi * wi;
+  }
+}
+
+__device__ void cheb_nodes(double lo, double hi, int n, double* s) {
+#pragma clang fp contract(off)
+  const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+  for (int k = 0; k <= n; ++k) s[k] = c + h * cos(M_PI * k / n);
+  s[0] = hi;
+  s[n] = lo;
+}
+
+// R: coefficient rounds per thread (K <= R * kThreads); MB: charge sets per pass
+template <int R, int MB>
+__global__ __launch_bounds__(kThreads) void k_upward(
+    const UpItem* __restrict__ items, const int32_t* __restrict__ approx_node,
+    const double* __restrict__ box, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs,
+    const double* __restrict__ qs, const double* __restrict__ ws, int64_t n, int n_orb,
+    int m0, int n_sets, int degree, double* __restrict__ partial,
+    double* __restrict__ pnodes, float* __restrict__ pnodes32) {
+  const UpItem it = items[blockIdx.x];
+  const int np1 = degree + 1;
+  const int K = np1 * np1 * np1;
+  __shared__ double s_nodes[3][kMaxDegree + 1];
+  __shared__ double s_b[kMaxDegree + 1];
+  __shared__ double s_L[3][kStage][kMaxDegree + 1];
+  const int c = approx_node[it.slot];
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x;
+    cheb_nodes(box[c * 6 + d], box[c * 6 + 3 + d], degree, s_nodes[d]);
+  }
+  if (threadIdx.x <= degree) {
+    double b = (threadIdx.x & 1) ? -1.0 : 1.0;
+    if (threadIdx.x == 0 || threadIdx.x == degree) b *= 0.5;
+    s_b[threadIdx.x] = b;
+  }
+  __syncthreads();
+  // the first item of each cluster publishes the node coordinates
+  if (m0 == 0 && it.part == it.slot && threadIdx.x < 3 * np1) {
+    const int d = threadIdx.x / np1, k = threadIdx.x % np1;
+    const double v = s_nodes[d][k];
+    pnodes[((int64_t)it.slot * 3 + d) * np1 + k] = v;
+    const double ctr = 0.5 * (box[c * 6 + d] + box[c * 6 + 3 + d]);
+    pnodes32[((int64_t)it.slot * 3 + d) * np1 + k] = (float)(v - ctr);
+  }
+  int k1[R], k2[R], k3[R];
+  for (int r = 0; r < R; ++r) {
+    const int k = threadIdx.x + r * kThreads;
+    const int kk = k < K ? k : 0;
+    k1[r] = kk / (np1 * np1);
+    k2[r] = (kk / np1) % np1;
+    k3[r] = kk % np1;
+  }
+  double acc[R][MB];
+  for (int r = 0; r < R; ++r)
+    for (int m = 0; m < MB; ++m) acc[r][m] = 0.0;
+
+  for (int p0 = it.p0; p0 < it.p1; p0 += kStage) {
+    const int cnt = min(kStage, it.p1 - p0);
+    if (threadIdx.x < 3 * kStage) {
+      const int d = threadIdx.x / kStage, p = threadIdx.x % kStage;
+      double* L = s_L[d][p];
+      if (p < cnt) {
+        const double* cp = d == 0 ? xs : (d == 1 ? ys : zs);
+        const double t = cp[p0 + p];
+        const double* s = s_nodes[d];
+        if (s[0] == s[degree]) {  // zero-extent dimension
+          for (int k = 0; k <= degree; ++k) L[k] = k == 0 ? 1.0 : 0.0;
+        } else {
+          int hit = -1;
+          for (int k = 0; k <= degree; ++k)
+            if (t == s[k]) hit = k;
+          if (hit >= 0) {
+            for (int k = 0; k <= degree; ++k) L[k] = k == hit ? 1.0 : 0.0;
+          } else {
+            double sum = 0.0;
+            for (int k = 0; k <= degree; ++k) {
+              const double a = s_b[k] / (t - s[k]);
+              L[k] = a;
+              sum += a;
+            }
+            for (int k = 0; k <= degree; ++k) L[k] = L[k] / sum;
+          }
+        }
+      } else {
+        for (int k = 0; k <= degree; ++k) L[k] = 0.0;
+      }
+    }
+    __syncthreads();
+    for (int p = 0; p < cnt; ++p) {
+      const int64_t j = p0 + p;
+      double q[MB];
+      for (int m = 0; m < MB; ++m) {
+        const int set = m0 + m;
+        q[m] = set < n_orb ? qs[(int64_t)set * n + j] : (set == n_orb ? ws[j] : 0.0);
+      }
+      for (int r = 0; r < R; ++r) {
+        const double phi = s_L[0][p][k1[r]] * s_L[1][p][k2[r]] * s_L[2][p][k3[r]];
+        for (int m = 0; m < MB; ++m) acc[r][m] = fma(phi, q[m], acc[r][m]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int r = 0; r < R; ++r) {
+    const int k = threadIdx.x + r * kThreads;
+    if (k >= K) continue;
+    for (int m = 0; m < MB; ++m)
+      if (m < n_sets) partial[((int64_t)blockIdx.x * MB + m) * K + k] = acc[r][m];
+  }
+}
+
+// sum the partial charges of each cluster's items in item order
+__global__ void k_upward_reduce(const int32_t* __restrict__ slot_first,
+                                const double* __restrict__ partial, int n_approx, int K, int MB,
+                                int m0, int n_sets, int n_orb, double* __restrict__ qhat,
+                                double* __restrict__ what) {
+  const int slot = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_sets * K) return;
+  const int m = (int)(idx / K), k = (int)(idx % K);
+  double s = 0.0;
+  for (int i = slot_first[slot]; i < slot_first[slot + 1]; ++i)
+    s += partial[((int64_t)i * MB + m) * K + k];
+  const int set = m0 + m;
+  if (set < n_orb)
+    qhat[((int64_t)set * n_approx + slot) * K + k] = s;
+  else
+    what[(int64_t)slot * K + k] = s;
+}
+
+template <int R, int MB>
+void launch_upward(int n_items, hipStream_t s, const UpItem* items, tagi_tree* t, int m0,
+                   int n_sets, double* partial) {
+  hipLaunchKernelGGL((k_upward<R, MB>), dim3(n_items), dim3(kThreads), 0, s, items,
+                     t->approx_node.as<int32_t>(), t->nd_box.as<double>(), t->xs.as<double>(),
+                     t->ys.as<double>(), t->zs.as<double>(), t->qs.as<double>(),
+                     t->ws.as<double>(), t->n, t->n_orb, m0, n_sets, t->degree, partial,
+                     t->pnodes.as<double>(), t->pnodes32.as<float>());
+}
+
+}  // namespace
+
+int upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree,
+           hipStream_t s) {
+  const int64_t n = t->n;
+  t->degree = 0;  // invalid until complete
+  phase_begin(t, kPhaseUpward, s);
+  TAGI_TRY(t->ws.ensure(n * sizeof(double)));
+  TAGI_TRY(t->fs.ensure((size_t)n_orb * n * sizeof(double)));
+  TAGI_TRY(t->qs.ensure((size_t)n_orb * n * sizeof(double)));
+  hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, t->perm.as<int32_t>(), f,
+                     w, n, n_orb, t->fs.as<double>(), t->qs.as<double>(), t->ws.as<double>());
+  TAGI_HIP(hipGetLastError());
+
+  const int np1 = degree + 1;
+  const int K = np1 * np1 * np1;
+  // approximable clusters: more than (n+1)^3 sources; the root is skipped because
+  // every batch centre lies inside it, so the distance test can never accept it
+  t->approx_nodes.clear();
+  std::vector<int32_t>& slot_of = t->h_slot_of;
+  slot_of.assign(t->nodes.size(), -1);
+  for (size_t c = 1; c < t->nodes.size(); ++c)
+    if (t->nodes[c].end - t->nodes[c].begin > K) {
+      slot_of[c] = (int32_t)t->approx_nodes.size();
+      t->approx_nodes.push_back((int32_t)c);
+    }
+  const int na = (int)t->approx_nodes.size();
+  t->n_approx = na;
+  t->n_orb = n_orb;
+  t->degree = degree;
+  TAGI_TRY(t->slot_of_node.ensure(slot_of.size() * 4));
+  TAGI_HIP(hipMemcpyAsync(t->slot_of_node.p, slot_of.data(), slot_of.size() * 4,
+                          hipMemcpyHostToDevice, s));
+  if (na == 0) {
+    phase_end(t, kPhaseUpward, s);
+    TAGI_HIP(hipStreamSynchronize(s));
+    return TAGI_OK;
+  }
+  TAGI_TRY(t->approx_node.ensure(na * 4));
+  TAGI_HIP(hipMemcpyAsync(t->approx_node.p, t->approx_nodes.data(), na * 4,
+                          hipMemcpyHostToDevice, s));
+  std::vector<UpItem> items;
+  std::vector<int32_t> slot_first(na + 1);
+  for (int sl = 0; sl < na; ++sl) {
+    slot_first[sl] = (int32_t)items.size();
+    const HostNode& q = t->nodes[t->approx_nodes[sl]];
+    for (int32_t p = q.begin; p < q.end; p += kItemPts) items.push_back({sl, p, std::min(q.end, p + kItemPts), 0});
+  }
+  slot_first[na] = (int32_t)items.size();
+  // `part` marks the first item of each cluster (it publishes the node coordinates)
+  for (int sl = 0; sl < na; ++sl)
+    for (int i = slot_first[sl]; i < slot_first[sl + 1]; ++i) items[i].part = i == slot_first[sl] ? sl : -1;
+  const int n_items = (int)items.size();
+  // host staging lives in the tree so the asynchronous uploads never outlive it
+  t->h_up_items.resize(items.size() * 4);
+  std::memcpy(t->h_up_items.data(), items.data(), items.size() * sizeof(UpItem));
+  t->h_slot_first = slot_first;
+  TAGI_TRY(t->up_items.ensure(items.size() * sizeof(UpItem) + (na + 1) * 4));
+  TAGI_HIP(hipMemcpyAsync(t->up_items.p, t->h_up_items.data(), items.size() * sizeof(UpItem),
+                          hipMemcpyHostToDevice, s));
+  int32_t* d_slot_first = reinterpret_cast<int32_t*>(t->up_items.as<char>() + items.size() * sizeof(UpItem));
+  TAGI_HIP(hipMemcpyAsync(d_slot_first, t->h_slot_first.data(), (na + 1) * 4,
+                          hipMemcpyHostToDevice, s));
+  TAGI_TRY(t->pnodes.ensure((size_t)na * 3 * np1 * sizeof(double)));
+  TAGI_TRY(t->pnodes32.ensure((size_t)na * 3 * np1 * sizeof(float)));
+  TAGI_TRY(t->qhat.ensure((size_t)n_orb * na * K * sizeof(double)));
+  TAGI_TRY(t->what.ensure((size_t)na * K * sizeof(double)));
+
+  const int n_sets_total = n_orb + 1;
+  const int R = (K + kThreads - 1) / kThreads;
+  const int MB = R <= 3 ? 8 : (R <= 6 ? 4 : (R <= 10 ? 2 : 1));
+  TAGI_TRY(t->up_partial.ensure((size_t)n_items * MB * K * sizeof(double)));
+  const UpItem* d_items = t->up_items.as<UpItem>();
+  double* partial = t->up_partial.as<double>();
+  for (int m0 = 0; m0 < n_sets_total; m0 += MB) {
+    const int n_sets = std::min(MB, n_sets_total - m0);
+    switch (R) {
+      case 1: launch_upward<1, 8>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 2: launch_upward<2, 8>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 3: launch_upward<3, 8>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 4: launch_upward<4, 4>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 5: launch_upward<5, 4>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 6: launch_upward<6, 4>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 7: launch_upward<7, 2>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 8: launch_upward<8, 2>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 9: launch_upward<9, 2>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      case 10: launch_upward<10, 2>(n_items, s, d_items, t, m0, n_sets, partial); break;
+      default: launch_upward<20, 1>(n_items, s, d_items, t, m0, n_sets, partial); break;
+    }
+    TAGI_HIP(hipGetLastError());
+    const int64_t tot = (int64_t)n_sets * K;
+    hipLaunchKernelGGL(k_upward_reduce, dim3((tot + 255) / 256, na), dim3(256), 0, s,
+                       d_slot_first, partial, na, K, MB, m0, n_sets, n_orb,
+                       t->qhat.as<double>(), t->what.as<double>());
+    TAGI_HIP(hipGetLastError());
+  }
+  phase_end(t, kPhaseUpward, s);
+  return TAGI_OK;
+}
+
+}  // namespace tagi

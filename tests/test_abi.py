@@ -1,0 +1,66 @@
+"""CPU-side checks of the boundary: the library loads, exports every function that
+include/tagi.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tagi.h")
+LIB = os.path.join(ROOT, "paper_2003_01833_amd", "libtagi.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tagi_[a-z_]+)\s*\(", src)))
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        from paper_2003_01833_amd import build
+        build.build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_validation_rejects_before_any_device_work():
+    lib = _lib()
+    lib.tagi_last_error.restype = ctypes.c_char_p
+    vp = ctypes.c_void_p
+    out = vp()
+    bogus = vp(0x1000)  # never dereferenced: every call below fails validation first
+    lib.tagi_tree_build.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int, vp,
+                                    ctypes.POINTER(vp)]
+    assert lib.tagi_tree_build(None, bogus, bogus, 10, None, 4, None, ctypes.byref(out)) == -1
+    assert lib.tagi_tree_build(bogus, bogus, bogus, 0, None, 4, None, ctypes.byref(out)) == -1
+    assert lib.tagi_tree_build(bogus, bogus, bogus, 10, None, 0, None, ctypes.byref(out)) == -1
+    assert b"leaf_size" in lib.tagi_last_error()
+    lib.tagi_upward.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    assert lib.tagi_upward(None, bogus, bogus, 1, 4, None) == -1
+    lib.tagi_convolve.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_int, vp, vp]
+    assert lib.tagi_convolve(None, None, 0, None, 1.0, 0.5, 4, 0, bogus, None) == -1
+    lib.tagi_direct.argtypes = [vp] * 5 + [ctypes.c_int64] + [vp] * 4 + [ctypes.c_int64, ctypes.c_int,
+                                                                        ctypes.c_double, ctypes.c_double,
+                                                                        vp, vp]
+    # Yukawa with kappa <= 0, and a missing tf for a subtracted kernel
+    assert lib.tagi_direct(bogus, bogus, bogus, bogus, bogus, 4, bogus, bogus, bogus, bogus, 4,
+                           0, 0.0, 1.0, bogus, None) == -1
+    assert lib.tagi_direct(bogus, bogus, bogus, bogus, bogus, 4, bogus, bogus, bogus, None, 4,
+                           1, 1.0, 1.0, bogus, None) == -1
+    assert lib.tagi_direct(bogus, bogus, bogus, bogus, bogus, 4, bogus, bogus, bogus, bogus, 4,
+                           7, 1.0, 1.0, bogus, None) == -1
+    assert lib.tagi_tree_destroy(None) == 0
