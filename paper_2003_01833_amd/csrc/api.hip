@@ -149,10 +149,6 @@ int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* k
   }
   if (kernel == TAGI_COULOMB_SS)
     REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_convolve: alpha = %g must be > 0", alpha);
-  if (precision == TAGI_MIXED) {
-    set_error("tagi_convolve: TAGI_MIXED is not available in this build");
-    return TAGI_E_UNSUPPORTED;
-  }
   hipStream_t s = (hipStream_t)stream;
   const int ob = orbital_block(kernel, t->n_orb);
   const bool rebuild = !(t->list_theta == theta && t->list_degree == degree) ||
@@ -326,7 +322,7 @@ int tagi_tree_destroy(tagi_tree* t) {
   DBuf* bufs[] = {&t->perm, &t->xs, &t->ys, &t->zs, &t->leaf_of_pos, &t->nd_begin, &t->nd_end,
                   &t->nd_first_child, &t->nd_n_child, &t->nd_geom, &t->nd_box, &t->leaf_node,
                   &t->slot_of_node, &t->approx_node, &t->pnodes, &t->qhat, &t->what,
-                  &t->pnodes32, &t->ws, &t->fs, &t->qs, &t->up_items, &t->up_partial,
+                  &t->pnodes32, &t->qhat32, &t->what32, &t->ws, &t->fs, &t->qs, &t->up_items, &t->up_partial,
                   &t->far_off, &t->near_off, &t->far_id, &t->near_id, &t->chunks, &t->items,
                   &t->group_first_item, &t->batch_group_base, &t->batch_chunks, &t->partial,
                   &t->kappa_dev};

@@ -1,0 +1,56 @@
+// Device math for the kernel evaluations: exp on non-positive arguments and the
+// reciprocal square root, in FP64, without the special-case handling that the
+// general library routines carry (inputs here are finite, exp arguments lie in
+// [-745, 0], and square roots are taken of positive squared distances).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tagi {
+
+// exp(x) for finite x <= 0. Cody and Waite's additive range reduction
+// (W. J. Cody and W. Waite, Software Manual for the Elementary Functions, 1980):
+// k = nearest integer to x / ln 2, r = x - k ln 2 with ln 2 split in two parts
+// (both products taken inside fused multiply-adds), |r| <= ln(2)/2; then
+// exp(r) by the degree-11 polynomial that interpolates exp at the 12 Chebyshev
+// points of [-ln 2 / 2, ln 2 / 2] (coefficients computed in 60-digit arithmetic
+// by gen_exp_coeffs.py beside this file and rounded to double; relative error of
+// the polynomial below one ulp on the interval), and exp(x) = 2^k exp(r).
+// The nearest integer is formed by adding 1.5 * 2^52, whose ulp is 1, so the
+// low word of the sum holds k in two's complement.
+__device__ __forceinline__ double exp_nonpos(double x) {
+  constexpr double kLog2e = 0x1.71547652b82fep+0;
+  constexpr double kShift = 0x1.8p52;
+  constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;
+  constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;
+  const double t = __builtin_fma(x, kLog2e, kShift);
+  const double kd = t - kShift;
+  const int k = (int)__double2loint(t);
+  double r = __builtin_fma(kd, -kLn2Hi, x);
+  r = __builtin_fma(kd, -kLn2Lo, r);
+  double p = 0x1.af631d0059becp-26;
+  p = __builtin_fma(p, r, 0x1.28b4057f44145p-22);
+  p = __builtin_fma(p, r, 0x1.71ddf5749d126p-19);
+  p = __builtin_fma(p, r, 0x1.a01991ac8730ap-16);
+  p = __builtin_fma(p, r, 0x1.a01a01b14378fp-13);
+  p = __builtin_fma(p, r, 0x1.6c16c187fbe02p-10);
+  p = __builtin_fma(p, r, 0x1.111111110f225p-7);
+  p = __builtin_fma(p, r, 0x1.555555554f0cfp-5);
+  p = __builtin_fma(p, r, 0x1.555555555555ap-3);
+  p = __builtin_fma(p, r, 0x1.0000000000011p-1);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, k);
+}
+
+// 1/sqrt(x) for finite x > 0: the hardware estimate y of v_rsq_f64 refined by one
+// step of the third-order iteration y' = y (1 + e/2 + 3 e^2/8), e = 1 - x y^2
+// (the Taylor expansion of (1 - e)^(-1/2)), which triples the number of
+// correct bits of the estimate.
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);
+}
+
+}  // namespace tagi

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "devmath.hpp"
 #include "internal.hpp"
 
 namespace tagi {
@@ -41,124 +42,260 @@ struct Chunk {
   int32_t kind, e0, e1, cost;
 };
 
+// Accumulates one source with charges c[o] (per orbital) and m (orbital
+// independent) at squared distance r2 with inverse distance rinv (0 for a
+// coincident pair, which then adds nothing).
 template <int KER>
 struct Pair {
-  // accumulate one source (charges c[o], m) at squared distance r2 > 0 with
-  // inverse distance rinv, distance r
   template <int OB>
-  __device__ __forceinline__ static void add(double r2, double r, double rinv, const double* c,
-                                             double m, const double* kap, double ia2,
-                                             double* a1, double* a2) {
-    if constexpr (KER == TAGI_YUKAWA_SS) {
+  __device__ __forceinline__ static void add(double r2, double rinv, const double* c, double m,
+                                             const double* nkap, double nia2, double* a1,
+                                             double* a2) {
+    if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
+      const double r = r2 * rinv;
 #pragma unroll
       for (int o = 0; o < OB; ++o) {
-        const double g = exp(-kap[o] * r) * rinv;
-        a1[o] = fma(g, c[o], a1[o]);
-        a2[o] = fma(g, m, a2[o]);
+        const double g = exp_nonpos(nkap[o] * r) * rinv;
+        a1[o] = __builtin_fma(g, c[o], a1[o]);
+        if constexpr (KER == TAGI_YUKAWA_SS) a2[o] = __builtin_fma(g, m, a2[o]);
       }
-    } else if constexpr (KER == TAGI_YUKAWA) {
-#pragma unroll
-      for (int o = 0; o < OB; ++o) a1[o] = fma(exp(-kap[o] * r) * rinv, c[o], a1[o]);
-    } else if constexpr (KER == TAGI_COULOMB_SS) {
-      a2[0] = fma(exp(-r2 * ia2) * rinv, m, a2[0]);
-#pragma unroll
-      for (int o = 0; o < OB; ++o) a1[o] = fma(rinv, c[o], a1[o]);
     } else {
+      if constexpr (KER == TAGI_COULOMB_SS)
+        a2[0] = __builtin_fma(exp_nonpos(r2 * nia2) * rinv, m, a2[0]);
 #pragma unroll
-      for (int o = 0; o < OB; ++o) a1[o] = fma(rinv, c[o], a1[o]);
+      for (int o = 0; o < OB; ++o) a1[o] = __builtin_fma(rinv, c[o], a1[o]);
     }
   }
 };
 
-template <int KER, int OB>
-__global__ __launch_bounds__(kBlock) void k_interact(
-    const int4* __restrict__ items, int64_t n_items, const Chunk* __restrict__ chunks,
-    const int32_t* __restrict__ leaf_node, const int32_t* __restrict__ nbeg,
-    const int32_t* __restrict__ nend, const int32_t* __restrict__ far_id,
-    const int32_t* __restrict__ near_id, const int32_t* __restrict__ slot_of,
-    const double* __restrict__ xs, const double* __restrict__ ys, const double* __restrict__ zs,
-    const double* __restrict__ qs, const double* __restrict__ ws,
-    const double* __restrict__ pnodes, const double* __restrict__ qhat,
-    const double* __restrict__ what, int64_t n, int n_orb, int n_approx, int degree,
-    double ia2, OrbArg orb, double* __restrict__ partial) {
-  const int lane = threadIdx.x % kWave;
-  const int it = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
-  if (it >= n_items) return;
-  const int4 item = items[it];
-  const int B = leaf_node[item.x];
-  const int tb = nbeg[B] + item.y * kWave;
-  const int te = min(nend[B], tb + kWave);
-  const int i = tb + lane < te ? tb + lane : tb;
-  const double xi = xs[i], yi = ys[i], zi = zs[i];
-  const int o0 = item.z * OB;
-  double kap[OB];
-  int orb_row[OB];
+// Far pairs of one cluster: proxy points s_k on the tensor grid px x py x pz
+// (NP1 = degree + 1 points per dimension; NP1 == 0 means a run-time degree).
+template <int KER, int OB, int NP1>
+__device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int np1_rt,
+                                            const double* __restrict__ px,
+                                            const double* __restrict__ wk,
+                                            const double* const* qk, const double* nkap,
+                                            double nia2, double* a1, double* a2) {
+  const int np1 = NP1 ? NP1 : np1_rt;
+  const double* py = px + np1;
+  const double* pz = py + np1;
+  int k = 0;
+  for (int k1 = 0; k1 < np1; ++k1) {
+    const double dx = xi - px[k1];
+    const double dx2 = dx * dx;
+    for (int k2 = 0; k2 < np1; ++k2) {
+      const double dy = yi - py[k2];
+      const double dxy = __builtin_fma(dy, dy, dx2);
+      if constexpr (NP1 > 0) {
 #pragma unroll
-  for (int o = 0; o < OB; ++o) {
-    orb_row[o] = min(o0 + o, n_orb - 1);
-    kap[o] = orb.kappa[orb_row[o]];
-  }
-  double a1[OB], a2[OB];
+        for (int k3 = 0; k3 < NP1; ++k3) {
+          const double dz = zi - pz[k3];
+          const double r2 = __builtin_fma(dz, dz, dxy);
+          double c[OB];
 #pragma unroll
-  for (int o = 0; o < OB; ++o) a1[o] = a2[o] = 0.0;
-  const Chunk ch = chunks[item.w];
-  if (ch.kind == 0) {
-    const int np1 = degree + 1;
-    const int K = np1 * np1 * np1;
-    for (int e = ch.e0; e < ch.e1; ++e) {
-      const int slot = slot_of[far_id[e]];
-      if (slot < 0) continue;  // never taken: far clusters always hold proxy charges
-      const double* px = pnodes + (int64_t)slot * 3 * np1;
-      const double* py = px + np1;
-      const double* pz = py + np1;
-      const double* wk = what + (int64_t)slot * K;
-      const double* qk[OB];
+          for (int o = 0; o < OB; ++o) c[o] = qk[o][k + k3];
+          Pair<KER>::template add<OB>(r2, rsqrt_pos(r2), c, wk[k + k3], nkap, nia2, a1, a2);
+        }
+        k += NP1;
+      } else {
+        for (int k3 = 0; k3 < np1; ++k3, ++k) {
+          const double dz = zi - pz[k3];
+          const double r2 = __builtin_fma(dz, dz, dxy);
+          double c[OB];
 #pragma unroll
-      for (int o = 0; o < OB; ++o) qk[o] = qhat + ((int64_t)orb_row[o] * n_approx + slot) * K;
-      int k = 0;
-      for (int k1 = 0; k1 < np1; ++k1) {
-        const double dx = xi - px[k1];
-        const double dx2 = dx * dx;
-        for (int k2 = 0; k2 < np1; ++k2) {
-          const double dy = yi - py[k2];
-          const double dxy = fma(dy, dy, dx2);
-          for (int k3 = 0; k3 < np1; ++k3, ++k) {
-            const double dz = zi - pz[k3];
-            const double r2 = fma(dz, dz, dxy);
-            const double rinv = rsqrt(r2);
-            const double r = r2 * rinv;
-            double c[OB];
-#pragma unroll
-            for (int o = 0; o < OB; ++o) c[o] = qk[o][k];
-            Pair<KER>::template add<OB>(r2, r, rinv, c, wk[k], kap, ia2, a1, a2);
-          }
+          for (int o = 0; o < OB; ++o) c[o] = qk[o][k];
+          Pair<KER>::template add<OB>(r2, rsqrt_pos(r2), c, wk[k], nkap, nia2, a1, a2);
         }
       }
     }
-  } else {
-    for (int e = ch.e0; e < ch.e1; ++e) {
-      const int C = near_id[e];
-      const int j1 = nend[C];
-      for (int j = nbeg[C]; j < j1; ++j) {
-        const double dx = xi - xs[j];
-        const double dy = yi - ys[j];
-        const double dz = zi - zs[j];
-        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
-        const double r = r2 * rinv;
-        double c[OB];
+  }
+}
+
+// Far pairs of one cluster in FP32 (mixed precision): the target's offset from
+// the cluster centre o = r_i - c_C is formed in FP64 and rounded once, the proxy
+// points are stored as FP32 offsets from the same centre, so every difference
+// o - (s_k - c_C) is taken between numbers no larger than the batch-cluster
+// distance. Kernel values use the hardware v_rsq_f32 and v_exp_f32 (2^x, with the
+// exponent pre-scaled by log2 e); the cluster's sums accumulate in FP32 and are
+// added to the FP64 accumulators once per cluster.
+template <int KER, int OB, int NP1>
+__device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int np1_rt,
+                                              const float* __restrict__ px,
+                                              const float* __restrict__ wk,
+                                              const float* const* qk, const float* nkl2,
+                                              float nial2, double* a1, double* a2) {
+  const int np1 = NP1 ? NP1 : np1_rt;
+  const float* py = px + np1;
+  const float* pz = py + np1;
+  float b1[OB], b2[OB];
 #pragma unroll
-        for (int o = 0; o < OB; ++o) c[o] = qs[(int64_t)orb_row[o] * n + j];
-        Pair<KER>::template add<OB>(r2, r, rinv, c, ws[j], kap, ia2, a1, a2);
+  for (int o = 0; o < OB; ++o) b1[o] = b2[o] = 0.0f;
+  int k = 0;
+  for (int k1 = 0; k1 < np1; ++k1) {
+    const float dx = ox - px[k1];
+    const float dx2 = dx * dx;
+    for (int k2 = 0; k2 < np1; ++k2) {
+      const float dy = oy - py[k2];
+      const float dxy = __builtin_fmaf(dy, dy, dx2);
+#pragma unroll(NP1 > 0 ? NP1 : 1)
+      for (int k3 = 0; k3 < np1; ++k3) {
+        const float dz = oz - pz[k3];
+        const float r2 = __builtin_fmaf(dz, dz, dxy);
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float m = wk[k + k3];
+        if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
+          const float r = r2 * rinv;
+#pragma unroll
+          for (int o = 0; o < OB; ++o) {
+            const float g = __builtin_amdgcn_exp2f(nkl2[o] * r) * rinv;
+            b1[o] = __builtin_fmaf(g, qk[o][k + k3], b1[o]);
+            if constexpr (KER == TAGI_YUKAWA_SS) b2[o] = __builtin_fmaf(g, m, b2[o]);
+          }
+        } else {
+          if constexpr (KER == TAGI_COULOMB_SS)
+            b2[0] = __builtin_fmaf(__builtin_amdgcn_exp2f(r2 * nial2) * rinv, m, b2[0]);
+#pragma unroll
+          for (int o = 0; o < OB; ++o) b1[o] = __builtin_fmaf(rinv, qk[o][k + k3], b1[o]);
+        }
       }
+      k += np1;
     }
   }
-  double* out = partial + (int64_t)it * OB * 2 * kWave;
+#pragma unroll
+  for (int o = 0; o < OB; ++o) {
+    a1[o] += (double)b1[o];
+    a2[o] += (double)b2[o];
+  }
+}
+
+// Near pairs with the particles [j0, j1): coincident points are masked out.
+template <int KER, int OB>
+__device__ __forceinline__ void near_range(double xi, double yi, double zi, int j0, int j1,
+                                           const double* __restrict__ xs,
+                                           const double* __restrict__ ys,
+                                           const double* __restrict__ zs,
+                                           const double* __restrict__ ws,
+                                           const double* const* qr, const double* nkap,
+                                           double nia2, double* a1, double* a2) {
+  constexpr int U = 4;
+  int j = j0;
+  for (; j + U <= j1; j += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double dx = xi - xs[j + u];
+      const double dy = yi - ys[j + u];
+      const double dz = zi - zs[j + u];
+      const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+      const double rinv = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+      double c[OB];
+#pragma unroll
+      for (int o = 0; o < OB; ++o) c[o] = qr[o][j + u];
+      Pair<KER>::template add<OB>(r2, rinv, c, ws[j + u], nkap, nia2, a1, a2);
+    }
+  }
+  for (; j < j1; ++j) {
+    const double dx = xi - xs[j];
+    const double dy = yi - ys[j];
+    const double dz = zi - zs[j];
+    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    const double rinv = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+    double c[OB];
+#pragma unroll
+    for (int o = 0; o < OB; ++o) c[o] = qr[o][j];
+    Pair<KER>::template add<OB>(r2, rinv, c, ws[j], nkap, nia2, a1, a2);
+  }
+}
+
+// Everything the interaction kernel reads, passed by value.
+struct InteractArgs {
+  const int4* items;
+  int64_t n_items;
+  const Chunk* chunks;
+  const int32_t *leaf_node, *nbeg, *nend, *far_id, *near_id, *slot_of;
+  const double *xs, *ys, *zs, *qs, *ws;
+  const double *pnodes, *qhat, *what, *geom;
+  const float *pnodes32, *qhat32, *what32;
+  int64_t n;
+  int n_orb, n_approx, degree;
+  double ia2;
+  double* partial;
+};
+
+template <int KER, int OB, int NP1, bool MIX>
+__global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb) {
+  const int lane = threadIdx.x % kWave;
+  const int it = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
+  if (it >= A.n_items) return;
+  const int4 item = A.items[it];
+  const int B = A.leaf_node[item.x];
+  const int tb = A.nbeg[B] + item.y * kWave;
+  const int te = min(A.nend[B], tb + kWave);
+  const int i = tb + lane < te ? tb + lane : tb;
+  const double xi = A.xs[i], yi = A.ys[i], zi = A.zs[i];
+  const int o0 = item.z * OB;
+  double nkap[OB];
+  int orb_row[OB];
+#pragma unroll
+  for (int o = 0; o < OB; ++o) {
+    orb_row[o] = min(o0 + o, A.n_orb - 1);
+    nkap[o] = -orb.kappa[orb_row[o]];
+  }
+  const double nia2 = -A.ia2;
+  double a1[OB], a2[OB];
+#pragma unroll
+  for (int o = 0; o < OB; ++o) a1[o] = a2[o] = 0.0;
+  const Chunk ch = A.chunks[item.w];
+  if (ch.kind == 0) {
+    const int np1 = A.degree + 1;
+    const int K = np1 * np1 * np1;
+    for (int e = ch.e0; e < ch.e1; ++e) {
+      const int C = A.far_id[e];
+      const int slot = A.slot_of[C];
+      if (slot < 0) continue;  // never taken: far clusters always hold proxy charges
+      if constexpr (MIX) {
+        constexpr double kLog2e = 0x1.71547652b82fep+0;
+        float nkl2[OB];
+        const float* qk[OB];
+#pragma unroll
+        for (int o = 0; o < OB; ++o) {
+          nkl2[o] = (float)(nkap[o] * kLog2e);
+          qk[o] = A.qhat32 + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
+        }
+        const float ox = (float)(xi - A.geom[C * 4 + 0]);
+        const float oy = (float)(yi - A.geom[C * 4 + 1]);
+        const float oz = (float)(zi - A.geom[C * 4 + 2]);
+        far_cluster32<KER, OB, NP1>(ox, oy, oz, np1, A.pnodes32 + (int64_t)slot * 3 * np1,
+                                    A.what32 + (int64_t)slot * K, qk, nkl2,
+                                    (float)(nia2 * kLog2e), a1, a2);
+      } else {
+        const double* qk[OB];
+#pragma unroll
+        for (int o = 0; o < OB; ++o) qk[o] = A.qhat + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
+        far_cluster<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
+                                  A.what + (int64_t)slot * K, qk, nkap, nia2, a1, a2);
+      }
+    }
+  } else {
+    const double* qr[OB];
+#pragma unroll
+    for (int o = 0; o < OB; ++o) qr[o] = A.qs + (int64_t)orb_row[o] * A.n;
+    for (int e = ch.e0; e < ch.e1; ++e) {
+      const int C = A.near_id[e];
+      near_range<KER, OB>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws, qr, nkap,
+                          nia2, a1, a2);
+    }
+  }
+  double* out = A.partial + (int64_t)it * OB * 2 * kWave;
 #pragma unroll
   for (int o = 0; o < OB; ++o) {
     out[(o * 2 + 0) * kWave + lane] = a1[o];
     out[(o * 2 + 1) * kWave + lane] = KER == TAGI_COULOMB_SS ? a2[0] : a2[o];
   }
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
 }
 
 __global__ void k_combine(int64_t n, int n_orb, int OB, int ss, const int32_t* __restrict__ perm,
@@ -192,36 +329,51 @@ __global__ void k_combine(int64_t n, int n_orb, int OB, int ss, const int32_t* _
   out[(int64_t)o * n + perm[i]] = u;
 }
 
-template <int KER, int OB>
-void launch_interact(tagi_tree* t, double ia2, const OrbArg& orb, hipStream_t s) {
+template <int KER, int OB, int NP1>
+void launch_interact(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
+                     hipStream_t s) {
   const int64_t blocks = (t->n_items + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((k_interact<KER, OB>), dim3(blocks), dim3(kBlock), 0, s,
-                     t->items.as<int4>(), t->n_items, t->chunks.as<Chunk>(),
-                     t->leaf_node.as<int32_t>(), t->nd_begin.as<int32_t>(),
-                     t->nd_end.as<int32_t>(), t->far_id.as<int32_t>(), t->near_id.as<int32_t>(),
-                     t->slot_of_node.as<int32_t>(), t->xs.as<double>(), t->ys.as<double>(),
-                     t->zs.as<double>(), t->qs.as<double>(), t->ws.as<double>(),
-                     t->pnodes.as<double>(), t->qhat.as<double>(), t->what.as<double>(), t->n,
-                     t->n_orb, t->n_approx, t->degree, ia2, orb, t->partial.as<double>());
+  if (mix)
+    hipLaunchKernelGGL((k_interact<KER, OB, NP1, true>), dim3(blocks), dim3(kBlock), 0, s, A, orb);
+  else
+    hipLaunchKernelGGL((k_interact<KER, OB, NP1, false>), dim3(blocks), dim3(kBlock), 0, s, A, orb);
+}
+
+template <int KER, int OB>
+void launch_interact_np(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
+                        hipStream_t s) {
+  switch (t->degree + 1) {
+    case 7: launch_interact<KER, OB, 7>(t, mix, A, orb, s); break;
+    case 8: launch_interact<KER, OB, 8>(t, mix, A, orb, s); break;
+    case 9: launch_interact<KER, OB, 9>(t, mix, A, orb, s); break;
+    default: launch_interact<KER, OB, 0>(t, mix, A, orb, s); break;
+  }
 }
 
 template <int KER>
-void launch_interact_ob(int ob, tagi_tree* t, double ia2, const OrbArg& orb, hipStream_t s) {
+void launch_interact_ob(int ob, tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
+                        hipStream_t s) {
   switch (ob) {
-    case 1: launch_interact<KER, 1>(t, ia2, orb, s); break;
-    case 2: launch_interact<KER, 2>(t, ia2, orb, s); break;
-    case 4: launch_interact<KER, 4>(t, ia2, orb, s); break;
-    default: launch_interact<KER, 8>(t, ia2, orb, s); break;
+    case 1: launch_interact_np<KER, 1>(t, mix, A, orb, s); break;
+    case 2: launch_interact_np<KER, 2>(t, mix, A, orb, s); break;
+    case 4: launch_interact_np<KER, 4>(t, mix, A, orb, s); break;
+    default: launch_interact_np<KER, 8>(t, mix, A, orb, s); break;
   }
 }
 
 // ---------------------------------------------------------------------------
 // direct sum: wave = (64-target group, source chunk)
 
+__global__ void k_charge(const double* __restrict__ sf, const double* __restrict__ sw, int64_t ns,
+                         double* __restrict__ q) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < ns) q[j] = sf[j] * sw[j];
+}
+
 template <int KER>
 __global__ __launch_bounds__(kBlock) void k_direct(
     const double* __restrict__ sx, const double* __restrict__ sy, const double* __restrict__ sz,
-    const double* __restrict__ sf, const double* __restrict__ sw, int64_t ns,
+    const double* __restrict__ sq, const double* __restrict__ sw, int64_t ns,
     const double* __restrict__ tx, const double* __restrict__ ty, const double* __restrict__ tz,
     int64_t nt, int n_sc, int64_t sc_len, double kappa, double ia2, double* __restrict__ partial) {
   const int lane = threadIdx.x % kWave;
@@ -232,20 +384,11 @@ __global__ __launch_bounds__(kBlock) void k_direct(
   const int sc = w % n_sc;
   const int64_t t = g * kWave + lane < nt ? g * kWave + lane : g * kWave;
   const double xi = tx[t], yi = ty[t], zi = tz[t];
-  const int64_t j0 = sc * sc_len, j1 = min(ns, j0 + sc_len);
+  const int j0 = (int)(sc * sc_len), j1 = (int)min(ns, j0 + sc_len);
   double a1[1] = {0.0}, a2[1] = {0.0};
-  const double kap[1] = {kappa};
-  for (int64_t j = j0; j < j1; ++j) {
-    const double dx = xi - sx[j];
-    const double dy = yi - sy[j];
-    const double dz = zi - sz[j];
-    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
-    const double r = r2 * rinv;
-    const double wj = sw[j];
-    const double c[1] = {sf[j] * wj};
-    Pair<KER>::template add<1>(r2, r, rinv, c, wj, kap, ia2, a1, a2);
-  }
+  const double nkap[1] = {-kappa};
+  const double* qr[1] = {sq};
+  near_range<KER, 1>(xi, yi, zi, j0, j1, sx, sy, sz, sw, qr, nkap, -ia2, a1, a2);
   double* out = partial + (int64_t)w * 2 * kWave;
   out[lane] = a1[0];
   out[kWave + lane] = a2[0];
@@ -276,7 +419,6 @@ __global__ void k_direct_combine(int64_t nt, int n_sc, int ss, double self,
 
 int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
              double* out, hipStream_t s) {
-  (void)precision;
   const int n_orb = t->n_orb;
   const int ob = orbital_block(kernel, n_orb);
   if (t->items_orb_block != ob || t->items_n_orb != n_orb || t->n_items == 0) {
@@ -291,14 +433,56 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
                                            : (kernel == TAGI_COULOMB_SS ? 2.0 * M_PI * alpha * alpha : 0.0);
   }
   const double ia2 = kernel == TAGI_COULOMB_SS ? 1.0 / (alpha * alpha) : 0.0;
+  const bool mix = precision == TAGI_MIXED;
+  const int np1 = t->degree + 1;
+  const int64_t K = (int64_t)np1 * np1 * np1;
+  if (mix && t->n_approx > 0) {
+    // FP32 copies of the FP64 proxy charges for the FP32 far-field tiles
+    const int64_t nq = (int64_t)n_orb * t->n_approx * K, nw = (int64_t)t->n_approx * K;
+    TAGI_TRY(t->qhat32.ensure(nq * sizeof(float)));
+    TAGI_TRY(t->what32.ensure(nw * sizeof(float)));
+    hipLaunchKernelGGL(k_to_f32, dim3((nq + 255) / 256), dim3(256), 0, s, t->qhat.as<double>(),
+                       t->qhat32.as<float>(), nq);
+    hipLaunchKernelGGL(k_to_f32, dim3((nw + 255) / 256), dim3(256), 0, s, t->what.as<double>(),
+                       t->what32.as<float>(), nw);
+    TAGI_HIP(hipGetLastError());
+  }
+  InteractArgs A{};
+  A.items = t->items.as<int4>();
+  A.n_items = t->n_items;
+  A.chunks = t->chunks.as<Chunk>();
+  A.leaf_node = t->leaf_node.as<int32_t>();
+  A.nbeg = t->nd_begin.as<int32_t>();
+  A.nend = t->nd_end.as<int32_t>();
+  A.far_id = t->far_id.as<int32_t>();
+  A.near_id = t->near_id.as<int32_t>();
+  A.slot_of = t->slot_of_node.as<int32_t>();
+  A.xs = t->xs.as<double>();
+  A.ys = t->ys.as<double>();
+  A.zs = t->zs.as<double>();
+  A.qs = t->qs.as<double>();
+  A.ws = t->ws.as<double>();
+  A.pnodes = t->pnodes.as<double>();
+  A.qhat = t->qhat.as<double>();
+  A.what = t->what.as<double>();
+  A.geom = t->nd_geom.as<double>();
+  A.pnodes32 = t->pnodes32.as<float>();
+  A.qhat32 = t->qhat32.as<float>();
+  A.what32 = t->what32.as<float>();
+  A.n = t->n;
+  A.n_orb = n_orb;
+  A.n_approx = t->n_approx;
+  A.degree = t->degree;
+  A.ia2 = ia2;
+  A.partial = t->partial.as<double>();
   if (t->n_items > 0) {
     phase_begin(t, kPhaseInteract, s);
     ++t->interact_launches;
     switch (kernel) {
-      case TAGI_YUKAWA_SS: launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, ia2, orb, s); break;
-      case TAGI_COULOMB_SS: launch_interact_ob<TAGI_COULOMB_SS>(ob, t, ia2, orb, s); break;
-      case TAGI_YUKAWA: launch_interact_ob<TAGI_YUKAWA>(ob, t, ia2, orb, s); break;
-      default: launch_interact_ob<TAGI_COULOMB>(ob, t, ia2, orb, s); break;
+      case TAGI_YUKAWA_SS: launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, s); break;
+      case TAGI_COULOMB_SS: launch_interact_ob<TAGI_COULOMB_SS>(ob, t, mix, A, orb, s); break;
+      case TAGI_YUKAWA: launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, s); break;
+      default: launch_interact_ob<TAGI_COULOMB>(ob, t, mix, A, orb, s); break;
     }
     phase_end(t, kPhaseInteract, s);
     TAGI_HIP(hipGetLastError());
@@ -334,37 +518,33 @@ int direct(const double* sx, const double* sy, const double* sz, const double* s
   const int64_t sc_len = (ns + n_sc - 1) / n_sc;
   n_sc = (ns + sc_len - 1) / sc_len;
   // stream-ordered scratch: allocated and freed on `s`, so no host synchronisation
-  DBuf part;
-  TAGI_HIP(hipMallocAsync(&part.p, (size_t)n_groups * n_sc * 2 * kWave * sizeof(double), s));
+  double* part = nullptr;
+  double* q = nullptr;
+  TAGI_HIP(hipMallocAsync((void**)&part, (size_t)n_groups * n_sc * 2 * kWave * sizeof(double), s));
+  TAGI_HIP(hipMallocAsync((void**)&q, (size_t)ns * sizeof(double), s));
+  hipLaunchKernelGGL(k_charge, dim3((ns + 255) / 256), dim3(256), 0, s, sf, sw, ns, q);
   const double ia2 = kernel == TAGI_COULOMB_SS ? 1.0 / (alpha * alpha) : 0.0;
   const int64_t waves = n_groups * n_sc;
   const dim3 grid((unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock));
+#define TAGI_DIRECT(K)                                                                          \
+  hipLaunchKernelGGL(k_direct<K>, grid, dim3(kBlock), 0, s, sx, sy, sz, q, sw, ns, tx, ty, tz, \
+                     nt, (int)n_sc, sc_len, kappa, ia2, part)
   switch (kernel) {
-    case TAGI_YUKAWA_SS:
-      hipLaunchKernelGGL(k_direct<TAGI_YUKAWA_SS>, grid, dim3(kBlock), 0, s, sx, sy, sz, sf, sw, ns,
-                         tx, ty, tz, nt, (int)n_sc, sc_len, kappa, ia2, part.as<double>());
-      break;
-    case TAGI_COULOMB_SS:
-      hipLaunchKernelGGL(k_direct<TAGI_COULOMB_SS>, grid, dim3(kBlock), 0, s, sx, sy, sz, sf, sw,
-                         ns, tx, ty, tz, nt, (int)n_sc, sc_len, kappa, ia2, part.as<double>());
-      break;
-    case TAGI_YUKAWA:
-      hipLaunchKernelGGL(k_direct<TAGI_YUKAWA>, grid, dim3(kBlock), 0, s, sx, sy, sz, sf, sw, ns,
-                         tx, ty, tz, nt, (int)n_sc, sc_len, kappa, ia2, part.as<double>());
-      break;
-    default:
-      hipLaunchKernelGGL(k_direct<TAGI_COULOMB>, grid, dim3(kBlock), 0, s, sx, sy, sz, sf, sw, ns,
-                         tx, ty, tz, nt, (int)n_sc, sc_len, kappa, ia2, part.as<double>());
-      break;
+    case TAGI_YUKAWA_SS: TAGI_DIRECT(TAGI_YUKAWA_SS); break;
+    case TAGI_COULOMB_SS: TAGI_DIRECT(TAGI_COULOMB_SS); break;
+    case TAGI_YUKAWA: TAGI_DIRECT(TAGI_YUKAWA); break;
+    default: TAGI_DIRECT(TAGI_COULOMB); break;
   }
+#undef TAGI_DIRECT
   TAGI_HIP(hipGetLastError());
   const int ss = kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS;
   const double self = kernel == TAGI_YUKAWA_SS ? 4.0 * M_PI / (kappa * kappa)
                                                : (kernel == TAGI_COULOMB_SS ? 2.0 * M_PI * alpha * alpha : 0.0);
   hipLaunchKernelGGL(k_direct_combine, dim3((nt + 255) / 256), dim3(256), 0, s, nt, (int)n_sc, ss,
-                     self, tf, part.as<double>(), out);
+                     self, tf, part, out);
   TAGI_HIP(hipGetLastError());
-  TAGI_HIP(hipFreeAsync(part.p, s));
+  TAGI_HIP(hipFreeAsync(q, s));
+  TAGI_HIP(hipFreeAsync(part, s));
   return TAGI_OK;
 }
 

@@ -90,6 +90,7 @@ struct tagi_tree {
   tagi::DBuf qhat;                  // double [n_orb][n_approx][(degree+1)^3]
   tagi::DBuf what;                  // double [n_approx][(degree+1)^3]
   tagi::DBuf pnodes32;              // float [n_approx][3][degree+1], centred on the cluster
+  tagi::DBuf qhat32, what32;        // FP32 copies of qhat / what for mixed-precision tiles
   tagi::DBuf ws;                    // double [n] tree-ordered weights
   tagi::DBuf fs;                    // double [n_orb][n] tree-ordered values
   tagi::DBuf qs;                    // double [n_orb][n] f*w tree-ordered
