@@ -89,6 +89,80 @@ def cpu_baseline(wl, seconds: float):
                       f"{len(wl['convs'])} kernel(s), {dt:.1f} s"}
 
 
+def compare_batched(tagi, torch, theta=0.7, degree=8, leaf=500, samples=1000, reps=1):
+    """The benzene workload (4,143,104 points, 21 orbitals, one kappa each): the
+    per-orbital FP64 loop, one batched FP64 launch sequence, and batched with the
+    mixed-precision far field. Times exclude the tree build and include upward,
+    lists (cached after the first call) and the convolution; errors are per
+    orbital against the GPU direct sum at sampled targets."""
+    from workloads.configs import DOMAIN, benzene_mesh, benzene_orbitals, sample_targets
+    _log("compare: building the benzene mesh and 21 orbitals")
+    m = benzene_mesh()
+    orb = benzene_orbitals(m["x"], m["y"], m["z"])
+    n = m["x"].size
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    x, y, z, w = dev(m["x"]), dev(m["y"]), dev(m["z"]), dev(m["w"])
+    F = dev(orb["psi"])
+    kap = orb["kappa"]
+    n_orb = F.shape[0]
+    t = tagi.Tree(x, y, z, leaf, (*DOMAIN[0], *DOMAIN[1]))
+    idx = torch.from_numpy(sample_targets(n, samples, seed=4)).cuda()
+    sub = lambda a: a[idx].contiguous()  # noqa: E731
+    refs = [tagi.direct("yukawa_ss", x, y, z, F[o].contiguous(), w, sub(x), sub(y), sub(z),
+                        sub(F[o]), kappa=float(kap[o])) for o in range(n_orb)]
+
+    def errors(U):
+        e = []
+        for o in range(n_orb):
+            u = U[o, idx]
+            e.append((float(torch.linalg.norm(u - refs[o]) / torch.linalg.norm(refs[o])),
+                      float((u - refs[o]).abs().max() / refs[o].abs().max())))
+        return {"rel_l2_max_over_orbitals": max(a for a, _ in e),
+                "rel_max_max_over_orbitals": max(b for _, b in e)}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, 1e3 * (time.perf_counter() - t0) / reps
+
+    U_plain = torch.empty((n_orb, n), dtype=torch.float64, device="cuda")
+
+    def plain():
+        for o in range(n_orb):
+            t.upward(F[o].contiguous(), w, degree)
+            t.convolve("yukawa_ss", float(kap[o]), theta, degree, out=U_plain[o:o + 1])
+        return U_plain
+
+    res = {"workload": "benzene_mesh_21_orbitals", "n_points": n, "n_orb": n_orb, "theta": theta,
+           "degree": degree, "leaf_size": leaf}
+    _log("compare: plain per-orbital loop")
+    U, ms = timed(plain)
+    res["plain_fp64"] = {"ms": ms, **errors(U)}
+
+    def batched(precision):
+        def run():
+            t.upward(F, w, degree)
+            return t.convolve("yukawa_ss", kap, theta, degree, precision=precision)
+        return run
+
+    _log("compare: batched FP64")
+    U, ms = timed(batched("fp64"))
+    res["batched_fp64"] = {"ms": ms, **errors(U)}
+    _log("compare: batched mixed")
+    U, ms = timed(batched("mixed"))
+    res["batched_mixed"] = {"ms": ms, **errors(U)}
+    st = t.stats()
+    res["interactions_per_orbital"] = st["far_interactions"] + st["near_interactions"]
+    res["speedup_batched_vs_plain"] = res["plain_fp64"]["ms"] / res["batched_fp64"]["ms"]
+    res["speedup_mixed_vs_plain"] = res["plain_fp64"]["ms"] / res["batched_mixed"]["ms"]
+    t.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +172,8 @@ def main():
     ap.add_argument("--samples", type=int, default=2000, help="targets for the accuracy check")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the batched/mixed vs plain comparison on the benzene workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -167,6 +243,10 @@ def main():
         acc[kernel] = {"rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
                        "rel_max": float((u - ref).abs().max() / ref.abs().max())}
 
+    comparison = None
+    if not args.no_compare:
+        comparison = compare_batched(tagi, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         _log("bench: timing the CPU oracle on a bounded sample")
@@ -190,6 +270,7 @@ def main():
         "cpu_baseline": cpu,
         "phases_ms": phases,
         "accuracy_vs_direct": acc,
+        "batched_mixed_vs_plain": comparison,
     }
     print(json.dumps(line), flush=True)
 

@@ -209,6 +209,28 @@ int tagi_lists_export(tagi_tree* tree, double theta, int degree, int64_t* far_of
 int tagi_upward_export(const tagi_tree* tree, int32_t* cluster, double* nodes, double* qhat,
                        double* what, void* stream);
 
+/*
+ * One step of a Green iteration, captured once as a HIP graph and replayed: the
+ * upward pass (Algorithm 3, line 2) and the convolution (line 3) for fixed
+ * buffers, exactly as tagi_upward followed by tagi_convolve with the same
+ * arguments. Intended for iterations where f is rewritten in place between
+ * steps (f = V_eff psi): each replay reads the current contents of f and w and
+ * writes out.
+ *   tagi_graph_create runs the step once on `stream` (which prepares and caches
+ *   every plan, list and buffer), synchronises, then captures the kernels of a
+ *   second run on an internal stream. f, w, kappa values, out and every other
+ *   argument are frozen into the graph; the tree must outlive the graph and must
+ *   not be used with other arguments while the graph is in use.
+ *   tagi_graph_launch enqueues one replay on `stream`.
+ * Errors: as tagi_upward and tagi_convolve; TAGI_E_HIP if capture fails.
+ */
+typedef struct tagi_graph tagi_graph;
+int tagi_graph_create(tagi_tree* tree, const double* f, const double* w, int n_orb, int degree,
+                      int kernel, const double* kappa, double alpha, double theta, int precision,
+                      double* out, void* stream, tagi_graph** graph);
+int tagi_graph_launch(tagi_graph* graph, void* stream);
+int tagi_graph_destroy(tagi_graph* graph);
+
 /* Per-phase device time of the calls made on a tree while timing is enabled,
  * measured with HIP events recorded on the calls' stream around each phase's
  * kernels (host-side work between kernels is not included). */

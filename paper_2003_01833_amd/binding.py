@@ -27,7 +27,8 @@ STATUS = {0: "TAGI_OK", -1: "TAGI_E_ARG", -2: "TAGI_E_STATE", -3: "TAGI_E_OOM",
 
 EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct", "tagi_tree_stats",
             "tagi_tree_export", "tagi_lists_export", "tagi_upward_export", "tagi_tree_set_timing",
-            "tagi_tree_timing", "tagi_tree_destroy", "tagi_last_error"]
+            "tagi_tree_timing", "tagi_graph_create", "tagi_graph_launch", "tagi_graph_destroy",
+            "tagi_tree_destroy", "tagi_last_error"]
 
 
 class TagiError(RuntimeError):
@@ -79,6 +80,10 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_upward_export.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.tagi_tree_destroy.argtypes = [vp]
     lib.tagi_tree_set_timing.argtypes = [vp, i32]
+    lib.tagi_graph_create.argtypes = [vp, vp, vp, i32, i32, i32, vp, dbl, dbl, i32, vp, vp,
+                                      ctypes.POINTER(vp)]
+    lib.tagi_graph_launch.argtypes = [vp, vp]
+    lib.tagi_graph_destroy.argtypes = [vp]
     lib.tagi_tree_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     lib.tagi_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -181,6 +186,11 @@ class Tree:
                                             _stream()))
         return out
 
+    def graph(self, f: torch.Tensor, w: torch.Tensor, degree: int, kernel: str, kappa,
+              theta: float, out: torch.Tensor, alpha: float = 1.0, precision: str = "fp64"):
+        """Captures upward + convolve for these buffers as a HIP graph (GreenStep)."""
+        return GreenStep(self, f, w, degree, kernel, kappa, theta, out, alpha, precision)
+
     def set_timing(self, enable: bool = True):
         _check(load_library().tagi_tree_set_timing(self._h, int(bool(enable))))
 
@@ -232,6 +242,39 @@ class Tree:
         _check(load_library().tagi_upward_export(self._h, _hptr(cl), _hptr(nodes), _hptr(qh),
                                                  _hptr(wh), _stream()))
         return dict(cluster=cl[:na], nodes=nodes[:na], qhat=qh[:, :na], what=wh[:na])
+
+
+class GreenStep:
+    """tagi_graph: a captured upward + convolve, replayed with launch()."""
+
+    def __init__(self, tree: Tree, f, w, degree, kernel, kappa, theta, out, alpha, precision):
+        lib = load_library()
+        n_orb = 1 if f.dim() == 1 else f.shape[0]
+        self._kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64),
+                                                         (n_orb,)))
+        self._keep = (tree, f, w, out)
+        h = ctypes.c_void_p()
+        _check(lib.tagi_graph_create(tree._h, _dptr(f, "f", n_orb * tree.n), _dptr(w, "w", tree.n),
+                                     n_orb, int(degree), KERNELS[kernel], _hptr(self._kap),
+                                     float(alpha), float(theta), PRECISIONS[precision],
+                                     _dptr(out, "out", n_orb * tree.n), _stream(),
+                                     ctypes.byref(h)))
+        tree.n_orb, tree.degree = n_orb, int(degree)
+        self._h = h
+
+    def launch(self):
+        _check(load_library().tagi_graph_launch(self._h, _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().tagi_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_size: int,

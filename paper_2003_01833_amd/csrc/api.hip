@@ -273,6 +273,87 @@ int tagi_upward_export(const tagi_tree* t, int32_t* cluster, double* nodes, doub
   return TAGI_OK;
 }
 
+}  // extern "C"
+
+struct tagi_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int tagi_graph_create(tagi_tree* t, const double* f, const double* w, int n_orb, int degree,
+                      int kernel, const double* kappa, double alpha, double theta, int precision,
+                      double* out, void* stream, tagi_graph** graph) {
+  g_err[0] = 0;
+  REQUIRE(graph, "tagi_graph_create: graph is NULL");
+  *graph = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  int st = tagi_upward(t, f, w, n_orb, degree, stream);
+  if (st == TAGI_OK)
+    st = tagi_convolve(t, nullptr, kernel, kappa, alpha, theta, degree, precision, out, stream);
+  if (st != TAGI_OK) return st;
+  TAGI_HIP(hipStreamSynchronize(s));
+  hipStream_t cs;
+  TAGI_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  tagi_graph* g = new (std::nothrow) tagi_graph();
+  if (!g) {
+    (void)hipStreamDestroy(cs);
+    set_error("tagi_graph_create: host allocation failed");
+    return TAGI_E_OOM;
+  }
+  const bool timing = t->timing;
+  t->timing = false;  // no event records inside the capture
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = upward(t, f, w, n_orb, degree, cs);
+    if (st == TAGI_OK) st = convolve(t, kernel, kappa, alpha, precision, out, cs);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &gr);
+    if (e2 != hipSuccess && st == TAGI_OK) {
+      set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e2));
+      st = TAGI_E_HIP;
+    }
+    g->graph = gr;
+  } else {
+    set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+    st = TAGI_E_HIP;
+  }
+  t->timing = timing;
+  if (st == TAGI_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+      st = TAGI_E_HIP;
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (st != TAGI_OK) {
+    char keep[1024];
+    std::memcpy(keep, g_err, sizeof(keep));
+    tagi_graph_destroy(g);
+    std::memcpy(g_err, keep, sizeof(keep));
+    return st;
+  }
+  *graph = g;
+  return TAGI_OK;
+}
+
+int tagi_graph_launch(tagi_graph* g, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(g && g->exec, "tagi_graph_launch: graph is NULL");
+  TAGI_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return TAGI_OK;
+}
+
+int tagi_graph_destroy(tagi_graph* g) {
+  if (!g) return TAGI_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return TAGI_OK;
+}
+
 static void drop_events(tagi_tree* t) {
   for (auto& v : t->events) {
     for (auto& e : v) {

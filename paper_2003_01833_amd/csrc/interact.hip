@@ -1,297 +1,24 @@
 // Batch-cluster interactions (Algorithm 3, line 3; Eqs. direct-sum_2 and
 // particle-cluster-approx-rearranged) with the singularity subtraction of
 // Section 4.3, the combine step, and the plain direct sum (Eq. direct-sum).
-//
-// One wave processes one work item = (batch, group of <= 64 targets, block of
-// OB orbitals, chunk of the batch's far or near list); lane l owns target l of the
-// group. Sources (proxy points of a far cluster, or particles of a near cluster)
-// are the same for every lane, so their coordinates and charges are wave-uniform
-// and arrive through scalar loads; the kernel evaluation per pair is vector FP64.
-// Per target the wave accumulates
-//     a1 = sum K1(d) c      (c = proxy charge of f w, or f_j w_j)
-//     a2 = sum K2(d) m      (m = proxy charge of w,   or w_j)
-// and the combine kernel forms u_i = a1 - f_i a2 + s f_i with the analytic term
-// s = 4 pi / k^2 (Yukawa) or 2 pi a^2 (Coulomb); for the plain kernels u_i = a1.
-// Yukawa: K1 = K2 = exp(-k d)/d. Coulomb with Gaussian subtraction: K1 = 1/d,
-// K2 = exp(-d^2/a^2)/d. Pairs at distance zero contribute nothing.
-//
-// Far pairs use the tensor structure of the proxy grid: d^2 is built from the
-// per-dimension differences in three nested loops, so one pair costs one
-// multiply-add for its squared distance. Items write partial sums per chunk;
-// the combine adds them in chunk order, so results are bitwise repeatable.
+// This file: combine, direct sum and the host side of the convolution.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 
-#include "devmath.hpp"
-#include "internal.hpp"
+#include "interact_impl.hpp"
 
 namespace tagi {
+namespace ik {
+extern template void launch_interact_ob<TAGI_YUKAWA_SS>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_ob<TAGI_COULOMB_SS>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_ob<TAGI_YUKAWA>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_ob<TAGI_COULOMB>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+}  // namespace ik
+
 namespace {
-
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
-
-struct OrbArg {
-  double kappa[kMaxOrb];  // Yukawa decay rate per orbital
-  double self[kMaxOrb];   // analytic subtraction term per orbital
-};
-
-struct Chunk {
-  int32_t kind, e0, e1, cost;
-};
-
-// Accumulates one source with charges c[o] (per orbital) and m (orbital
-// independent) at squared distance r2 with inverse distance rinv (0 for a
-// coincident pair, which then adds nothing).
-template <int KER>
-struct Pair {
-  template <int OB>
-  __device__ __forceinline__ static void add(double r2, double rinv, const double* c, double m,
-                                             const double* nkap, double nia2, double* a1,
-                                             double* a2) {
-    if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
-      const double r = r2 * rinv;
-#pragma unroll
-      for (int o = 0; o < OB; ++o) {
-        const double g = exp_nonpos(nkap[o] * r) * rinv;
-        a1[o] = __builtin_fma(g, c[o], a1[o]);
-        if constexpr (KER == TAGI_YUKAWA_SS) a2[o] = __builtin_fma(g, m, a2[o]);
-      }
-    } else {
-      if constexpr (KER == TAGI_COULOMB_SS)
-        a2[0] = __builtin_fma(exp_nonpos(r2 * nia2) * rinv, m, a2[0]);
-#pragma unroll
-      for (int o = 0; o < OB; ++o) a1[o] = __builtin_fma(rinv, c[o], a1[o]);
-    }
-  }
-};
-
-// Far pairs of one cluster: proxy points s_k on the tensor grid px x py x pz
-// (NP1 = degree + 1 points per dimension; NP1 == 0 means a run-time degree).
-template <int KER, int OB, int NP1>
-__device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int np1_rt,
-                                            const double* __restrict__ px,
-                                            const double* __restrict__ wk,
-                                            const double* const* qk, const double* nkap,
-                                            double nia2, double* a1, double* a2) {
-  const int np1 = NP1 ? NP1 : np1_rt;
-  const double* py = px + np1;
-  const double* pz = py + np1;
-  int k = 0;
-  for (int k1 = 0; k1 < np1; ++k1) {
-    const double dx = xi - px[k1];
-    const double dx2 = dx * dx;
-    for (int k2 = 0; k2 < np1; ++k2) {
-      const double dy = yi - py[k2];
-      const double dxy = __builtin_fma(dy, dy, dx2);
-      if constexpr (NP1 > 0) {
-#pragma unroll
-        for (int k3 = 0; k3 < NP1; ++k3) {
-          const double dz = zi - pz[k3];
-          const double r2 = __builtin_fma(dz, dz, dxy);
-          double c[OB];
-#pragma unroll
-          for (int o = 0; o < OB; ++o) c[o] = qk[o][k + k3];
-          Pair<KER>::template add<OB>(r2, rsqrt_pos(r2), c, wk[k + k3], nkap, nia2, a1, a2);
-        }
-        k += NP1;
-      } else {
-        for (int k3 = 0; k3 < np1; ++k3, ++k) {
-          const double dz = zi - pz[k3];
-          const double r2 = __builtin_fma(dz, dz, dxy);
-          double c[OB];
-#pragma unroll
-          for (int o = 0; o < OB; ++o) c[o] = qk[o][k];
-          Pair<KER>::template add<OB>(r2, rsqrt_pos(r2), c, wk[k], nkap, nia2, a1, a2);
-        }
-      }
-    }
-  }
-}
-
-// Far pairs of one cluster in FP32 (mixed precision): the target's offset from
-// the cluster centre o = r_i - c_C is formed in FP64 and rounded once, the proxy
-// points are stored as FP32 offsets from the same centre, so every difference
-// o - (s_k - c_C) is taken between numbers no larger than the batch-cluster
-// distance. Kernel values use the hardware v_rsq_f32 and v_exp_f32 (2^x, with the
-// exponent pre-scaled by log2 e); the cluster's sums accumulate in FP32 and are
-// added to the FP64 accumulators once per cluster.
-template <int KER, int OB, int NP1>
-__device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int np1_rt,
-                                              const float* __restrict__ px,
-                                              const float* __restrict__ wk,
-                                              const float* const* qk, const float* nkl2,
-                                              float nial2, double* a1, double* a2) {
-  const int np1 = NP1 ? NP1 : np1_rt;
-  const float* py = px + np1;
-  const float* pz = py + np1;
-  float b1[OB], b2[OB];
-#pragma unroll
-  for (int o = 0; o < OB; ++o) b1[o] = b2[o] = 0.0f;
-  int k = 0;
-  for (int k1 = 0; k1 < np1; ++k1) {
-    const float dx = ox - px[k1];
-    const float dx2 = dx * dx;
-    for (int k2 = 0; k2 < np1; ++k2) {
-      const float dy = oy - py[k2];
-      const float dxy = __builtin_fmaf(dy, dy, dx2);
-#pragma unroll(NP1 > 0 ? NP1 : 1)
-      for (int k3 = 0; k3 < np1; ++k3) {
-        const float dz = oz - pz[k3];
-        const float r2 = __builtin_fmaf(dz, dz, dxy);
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float m = wk[k + k3];
-        if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
-          const float r = r2 * rinv;
-#pragma unroll
-          for (int o = 0; o < OB; ++o) {
-            const float g = __builtin_amdgcn_exp2f(nkl2[o] * r) * rinv;
-            b1[o] = __builtin_fmaf(g, qk[o][k + k3], b1[o]);
-            if constexpr (KER == TAGI_YUKAWA_SS) b2[o] = __builtin_fmaf(g, m, b2[o]);
-          }
-        } else {
-          if constexpr (KER == TAGI_COULOMB_SS)
-            b2[0] = __builtin_fmaf(__builtin_amdgcn_exp2f(r2 * nial2) * rinv, m, b2[0]);
-#pragma unroll
-          for (int o = 0; o < OB; ++o) b1[o] = __builtin_fmaf(rinv, qk[o][k + k3], b1[o]);
-        }
-      }
-      k += np1;
-    }
-  }
-#pragma unroll
-  for (int o = 0; o < OB; ++o) {
-    a1[o] += (double)b1[o];
-    a2[o] += (double)b2[o];
-  }
-}
-
-// Near pairs with the particles [j0, j1): coincident points are masked out.
-template <int KER, int OB>
-__device__ __forceinline__ void near_range(double xi, double yi, double zi, int j0, int j1,
-                                           const double* __restrict__ xs,
-                                           const double* __restrict__ ys,
-                                           const double* __restrict__ zs,
-                                           const double* __restrict__ ws,
-                                           const double* const* qr, const double* nkap,
-                                           double nia2, double* a1, double* a2) {
-  constexpr int U = 4;
-  int j = j0;
-  for (; j + U <= j1; j += U) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const double dx = xi - xs[j + u];
-      const double dy = yi - ys[j + u];
-      const double dz = zi - zs[j + u];
-      const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-      const double rinv = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
-      double c[OB];
-#pragma unroll
-      for (int o = 0; o < OB; ++o) c[o] = qr[o][j + u];
-      Pair<KER>::template add<OB>(r2, rinv, c, ws[j + u], nkap, nia2, a1, a2);
-    }
-  }
-  for (; j < j1; ++j) {
-    const double dx = xi - xs[j];
-    const double dy = yi - ys[j];
-    const double dz = zi - zs[j];
-    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-    const double rinv = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
-    double c[OB];
-#pragma unroll
-    for (int o = 0; o < OB; ++o) c[o] = qr[o][j];
-    Pair<KER>::template add<OB>(r2, rinv, c, ws[j], nkap, nia2, a1, a2);
-  }
-}
-
-// Everything the interaction kernel reads, passed by value.
-struct InteractArgs {
-  const int4* items;
-  int64_t n_items;
-  const Chunk* chunks;
-  const int32_t *leaf_node, *nbeg, *nend, *far_id, *near_id, *slot_of;
-  const double *xs, *ys, *zs, *qs, *ws;
-  const double *pnodes, *qhat, *what, *geom;
-  const float *pnodes32, *qhat32, *what32;
-  int64_t n;
-  int n_orb, n_approx, degree;
-  double ia2;
-  double* partial;
-};
-
-template <int KER, int OB, int NP1, bool MIX>
-__global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb) {
-  const int lane = threadIdx.x % kWave;
-  const int it = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
-  if (it >= A.n_items) return;
-  const int4 item = A.items[it];
-  const int B = A.leaf_node[item.x];
-  const int tb = A.nbeg[B] + item.y * kWave;
-  const int te = min(A.nend[B], tb + kWave);
-  const int i = tb + lane < te ? tb + lane : tb;
-  const double xi = A.xs[i], yi = A.ys[i], zi = A.zs[i];
-  const int o0 = item.z * OB;
-  double nkap[OB];
-  int orb_row[OB];
-#pragma unroll
-  for (int o = 0; o < OB; ++o) {
-    orb_row[o] = min(o0 + o, A.n_orb - 1);
-    nkap[o] = -orb.kappa[orb_row[o]];
-  }
-  const double nia2 = -A.ia2;
-  double a1[OB], a2[OB];
-#pragma unroll
-  for (int o = 0; o < OB; ++o) a1[o] = a2[o] = 0.0;
-  const Chunk ch = A.chunks[item.w];
-  if (ch.kind == 0) {
-    const int np1 = A.degree + 1;
-    const int K = np1 * np1 * np1;
-    for (int e = ch.e0; e < ch.e1; ++e) {
-      const int C = A.far_id[e];
-      const int slot = A.slot_of[C];
-      if (slot < 0) continue;  // never taken: far clusters always hold proxy charges
-      if constexpr (MIX) {
-        constexpr double kLog2e = 0x1.71547652b82fep+0;
-        float nkl2[OB];
-        const float* qk[OB];
-#pragma unroll
-        for (int o = 0; o < OB; ++o) {
-          nkl2[o] = (float)(nkap[o] * kLog2e);
-          qk[o] = A.qhat32 + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
-        }
-        const float ox = (float)(xi - A.geom[C * 4 + 0]);
-        const float oy = (float)(yi - A.geom[C * 4 + 1]);
-        const float oz = (float)(zi - A.geom[C * 4 + 2]);
-        far_cluster32<KER, OB, NP1>(ox, oy, oz, np1, A.pnodes32 + (int64_t)slot * 3 * np1,
-                                    A.what32 + (int64_t)slot * K, qk, nkl2,
-                                    (float)(nia2 * kLog2e), a1, a2);
-      } else {
-        const double* qk[OB];
-#pragma unroll
-        for (int o = 0; o < OB; ++o) qk[o] = A.qhat + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
-        far_cluster<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
-                                  A.what + (int64_t)slot * K, qk, nkap, nia2, a1, a2);
-      }
-    }
-  } else {
-    const double* qr[OB];
-#pragma unroll
-    for (int o = 0; o < OB; ++o) qr[o] = A.qs + (int64_t)orb_row[o] * A.n;
-    for (int e = ch.e0; e < ch.e1; ++e) {
-      const int C = A.near_id[e];
-      near_range<KER, OB>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws, qr, nkap,
-                          nia2, a1, a2);
-    }
-  }
-  double* out = A.partial + (int64_t)it * OB * 2 * kWave;
-#pragma unroll
-  for (int o = 0; o < OB; ++o) {
-    out[(o * 2 + 0) * kWave + lane] = a1[o];
-    out[(o * 2 + 1) * kWave + lane] = KER == TAGI_COULOMB_SS ? a2[0] : a2[o];
-  }
-}
+using namespace ik;
 
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,38 +54,6 @@ __global__ void k_combine(int64_t n, int n_orb, int OB, int ss, const int32_t* _
     u = fma(-f, a2, a1) + orb.self[o] * f;
   }
   out[(int64_t)o * n + perm[i]] = u;
-}
-
-template <int KER, int OB, int NP1>
-void launch_interact(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
-                     hipStream_t s) {
-  const int64_t blocks = (t->n_items + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (mix)
-    hipLaunchKernelGGL((k_interact<KER, OB, NP1, true>), dim3(blocks), dim3(kBlock), 0, s, A, orb);
-  else
-    hipLaunchKernelGGL((k_interact<KER, OB, NP1, false>), dim3(blocks), dim3(kBlock), 0, s, A, orb);
-}
-
-template <int KER, int OB>
-void launch_interact_np(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
-                        hipStream_t s) {
-  switch (t->degree + 1) {
-    case 7: launch_interact<KER, OB, 7>(t, mix, A, orb, s); break;
-    case 8: launch_interact<KER, OB, 8>(t, mix, A, orb, s); break;
-    case 9: launch_interact<KER, OB, 9>(t, mix, A, orb, s); break;
-    default: launch_interact<KER, OB, 0>(t, mix, A, orb, s); break;
-  }
-}
-
-template <int KER>
-void launch_interact_ob(int ob, tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
-                        hipStream_t s) {
-  switch (ob) {
-    case 1: launch_interact_np<KER, 1>(t, mix, A, orb, s); break;
-    case 2: launch_interact_np<KER, 2>(t, mix, A, orb, s); break;
-    case 4: launch_interact_np<KER, 4>(t, mix, A, orb, s); break;
-    default: launch_interact_np<KER, 8>(t, mix, A, orb, s); break;
-  }
 }
 
 // ---------------------------------------------------------------------------

@@ -95,6 +95,7 @@ struct tagi_tree {
   tagi::DBuf fs;                    // double [n_orb][n] tree-ordered values
   tagi::DBuf qs;                    // double [n_orb][n] f*w tree-ordered
   tagi::DBuf up_items, up_partial;  // upward work items and partial charges
+  int up_plan_degree = 0, up_plan_n_orb = 0, up_n_items = 0;
 
   // cached interaction lists and compute schedule
   double list_theta = -1.0;

@@ -199,6 +199,25 @@ def test_uniform_cube_32768_meets_1e6_against_direct_sum():
     np.testing.assert_allclose(ud, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("kernel", ["yukawa_ss", "coulomb_ss"])
+def test_mixed_precision_far_field_within_1e6(ragged_tree, kernel):
+    # FP32 batch-proxy tiles, FP64 everywhere else: per-orbital error against the
+    # FP64 oracle treecode (same tree and lists) stays below 1e-6 relative
+    c = ragged_tree
+    t = c["t"]
+    g = SplitMix64(78)
+    F = np.stack([c["f"], g.uniform(c["f"].size, 0, 3)])
+    kap = np.array([0.6, 3.1])
+    deg, theta = 6, 0.7
+    dF, dw = _dev(F, c["w"])
+    t.upward(dF, dw, deg)
+    u = t.convolve(kernel, kap, theta, deg, precision="mixed").cpu().numpy()
+    ref = bltc.treecode(c["x"], c["y"], c["z"], F, c["w"], kernel, kap, theta, deg, 200, tree=c["ref"])
+    for o in range(2):
+        assert np.linalg.norm(u[o] - ref[o]) / np.linalg.norm(ref[o]) < 1e-6
+        assert np.abs(u[o] - ref[o]).max() / np.abs(ref[o]).max() < 1e-6
+
+
 def test_argument_errors():
     tagi = _tag()
     x, y, z, f, w = _dev(*uniform_cube(300, seed=1))
