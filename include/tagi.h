@@ -231,6 +231,79 @@ int tagi_graph_create(tagi_tree* tree, const double* f, const double* w, int n_o
 int tagi_graph_launch(tagi_graph* graph, void* stream);
 int tagi_graph_destroy(tagi_graph* graph);
 
+/*
+ * Learned degree/MAC selector (a project addition on top of Section 6.2-6.3).
+ *
+ * Network: 5 inputs -> 3 hidden tanh layers of 64 -> 9 linear outputs, FP32.
+ * Parameters are one flat array, layer by layer, each layer's weights W[out][in]
+ * (row-major) followed by its biases: 5*64+64, 64*64+64, 64*64+64, 64*9+9
+ * floats (tagi_selector_param_count()). Output k predicts log10 of the largest
+ * absolute error of approximating a batch-cluster pair at degree 4 + k.
+ *
+ * tagi_selector_samples: training data from the method itself. After an upward
+ * pass at degree 4 with f (one orbital) and w, the far pairs of the lists at
+ * (theta_max, degree 4) are the candidates; an evenly strided subset of at most
+ * max_pairs is kept. For each pair, HOST outputs:
+ *   features [m][5] = {r_C, R - r_B, kappa, N_S, l1 norm of C's degree-4 proxy
+ *                      charges of f w}, radii and R as in the MAC;
+ *   errors   [m][9] = max over the batch's first 64 targets of |approximated -
+ *                      direct| pair contribution (Yukawa with subtraction,
+ *                      Section 4.3) at degrees 4..12; NaN where the cluster holds
+ *                      too few sources for that degree ((n+1)^3 >= N_S);
+ *   pair_ids [m][2] = {batch leaf node id, cluster node id} (may be NULL).
+ * *n receives m. Synchronises the stream; leaves the tree's upward state at
+ * degree 12.
+ *
+ * tagi_selector_grad: loss and gradient of one batch (DEVICE X [m][5] inputs,
+ * Y [m][9] targets, M [m][9] mask of existing targets; loss = sum M (out-Y)^2 /
+ * (2 sum M)); grads DEVICE, same layout as params; *loss HOST.
+ *
+ * tagi_selector_train: mini-batch Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8)
+ * updating DEVICE params in place; `order` (HOST [m]) is a permutation of the
+ * rows, epoch e takes windows of `batch` consecutive rows of it starting at
+ * (b * batch + e * (batch / 3 + 1)) mod m; loss_hist (HOST [epochs], may be NULL)
+ * receives each epoch's mean mini-batch loss. Needs m >= batch.
+ */
+/*
+ * tagi_convolve_learned: Algorithm 3, line 3 with the degree and acceptance of
+ * every batch-cluster pair chosen by the selector network (Yukawa kernels only;
+ * requires a previous tagi_upward, whose f and w are used at every degree).
+ * A pair with (r_B + r_C) < theta_max R is evaluated by the network once per
+ * orbital on the features above, transformed as x_k = (ln(raw_k) - shift_k) *
+ * scale_k; it is approximated at the lowest degree n in 4..12 with
+ * (n+1)^3 < N_S whose predicted log10 error is <= log10(tol[o]) for every
+ * orbital o (tol: HOST [n_orb], absolute error budget of one pair per orbital);
+ * otherwise the cluster is opened (a
+ * leaf, or a cluster of at most 125 sources, is summed directly). If any
+ * ln(raw_k) lies outside [lo_k, hi_k] (the training range), the pair falls back
+ * to the fixed MAC with (theta_fb, degree_fb). Pairs failing the theta_max test
+ * are opened as in Algorithm 3.
+ *   params  HOST float [tagi_selector_param_count()]
+ *   norm    HOST float [20] = shift[5], scale[5], lo[5], hi[5]
+ *   0 < theta_fb, theta_max < 1; 4 <= degree_fb <= 12; tol[o] > 0.
+ * Lists and per-degree plans are cached per argument set (rebuilding them
+ * synchronises the stream); proxy charges are recomputed on every call.
+ * Errors: TAGI_E_ARG, TAGI_E_STATE (no upward), TAGI_E_UNSUPPORTED (Coulomb
+ * kernels, targets), TAGI_E_OOM, TAGI_E_HIP.
+ *
+ * tagi_learned_stats: HOST int64 out[17] = {far pairs, near pairs, far
+ * evaluations, near evaluations (one orbital), far pairs at degree 0..12}.
+ */
+int tagi_convolve_learned(tagi_tree* tree, int kernel, const double* kappa, double alpha,
+                          const float* params, const float* norm, const double* tol,
+                          double theta_max, double theta_fb, int degree_fb, int precision,
+                          double* out, void* stream);
+int tagi_learned_stats(const tagi_tree* tree, int64_t* out);
+int tagi_selector_param_count(void);
+int tagi_selector_samples(tagi_tree* tree, const double* f, const double* w, double kappa,
+                          double theta_max, int64_t max_pairs, float* features, float* errors,
+                          int32_t* pair_ids, int64_t* n, void* stream);
+int tagi_selector_grad(const float* params, const float* X, const float* Y, const float* M,
+                       int64_t m, float* grads, float* loss, void* stream);
+int tagi_selector_train(float* params, const float* X, const float* Y, const float* M, int64_t m,
+                        const int32_t* order, int epochs, int batch, float lr, float* loss_hist,
+                        void* stream);
+
 /* Per-phase device time of the calls made on a tree while timing is enabled,
  * measured with HIP events recorded on the calls' stream around each phase's
  * kernels (host-side work between kernels is not included). */

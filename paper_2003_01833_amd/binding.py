@@ -28,6 +28,8 @@ STATUS = {0: "TAGI_OK", -1: "TAGI_E_ARG", -2: "TAGI_E_STATE", -3: "TAGI_E_OOM",
 EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct", "tagi_tree_stats",
             "tagi_tree_export", "tagi_lists_export", "tagi_upward_export", "tagi_tree_set_timing",
             "tagi_tree_timing", "tagi_graph_create", "tagi_graph_launch", "tagi_graph_destroy",
+            "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
+            "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
             "tagi_tree_destroy", "tagi_last_error"]
 
 
@@ -85,6 +87,12 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_graph_launch.argtypes = [vp, vp]
     lib.tagi_graph_destroy.argtypes = [vp]
     lib.tagi_tree_timing.argtypes = [vp, ctypes.POINTER(Timing)]
+    lib.tagi_selector_param_count.argtypes = []
+    lib.tagi_selector_samples.argtypes = [vp, vp, vp, dbl, dbl, i64, vp, vp, vp, vp, vp]
+    lib.tagi_selector_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+    lib.tagi_selector_train.argtypes = [vp, vp, vp, vp, i64, vp, i32, i32, ctypes.c_float, vp, vp]
+    lib.tagi_convolve_learned.argtypes = [vp, i32, vp, dbl, vp, vp, vp, dbl, dbl, i32, i32, vp, vp]
+    lib.tagi_learned_stats.argtypes = [vp, vp]
     lib.tagi_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "tagi_last_error":
@@ -191,6 +199,52 @@ class Tree:
         """Captures upward + convolve for these buffers as a HIP graph (GreenStep)."""
         return GreenStep(self, f, w, degree, kernel, kappa, theta, out, alpha, precision)
 
+    def convolve_learned(self, kernel: str, kappa, selector, tol, theta_max: float = 0.9,
+                         theta_fb: float = 0.7, degree_fb: int = 8, alpha: float = 1.0,
+                         precision: str = "fp64", out: torch.Tensor | None = None):
+        """tagi_convolve_learned: degrees and acceptance chosen by `selector`
+        (an object with float32 `params` and `norm` arrays); tol per orbital."""
+        n_orb = max(self.n_orb, 1)
+        kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64), (n_orb,)))
+        tl = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (n_orb,)))
+        prm = np.ascontiguousarray(selector.params, dtype=np.float32)
+        nrm = np.ascontiguousarray(selector.norm, dtype=np.float32)
+        self._keep = (kap, tl, prm, nrm)
+        if out is None:
+            out = torch.empty((n_orb, self.n), dtype=torch.float64, device="cuda")
+        _check(load_library().tagi_convolve_learned(self._h, KERNELS[kernel], _hptr(kap),
+                                                    float(alpha), _hptr(prm), _hptr(nrm), _hptr(tl),
+                                                    float(theta_max), float(theta_fb),
+                                                    int(degree_fb), PRECISIONS[precision],
+                                                    _dptr(out, "out", n_orb * self.n), _stream()))
+        return out
+
+    def learned_stats(self) -> dict:
+        a = np.zeros(17, np.int64)
+        _check(load_library().tagi_learned_stats(self._h, _hptr(a)))
+        return {"far_pairs": int(a[0]), "near_pairs": int(a[1]), "far_interactions": int(a[2]),
+                "near_interactions": int(a[3]),
+                "far_pairs_by_degree": {d: int(a[4 + d]) for d in range(13) if a[4 + d]}}
+
+    def selector_samples(self, f: torch.Tensor, w: torch.Tensor, kappa: float,
+                         theta_max: float = 0.9, max_pairs: int = 50000, with_ids: bool = False):
+        """tagi_selector_samples: (features (m, 5), errors (m, 9)) as numpy float32,
+        and the (batch node, cluster node) ids (m, 2) when with_ids."""
+        feat = np.empty((max_pairs, 5), np.float32)
+        err = np.empty((max_pairs, 9), np.float32)
+        ids = np.empty((max_pairs, 2), np.int32)
+        m = ctypes.c_int64()
+        _check(load_library().tagi_selector_samples(self._h, _dptr(f, "f", self.n),
+                                                    _dptr(w, "w", self.n), float(kappa),
+                                                    float(theta_max), int(max_pairs), _hptr(feat),
+                                                    _hptr(err), _hptr(ids), ctypes.byref(m),
+                                                    _stream()))
+        self.n_orb, self.degree = 1, 12
+        k = m.value
+        if with_ids:
+            return feat[:k].copy(), err[:k].copy(), ids[:k].copy()
+        return feat[:k].copy(), err[:k].copy()
+
     def set_timing(self, enable: bool = True):
         _check(load_library().tagi_tree_set_timing(self._h, int(bool(enable))))
 
@@ -242,6 +296,44 @@ class Tree:
         _check(load_library().tagi_upward_export(self._h, _hptr(cl), _hptr(nodes), _hptr(qh),
                                                  _hptr(wh), _stream()))
         return dict(cluster=cl[:na], nodes=nodes[:na], qhat=qh[:, :na], what=wh[:na])
+
+
+def _fptr(t: torch.Tensor, name: str, n: int | None = None):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 tensor on the GPU")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def selector_param_count() -> int:
+    return int(load_library().tagi_selector_param_count())
+
+
+def selector_grad(params: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, M: torch.Tensor):
+    """tagi_selector_grad: (gradient tensor, loss) of one batch."""
+    m = X.shape[0]
+    npar = selector_param_count()
+    grads = torch.empty(npar, dtype=torch.float32, device="cuda")
+    loss = ctypes.c_float()
+    _check(load_library().tagi_selector_grad(_fptr(params, "params", npar), _fptr(X, "X", m * 5),
+                                             _fptr(Y, "Y", m * 9), _fptr(M, "M", m * 9), m,
+                                             _fptr(grads, "grads"), ctypes.byref(loss), _stream()))
+    return grads, loss.value
+
+
+def selector_train(params: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, M: torch.Tensor,
+                   order: np.ndarray, epochs: int, batch: int, lr: float) -> np.ndarray:
+    """tagi_selector_train: updates params in place, returns the per-epoch losses."""
+    m = X.shape[0]
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    hist = np.zeros(max(epochs, 1), np.float32)
+    _check(load_library().tagi_selector_train(_fptr(params, "params", selector_param_count()),
+                                              _fptr(X, "X", m * 5), _fptr(Y, "Y", m * 9),
+                                              _fptr(M, "M", m * 9), m, _hptr(order), int(epochs),
+                                              int(batch), ctypes.c_float(lr), _hptr(hist),
+                                              _stream()))
+    return hist[:epochs]
 
 
 class GreenStep:

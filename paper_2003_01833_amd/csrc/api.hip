@@ -194,7 +194,7 @@ int tagi_tree_stats(const tagi_tree* t, tagi_stats* o) {
   o->leaf_size = t->leaf_size;
   o->degree = t->degree;
   o->n_orb = t->n_orb;
-  o->n_approx = t->n_approx;
+  o->n_approx = t->px.n_approx;
   o->theta = t->list_degree >= 0 ? t->list_theta : -1.0;
   o->n_far_pairs = t->list_degree >= 0 ? t->n_far : 0;
   o->n_near_pairs = t->list_degree >= 0 ? t->n_near : 0;
@@ -261,14 +261,14 @@ int tagi_upward_export(const tagi_tree* t, int32_t* cluster, double* nodes, doub
     return TAGI_E_STATE;
   }
   hipStream_t s = (hipStream_t)stream;
-  const size_t na = t->n_approx, np1 = t->degree + 1, K = np1 * np1 * np1;
-  if (cluster && na) std::memcpy(cluster, t->approx_nodes.data(), na * 4);
+  const size_t na = t->px.n_approx, np1 = t->degree + 1, K = np1 * np1 * np1;
+  if (cluster && na) std::memcpy(cluster, t->px.nodes.data(), na * 4);
   if (nodes && na)
-    TAGI_HIP(hipMemcpyAsync(nodes, t->pnodes.p, na * 3 * np1 * 8, hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipMemcpyAsync(nodes, t->px.pnodes.p, na * 3 * np1 * 8, hipMemcpyDeviceToHost, s));
   if (qhat && na)
-    TAGI_HIP(hipMemcpyAsync(qhat, t->qhat.p, (size_t)t->n_orb * na * K * 8, hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipMemcpyAsync(qhat, t->px.qhat.p, (size_t)t->n_orb * na * K * 8, hipMemcpyDeviceToHost, s));
   if (what && na)
-    TAGI_HIP(hipMemcpyAsync(what, t->what.p, na * K * 8, hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipMemcpyAsync(what, t->px.what.p, na * K * 8, hipMemcpyDeviceToHost, s));
   TAGI_HIP(hipStreamSynchronize(s));
   return TAGI_OK;
 }
@@ -339,6 +339,82 @@ int tagi_graph_create(tagi_tree* t, const double* f, const double* w, int n_orb,
   return TAGI_OK;
 }
 
+int tagi_convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,
+                          const float* params, const float* norm, const double* tol,
+                          double theta_max, double theta_fb, int degree_fb, int precision,
+                          double* out, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t && params && norm && out && kappa && tol, "tagi_convolve_learned: null argument");
+  if (kernel != TAGI_YUKAWA_SS && kernel != TAGI_YUKAWA) {
+    set_error("tagi_convolve_learned: the selector covers the Yukawa kernels only");
+    return TAGI_E_UNSUPPORTED;
+  }
+  REQUIRE(precision == TAGI_FP64 || precision == TAGI_MIXED, "tagi_convolve_learned: precision");
+  REQUIRE(theta_max > 0.0 && theta_max < 1.0, "tagi_convolve_learned: theta_max out of (0, 1)");
+  REQUIRE(theta_fb > 0.0 && theta_fb < 1.0, "tagi_convolve_learned: theta_fb out of (0, 1)");
+  REQUIRE(degree_fb >= 4 && degree_fb <= 12, "tagi_convolve_learned: degree_fb out of [4, 12]");
+  if (t->degree == 0) {
+    set_error("tagi_convolve_learned: tagi_upward has not run on this tree");
+    return TAGI_E_STATE;
+  }
+  for (int o = 0; o < t->n_orb; ++o)
+    REQUIRE(std::isfinite(kappa[o]) && kappa[o] > 0.0 && std::isfinite(tol[o]) && tol[o] > 0.0,
+            "tagi_convolve_learned: kappa[%d] or tol[%d] not finite and > 0", o, o);
+  for (int k = 0; k < selector_param_count(); ++k)
+    REQUIRE(std::isfinite(params[k]), "tagi_convolve_learned: params[%d] not finite", k);
+  return convolve_learned(t, kernel, kappa, alpha, params, norm, tol, theta_max, theta_fb,
+                          degree_fb, precision, out, (hipStream_t)stream);
+}
+
+int tagi_learned_stats(const tagi_tree* t, int64_t* o) {
+  g_err[0] = 0;
+  REQUIRE(t && o, "tagi_learned_stats: null argument");
+  const LearnedState& S = t->learned;
+  o[0] = S.n_far;
+  o[1] = S.n_near;
+  o[2] = S.far_inter;
+  o[3] = S.near_inter;
+  for (int d = 0; d <= kMaxDegree && d < 13; ++d) o[4 + d] = S.far_by_degree[d];
+  return TAGI_OK;
+}
+
+int tagi_selector_param_count(void) { return selector_param_count(); }
+
+int tagi_selector_samples(tagi_tree* t, const double* f, const double* w, double kappa,
+                          double theta_max, int64_t max_pairs, float* features, float* errors,
+                          int32_t* pair_ids, int64_t* n, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t && f && w && features && errors && n, "tagi_selector_samples: null argument");
+  REQUIRE(std::isfinite(kappa) && kappa > 0.0, "tagi_selector_samples: kappa must be > 0");
+  REQUIRE(theta_max > 0.0 && theta_max < 1.0, "tagi_selector_samples: theta_max out of (0, 1)");
+  REQUIRE(max_pairs >= 1 && max_pairs < (int64_t)INT32_MAX, "tagi_selector_samples: bad max_pairs");
+  *n = 0;
+  return selector_samples(t, f, w, kappa, theta_max, max_pairs, features, errors, pair_ids, n,
+                          (hipStream_t)stream);
+}
+
+int tagi_selector_grad(const float* params, const float* X, const float* Y, const float* M,
+                       int64_t m, float* grads, float* loss, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(params && X && Y && M && grads, "tagi_selector_grad: null argument");
+  REQUIRE(m >= 1 && m < (int64_t)INT32_MAX, "tagi_selector_grad: bad m");
+  return selector_grad(params, X, Y, M, m, grads, loss, (hipStream_t)stream);
+}
+
+int tagi_selector_train(float* params, const float* X, const float* Y, const float* M, int64_t m,
+                        const int32_t* order, int epochs, int batch, float lr, float* loss_hist,
+                        void* stream) {
+  g_err[0] = 0;
+  REQUIRE(params && X && Y && M && order, "tagi_selector_train: null argument");
+  REQUIRE(m >= 1 && m < (int64_t)INT32_MAX, "tagi_selector_train: bad m");
+  REQUIRE(batch >= 1 && epochs >= 0 && lr > 0.0f, "tagi_selector_train: bad batch/epochs/lr");
+  for (int64_t r = 0; r < m; ++r)
+    REQUIRE(order[r] >= 0 && order[r] < m, "tagi_selector_train: order[%lld] out of range",
+            (long long)r);
+  return selector_train(params, X, Y, M, m, order, epochs, batch, lr, loss_hist,
+                        (hipStream_t)stream);
+}
+
 int tagi_graph_launch(tagi_graph* g, void* stream) {
   g_err[0] = 0;
   REQUIRE(g && g->exec, "tagi_graph_launch: graph is NULL");
@@ -402,12 +478,13 @@ int tagi_tree_destroy(tagi_tree* t) {
   drop_events(t);
   DBuf* bufs[] = {&t->perm, &t->xs, &t->ys, &t->zs, &t->leaf_of_pos, &t->nd_begin, &t->nd_end,
                   &t->nd_first_child, &t->nd_n_child, &t->nd_geom, &t->nd_box, &t->leaf_node,
-                  &t->slot_of_node, &t->approx_node, &t->pnodes, &t->qhat, &t->what,
-                  &t->pnodes32, &t->qhat32, &t->what32, &t->ws, &t->fs, &t->qs, &t->up_items, &t->up_partial,
-                  &t->far_off, &t->near_off, &t->far_id, &t->near_id, &t->chunks, &t->items,
-                  &t->group_first_item, &t->batch_group_base, &t->batch_chunks, &t->partial,
-                  &t->kappa_dev};
+                  &t->ws, &t->fs, &t->qs, &t->far_off, &t->near_off, &t->far_id, &t->near_id,
+                  &t->chunks, &t->items, &t->group_first_item, &t->batch_group_base,
+                  &t->batch_chunks, &t->partial, &t->kappa_dev};
   for (DBuf* b : bufs) b->release();
+  t->px.release();
+  for (ProxySet& ps : t->lx) ps.release();
+  t->learned.release();
   delete t;
   return TAGI_OK;
 }

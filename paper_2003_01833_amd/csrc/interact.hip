@@ -131,15 +131,15 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   const bool mix = precision == TAGI_MIXED;
   const int np1 = t->degree + 1;
   const int64_t K = (int64_t)np1 * np1 * np1;
-  if (mix && t->n_approx > 0) {
+  if (mix && t->px.n_approx > 0) {
     // FP32 copies of the FP64 proxy charges for the FP32 far-field tiles
-    const int64_t nq = (int64_t)n_orb * t->n_approx * K, nw = (int64_t)t->n_approx * K;
-    TAGI_TRY(t->qhat32.ensure(nq * sizeof(float)));
-    TAGI_TRY(t->what32.ensure(nw * sizeof(float)));
-    hipLaunchKernelGGL(k_to_f32, dim3((nq + 255) / 256), dim3(256), 0, s, t->qhat.as<double>(),
-                       t->qhat32.as<float>(), nq);
-    hipLaunchKernelGGL(k_to_f32, dim3((nw + 255) / 256), dim3(256), 0, s, t->what.as<double>(),
-                       t->what32.as<float>(), nw);
+    const int64_t nq = (int64_t)n_orb * t->px.n_approx * K, nw = (int64_t)t->px.n_approx * K;
+    TAGI_TRY(t->px.qhat32.ensure(nq * sizeof(float)));
+    TAGI_TRY(t->px.what32.ensure(nw * sizeof(float)));
+    hipLaunchKernelGGL(k_to_f32, dim3((nq + 255) / 256), dim3(256), 0, s, t->px.qhat.as<double>(),
+                       t->px.qhat32.as<float>(), nq);
+    hipLaunchKernelGGL(k_to_f32, dim3((nw + 255) / 256), dim3(256), 0, s, t->px.what.as<double>(),
+                       t->px.what32.as<float>(), nw);
     TAGI_HIP(hipGetLastError());
   }
   InteractArgs A{};
@@ -151,22 +151,22 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   A.nend = t->nd_end.as<int32_t>();
   A.far_id = t->far_id.as<int32_t>();
   A.near_id = t->near_id.as<int32_t>();
-  A.slot_of = t->slot_of_node.as<int32_t>();
+  A.slot_of = t->px.slot_of.as<int32_t>();
   A.xs = t->xs.as<double>();
   A.ys = t->ys.as<double>();
   A.zs = t->zs.as<double>();
   A.qs = t->qs.as<double>();
   A.ws = t->ws.as<double>();
-  A.pnodes = t->pnodes.as<double>();
-  A.qhat = t->qhat.as<double>();
-  A.what = t->what.as<double>();
+  A.pnodes = t->px.pnodes.as<double>();
+  A.qhat = t->px.qhat.as<double>();
+  A.what = t->px.what.as<double>();
   A.geom = t->nd_geom.as<double>();
-  A.pnodes32 = t->pnodes32.as<float>();
-  A.qhat32 = t->qhat32.as<float>();
-  A.what32 = t->what32.as<float>();
+  A.pnodes32 = t->px.pnodes32.as<float>();
+  A.qhat32 = t->px.qhat32.as<float>();
+  A.what32 = t->px.what32.as<float>();
   A.n = t->n;
   A.n_orb = n_orb;
-  A.n_approx = t->n_approx;
+  A.n_approx = t->px.n_approx;
   A.degree = t->degree;
   A.ia2 = ia2;
   A.partial = t->partial.as<double>();
@@ -194,6 +194,39 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   TAGI_HIP(hipGetLastError());
   return TAGI_OK;
 }
+
+namespace ik {
+
+int launch_combine(tagi_tree* t, int ob, int ss, const int32_t* group_base,
+                   const int32_t* group_first, const int2* batch_chunks, const double* partial,
+                   const OrbArg& orb, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3((t->n + 255) / 256, t->n_orb), dim3(256), 0, s, t->n,
+                     t->n_orb, ob, ss, t->perm.as<int32_t>(), t->leaf_of_pos.as<int32_t>(),
+                     t->leaf_node.as<int32_t>(), t->nd_begin.as<int32_t>(), group_base, group_first,
+                     batch_chunks, t->fs.as<double>(), partial, orb, out);
+  TAGI_HIP(hipGetLastError());
+  return TAGI_OK;
+}
+
+int launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
+  if (n <= 0) return TAGI_OK;
+  hipLaunchKernelGGL(k_to_f32, dim3((n + 255) / 256), dim3(256), 0, s, a, b, n);
+  TAGI_HIP(hipGetLastError());
+  return TAGI_OK;
+}
+
+OrbArg make_orb(int kernel, int n_orb, const double* kappa, double alpha) {
+  OrbArg orb{};
+  for (int o = 0; o < n_orb; ++o) {
+    const bool yuk = kernel == TAGI_YUKAWA_SS || kernel == TAGI_YUKAWA;
+    orb.kappa[o] = yuk ? kappa[o] : 0.0;
+    orb.self[o] = kernel == TAGI_YUKAWA_SS ? 4.0 * M_PI / (kappa[o] * kappa[o])
+                                           : (kernel == TAGI_COULOMB_SS ? 2.0 * M_PI * alpha * alpha : 0.0);
+  }
+  return orb;
+}
+
+}  // namespace ik
 
 int orbital_block(int kernel, int n_orb) {
   // Coulomb kernels share all geometry across orbitals, so wider blocks pay off

@@ -217,20 +217,23 @@ struct InteractArgs {
   int64_t n_items;
   const Chunk* chunks;
   const int32_t *leaf_node, *nbeg, *nend, *far_id, *near_id, *slot_of;
-  const double *xs, *ys, *zs, *qs, *ws;
+  const double *xs, *ys, *zs, *qs, *ws, *fs;
   const double *pnodes, *qhat, *what, *geom;
   const float *pnodes32, *qhat32, *what32;
   int64_t n;
   int n_orb, n_approx, degree;
   double ia2;
   double* partial;
+  const int32_t* item_list;  // optional: this launch processes items item_list[0 .. n_list)
+  int64_t n_list;
 };
 
 template <int KER, int OB, int NP1, bool MIX>
 __global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb) {
   const int lane = threadIdx.x % kWave;
-  const int it = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
-  if (it >= A.n_items) return;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
+  if (A.item_list ? wv >= A.n_list : wv >= A.n_items) return;
+  const int it = A.item_list ? __builtin_amdgcn_readfirstlane(A.item_list[wv]) : wv;
   const int4 item = A.items[it];
   const int B = A.leaf_node[item.x];
   const int tb = A.nbeg[B] + item.y * kWave;
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb)
 #pragma unroll
   for (int o = 0; o < OB; ++o) a1[o] = a2[o] = 0.0;
   const Chunk ch = A.chunks[item.w];
-  if (ch.kind == 0) {
+  if (ch.kind != 1) {  // far chunk (kind 0, or 16 + degree in learned lists)
     const int np1 = A.degree + 1;
     const int K = np1 * np1 * np1;
     for (int e = ch.e0; e < ch.e1; ++e) {
@@ -301,7 +304,9 @@ __global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb)
 template <int KER, int OB, int NP1>
 void launch_interact(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
                      hipStream_t s) {
-  const int64_t blocks = (t->n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int64_t waves = A.item_list ? A.n_list : A.n_items;
+  const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks == 0) return;
   if (mix)
     hipLaunchKernelGGL((k_interact<KER, OB, NP1, true>), dim3(blocks), dim3(kBlock), 0, s, A, orb);
   else
@@ -311,8 +316,9 @@ void launch_interact(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg
 template <int KER, int OB>
 void launch_interact_np(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
                         hipStream_t s) {
-  switch (t->degree + 1) {
+  switch (A.degree + 1) {
     case 5: launch_interact<KER, OB, 5>(t, mix, A, orb, s); break;
+    case 6: launch_interact<KER, OB, 6>(t, mix, A, orb, s); break;
     case 7: launch_interact<KER, OB, 7>(t, mix, A, orb, s); break;
     case 8: launch_interact<KER, OB, 8>(t, mix, A, orb, s); break;
     case 9: launch_interact<KER, OB, 9>(t, mix, A, orb, s); break;
@@ -332,6 +338,13 @@ void launch_interact_ob(int ob, tagi_tree* t, bool mix, const InteractArgs& A, c
     default: launch_interact_np<KER, 8>(t, mix, A, orb, s); break;
   }
 }
+
+// host helpers defined in interact.hip
+int launch_combine(tagi_tree* t, int ob, int ss, const int32_t* group_base,
+                   const int32_t* group_first, const int2* batch_chunks, const double* partial,
+                   const OrbArg& orb, double* out, hipStream_t s);
+int launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
+OrbArg make_orb(int kernel, int n_orb, const double* kappa, double alpha);
 
 }  // namespace ik
 }  // namespace tagi

@@ -55,6 +55,56 @@ struct HostNode {
   double lo[3], hi[3];
 };
 
+// Proxy data (Section 6.2) of a set of clusters at one degree.
+struct ProxySet {
+  int degree = 0;                   // degree of the plan (0 = none)
+  int n_orb = 0;
+  int n_approx = 0;                 // clusters ("slots") in the set
+  int n_items = 0;                  // upward work items
+  std::vector<int32_t> nodes;       // host: node id per slot
+  std::vector<int32_t> h_slot_of, h_items, h_slot_first;  // host staging for uploads
+  DBuf slot_of;                     // int32 [n_nodes], -1 if the node has no slot
+  DBuf node;                        // int32 [n_approx]
+  DBuf pnodes;                      // double [n_approx][3][degree+1]
+  DBuf pnodes32;                    // float [n_approx][3][degree+1], offsets from the cluster centre
+  DBuf qhat;                        // double [n_orb][n_approx][(degree+1)^3]
+  DBuf what;                        // double [n_approx][(degree+1)^3]
+  DBuf qhat32, what32;              // FP32 copies for mixed-precision tiles
+  DBuf items, partial;              // upward work items (+ slot_first) and partial charges
+  void release() {
+    for (DBuf* b : {&slot_of, &node, &pnodes, &pnodes32, &qhat, &what, &qhat32, &what32, &items,
+                    &partial})
+      b->release();
+    degree = n_orb = n_approx = n_items = 0;
+  }
+};
+
+// Cached state of the learned degree/MAC selection.
+struct LearnedState {
+  std::vector<double> key;          // arguments the cached lists were built for
+  ProxySet l1set;                   // degree-4 charges of every candidate cluster (features)
+  DBuf l1n;                         // float [n_orb][n_nodes] l1 norms of those charges
+  DBuf params;                      // float network parameters
+  DBuf cnt;                         // int64 [n_leaves][kDegSlots] counts, then offsets
+  DBuf far_id, near_id;             // int32 lists (far grouped by degree within a batch)
+  DBuf chunks, items, group_first, group_base, batch_chunks, partial, item_lists;
+  std::vector<int32_t> h_items, h_chunks, h_group_first, h_group_base, h_batch_chunks, h_lists;
+  std::vector<int64_t> list_begin;  // per launch: offset into item_lists
+  std::vector<int> list_degree;     // per launch: degree (0 = near items)
+  int64_t n_items = 0;
+  int ob = 0;
+  int64_t n_far = 0, n_near = 0, far_inter = 0, near_inter = 0;
+  int64_t far_by_degree[kMaxDegree + 1] = {};
+  void release() {
+    l1set.release();
+    for (DBuf* b : {&l1n, &params, &cnt, &far_id, &near_id, &chunks, &items, &group_first,
+                    &group_base, &batch_chunks, &partial, &item_lists})
+      b->release();
+    key.clear();
+    n_items = 0;
+  }
+};
+
 }  // namespace tagi
 
 struct tagi_tree {
@@ -76,26 +126,15 @@ struct tagi_tree {
   tagi::DBuf nd_box;                // double [n_nodes][6] lo xyz, hi xyz
   tagi::DBuf leaf_node;             // int32 [n_leaves]
 
-  // upward state
+  // upward state: tree-ordered values and the proxy charges of the last upward
   int degree = 0;
   int n_orb = 0;
-  int n_approx = 0;
-  std::vector<int32_t> approx_nodes;  // host: node id per slot
-  std::vector<int32_t> h_slot_of;     // host staging kept alive across async uploads
-  std::vector<int32_t> h_up_items;
-  std::vector<int32_t> h_slot_first;
-  tagi::DBuf slot_of_node;          // int32 [n_nodes], -1 if none
-  tagi::DBuf approx_node;           // int32 [n_approx]
-  tagi::DBuf pnodes;                // double [n_approx][3][degree+1]
-  tagi::DBuf qhat;                  // double [n_orb][n_approx][(degree+1)^3]
-  tagi::DBuf what;                  // double [n_approx][(degree+1)^3]
-  tagi::DBuf pnodes32;              // float [n_approx][3][degree+1], centred on the cluster
-  tagi::DBuf qhat32, what32;        // FP32 copies of qhat / what for mixed-precision tiles
   tagi::DBuf ws;                    // double [n] tree-ordered weights
   tagi::DBuf fs;                    // double [n_orb][n] tree-ordered values
   tagi::DBuf qs;                    // double [n_orb][n] f*w tree-ordered
-  tagi::DBuf up_items, up_partial;  // upward work items and partial charges
-  int up_plan_degree = 0, up_plan_n_orb = 0, up_n_items = 0;
+  tagi::ProxySet px;                // degree `degree`, every cluster with (n+1)^3 < N_S
+  tagi::ProxySet lx[tagi::kMaxDegree + 1];  // learned path: per degree, clusters in use
+  tagi::LearnedState learned;
 
   // cached interaction lists and compute schedule
   double list_theta = -1.0;
@@ -149,11 +188,28 @@ inline void phase_end(tagi_tree* t, int ph, hipStream_t s) {
 int build_tree(tagi_tree* t, const double* x, const double* y, const double* z,
                const double* box, hipStream_t s);
 int upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree, hipStream_t s);
+// plan (host lists, uploads, buffers) of proxy charges at `degree` for `nodes`
+int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& nodes, int degree,
+                    int n_orb, hipStream_t s);
+// proxy charges of the planned set from the tree-ordered q = f w and w
+int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s);
 int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s);
 int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s);
 int orbital_block(int kernel, int n_orb);
 int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
              double* out, hipStream_t s);
+int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,
+                     const float* params, const float* norm, const double* tol, double theta_max,
+                     double theta_fb, int degree_fb, int precision, double* out, hipStream_t s);
+int selector_param_count();
+int selector_samples(tagi_tree* t, const double* f, const double* w, double kappa,
+                     double theta_max, int64_t max_pairs, float* feat, float* err,
+                     int32_t* pair_ids, int64_t* n_out, hipStream_t s);
+int selector_grad(const float* params, const float* X, const float* Y, const float* M, int64_t m,
+                  float* grads, float* loss, hipStream_t s);
+int selector_train(float* params, const float* X, const float* Y, const float* M, int64_t m,
+                   const int32_t* order, int epochs, int batch, float lr, float* loss_hist,
+                   hipStream_t s);
 int direct(const double* sx, const double* sy, const double* sz, const double* sf,
            const double* sw, int64_t ns, const double* tx, const double* ty, const double* tz,
            const double* tf, int64_t nt, int kernel, double kappa, double alpha, double* out,

@@ -1,0 +1,496 @@
+// Learned degree/MAC selection (a project addition on Algorithm 3): the
+// interaction lists are built by the same per-batch ComputePotential traversal,
+// but for a pair that passes a permissive geometric test (r_B + r_C) < theta_max R
+// the selector network predicts the approximation error at every degree 4..12
+// from (r_C, R - r_B, kappa, N_S, l1 norm of the cluster's degree-4 proxy
+// charges), one orbital at a time. The pair is approximated at the lowest degree
+// whose predicted error meets the per-pair budget for every orbital (and whose
+// (n+1)^3 is below N_S); if no degree does, the cluster is opened (a leaf is
+// summed directly). Where any feature lies outside the range the network was
+// trained on, the pair falls back to the fixed MAC (theta_fb, degree_fb).
+//
+// Far entries are written grouped by degree within each batch; every degree in
+// use gets its own proxy set (only the clusters used at that degree), and the
+// far field is launched once per degree with the degree's compiled kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "interact_impl.hpp"
+#include "internal.hpp"
+
+namespace tagi {
+namespace ik {
+extern template void launch_interact_ob<TAGI_YUKAWA_SS>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_ob<TAGI_YUKAWA>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+}  // namespace ik
+
+namespace {
+using namespace ik;
+
+constexpr int kDegMin = 4, kDegMax = 12, kNDeg = kDegMax - kDegMin + 1;
+constexpr int kSlots = kNDeg + 1;  // per batch: far entries per degree, then near entries
+constexpr int kH = 64, kIn = 5, kOut = 9;
+constexpr int kNParam = (kIn * kH + kH) + 2 * (kH * kH + kH) + (kH * kOut + kOut);
+
+struct LearnArgs {
+  int n_leaves, n_nodes, n_orb;
+  const int32_t *leaf_node, *nbeg, *nend, *first_child, *n_child;
+  const double* geom;
+  const float* l1n;
+  const float* params;
+  double theta_max, theta_fb;
+  int degree_fb;
+  float log_tol[kMaxOrb];  // per orbital: log10 of the pair error budget
+  float shift[kIn], scale[kIn], lo[kIn], hi[kIn];
+  float logk[kMaxOrb];
+  int fill;
+  int64_t* cnt;        // count pass: [n_leaves][kSlots]
+  const int64_t* off;  // fill pass: [n_leaves][kSlots] start offsets
+  int32_t* far_id;
+  int32_t* near_id;
+  int32_t* overflow;
+};
+
+// l1 norm of every slot's charges per orbital, scattered to a per-node array
+__global__ void k_l1_nodes(const double* __restrict__ qhat, const int32_t* __restrict__ node,
+                           int n_approx, int K, int n_nodes, float* __restrict__ l1n) {
+  const int slot = blockIdx.x, o = blockIdx.y;
+  const double* q = qhat + ((int64_t)o * n_approx + slot) * K;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) s += fabs(q[k]);
+  for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (threadIdx.x == 0) l1n[(int64_t)o * n_nodes + node[slot]] = (float)s;
+}
+
+// network forward for one lane; hA, hB are this block's [64][64] LDS buffers
+// (unit-major, lane-minor), P the parameters in LDS
+__device__ void mlp_forward(const float* P, const float* x, float* hA, float* hB, int lane,
+                            float* out) {
+  const float* W0 = P;
+  const float* b0 = W0 + kH * kIn;
+  const float* W1 = b0 + kH;
+  const float* b1 = W1 + kH * kH;
+  const float* W2 = b1 + kH;
+  const float* b2 = W2 + kH * kH;
+  const float* W3 = b2 + kH;
+  const float* b3 = W3 + kOut * kH;
+  for (int o = 0; o < kH; ++o) {
+    float s = b0[o];
+#pragma unroll
+    for (int i = 0; i < kIn; ++i) s = __builtin_fmaf(W0[o * kIn + i], x[i], s);
+    hA[o * kWave + lane] = tanhf(s);
+  }
+  for (int o = 0; o < kH; ++o) {
+    float s = b1[o];
+#pragma unroll 16
+    for (int i = 0; i < kH; ++i) s = __builtin_fmaf(W1[o * kH + i], hA[i * kWave + lane], s);
+    hB[o * kWave + lane] = tanhf(s);
+  }
+  for (int o = 0; o < kH; ++o) {
+    float s = b2[o];
+#pragma unroll 16
+    for (int i = 0; i < kH; ++i) s = __builtin_fmaf(W2[o * kH + i], hB[i * kWave + lane], s);
+    hA[o * kWave + lane] = tanhf(s);
+  }
+#pragma unroll
+  for (int k = 0; k < kOut; ++k) {
+    float s = b3[k];
+#pragma unroll 16
+    for (int i = 0; i < kH; ++i) s = __builtin_fmaf(W3[k * kH + i], hA[i * kWave + lane], s);
+    out[k] = s;
+  }
+}
+
+// one wave per block of 64 batches
+__global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
+  __shared__ float sP[kNParam];
+  __shared__ float hbuf[2][kH * kWave];
+  for (int i = threadIdx.x; i < kNParam; i += blockDim.x) sP[i] = L.params[i];
+  __syncthreads();
+  const int lane = threadIdx.x;
+  const int b = blockIdx.x * blockDim.x + lane;
+  if (b >= L.n_leaves) return;
+  const int B = L.leaf_node[b];
+  const double rB = L.geom[B * 4 + 3];
+  int64_t c[kSlots];
+  for (int k = 0; k < kSlots; ++k) c[k] = 0;
+  int stack[512];
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp > 0) {
+    const int C = stack[--sp];
+    const int cnt = L.nend[C] - L.nbeg[C];
+    const bool leaf = L.n_child[C] == 0;
+    double R, rC;
+    {
+#pragma clang fp contract(off)
+      const double dx = L.geom[B * 4 + 0] - L.geom[C * 4 + 0];
+      const double dy = L.geom[B * 4 + 1] - L.geom[C * 4 + 1];
+      const double dz = L.geom[B * 4 + 2] - L.geom[C * 4 + 2];
+      R = sqrt(dx * dx + dy * dy + dz * dz);
+      rC = L.geom[C * 4 + 3];
+    }
+    int kind;  // 0 far (at degree deg), 1 near, 2 open
+    int deg = 0;
+    if (!((rB + rC) < L.theta_max * R)) {
+      kind = leaf ? 1 : 2;
+    } else if (cnt <= (kDegMin + 1) * (kDegMin + 1) * (kDegMin + 1)) {
+      kind = 1;  // too few sources for any degree: direct, as a size-rejected pair
+    } else {
+      bool fallback = false, ok = true;
+      int dmax = kDegMin;
+      for (int o = 0; o < L.n_orb && ok && !fallback; ++o) {
+        float raw[kIn];
+        raw[0] = logf((float)rC);
+        raw[1] = logf((float)fmax(R - rB, 1e-12));
+        raw[2] = L.logk[o];
+        raw[3] = logf((float)cnt);
+        raw[4] = logf(fmaxf(L.l1n[(int64_t)o * L.n_nodes + C], 1e-30f));
+        float x[kIn];
+        for (int k = 0; k < kIn; ++k) {
+          if (!(raw[k] >= L.lo[k] && raw[k] <= L.hi[k])) fallback = true;
+          x[k] = (raw[k] - L.shift[k]) * L.scale[k];
+        }
+        if (fallback) break;
+        float pred[kOut];
+        mlp_forward(sP, x, hbuf[0], hbuf[1], lane, pred);
+        int d_o = -1;
+        for (int d = kDegMin; d <= kDegMax; ++d) {
+          if ((d + 1) * (d + 1) * (d + 1) >= cnt) break;
+          if (pred[d - kDegMin] <= L.log_tol[o]) {
+            d_o = d;
+            break;
+          }
+        }
+        if (d_o < 0) ok = false;
+        else dmax = max(dmax, d_o);
+      }
+      if (fallback) {
+        const int nf = L.degree_fb + 1;
+        const bool dist = (rB + rC) < L.theta_fb * R;
+        if (dist && nf * nf * nf < cnt) {
+          kind = 0;
+          deg = L.degree_fb;
+        } else if (!dist) {
+          kind = leaf ? 1 : 2;
+        } else {
+          kind = 1;
+        }
+      } else if (ok) {
+        kind = 0;
+        deg = dmax;
+      } else {
+        kind = leaf ? 1 : 2;
+      }
+    }
+    if (kind == 0) {
+      const int slot = deg - kDegMin;
+      if (L.fill) L.far_id[L.off[(int64_t)b * kSlots + slot] + c[slot]] = C;
+      ++c[slot];
+    } else if (kind == 1) {
+      if (L.fill) L.near_id[L.off[(int64_t)b * kSlots + kNDeg] + c[kNDeg]] = C;
+      ++c[kNDeg];
+    } else {
+      const int fc = L.first_child[C], nc = L.n_child[C];
+      if (sp + nc > 512) {
+        atomicExch(L.overflow, 1);
+        return;
+      }
+      for (int k = nc - 1; k >= 0; --k) stack[sp++] = fc + k;
+    }
+  }
+  if (!L.fill)
+    for (int k = 0; k < kSlots; ++k) L.cnt[(int64_t)b * kSlots + k] = c[k];
+}
+
+}  // namespace
+
+int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,
+                     const float* params, const float* norm, const double* tol, double theta_max,
+                     double theta_fb, int degree_fb, int precision, double* out, hipStream_t s) {
+  LearnedState& S = t->learned;
+  const int n_orb = t->n_orb;
+  const int nl = (int)t->leaves.size();
+  const int nn = (int)t->nodes.size();
+  // cache key: everything the lists depend on
+  std::vector<double> key = {(double)n_orb, theta_max, theta_fb, (double)degree_fb,
+                             (double)kernel};
+  for (int o = 0; o < n_orb; ++o) key.push_back(kappa[o]);
+  for (int o = 0; o < n_orb; ++o) key.push_back(tol[o]);
+  for (int k = 0; k < 4 * kIn; ++k) key.push_back(norm[k]);
+  for (int k = 0; k < kNParam; ++k) key.push_back(params[k]);
+  const int ob = orbital_block(kernel, n_orb);
+  if (key != S.key) {
+    phase_begin(t, kPhaseLists, s);
+    S.key.clear();
+    // features: l1 norms of the degree-4 charges of every cluster that could be approximated
+    std::vector<int32_t> cand;
+    const int K4 = (kDegMin + 1) * (kDegMin + 1) * (kDegMin + 1);
+    for (int c = 1; c < nn; ++c)
+      if (t->nodes[c].end - t->nodes[c].begin > K4) cand.push_back(c);
+    TAGI_TRY(prepare_proxies(t, S.l1set, cand, kDegMin, n_orb, s));
+    TAGI_TRY(compute_proxies(t, S.l1set, s));
+    TAGI_TRY(S.l1n.ensure((size_t)n_orb * nn * sizeof(float)));
+    TAGI_HIP(hipMemsetAsync(S.l1n.p, 0, (size_t)n_orb * nn * sizeof(float), s));
+    if (S.l1set.n_approx > 0) {
+      hipLaunchKernelGGL(k_l1_nodes, dim3(S.l1set.n_approx, n_orb), dim3(64), 0, s,
+                         S.l1set.qhat.as<double>(), S.l1set.node.as<int32_t>(), S.l1set.n_approx,
+                         K4, nn, S.l1n.as<float>());
+      TAGI_HIP(hipGetLastError());
+    }
+    TAGI_TRY(S.params.ensure(kNParam * sizeof(float)));
+    TAGI_HIP(hipMemcpyAsync(S.params.p, params, kNParam * sizeof(float), hipMemcpyHostToDevice, s));
+    // lists: count, offsets, fill
+    LearnArgs L{};
+    L.n_leaves = nl;
+    L.n_nodes = nn;
+    L.n_orb = n_orb;
+    L.leaf_node = t->leaf_node.as<int32_t>();
+    L.nbeg = t->nd_begin.as<int32_t>();
+    L.nend = t->nd_end.as<int32_t>();
+    L.first_child = t->nd_first_child.as<int32_t>();
+    L.n_child = t->nd_n_child.as<int32_t>();
+    L.geom = t->nd_geom.as<double>();
+    L.l1n = S.l1n.as<float>();
+    L.params = S.params.as<float>();
+    L.theta_max = theta_max;
+    L.theta_fb = theta_fb;
+    L.degree_fb = degree_fb;
+    for (int o = 0; o < n_orb; ++o) L.log_tol[o] = (float)std::log10(tol[o]);
+    for (int k = 0; k < kIn; ++k) {
+      L.shift[k] = norm[k];
+      L.scale[k] = norm[kIn + k];
+      L.lo[k] = norm[2 * kIn + k];
+      L.hi[k] = norm[3 * kIn + k];
+    }
+    for (int o = 0; o < n_orb; ++o) L.logk[o] = (float)std::log(kappa[o]);
+    TAGI_TRY(S.cnt.ensure((size_t)nl * kSlots * 2 * sizeof(int64_t) + 4));
+    int64_t* d_cnt = S.cnt.as<int64_t>();
+    int64_t* d_off = d_cnt + (size_t)nl * kSlots;
+    int32_t* d_over = reinterpret_cast<int32_t*>(d_off + (size_t)nl * kSlots);
+    TAGI_HIP(hipMemsetAsync(d_over, 0, 4, s));
+    L.cnt = d_cnt;
+    L.overflow = d_over;
+    L.fill = 0;
+    const int grid = (nl + 63) / 64;
+    hipLaunchKernelGGL(k_lists_learned, dim3(grid), dim3(64), 0, s, L);
+    TAGI_HIP(hipGetLastError());
+    std::vector<int64_t> h((size_t)nl * kSlots);
+    int32_t over = 0;
+    TAGI_HIP(hipMemcpyAsync(h.data(), d_cnt, h.size() * 8, hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipMemcpyAsync(&over, d_over, 4, hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipStreamSynchronize(s));
+    if (over) {
+      set_error("learned lists: traversal stack overflow");
+      return TAGI_E_UNSUPPORTED;
+    }
+    std::vector<int64_t> off(h.size());
+    int64_t nf = 0, nnear = 0;
+    for (int b = 0; b < nl; ++b) {
+      for (int k = 0; k < kNDeg; ++k) {
+        off[(size_t)b * kSlots + k] = nf;
+        nf += h[(size_t)b * kSlots + k];
+      }
+      off[(size_t)b * kSlots + kNDeg] = nnear;
+      nnear += h[(size_t)b * kSlots + kNDeg];
+    }
+    if (nf >= INT32_MAX || nnear >= INT32_MAX) {
+      set_error("learned lists exceed 2^31 entries");
+      return TAGI_E_UNSUPPORTED;
+    }
+    S.n_far = nf;
+    S.n_near = nnear;
+    TAGI_TRY(S.far_id.ensure(std::max<int64_t>(nf, 1) * 4));
+    TAGI_TRY(S.near_id.ensure(std::max<int64_t>(nnear, 1) * 4));
+    TAGI_HIP(hipMemcpyAsync(d_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
+    L.fill = 1;
+    L.off = d_off;
+    L.far_id = S.far_id.as<int32_t>();
+    L.near_id = S.near_id.as<int32_t>();
+    hipLaunchKernelGGL(k_lists_learned, dim3(grid), dim3(64), 0, s, L);
+    TAGI_HIP(hipGetLastError());
+    std::vector<int32_t> fid(std::max<int64_t>(nf, 1)), nid(std::max<int64_t>(nnear, 1));
+    if (nf) TAGI_HIP(hipMemcpyAsync(fid.data(), S.far_id.p, nf * 4, hipMemcpyDeviceToHost, s));
+    if (nnear) TAGI_HIP(hipMemcpyAsync(nid.data(), S.near_id.p, nnear * 4, hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipStreamSynchronize(s));
+    // proxy sets per degree: the clusters used at that degree
+    for (int d = 0; d <= kMaxDegree; ++d) S.far_by_degree[d] = 0;
+    S.far_inter = S.near_inter = 0;
+    for (int k = 0; k < kNDeg; ++k) {
+      const int d = kDegMin + k;
+      std::vector<char> used(nn, 0);
+      for (int b = 0; b < nl; ++b) {
+        const int64_t e0 = off[(size_t)b * kSlots + k], e1 = e0 + h[(size_t)b * kSlots + k];
+        const HostNode& q = t->nodes[t->leaves[b]];
+        S.far_by_degree[d] += e1 - e0;
+        S.far_inter += (int64_t)(q.end - q.begin) * (e1 - e0) * (d + 1) * (d + 1) * (d + 1);
+        for (int64_t e = e0; e < e1; ++e) used[fid[e]] = 1;
+      }
+      std::vector<int32_t> nodes;
+      for (int c = 0; c < nn; ++c)
+        if (used[c]) nodes.push_back(c);
+      if (nodes.empty()) {
+        t->lx[d].release();
+      } else {
+        TAGI_TRY(prepare_proxies(t, t->lx[d], nodes, d, n_orb, s));
+      }
+    }
+    // chunks (host): far segments per degree, then the near list, each cut by cost
+    const int64_t total = S.far_inter + 1;
+    S.h_chunks.clear();
+    std::vector<int32_t> bfirst(nl), bcount(nl);
+    for (int b = 0; b < nl; ++b) {
+      const HostNode& q = t->nodes[t->leaves[b]];
+      const int64_t nb = q.end - q.begin;
+      for (int64_t e = off[(size_t)b * kSlots + kNDeg]; e < off[(size_t)b * kSlots + kNDeg] + h[(size_t)b * kSlots + kNDeg]; ++e)
+        S.near_inter += nb * (t->nodes[nid[e]].end - t->nodes[nid[e]].begin);
+    }
+    const int64_t cap = std::max<int64_t>((total + S.near_inter / std::max<int64_t>(1, t->n / nl)) / 16384, 4096);
+    for (int b = 0; b < nl; ++b) {
+      bfirst[b] = (int32_t)(S.h_chunks.size() / 4);
+      for (int k = 0; k <= kNDeg; ++k) {
+        const int64_t e0 = off[(size_t)b * kSlots + k], e1 = e0 + h[(size_t)b * kSlots + k];
+        const int kindv = k < kNDeg ? 16 + kDegMin + k : 1;
+        int64_t start = e0, cost = 0;
+        for (int64_t e = e0; e < e1; ++e) {
+          const int64_t cst = k < kNDeg ? (int64_t)(kDegMin + k + 1) * (kDegMin + k + 1) * (kDegMin + k + 1)
+                                        : (int64_t)(t->nodes[nid[e]].end - t->nodes[nid[e]].begin);
+          if (cost > 0 && cost + cst > cap) {
+            S.h_chunks.insert(S.h_chunks.end(), {kindv, (int32_t)start, (int32_t)e, (int32_t)std::min<int64_t>(cost, INT32_MAX)});
+            start = e;
+            cost = 0;
+          }
+          cost += cst;
+        }
+        if (e1 > start)
+          S.h_chunks.insert(S.h_chunks.end(), {kindv, (int32_t)start, (int32_t)e1, (int32_t)std::min<int64_t>(cost, INT32_MAX)});
+      }
+      bcount[b] = (int32_t)(S.h_chunks.size() / 4) - bfirst[b];
+    }
+    // items (batch, group, orbital block, chunk); launch lists per degree and near
+    const int n_ob = (n_orb + ob - 1) / ob;
+    S.h_items.clear();
+    S.h_group_first.clear();
+    S.h_group_base.assign(nl, 0);
+    S.h_batch_chunks.assign(2 * (size_t)nl, 0);
+    std::vector<std::vector<int32_t>> per(kNDeg + 1);
+    for (int b = 0; b < nl; ++b) {
+      const HostNode& q = t->nodes[t->leaves[b]];
+      const int ng = (q.end - q.begin + kWave - 1) / kWave;
+      S.h_group_base[b] = (int32_t)S.h_group_first.size();
+      S.h_batch_chunks[2 * b] = bfirst[b];
+      S.h_batch_chunks[2 * b + 1] = bcount[b];
+      for (int g = 0; g < ng; ++g) {
+        S.h_group_first.push_back((int32_t)(S.h_items.size() / 4));
+        for (int o = 0; o < n_ob; ++o)
+          for (int cidx = 0; cidx < bcount[b]; ++cidx) {
+            const int ch = bfirst[b] + cidx;
+            const int kindv = S.h_chunks[(size_t)ch * 4];
+            const int slot = kindv == 1 ? kNDeg : kindv - 16 - kDegMin;
+            per[slot].push_back((int32_t)(S.h_items.size() / 4));
+            S.h_items.insert(S.h_items.end(), {b, g, o, ch});
+          }
+      }
+    }
+    S.n_items = (int64_t)S.h_items.size() / 4;
+    S.h_lists.clear();
+    S.list_begin.clear();
+    S.list_degree.clear();
+    for (int k = 0; k <= kNDeg; ++k) {
+      if (per[k].empty()) continue;
+      S.list_begin.push_back((int64_t)S.h_lists.size());
+      S.list_degree.push_back(k < kNDeg ? kDegMin + k : 0);
+      S.h_lists.insert(S.h_lists.end(), per[k].begin(), per[k].end());
+    }
+    S.list_begin.push_back((int64_t)S.h_lists.size());
+    auto up = [&](DBuf& buf, const std::vector<int32_t>& v) -> int {
+      TAGI_TRY(buf.ensure(std::max<size_t>(v.size(), 1) * 4));
+      if (!v.empty()) TAGI_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+      return TAGI_OK;
+    };
+    TAGI_TRY(up(S.chunks, S.h_chunks));
+    TAGI_TRY(up(S.items, S.h_items));
+    TAGI_TRY(up(S.group_first, S.h_group_first));
+    TAGI_TRY(up(S.group_base, S.h_group_base));
+    TAGI_TRY(up(S.batch_chunks, S.h_batch_chunks));
+    TAGI_TRY(up(S.item_lists, S.h_lists));
+    TAGI_TRY(S.partial.ensure(std::max<int64_t>(S.n_items, 1) * ob * 2 * kWave * sizeof(double)));
+    TAGI_HIP(hipStreamSynchronize(s));
+    S.ob = ob;
+    S.key = key;
+    phase_end(t, kPhaseLists, s);
+  }
+  // proxy charges at every degree in use, from the current tree-ordered values
+  const bool mix = precision == TAGI_MIXED;
+  for (size_t li = 0; li + 1 < S.list_begin.size(); ++li) {
+    const int d = S.list_degree[li];
+    if (d == 0) continue;
+    ProxySet& ps = t->lx[d];
+    TAGI_TRY(compute_proxies(t, ps, s));
+    if (mix) {
+      const int64_t K = (int64_t)(d + 1) * (d + 1) * (d + 1);
+      TAGI_TRY(ps.qhat32.ensure((size_t)n_orb * ps.n_approx * K * sizeof(float)));
+      TAGI_TRY(ps.what32.ensure((size_t)ps.n_approx * K * sizeof(float)));
+      TAGI_TRY(launch_to_f32(ps.qhat.as<double>(), ps.qhat32.as<float>(), n_orb * ps.n_approx * K, s));
+      TAGI_TRY(launch_to_f32(ps.what.as<double>(), ps.what32.as<float>(), ps.n_approx * K, s));
+    }
+  }
+  const OrbArg orb = make_orb(kernel, n_orb, kappa, alpha);
+  phase_begin(t, kPhaseInteract, s);
+  for (size_t li = 0; li + 1 < S.list_begin.size(); ++li) {
+    const int d = S.list_degree[li];
+    InteractArgs A{};
+    A.items = S.items.as<int4>();
+    A.n_items = S.n_items;
+    A.chunks = reinterpret_cast<const Chunk*>(S.chunks.p);
+    A.leaf_node = t->leaf_node.as<int32_t>();
+    A.nbeg = t->nd_begin.as<int32_t>();
+    A.nend = t->nd_end.as<int32_t>();
+    A.far_id = S.far_id.as<int32_t>();
+    A.near_id = S.near_id.as<int32_t>();
+    A.xs = t->xs.as<double>();
+    A.ys = t->ys.as<double>();
+    A.zs = t->zs.as<double>();
+    A.qs = t->qs.as<double>();
+    A.ws = t->ws.as<double>();
+    A.geom = t->nd_geom.as<double>();
+    A.n = t->n;
+    A.n_orb = n_orb;
+    A.partial = S.partial.as<double>();
+    A.item_list = S.item_lists.as<int32_t>() + S.list_begin[li];
+    A.n_list = S.list_begin[li + 1] - S.list_begin[li];
+    if (d > 0) {
+      const ProxySet& ps = t->lx[d];
+      A.slot_of = ps.slot_of.as<int32_t>();
+      A.pnodes = ps.pnodes.as<double>();
+      A.qhat = ps.qhat.as<double>();
+      A.what = ps.what.as<double>();
+      A.pnodes32 = ps.pnodes32.as<float>();
+      A.qhat32 = ps.qhat32.as<float>();
+      A.what32 = ps.what32.as<float>();
+      A.n_approx = ps.n_approx;
+      A.degree = d;
+    } else {
+      A.degree = 0;  // near items only: any compiled variant
+    }
+    ++t->interact_launches;
+    if (kernel == TAGI_YUKAWA_SS)
+      launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, s);
+    else
+      launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, s);
+    TAGI_HIP(hipGetLastError());
+  }
+  phase_end(t, kPhaseInteract, s);
+  phase_begin(t, kPhaseCombine, s);
+  TAGI_TRY(launch_combine(t, ob, kernel == TAGI_YUKAWA_SS, S.group_base.as<int32_t>(),
+                          S.group_first.as<int32_t>(), S.batch_chunks.as<int2>(),
+                          S.partial.as<double>(), orb, out, s));
+  phase_end(t, kPhaseCombine, s);
+  return TAGI_OK;
+}
+
+}  // namespace tagi

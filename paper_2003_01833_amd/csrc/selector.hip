@@ -1,0 +1,450 @@
+// Learned degree/MAC selector: training data from the method itself, and the
+// network's training kernels.
+//
+// Samples. For a candidate batch-cluster pair (B, C) and a degree n, the label is
+// the largest absolute error, over the first 64 targets of B, of the
+// particle-cluster approximation of Eq. particle-cluster-approx-rearranged against
+// the direct sum of Eq. direct-sum_2 (both with the Section 4.3 subtraction, i.e.
+// the pair's contribution a1 - f_i a2). Features: cluster radius r_C, distance
+// from the batch's bounding sphere to the cluster centre R - r_B, kappa, N_S and
+// the l1 norm of the cluster's degree-4 proxy charges.
+//
+// Network (FP32): 5 inputs, three tanh layers of 64, 9 linear outputs (the
+// log10 errors at degrees 4..12). Training is mini-batch Adam with one kernel per
+// dense layer in each direction; every reduction runs in a fixed order, so
+// training is repeatable bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "interact_impl.hpp"
+#include "internal.hpp"
+
+namespace tagi {
+namespace {
+
+using namespace ik;
+
+constexpr int kSelIn = 5, kSelH = 64, kSelOut = 9;
+
+// ---------------------------------------------------------------------------
+// sample generation
+
+// exact (direct) contribution of cluster C to the first 64 targets of batch B
+__global__ __launch_bounds__(256) void k_pair_exact(const int2* __restrict__ pairs, int n_pairs,
+                                                    InteractArgs A, double kappa,
+                                                    double* __restrict__ out) {
+  const int lane = threadIdx.x % kWave;
+  const int p = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + threadIdx.x / kWave));
+  if (p >= n_pairs) return;
+  const int2 pr = pairs[p];
+  const int B = pr.x, C = pr.y;
+  const int tb = A.nbeg[B], te = min(A.nend[B], tb + kWave);
+  const int i = tb + lane < te ? tb + lane : tb;
+  double a1[1] = {0.0}, a2[1] = {0.0};
+  const double nkap[1] = {-kappa};
+  const double* qr[1] = {A.qs};
+  near_range<TAGI_YUKAWA_SS, 1>(A.xs[i], A.ys[i], A.zs[i], A.nbeg[C], A.nend[C], A.xs, A.ys,
+                                A.zs, A.ws, qr, nkap, 0.0, a1, a2);
+  out[(int64_t)p * kWave + lane] = __builtin_fma(-A.fs[i], a2[0], a1[0]);
+}
+
+// approximated contribution at the degree of the current upward pass; lanes past
+// the batch's end and pairs without proxies at this degree write NaN
+__global__ __launch_bounds__(256) void k_pair_approx(const int2* __restrict__ pairs, int n_pairs,
+                                                     InteractArgs A, double kappa,
+                                                     const double* __restrict__ exact,
+                                                     float* __restrict__ err) {
+  const int lane = threadIdx.x % kWave;
+  const int p = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + threadIdx.x / kWave));
+  if (p >= n_pairs) return;
+  const int2 pr = pairs[p];
+  const int B = pr.x, C = pr.y;
+  const int slot = A.slot_of[C];
+  const int tb = A.nbeg[B], te = min(A.nend[B], tb + kWave);
+  const bool live = tb + lane < te;
+  const int i = live ? tb + lane : tb;
+  double e = 0.0;
+  if (slot >= 0) {
+    const int np1 = A.degree + 1;
+    const int K = np1 * np1 * np1;
+    double a1[1] = {0.0}, a2[1] = {0.0};
+    const double nkap[1] = {-kappa};
+    const double* qk[1] = {A.qhat + (int64_t)slot * K};
+    far_cluster<TAGI_YUKAWA_SS, 1, 0>(A.xs[i], A.ys[i], A.zs[i], np1,
+                                      A.pnodes + (int64_t)slot * 3 * np1, A.what + (int64_t)slot * K,
+                                      qk, nkap, 0.0, a1, a2);
+    const double u = __builtin_fma(-A.fs[i], a2[0], a1[0]);
+    e = live ? fabs(u - exact[(int64_t)p * kWave + lane]) : 0.0;
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) e = fmax(e, __shfl_xor(e, off));
+  if (lane == 0) err[p] = slot >= 0 ? (float)e : NAN;
+}
+
+// l1 norm of each slot's proxy charges (orbital 0)
+__global__ void k_slot_l1(const double* __restrict__ qhat, int n_approx, int K,
+                          double* __restrict__ l1) {
+  const int slot = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) s += fabs(qhat[(int64_t)slot * K + k]);
+  for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  __shared__ double red[4];
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) l1[slot] = red[0] + red[1] + red[2] + red[3];
+}
+
+InteractArgs args_of(tagi_tree* t) {
+  InteractArgs A{};
+  A.nbeg = t->nd_begin.as<int32_t>();
+  A.nend = t->nd_end.as<int32_t>();
+  A.slot_of = t->px.slot_of.as<int32_t>();
+  A.xs = t->xs.as<double>();
+  A.ys = t->ys.as<double>();
+  A.zs = t->zs.as<double>();
+  A.qs = t->qs.as<double>();
+  A.ws = t->ws.as<double>();
+  A.fs = t->fs.as<double>();
+  A.pnodes = t->px.pnodes.as<double>();
+  A.qhat = t->px.qhat.as<double>();
+  A.what = t->px.what.as<double>();
+  A.geom = t->nd_geom.as<double>();
+  A.n = t->n;
+  A.n_orb = t->n_orb;
+  A.n_approx = t->px.n_approx;
+  A.degree = t->degree;
+  return A;
+}
+
+// ---------------------------------------------------------------------------
+// network training (FP32)
+
+// H[b][o] = act(sum_i W[o][i] X[b][i] + bias[o]), act = tanh or identity
+__global__ void k_dense_fwd(const float* __restrict__ X, int nin, const float* __restrict__ W,
+                            const float* __restrict__ bias, int nout, int m, int act,
+                            float* __restrict__ H) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)m * nout) return;
+  const int b = (int)(id / nout), o = (int)(id % nout);
+  float s = bias[o];
+  for (int i = 0; i < nin; ++i) s = __builtin_fmaf(W[o * nin + i], X[(int64_t)b * nin + i], s);
+  H[id] = act ? tanhf(s) : s;
+}
+
+// G[b][k] = mask (out - y) / count;  loss partial per block
+__global__ void k_out_grad(const float* __restrict__ out, const float* __restrict__ Y,
+                           const float* __restrict__ M, int64_t total, float inv_cnt,
+                           float* __restrict__ G, float* __restrict__ loss_part) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.0f;
+  if (id < total) {
+    const float r = (out[id] - Y[id]) * M[id];
+    G[id] = r * inv_cnt;
+    l = 0.5f * r * r * inv_cnt;
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) l += __shfl_xor(l, off);
+  __shared__ float red[4];
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// dW[o][i] = sum_b G[b][o] H[b][i];  db[o] = sum_b G[b][o]  (thread per weight)
+__global__ void k_dense_wgrad(const float* __restrict__ G, int nout, const float* __restrict__ H,
+                              int nin, int m, float* __restrict__ dW, float* __restrict__ db) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nout * (nin + 1)) return;
+  const int o = id / (nin + 1), i = id % (nin + 1);
+  float s = 0.0f;
+  if (i < nin) {
+    for (int b = 0; b < m; ++b) s = __builtin_fmaf(G[(int64_t)b * nout + o], H[(int64_t)b * nin + i], s);
+    dW[o * nin + i] = s;
+  } else {
+    for (int b = 0; b < m; ++b) s += G[(int64_t)b * nout + o];
+    db[o] = s;
+  }
+}
+
+// Gin[b][i] = (sum_o G[b][o] W[o][i]) (1 - H[b][i]^2)   (back through tanh)
+__global__ void k_dense_bgrad(const float* __restrict__ G, int nout, const float* __restrict__ W,
+                              const float* __restrict__ H, int nin, int m,
+                              float* __restrict__ Gin) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)m * nin) return;
+  const int b = (int)(id / nin), i = (int)(id % nin);
+  float s = 0.0f;
+  for (int o = 0; o < nout; ++o) s = __builtin_fmaf(G[(int64_t)b * nout + o], W[o * nin + i], s);
+  const float h = H[id];
+  Gin[id] = s * (1.0f - h * h);
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const float gi = g[id];
+  const float mi = b1 * m[id] + (1.0f - b1) * gi;
+  const float vi = b2 * v[id] + (1.0f - b2) * gi * gi;
+  m[id] = mi;
+  v[id] = vi;
+  p[id] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_gather_rows(const float* __restrict__ src, const int32_t* __restrict__ idx,
+                              int width, int m, float* __restrict__ dst) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)m * width) return;
+  const int r = (int)(id / width), c = (int)(id % width);
+  dst[id] = src[(int64_t)idx[r] * width + c];
+}
+
+int grid_of(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+int selector_param_count() {
+  return (kSelIn * kSelH + kSelH) + 2 * (kSelH * kSelH + kSelH) + (kSelH * kSelOut + kSelOut);
+}
+
+// Forward, loss gradient and backward of one mini-batch; fills grads (same layout
+// as params) and returns the loss. Buffers: acts = 4 * m * 64 floats, g = 2 * m * 64.
+static int mlp_batch_grad(const float* params, const float* X, const float* Y, const float* M,
+                          int m, float inv_cnt, float* acts, float* gbuf, float* grads,
+                          float* loss_part, int* n_loss_part, hipStream_t s) {
+  const int sizes[5] = {kSelIn, kSelH, kSelH, kSelH, kSelOut};
+  const float* W[4];
+  const float* Bv[4];
+  float* dW[4];
+  float* dB[4];
+  int off = 0;
+  for (int l = 0; l < 4; ++l) {
+    W[l] = params + off;
+    dW[l] = grads + off;
+    off += sizes[l] * sizes[l + 1];
+    Bv[l] = params + off;
+    dB[l] = grads + off;
+    off += sizes[l + 1];
+  }
+  float* H[5];
+  H[0] = const_cast<float*>(X);
+  for (int l = 1; l <= 4; ++l) H[l] = acts + (int64_t)(l - 1) * m * kSelH;
+  for (int l = 0; l < 4; ++l) {
+    hipLaunchKernelGGL(k_dense_fwd, dim3(grid_of((int64_t)m * sizes[l + 1])), dim3(256), 0, s, H[l],
+                       sizes[l], W[l], Bv[l], sizes[l + 1], m, l < 3 ? 1 : 0, H[l + 1]);
+  }
+  float* G = gbuf;
+  float* G2 = gbuf + (int64_t)m * kSelH;
+  const int64_t tot = (int64_t)m * kSelOut;
+  *n_loss_part = grid_of(tot);
+  hipLaunchKernelGGL(k_out_grad, dim3(*n_loss_part), dim3(256), 0, s, H[4], Y, M, tot, inv_cnt, G,
+                     loss_part);
+  for (int l = 3; l >= 0; --l) {
+    hipLaunchKernelGGL(k_dense_wgrad, dim3(grid_of(sizes[l + 1] * (sizes[l] + 1))), dim3(256), 0,
+                       s, G, sizes[l + 1], H[l], sizes[l], m, dW[l], dB[l]);
+    if (l > 0) {
+      hipLaunchKernelGGL(k_dense_bgrad, dim3(grid_of((int64_t)m * sizes[l])), dim3(256), 0, s, G,
+                         sizes[l + 1], W[l], H[l], sizes[l], m, G2);
+      std::swap(G, G2);
+    }
+  }
+  TAGI_HIP(hipGetLastError());
+  return TAGI_OK;
+}
+
+int selector_grad(const float* params, const float* X, const float* Y, const float* M, int64_t m,
+                  float* grads, float* loss, hipStream_t s) {
+  float *acts = nullptr, *gbuf = nullptr, *lp = nullptr;
+  TAGI_HIP(hipMallocAsync((void**)&acts, (size_t)4 * m * kSelH * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&gbuf, (size_t)2 * m * kSelH * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&lp, (size_t)grid_of(m * kSelOut) * sizeof(float), s));
+  std::vector<float> hm(m * kSelOut);
+  TAGI_HIP(hipMemcpyAsync(hm.data(), M, hm.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  double cnt = 0.0;
+  for (float v : hm) cnt += v;
+  int nlp = 0;
+  int st = mlp_batch_grad(params, X, Y, M, (int)m, (float)(1.0 / std::max(cnt, 1.0)), acts, gbuf,
+                          grads, lp, &nlp, s);
+  if (st == TAGI_OK && loss) {
+    std::vector<float> h(nlp);
+    TAGI_HIP(hipMemcpyAsync(h.data(), lp, nlp * sizeof(float), hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipStreamSynchronize(s));
+    double l = 0.0;
+    for (float v : h) l += v;
+    *loss = (float)l;
+  }
+  TAGI_HIP(hipFreeAsync(acts, s));
+  TAGI_HIP(hipFreeAsync(gbuf, s));
+  TAGI_HIP(hipFreeAsync(lp, s));
+  return st;
+}
+
+int selector_train(float* params, const float* X, const float* Y, const float* M, int64_t m,
+                   const int32_t* order, int epochs, int batch, float lr, float* loss_hist,
+                   hipStream_t s) {
+  if (m < batch) {
+    set_error("selector_train: %lld samples are fewer than one mini-batch of %d", (long long)m, batch);
+    return TAGI_E_ARG;
+  }
+  const int np = selector_param_count();
+  float *acts, *gbuf, *lp, *grads, *mom, *vel, *bx, *by, *bm;
+  int32_t* didx;
+  TAGI_HIP(hipMallocAsync((void**)&acts, (size_t)4 * batch * kSelH * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&gbuf, (size_t)2 * batch * kSelH * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&lp, (size_t)grid_of((int64_t)batch * kSelOut) * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&grads, np * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&mom, np * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&vel, np * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&bx, (size_t)batch * kSelIn * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&by, (size_t)batch * kSelOut * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&bm, (size_t)batch * kSelOut * sizeof(float), s));
+  TAGI_HIP(hipMallocAsync((void**)&didx, (size_t)(m + batch) * sizeof(int32_t), s));
+  TAGI_HIP(hipMemsetAsync(mom, 0, np * sizeof(float), s));
+  TAGI_HIP(hipMemsetAsync(vel, 0, np * sizeof(float), s));
+  // the order, followed by its first `batch` entries, so any window of `batch`
+  // consecutive rows starting below m is contiguous
+  std::vector<int32_t> hord((size_t)(m + batch));
+  for (int64_t r = 0; r < m + batch; ++r) hord[r] = order[r % m];
+  TAGI_HIP(hipMemcpyAsync(didx, hord.data(), hord.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  std::vector<float> hm((size_t)m * kSelOut);
+  TAGI_HIP(hipMemcpyAsync(hm.data(), M, hm.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const int64_t nb = m / batch;        // mini-batches per epoch
+  const int64_t shift = batch / 3 + 1; // epochs start at shifted windows of the order
+  int step = 0, st = TAGI_OK;
+  std::vector<float> hl;
+  for (int ep = 0; ep < epochs && st == TAGI_OK; ++ep) {
+    double ep_loss = 0.0;
+    for (int64_t bi = 0; bi < nb; ++bi) {
+      const int64_t base = (bi * batch + ep * shift) % m;
+      double cnt = 0.0;
+      for (int r = 0; r < batch; ++r)
+        for (int k = 0; k < kSelOut; ++k) cnt += hm[(size_t)hord[base + r] * kSelOut + k];
+      const int32_t* rows = didx + base;
+      hipLaunchKernelGGL(k_gather_rows, dim3(grid_of((int64_t)batch * kSelIn)), dim3(256), 0, s, X, rows, kSelIn, batch, bx);
+      hipLaunchKernelGGL(k_gather_rows, dim3(grid_of((int64_t)batch * kSelOut)), dim3(256), 0, s, Y, rows, kSelOut, batch, by);
+      hipLaunchKernelGGL(k_gather_rows, dim3(grid_of((int64_t)batch * kSelOut)), dim3(256), 0, s, M, rows, kSelOut, batch, bm);
+      int nlp = 0;
+      st = mlp_batch_grad(params, bx, by, bm, batch, (float)(1.0 / std::max(cnt, 1.0)), acts, gbuf,
+                          grads, lp, &nlp, s);
+      if (st != TAGI_OK) break;
+      ++step;
+      const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+      hipLaunchKernelGGL(k_adam, dim3(grid_of(np)), dim3(256), 0, s, params, grads, mom, vel, np,
+                         lr, b1, b2, eps, c1, c2);
+      if (loss_hist) {
+        hl.resize(nlp);
+        TAGI_HIP(hipMemcpyAsync(hl.data(), lp, nlp * sizeof(float), hipMemcpyDeviceToHost, s));
+        TAGI_HIP(hipStreamSynchronize(s));
+        for (float v : hl) ep_loss += v;
+      }
+    }
+    if (loss_hist) loss_hist[ep] = (float)(ep_loss / std::max<int64_t>(nb, 1));
+  }
+  TAGI_HIP(hipGetLastError());
+  for (void* p : {(void*)acts, (void*)gbuf, (void*)lp, (void*)grads, (void*)mom, (void*)vel,
+                  (void*)bx, (void*)by, (void*)bm, (void*)didx})
+    TAGI_HIP(hipFreeAsync(p, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  return st;
+}
+
+int selector_samples(tagi_tree* t, const double* f, const double* w, double kappa,
+                     double theta_max, int64_t max_pairs, float* feat, float* err,
+                     int32_t* pair_ids, int64_t* n_out, hipStream_t s) {
+  // candidate pairs: the far pairs of the lists at (theta_max, degree 4)
+  const int d0 = 4;
+  TAGI_TRY(upward(t, f, w, 1, d0, s));
+  TAGI_TRY(ensure_lists(t, theta_max, d0, s));
+  const int nl = (int)t->leaves.size();
+  std::vector<int32_t> fid(std::max<int64_t>(t->n_far, 1));
+  if (t->n_far)
+    TAGI_HIP(hipMemcpyAsync(fid.data(), t->far_id.p, t->n_far * 4, hipMemcpyDeviceToHost, s));
+  // per-slot l1 norms of the degree-4 proxy charges
+  const int K4 = (d0 + 1) * (d0 + 1) * (d0 + 1);
+  std::vector<double> l1(std::max(t->px.n_approx, 1));
+  std::vector<int32_t> slot4 = t->px.h_slot_of;
+  if (t->px.n_approx > 0) {
+    double* dl1;
+    TAGI_HIP(hipMallocAsync((void**)&dl1, t->px.n_approx * sizeof(double), s));
+    hipLaunchKernelGGL(k_slot_l1, dim3(t->px.n_approx), dim3(256), 0, s, t->px.qhat.as<double>(),
+                       t->px.n_approx, K4, dl1);
+    TAGI_HIP(hipMemcpyAsync(l1.data(), dl1, t->px.n_approx * sizeof(double), hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipFreeAsync(dl1, s));
+  }
+  TAGI_HIP(hipStreamSynchronize(s));
+  // evenly strided subset of the far pairs, in list order
+  std::vector<int2> pairs;
+  const int64_t nf = t->n_far;
+  const int64_t want = std::min<int64_t>(max_pairs, nf);
+  if (want > 0) {
+    pairs.reserve(want);
+    int b = 0;
+    for (int64_t k = 0; k < want; ++k) {
+      const int64_t e = k * nf / want;
+      while (t->h_far_off[b + 1] <= e) ++b;
+      pairs.push_back({t->leaves[b], fid[e]});
+    }
+  }
+  const int np = (int)pairs.size();
+  *n_out = np;
+  if (np == 0) return TAGI_OK;
+  for (int p = 0; p < np; ++p) {
+    const HostNode& B = t->nodes[pairs[p].x];
+    const HostNode& C = t->nodes[pairs[p].y];
+    double cb[3], cc[3], hb[3], hc[3];
+    for (int k = 0; k < 3; ++k) {
+      cb[k] = 0.5 * (B.lo[k] + B.hi[k]);
+      cc[k] = 0.5 * (C.lo[k] + C.hi[k]);
+      hb[k] = 0.5 * (B.hi[k] - B.lo[k]);
+      hc[k] = 0.5 * (C.hi[k] - C.lo[k]);
+    }
+    const double rb = std::sqrt(hb[0] * hb[0] + hb[1] * hb[1] + hb[2] * hb[2]);
+    const double rc = std::sqrt(hc[0] * hc[0] + hc[1] * hc[1] + hc[2] * hc[2]);
+    const double R = std::sqrt((cb[0] - cc[0]) * (cb[0] - cc[0]) + (cb[1] - cc[1]) * (cb[1] - cc[1]) +
+                               (cb[2] - cc[2]) * (cb[2] - cc[2]));
+    const int sl = slot4[pairs[p].y];
+    feat[p * 5 + 0] = (float)rc;
+    feat[p * 5 + 1] = (float)(R - rb);
+    feat[p * 5 + 2] = (float)kappa;
+    feat[p * 5 + 3] = (float)(C.end - C.begin);
+    feat[p * 5 + 4] = (float)(sl >= 0 ? l1[sl] : 0.0);
+    if (pair_ids) {
+      pair_ids[2 * p] = pairs[p].x;
+      pair_ids[2 * p + 1] = pairs[p].y;
+    }
+  }
+  int2* dp;
+  double* exact;
+  float* derr;
+  TAGI_HIP(hipMallocAsync((void**)&dp, np * sizeof(int2), s));
+  TAGI_HIP(hipMallocAsync((void**)&exact, (size_t)np * kWave * sizeof(double), s));
+  TAGI_HIP(hipMallocAsync((void**)&derr, (size_t)np * sizeof(float), s));
+  TAGI_HIP(hipMemcpyAsync(dp, pairs.data(), np * sizeof(int2), hipMemcpyHostToDevice, s));
+  InteractArgs A = args_of(t);
+  hipLaunchKernelGGL(k_pair_exact, dim3((np + 3) / 4), dim3(256), 0, s, dp, np, A, kappa, exact);
+  TAGI_HIP(hipGetLastError());
+  std::vector<float> e(np);
+  for (int d = 4; d <= 12 && true; ++d) {
+    TAGI_TRY(upward(t, f, w, 1, d, s));
+    A = args_of(t);
+    hipLaunchKernelGGL(k_pair_approx, dim3((np + 3) / 4), dim3(256), 0, s, dp, np, A, kappa,
+                       exact, derr);
+    TAGI_HIP(hipGetLastError());
+    TAGI_HIP(hipMemcpyAsync(e.data(), derr, np * sizeof(float), hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipStreamSynchronize(s));
+    for (int p = 0; p < np; ++p) err[p * 9 + (d - 4)] = e[p];
+  }
+  TAGI_HIP(hipFreeAsync(dp, s));
+  TAGI_HIP(hipFreeAsync(exact, s));
+  TAGI_HIP(hipFreeAsync(derr, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  (void)nl;
+  return TAGI_OK;
+}
+
+}  // namespace tagi

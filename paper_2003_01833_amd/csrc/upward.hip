@@ -184,49 +184,44 @@ __global__ void k_upward_reduce(const int32_t* __restrict__ slot_first,
 }
 
 template <int R, int MB>
-void launch_upward(int n_items, hipStream_t s, const UpItem* items, tagi_tree* t, int m0,
-                   int n_sets, double* partial) {
-  hipLaunchKernelGGL((k_upward<R, MB>), dim3(n_items), dim3(kThreads), 0, s, items,
-                     t->approx_node.as<int32_t>(), t->nd_box.as<double>(), t->xs.as<double>(),
-                     t->ys.as<double>(), t->zs.as<double>(), t->qs.as<double>(),
-                     t->ws.as<double>(), t->n, t->n_orb, m0, n_sets, t->degree, partial,
-                     t->pnodes.as<double>(), t->pnodes32.as<float>());
+void launch_upward(hipStream_t s, tagi_tree* t, ProxySet& ps, int m0, int n_sets) {
+  hipLaunchKernelGGL((k_upward<R, MB>), dim3(ps.n_items), dim3(kThreads), 0, s,
+                     ps.items.as<UpItem>(), ps.node.as<int32_t>(), t->nd_box.as<double>(),
+                     t->xs.as<double>(), t->ys.as<double>(), t->zs.as<double>(),
+                     t->qs.as<double>(), t->ws.as<double>(), t->n, ps.n_orb, m0, n_sets,
+                     ps.degree, ps.partial.as<double>(), ps.pnodes.as<double>(),
+                     ps.pnodes32.as<float>());
+}
+
+int charge_blocking(int K, int* R_out) {
+  const int R = (K + kThreads - 1) / kThreads;
+  *R_out = R;
+  return R <= 3 ? 8 : (R <= 6 ? 4 : (R <= 10 ? 2 : 1));
 }
 
 }  // namespace
 
-// Host plan of the upward pass for (degree, n_orb): the approximable clusters,
-// the work items and the device buffers. Built once and reused, so a repeated
-// tagi_upward only launches kernels (and can be captured in a HIP graph).
-static int prepare_upward(tagi_tree* t, int n_orb, int degree, hipStream_t s) {
-  if (t->up_plan_degree == degree && t->up_plan_n_orb == n_orb) return TAGI_OK;
-  t->up_plan_degree = t->up_plan_n_orb = 0;
-  const int64_t n = t->n;
-  TAGI_TRY(t->ws.ensure(n * sizeof(double)));
-  TAGI_TRY(t->fs.ensure((size_t)n_orb * n * sizeof(double)));
-  TAGI_TRY(t->qs.ensure((size_t)n_orb * n * sizeof(double)));
+// Host plan of the proxy charges of `nodes` at `degree`: slots, work items and
+// device buffers. Built once per (set, degree, n_orb) and reused, so a repeated
+// upward pass only launches kernels (and can be captured in a HIP graph).
+int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& nodes, int degree,
+                    int n_orb, hipStream_t s) {
+  ps.degree = ps.n_orb = 0;
   const int np1 = degree + 1;
   const int K = np1 * np1 * np1;
-  // approximable clusters: more than (n+1)^3 sources; the root is skipped because
-  // every batch centre lies inside it, so the distance test can never accept it
-  t->approx_nodes.clear();
-  std::vector<int32_t>& slot_of = t->h_slot_of;
-  slot_of.assign(t->nodes.size(), -1);
-  for (size_t c = 1; c < t->nodes.size(); ++c)
-    if (t->nodes[c].end - t->nodes[c].begin > K) {
-      slot_of[c] = (int32_t)t->approx_nodes.size();
-      t->approx_nodes.push_back((int32_t)c);
-    }
-  const int na = (int)t->approx_nodes.size();
-  t->n_approx = na;
-  TAGI_TRY(t->slot_of_node.ensure(slot_of.size() * 4));
-  TAGI_HIP(hipMemcpyAsync(t->slot_of_node.p, slot_of.data(), slot_of.size() * 4,
+  ps.nodes = nodes;
+  ps.h_slot_of.assign(t->nodes.size(), -1);
+  for (size_t sl = 0; sl < nodes.size(); ++sl) ps.h_slot_of[nodes[sl]] = (int32_t)sl;
+  const int na = (int)nodes.size();
+  ps.n_approx = na;
+  TAGI_TRY(ps.slot_of.ensure(ps.h_slot_of.size() * 4));
+  TAGI_HIP(hipMemcpyAsync(ps.slot_of.p, ps.h_slot_of.data(), ps.h_slot_of.size() * 4,
                           hipMemcpyHostToDevice, s));
   std::vector<UpItem> items;
   std::vector<int32_t> slot_first(na + 1, 0);
   for (int sl = 0; sl < na; ++sl) {
     slot_first[sl] = (int32_t)items.size();
-    const HostNode& q = t->nodes[t->approx_nodes[sl]];
+    const HostNode& q = t->nodes[nodes[sl]];
     for (int32_t p = q.begin; p < q.end; p += kItemPts)
       items.push_back({sl, p, std::min(q.end, p + kItemPts), 0});
   }
@@ -235,30 +230,64 @@ static int prepare_upward(tagi_tree* t, int n_orb, int degree, hipStream_t s) {
   for (int sl = 0; sl < na; ++sl)
     for (int i = slot_first[sl]; i < slot_first[sl + 1]; ++i)
       items[i].part = i == slot_first[sl] ? sl : -1;
-  t->up_n_items = (int)items.size();
+  ps.n_items = (int)items.size();
   if (na > 0) {
-    TAGI_TRY(t->approx_node.ensure(na * 4));
-    TAGI_HIP(hipMemcpyAsync(t->approx_node.p, t->approx_nodes.data(), na * 4,
+    TAGI_TRY(ps.node.ensure(na * 4));
+    TAGI_HIP(hipMemcpyAsync(ps.node.p, ps.nodes.data(), na * 4, hipMemcpyHostToDevice, s));
+    // host staging lives in the set so the asynchronous uploads never outlive it
+    ps.h_items.resize(items.size() * 4);
+    std::memcpy(ps.h_items.data(), items.data(), items.size() * sizeof(UpItem));
+    ps.h_slot_first = slot_first;
+    TAGI_TRY(ps.items.ensure(items.size() * sizeof(UpItem) + (na + 1) * 4));
+    TAGI_HIP(hipMemcpyAsync(ps.items.p, ps.h_items.data(), items.size() * sizeof(UpItem),
                             hipMemcpyHostToDevice, s));
-    // host staging lives in the tree so the asynchronous uploads never outlive it
-    t->h_up_items.resize(items.size() * 4);
-    std::memcpy(t->h_up_items.data(), items.data(), items.size() * sizeof(UpItem));
-    t->h_slot_first = slot_first;
-    TAGI_TRY(t->up_items.ensure(items.size() * sizeof(UpItem) + (na + 1) * 4));
-    TAGI_HIP(hipMemcpyAsync(t->up_items.p, t->h_up_items.data(), items.size() * sizeof(UpItem),
-                            hipMemcpyHostToDevice, s));
-    TAGI_HIP(hipMemcpyAsync(t->up_items.as<char>() + items.size() * sizeof(UpItem),
-                            t->h_slot_first.data(), (na + 1) * 4, hipMemcpyHostToDevice, s));
-    TAGI_TRY(t->pnodes.ensure((size_t)na * 3 * np1 * sizeof(double)));
-    TAGI_TRY(t->pnodes32.ensure((size_t)na * 3 * np1 * sizeof(float)));
-    TAGI_TRY(t->qhat.ensure((size_t)n_orb * na * K * sizeof(double)));
-    TAGI_TRY(t->what.ensure((size_t)na * K * sizeof(double)));
-    const int R = (K + kThreads - 1) / kThreads;
-    const int MB = R <= 3 ? 8 : (R <= 6 ? 4 : (R <= 10 ? 2 : 1));
-    TAGI_TRY(t->up_partial.ensure((size_t)t->up_n_items * MB * K * sizeof(double)));
+    TAGI_HIP(hipMemcpyAsync(ps.items.as<char>() + items.size() * sizeof(UpItem),
+                            ps.h_slot_first.data(), (na + 1) * 4, hipMemcpyHostToDevice, s));
+    TAGI_TRY(ps.pnodes.ensure((size_t)na * 3 * np1 * sizeof(double)));
+    TAGI_TRY(ps.pnodes32.ensure((size_t)na * 3 * np1 * sizeof(float)));
+    TAGI_TRY(ps.qhat.ensure((size_t)n_orb * na * K * sizeof(double)));
+    TAGI_TRY(ps.what.ensure((size_t)na * K * sizeof(double)));
+    int R;
+    const int MB = charge_blocking(K, &R);
+    TAGI_TRY(ps.partial.ensure((size_t)ps.n_items * MB * K * sizeof(double)));
   }
-  t->up_plan_degree = degree;
-  t->up_plan_n_orb = n_orb;
+  ps.degree = degree;
+  ps.n_orb = n_orb;
+  return TAGI_OK;
+}
+
+int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s) {
+  const int na = ps.n_approx;
+  if (na == 0) return TAGI_OK;
+  const int np1 = ps.degree + 1;
+  const int K = np1 * np1 * np1;
+  const int n_sets_total = ps.n_orb + 1;
+  int R;
+  const int MB = charge_blocking(K, &R);
+  const int32_t* d_slot_first =
+      reinterpret_cast<const int32_t*>(ps.items.as<char>() + (size_t)ps.n_items * sizeof(UpItem));
+  for (int m0 = 0; m0 < n_sets_total; m0 += MB) {
+    const int n_sets = std::min(MB, n_sets_total - m0);
+    switch (R) {
+      case 1: launch_upward<1, 8>(s, t, ps, m0, n_sets); break;
+      case 2: launch_upward<2, 8>(s, t, ps, m0, n_sets); break;
+      case 3: launch_upward<3, 8>(s, t, ps, m0, n_sets); break;
+      case 4: launch_upward<4, 4>(s, t, ps, m0, n_sets); break;
+      case 5: launch_upward<5, 4>(s, t, ps, m0, n_sets); break;
+      case 6: launch_upward<6, 4>(s, t, ps, m0, n_sets); break;
+      case 7: launch_upward<7, 2>(s, t, ps, m0, n_sets); break;
+      case 8: launch_upward<8, 2>(s, t, ps, m0, n_sets); break;
+      case 9: launch_upward<9, 2>(s, t, ps, m0, n_sets); break;
+      case 10: launch_upward<10, 2>(s, t, ps, m0, n_sets); break;
+      default: launch_upward<20, 1>(s, t, ps, m0, n_sets); break;
+    }
+    TAGI_HIP(hipGetLastError());
+    const int64_t tot = (int64_t)n_sets * K;
+    hipLaunchKernelGGL(k_upward_reduce, dim3((tot + 255) / 256, na), dim3(256), 0, s,
+                       d_slot_first, ps.partial.as<double>(), na, K, MB, m0, n_sets, ps.n_orb,
+                       ps.qhat.as<double>(), ps.what.as<double>());
+    TAGI_HIP(hipGetLastError());
+  }
   return TAGI_OK;
 }
 
@@ -267,47 +296,24 @@ int upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree
   const int64_t n = t->n;
   t->degree = 0;  // invalid until complete
   phase_begin(t, kPhaseUpward, s);
-  TAGI_TRY(prepare_upward(t, n_orb, degree, s));
+  if (!(t->px.degree == degree && t->px.n_orb == n_orb)) {
+    TAGI_TRY(t->ws.ensure(n * sizeof(double)));
+    TAGI_TRY(t->fs.ensure((size_t)n_orb * n * sizeof(double)));
+    TAGI_TRY(t->qs.ensure((size_t)n_orb * n * sizeof(double)));
+    // approximable clusters: more than (n+1)^3 sources; the root is skipped because
+    // every batch centre lies inside it, so the distance test can never accept it
+    const int K = (degree + 1) * (degree + 1) * (degree + 1);
+    std::vector<int32_t> nodes;
+    for (size_t c = 1; c < t->nodes.size(); ++c)
+      if (t->nodes[c].end - t->nodes[c].begin > K) nodes.push_back((int32_t)c);
+    TAGI_TRY(prepare_proxies(t, t->px, nodes, degree, n_orb, s));
+  }
   hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, t->perm.as<int32_t>(), f,
                      w, n, n_orb, t->fs.as<double>(), t->qs.as<double>(), t->ws.as<double>());
   TAGI_HIP(hipGetLastError());
+  TAGI_TRY(compute_proxies(t, t->px, s));
   t->n_orb = n_orb;
   t->degree = degree;
-  const int na = t->n_approx;
-  if (na > 0) {
-    const int np1 = degree + 1;
-    const int K = np1 * np1 * np1;
-    const int n_items = t->up_n_items;
-    const int n_sets_total = n_orb + 1;
-    const int R = (K + kThreads - 1) / kThreads;
-    const int MB = R <= 3 ? 8 : (R <= 6 ? 4 : (R <= 10 ? 2 : 1));
-    const UpItem* d_items = t->up_items.as<UpItem>();
-    const int32_t* d_slot_first =
-        reinterpret_cast<const int32_t*>(t->up_items.as<char>() + (size_t)n_items * sizeof(UpItem));
-    double* partial = t->up_partial.as<double>();
-    for (int m0 = 0; m0 < n_sets_total; m0 += MB) {
-      const int n_sets = std::min(MB, n_sets_total - m0);
-      switch (R) {
-        case 1: launch_upward<1, 8>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 2: launch_upward<2, 8>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 3: launch_upward<3, 8>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 4: launch_upward<4, 4>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 5: launch_upward<5, 4>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 6: launch_upward<6, 4>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 7: launch_upward<7, 2>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 8: launch_upward<8, 2>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 9: launch_upward<9, 2>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        case 10: launch_upward<10, 2>(n_items, s, d_items, t, m0, n_sets, partial); break;
-        default: launch_upward<20, 1>(n_items, s, d_items, t, m0, n_sets, partial); break;
-      }
-      TAGI_HIP(hipGetLastError());
-      const int64_t tot = (int64_t)n_sets * K;
-      hipLaunchKernelGGL(k_upward_reduce, dim3((tot + 255) / 256, na), dim3(256), 0, s,
-                         d_slot_first, partial, na, K, MB, m0, n_sets, n_orb,
-                         t->qhat.as<double>(), t->what.as<double>());
-      TAGI_HIP(hipGetLastError());
-    }
-  }
   phase_end(t, kPhaseUpward, s);
   return TAGI_OK;
 }
