@@ -156,6 +156,7 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   A.ys = t->ys.as<double>();
   A.zs = t->zs.as<double>();
   A.qs = t->qs.as<double>();
+  A.fs = t->fs.as<double>();
   A.ws = t->ws.as<double>();
   A.pnodes = t->px.pnodes.as<double>();
   A.qhat = t->px.qhat.as<double>();

@@ -123,12 +123,19 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
 // distance. Kernel values use the hardware v_rsq_f32 and v_exp_f32 (2^x, with the
 // exponent pre-scaled by log2 e); the cluster's sums accumulate in FP32 and are
 // added to the FP64 accumulators once per cluster.
+// For the subtracted Yukawa kernel the per-proxy charge is formed in FP64 from
+// the FP64 proxy charges, c_k = q^_k - f_i w^_k (one FP64 multiply-add), and only
+// G c_k is summed in FP32: summing f_i G w^_k separately in FP32 would carry an
+// error of the size of the analytic term 4 pi f_i / k^2, which can exceed u_i by
+// orders of magnitude where f is peaked.
 template <int KER, int OB, int NP1>
 __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int np1_rt,
                                               const float* __restrict__ px,
                                               const float* __restrict__ wk,
                                               const float* const* qk, const float* nkl2,
-                                              float nial2, double* a1, double* a2) {
+                                              float nial2, const double* __restrict__ wk64,
+                                              const double* const* qk64, const double* fi,
+                                              double* a1, double* a2) {
   const int np1 = NP1 ? NP1 : np1_rt;
   const float* py = px + np1;
   const float* pz = py + np1;
@@ -153,8 +160,12 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
 #pragma unroll
           for (int o = 0; o < OB; ++o) {
             const float g = __builtin_amdgcn_exp2f(nkl2[o] * r) * rinv;
-            b1[o] = __builtin_fmaf(g, qk[o][k + k3], b1[o]);
-            if constexpr (KER == TAGI_YUKAWA_SS) b2[o] = __builtin_fmaf(g, m, b2[o]);
+            if constexpr (KER == TAGI_YUKAWA_SS) {
+              const float c = (float)__builtin_fma(-fi[o], wk64[k + k3], qk64[o][k + k3]);
+              b1[o] = __builtin_fmaf(g, c, b1[o]);
+            } else {
+              b1[o] = __builtin_fmaf(g, qk[o][k + k3], b1[o]);
+            }
           }
         } else {
           if constexpr (KER == TAGI_COULOMB_SS)
@@ -249,6 +260,14 @@ __global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb)
     nkap[o] = -orb.kappa[orb_row[o]];
   }
   const double nia2 = -A.ia2;
+  double fi[OB];  // target values, for the FP64 subtracted charges of mixed tiles
+#pragma unroll
+  for (int o = 0; o < OB; ++o) {
+    if constexpr (MIX && KER == TAGI_YUKAWA_SS)
+      fi[o] = A.fs[(int64_t)orb_row[o] * A.n + i];
+    else
+      fi[o] = 0.0;
+  }
   double a1[OB], a2[OB];
 #pragma unroll
   for (int o = 0; o < OB; ++o) a1[o] = a2[o] = 0.0;
@@ -264,17 +283,20 @@ __global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb)
         constexpr double kLog2e = 0x1.71547652b82fep+0;
         float nkl2[OB];
         const float* qk[OB];
+        const double* qk64[OB];
 #pragma unroll
         for (int o = 0; o < OB; ++o) {
           nkl2[o] = (float)(nkap[o] * kLog2e);
           qk[o] = A.qhat32 + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
+          qk64[o] = A.qhat + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
         }
         const float ox = (float)(xi - A.geom[C * 4 + 0]);
         const float oy = (float)(yi - A.geom[C * 4 + 1]);
         const float oz = (float)(zi - A.geom[C * 4 + 2]);
         far_cluster32<KER, OB, NP1>(ox, oy, oz, np1, A.pnodes32 + (int64_t)slot * 3 * np1,
                                     A.what32 + (int64_t)slot * K, qk, nkl2,
-                                    (float)(nia2 * kLog2e), a1, a2);
+                                    (float)(nia2 * kLog2e), A.what + (int64_t)slot * K, qk64,
+                                    fi, a1, a2);
       } else {
         const double* qk[OB];
 #pragma unroll

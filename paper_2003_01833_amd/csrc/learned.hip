@@ -457,6 +457,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     A.zs = t->zs.as<double>();
     A.qs = t->qs.as<double>();
     A.ws = t->ws.as<double>();
+    A.fs = t->fs.as<double>();
     A.geom = t->nd_geom.as<double>();
     A.n = t->n;
     A.n_orb = n_orb;
