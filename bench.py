@@ -204,7 +204,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the batched/mixed vs plain comparison on the benzene workload")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB five times (the "
+                         "reference for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe_mib > 0:
+        import torch
+        n = args.copy_probe_mib * 2 ** 20 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8, "copies": 5}), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures a single GPU; runs on more than one GPU are not part of this "
