@@ -92,7 +92,7 @@ typedef struct {
 } tagi_stats;
 
 /*
- * Algorithm 3, line 1 (Section 6.1): build the tree of source clusters and the
+ * Algorithm 3, tree step (Section 6.1): build the tree of source clusters and the
  * target batches.
  *   x, y, z    device [n] source coordinates.
  *   box        host double[6] = {lo_x, lo_y, lo_z, hi_x, hi_y, hi_z}: the domain
@@ -112,7 +112,7 @@ int tagi_tree_build(const double* x, const double* y, const double* z, int64_t n
                     const double* box, int leaf_size, void* stream, tagi_tree** out);
 
 /*
- * Algorithm 3, line 2 (Section 6.2, Eq. particle-cluster-approx-rearranged):
+ * Algorithm 3, proxy-charge step (Section 6.2, Eq. particle-cluster-approx-rearranged):
  * proxy charges of every cluster with more than (degree+1)^3 sources,
  *     q^_k = sum_{j in C} L_k1(x_j) L_k2(y_j) L_k3(z_j) q_j,
  * on the tensor grid of Chebyshev points of the second kind mapped to the
@@ -130,7 +130,7 @@ int tagi_upward(tagi_tree* tree, const double* f, const double* w, int n_orb, in
                 void* stream);
 
 /*
- * Algorithm 3, line 3 (Section 6.3): for every target batch, ComputePotential
+ * Algorithm 3, ComputePotential step (Section 6.3): for every target batch, ComputePotential
  * from the root with the MAC of Eq. MAC, (r_B + r_C) < theta R and
  * (n+1)^3 < N_S (r = half the diagonal of a shrunk box, R = distance between box
  * midpoints); accepted pairs use the proxy charges, rejected leaves and
@@ -211,7 +211,7 @@ int tagi_upward_export(const tagi_tree* tree, int32_t* cluster, double* nodes, d
 
 /*
  * One step of a Green iteration, captured once as a HIP graph and replayed: the
- * upward pass (Algorithm 3, line 2) and the convolution (line 3) for fixed
+ * upward pass (Algorithm 3, proxy-charge step) and the convolution (ComputePotential step) for fixed
  * buffers, exactly as tagi_upward followed by tagi_convolve with the same
  * arguments. Intended for iterations where f is rewritten in place between
  * steps (f = V_eff psi): each replay reads the current contents of f and w and
@@ -238,15 +238,21 @@ int tagi_graph_destroy(tagi_graph* graph);
  * Parameters are one flat array, layer by layer, each layer's weights W[out][in]
  * (row-major) followed by its biases: 5*64+64, 64*64+64, 64*64+64, 64*9+9
  * floats (tagi_selector_param_count()). Output k predicts log10 of the largest
- * absolute error of approximating a batch-cluster pair at degree 4 + k.
+ * absolute error of approximating a batch-cluster pair at degree 4 + k, minus
+ * the pair scale s = log10(l1) - kappa d log10(e) - log10(d), d = R - r_B,
+ * l1 = feature 5 below (the error relative to the size of the pair's far field).
  *
  * tagi_selector_samples: training data from the method itself. After an upward
  * pass at degree 4 with f (one orbital) and w, the far pairs of the lists at
  * (theta_max, degree 4) are the candidates; an evenly strided subset of at most
  * max_pairs is kept. For each pair, HOST outputs:
- *   features [m][5] = {r_C, R - r_B, kappa, N_S, l1 norm of C's degree-4 proxy
- *                      charges of f w}, radii and R as in the MAC;
- *   errors   [m][9] = max over the batch's first 64 targets of |approximated -
+ *   features [m][5] = {r_C, R - r_B, kappa, N_S, l1}, radii and R as in the
+ *                      MAC, l1 = |q^_C|_1 + max_B |f| |w^_C|_1 from C's degree-4
+ *                      proxy charges of f w (q^) and of w (w^): a bound on the
+ *                      l1 norm of the subtracted charges q^ - f_i w^;
+ *   errors   [m][9] = max over up to 256 of the batch's targets, spread
+ *                      evenly (target begin + k nb / min(nb, 256), k < min(nb, 256),
+ *                      nb = batch size), of |approximated -
  *                      direct| pair contribution (Yukawa with subtraction,
  *                      Section 4.3) at degrees 4..12; NaN where the cluster holds
  *                      too few sources for that degree ((n+1)^3 >= N_S);
@@ -255,7 +261,8 @@ int tagi_graph_destroy(tagi_graph* graph);
  * degree 12.
  *
  * tagi_selector_grad: loss and gradient of one batch (DEVICE X [m][5] inputs,
- * Y [m][9] targets, M [m][9] mask of existing targets; loss = sum M (out-Y)^2 /
+ * Y [m][9] targets, M [m][9] mask of existing targets; with r = out - Y and a(r) = 1 for
+ * r >= 0, 4 for r < 0 (under-prediction costs more): loss = sum M a(r) r^2 /
  * (2 sum M)); grads DEVICE, same layout as params; *loss HOST.
  *
  * tagi_selector_train: mini-batch Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8)
@@ -265,13 +272,14 @@ int tagi_graph_destroy(tagi_graph* graph);
  * receives each epoch's mean mini-batch loss. Needs m >= batch.
  */
 /*
- * tagi_convolve_learned: Algorithm 3, line 3 with the degree and acceptance of
+ * tagi_convolve_learned: the far/near split of Algorithm 3 with the degree and acceptance of
  * every batch-cluster pair chosen by the selector network (Yukawa kernels only;
  * requires a previous tagi_upward, whose f and w are used at every degree).
  * A pair with (r_B + r_C) < theta_max R is evaluated by the network once per
  * orbital on the features above, transformed as x_k = (ln(raw_k) - shift_k) *
  * scale_k; it is approximated at the lowest degree n in 4..12 with
- * (n+1)^3 < N_S whose predicted log10 error is <= log10(tol[o]) for every
+ * (n+1)^3 < N_S whose predicted log10 error (output + pair scale) is
+ * <= log10(tol[o]) for every
  * orbital o (tol: HOST [n_orb], absolute error budget of one pair per orbital);
  * otherwise the cluster is opened (a
  * leaf, or a cluster of at most 125 sources, is summed directly). If any

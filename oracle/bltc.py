@@ -273,7 +273,7 @@ def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
     F = f[:, perm]
     Q = F * W[None, :]
     ncoef = (degree + 1) ** 3
-    # line 2: proxy charges of every cluster that can ever be approximated
+    # proxy charges of every cluster that can ever be approximated
     nodes, fhat, what = {}, {}, {}
     for c in range(tree.n_nodes):
         if tree.count(c) > ncoef:
@@ -283,7 +283,7 @@ def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
             nodes[c] = nd
             fhat[c] = ch[:n_orb].reshape(n_orb, -1)
             what[c] = ch[n_orb].reshape(-1)
-    # line 3: batch-cluster interactions
+    # batch-cluster interactions
     batches, far, near = interaction_lists(tree, theta, degree)
     U = np.zeros((n_orb, N))
     for B, fl, nl in zip(batches, far, near):

@@ -6,7 +6,9 @@ Only tests/, the smoke check and the benchmark's CPU-baseline leg may import thi
 Network: 5 inputs -> three hidden layers of 64 tanh units -> 9 linear outputs.
 Layer l computes h_{l+1} = tanh(W_l h_l + b_l) (the last layer without tanh).
 Loss of a mini-batch of m samples with targets y (m, 9) and a mask M (m, 9) of
-the entries that exist:  L = sum(M (out - y)^2) / (2 sum(M)).
+the entries that exist, with residual r = out - y and weight a(r) = 1 for r >= 0
+and UNDER = 4 for r < 0 (predicting below the observed error costs more):
+  L = sum(M a(r) r^2) / (2 sum(M)).
 Adam (Kingma and Ba, 2015): with gradient g at step t,
   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
   p <- p - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
@@ -16,6 +18,7 @@ from __future__ import annotations
 import numpy as np
 
 SIZES = (5, 64, 64, 64, 9)
+UNDER = 4.0
 
 
 def init_params(seed_uniform, sizes=SIZES):
@@ -46,8 +49,9 @@ def loss_and_grads(params, X, Y, M):
     out, acts = forward(params, X)
     cnt = M.sum()
     r = (out - Y) * M
-    loss = 0.5 * np.sum(r * r) / cnt
-    g = r / cnt  # dL/dout
+    a = np.where(r < 0.0, UNDER, 1.0)
+    loss = 0.5 * np.sum(a * r * r) / cnt
+    g = a * r / cnt  # dL/dout
     grads = [None] * len(params)
     n_layers = len(params) // 2
     for l in range(n_layers - 1, -1, -1):

@@ -142,7 +142,7 @@ def direct(kernel: str, sx, sy, sz, sf, sw, tx=None, ty=None, tz=None, tf=None,
 
 
 class Tree:
-    """Owns a tagi_tree handle (Algorithm 3, line 1)."""
+    """Owns a tagi_tree handle (Algorithm 3, tree step)."""
 
     def __init__(self, x: torch.Tensor, y: torch.Tensor, z: torch.Tensor, leaf_size: int,
                  box=None):
@@ -172,7 +172,7 @@ class Tree:
             pass
 
     def upward(self, f: torch.Tensor, w: torch.Tensor, degree: int):
-        """Algorithm 3, line 2: proxy charges; f is (n,) or (n_orb, n)."""
+        """Algorithm 3, proxy-charge step: proxy charges; f is (n,) or (n_orb, n)."""
         n_orb = 1 if f.dim() == 1 else f.shape[0]
         _check(load_library().tagi_upward(self._h, _dptr(f, "f", n_orb * self.n),
                                           _dptr(w, "w", self.n), n_orb, int(degree), _stream()))
@@ -180,7 +180,7 @@ class Tree:
 
     def convolve(self, kernel: str, kappa, theta: float, degree: int | None = None,
                  alpha: float = 1.0, precision: str = "fp64", out: torch.Tensor | None = None):
-        """Algorithm 3, line 3 plus the subtraction term; returns (n_orb, n) in caller order."""
+        """Algorithm 3, ComputePotential step plus the subtraction term; returns (n_orb, n) in caller order."""
         degree = self.degree if degree is None else degree
         kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64),
                                                    (max(self.n_orb, 1),)))

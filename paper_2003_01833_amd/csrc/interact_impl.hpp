@@ -1,4 +1,4 @@
-// Batch-cluster interactions (Algorithm 3, line 3; Eqs. direct-sum_2 and
+// Batch-cluster interactions (Algorithm 3, ComputePotential step; Eqs. direct-sum_2 and
 // particle-cluster-approx-rearranged) with the singularity subtraction of
 // Section 4.3, the combine step, and the plain direct sum (Eq. direct-sum).
 //

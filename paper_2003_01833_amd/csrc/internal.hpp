@@ -83,7 +83,8 @@ struct ProxySet {
 struct LearnedState {
   std::vector<double> key;          // arguments the cached lists were built for
   ProxySet l1set;                   // degree-4 charges of every candidate cluster (features)
-  DBuf l1n;                         // float [n_orb][n_nodes] l1 norms of those charges
+  DBuf l1n;                         // float l1 norms of those charges: [n_orb][n_nodes] of f w,
+                                    // [n_nodes] of w, then [n_orb][n_leaves] max |f| per batch
   DBuf params;                      // float network parameters
   DBuf cnt;                         // int64 [n_leaves][kDegSlots] counts, then offsets
   DBuf far_id, near_id;             // int32 lists (far grouped by degree within a batch)
@@ -202,6 +203,11 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
                      const float* params, const float* norm, const double* tol, double theta_max,
                      double theta_fb, int degree_fb, int precision, double* out, hipStream_t s);
 int selector_param_count();
+// l1 norms of one charge set of a proxy set (set < n_orb: orbital, set == n_orb:
+// the weights' charges), written to out[node] for every slot's node
+int l1_to_nodes(const ProxySet& ps, int set, float* out, hipStream_t s);
+// max |f| over each batch's targets: out[o][leaf]
+int leaf_fmax(tagi_tree* t, float* out, hipStream_t s);
 int selector_samples(tagi_tree* t, const double* f, const double* w, double kappa,
                      double theta_max, int64_t max_pairs, float* feat, float* err,
                      int32_t* pair_ids, int64_t* n_out, hipStream_t s);

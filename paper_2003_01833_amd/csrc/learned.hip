@@ -2,8 +2,9 @@
 // interaction lists are built by the same per-batch ComputePotential traversal,
 // but for a pair that passes a permissive geometric test (r_B + r_C) < theta_max R
 // the selector network predicts the approximation error at every degree 4..12
-// from (r_C, R - r_B, kappa, N_S, l1 norm of the cluster's degree-4 proxy
-// charges), one orbital at a time. The pair is approximated at the lowest degree
+// from (r_C, R - r_B, kappa, N_S, l1 bound of the cluster's subtracted degree-4
+// proxy charges), one orbital at a time, as a residual over the scale
+// l1 exp(-kappa (R - r_B)) / (R - r_B) of the pair's far field. The pair is approximated at the lowest degree
 // whose predicted error meets the per-pair budget for every orbital (and whose
 // (n+1)^3 is below N_S); if no degree does, the cluster is opened (a leaf is
 // summed directly). Where any feature lies outside the range the network was
@@ -40,13 +41,16 @@ struct LearnArgs {
   int n_leaves, n_nodes, n_orb;
   const int32_t *leaf_node, *nbeg, *nend, *first_child, *n_child;
   const double* geom;
-  const float* l1n;
+  const float* l1n;        // [n_orb][n_nodes] l1 norm of the degree-4 charges of f w
+  const float* l1w;        // [n_nodes] l1 norm of the degree-4 charges of w
+  const float* fmax;       // [n_orb][n_leaves] max |f| over each batch
   const float* params;
   double theta_max, theta_fb;
   int degree_fb;
   float log_tol[kMaxOrb];  // per orbital: log10 of the pair error budget
   float shift[kIn], scale[kIn], lo[kIn], hi[kIn];
   float logk[kMaxOrb];
+  float kap[kMaxOrb];
   int fill;
   int64_t* cnt;        // count pass: [n_leaves][kSlots]
   const int64_t* off;  // fill pass: [n_leaves][kSlots] start offsets
@@ -54,17 +58,6 @@ struct LearnArgs {
   int32_t* near_id;
   int32_t* overflow;
 };
-
-// l1 norm of every slot's charges per orbital, scattered to a per-node array
-__global__ void k_l1_nodes(const double* __restrict__ qhat, const int32_t* __restrict__ node,
-                           int n_approx, int K, int n_nodes, float* __restrict__ l1n) {
-  const int slot = blockIdx.x, o = blockIdx.y;
-  const double* q = qhat + ((int64_t)o * n_approx + slot) * K;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) s += fabs(q[k]);
-  for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (threadIdx.x == 0) l1n[(int64_t)o * n_nodes + node[slot]] = (float)s;
-}
 
 // network forward for one lane; hA, hB are this block's [64][64] LDS buffers
 // (unit-major, lane-minor), P the parameters in LDS
@@ -149,7 +142,11 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
         raw[1] = logf((float)fmax(R - rB, 1e-12));
         raw[2] = L.logk[o];
         raw[3] = logf((float)cnt);
-        raw[4] = logf(fmaxf(L.l1n[(int64_t)o * L.n_nodes + C], 1e-30f));
+        // l1 norm bound of the subtracted charges q^ - f_i w^ over the batch's targets
+        const float l1 = fmaxf(L.l1n[(int64_t)o * L.n_nodes + C] +
+                                   L.fmax[(int64_t)o * L.n_leaves + b] * L.l1w[C],
+                               1e-30f);
+        raw[4] = logf(l1);
         float x[kIn];
         for (int k = 0; k < kIn; ++k) {
           if (!(raw[k] >= L.lo[k] && raw[k] <= L.hi[k])) fallback = true;
@@ -158,10 +155,14 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
         if (fallback) break;
         float pred[kOut];
         mlp_forward(sP, x, hbuf[0], hbuf[1], lane, pred);
+        // the network predicts the error relative to the magnitude scale
+        // l1 exp(-kappa d) / d of the pair, d = R - r_B
+        const float dd = (float)fmax(R - rB, 1e-12);
+        const float scl = log10f(l1) - 0.43429448f * L.kap[o] * dd - log10f(dd);
         int d_o = -1;
         for (int d = kDegMin; d <= kDegMax; ++d) {
           if ((d + 1) * (d + 1) * (d + 1) >= cnt) break;
-          if (pred[d - kDegMin] <= L.log_tol[o]) {
+          if (pred[d - kDegMin] + scl <= L.log_tol[o]) {
             d_o = d;
             break;
           }
@@ -234,14 +235,14 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       if (t->nodes[c].end - t->nodes[c].begin > K4) cand.push_back(c);
     TAGI_TRY(prepare_proxies(t, S.l1set, cand, kDegMin, n_orb, s));
     TAGI_TRY(compute_proxies(t, S.l1set, s));
-    TAGI_TRY(S.l1n.ensure((size_t)n_orb * nn * sizeof(float)));
-    TAGI_HIP(hipMemsetAsync(S.l1n.p, 0, (size_t)n_orb * nn * sizeof(float), s));
-    if (S.l1set.n_approx > 0) {
-      hipLaunchKernelGGL(k_l1_nodes, dim3(S.l1set.n_approx, n_orb), dim3(64), 0, s,
-                         S.l1set.qhat.as<double>(), S.l1set.node.as<int32_t>(), S.l1set.n_approx,
-                         K4, nn, S.l1n.as<float>());
-      TAGI_HIP(hipGetLastError());
-    }
+    // per node: l1 of each orbital's charges, then of w's; per batch: max |f|
+    TAGI_TRY(S.l1n.ensure((size_t)((n_orb + 1) * nn + n_orb * nl) * sizeof(float)));
+    TAGI_HIP(hipMemsetAsync(S.l1n.p, 0, (size_t)((n_orb + 1) * nn + n_orb * nl) * sizeof(float), s));
+    float* d_l1w = S.l1n.as<float>() + (size_t)n_orb * nn;
+    float* d_fmax = d_l1w + nn;
+    for (int o = 0; o <= n_orb; ++o)
+      TAGI_TRY(l1_to_nodes(S.l1set, o, S.l1n.as<float>() + (size_t)o * nn, s));
+    TAGI_TRY(leaf_fmax(t, d_fmax, s));
     TAGI_TRY(S.params.ensure(kNParam * sizeof(float)));
     TAGI_HIP(hipMemcpyAsync(S.params.p, params, kNParam * sizeof(float), hipMemcpyHostToDevice, s));
     // lists: count, offsets, fill
@@ -256,6 +257,8 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     L.n_child = t->nd_n_child.as<int32_t>();
     L.geom = t->nd_geom.as<double>();
     L.l1n = S.l1n.as<float>();
+    L.l1w = d_l1w;
+    L.fmax = d_fmax;
     L.params = S.params.as<float>();
     L.theta_max = theta_max;
     L.theta_fb = theta_fb;
@@ -267,7 +270,10 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       L.lo[k] = norm[2 * kIn + k];
       L.hi[k] = norm[3 * kIn + k];
     }
-    for (int o = 0; o < n_orb; ++o) L.logk[o] = (float)std::log(kappa[o]);
+    for (int o = 0; o < n_orb; ++o) {
+      L.logk[o] = (float)std::log(kappa[o]);
+      L.kap[o] = (float)kappa[o];
+    }
     TAGI_TRY(S.cnt.ensure((size_t)nl * kSlots * 2 * sizeof(int64_t) + 4));
     int64_t* d_cnt = S.cnt.as<int64_t>();
     int64_t* d_off = d_cnt + (size_t)nl * kSlots;

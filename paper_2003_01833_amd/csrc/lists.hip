@@ -1,4 +1,4 @@
-// Algorithm 3, line 3 (Section 6.3): the interaction lists of every target batch,
+// Algorithm 3, ComputePotential step (Section 6.3): the interaction lists of every target batch,
 // precomputed as the paper's GPU implementation does, and the compute schedule.
 //
 // One thread per batch runs ComputePotential(B, root) with an explicit stack

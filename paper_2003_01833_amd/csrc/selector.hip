@@ -2,12 +2,14 @@
 // network's training kernels.
 //
 // Samples. For a candidate batch-cluster pair (B, C) and a degree n, the label is
-// the largest absolute error, over the first 64 targets of B, of the
+// the largest absolute error, over up to kSampleT targets spread evenly over B
+// (all of them when B holds at most kSampleT), of the
 // particle-cluster approximation of Eq. particle-cluster-approx-rearranged against
 // the direct sum of Eq. direct-sum_2 (both with the Section 4.3 subtraction, i.e.
 // the pair's contribution a1 - f_i a2). Features: cluster radius r_C, distance
 // from the batch's bounding sphere to the cluster centre R - r_B, kappa, N_S and
-// the l1 norm of the cluster's degree-4 proxy charges.
+// l1 = |q^_C|_1 + max_B |f| |w^_C|_1 from the degree-4 proxy charges, a bound on
+// the l1 norm of the subtracted charges q^ - f_i w^ the pair's targets see.
 //
 // Network (FP32): 5 inputs, three tanh layers of 64, 9 linear outputs (the
 // log10 errors at degrees 4..12). Training is mini-batch Adam with one kernel per
@@ -32,7 +34,15 @@ constexpr int kSelIn = 5, kSelH = 64, kSelOut = 9;
 // ---------------------------------------------------------------------------
 // sample generation
 
-// exact (direct) contribution of cluster C to the first 64 targets of batch B
+constexpr int kSampleT = 256;  // targets per pair a label is taken over
+
+// k-th sampled target of a batch [tb, tb + nb): evenly spread, all when nb <= kSampleT
+__device__ inline int sample_target(int tb, int nb, int k) {
+  const int nt = min(nb, kSampleT);
+  return tb + (int)(((int64_t)k * nb) / nt);
+}
+
+// exact (direct) contribution of cluster C to the sampled targets of batch B
 __global__ __launch_bounds__(256) void k_pair_exact(const int2* __restrict__ pairs, int n_pairs,
                                                     InteractArgs A, double kappa,
                                                     double* __restrict__ out) {
@@ -41,18 +51,22 @@ __global__ __launch_bounds__(256) void k_pair_exact(const int2* __restrict__ pai
   if (p >= n_pairs) return;
   const int2 pr = pairs[p];
   const int B = pr.x, C = pr.y;
-  const int tb = A.nbeg[B], te = min(A.nend[B], tb + kWave);
-  const int i = tb + lane < te ? tb + lane : tb;
-  double a1[1] = {0.0}, a2[1] = {0.0};
+  const int tb = A.nbeg[B], nb = A.nend[B] - tb;
+  const int nt = min(nb, kSampleT);
   const double nkap[1] = {-kappa};
   const double* qr[1] = {A.qs};
-  near_range<TAGI_YUKAWA_SS, 1>(A.xs[i], A.ys[i], A.zs[i], A.nbeg[C], A.nend[C], A.xs, A.ys,
-                                A.zs, A.ws, qr, nkap, 0.0, a1, a2);
-  out[(int64_t)p * kWave + lane] = __builtin_fma(-A.fs[i], a2[0], a1[0]);
+  for (int k0 = 0; k0 < nt; k0 += kWave) {
+    const bool live = k0 + lane < nt;
+    const int i = sample_target(tb, nb, live ? k0 + lane : 0);
+    double a1[1] = {0.0}, a2[1] = {0.0};
+    near_range<TAGI_YUKAWA_SS, 1>(A.xs[i], A.ys[i], A.zs[i], A.nbeg[C], A.nend[C], A.xs, A.ys,
+                                  A.zs, A.ws, qr, nkap, 0.0, a1, a2);
+    if (live) out[(int64_t)p * kSampleT + k0 + lane] = __builtin_fma(-A.fs[i], a2[0], a1[0]);
+  }
 }
 
-// approximated contribution at the degree of the current upward pass; lanes past
-// the batch's end and pairs without proxies at this degree write NaN
+// approximated contribution at the degree of the current upward pass, its largest
+// error over the sampled targets; pairs without proxies at this degree write NaN
 __global__ __launch_bounds__(256) void k_pair_approx(const int2* __restrict__ pairs, int n_pairs,
                                                      InteractArgs A, double kappa,
                                                      const double* __restrict__ exact,
@@ -63,37 +77,51 @@ __global__ __launch_bounds__(256) void k_pair_approx(const int2* __restrict__ pa
   const int2 pr = pairs[p];
   const int B = pr.x, C = pr.y;
   const int slot = A.slot_of[C];
-  const int tb = A.nbeg[B], te = min(A.nend[B], tb + kWave);
-  const bool live = tb + lane < te;
-  const int i = live ? tb + lane : tb;
+  const int tb = A.nbeg[B], nb = A.nend[B] - tb;
+  const int nt = min(nb, kSampleT);
   double e = 0.0;
   if (slot >= 0) {
     const int np1 = A.degree + 1;
     const int K = np1 * np1 * np1;
-    double a1[1] = {0.0}, a2[1] = {0.0};
     const double nkap[1] = {-kappa};
     const double* qk[1] = {A.qhat + (int64_t)slot * K};
-    far_cluster<TAGI_YUKAWA_SS, 1, 0>(A.xs[i], A.ys[i], A.zs[i], np1,
-                                      A.pnodes + (int64_t)slot * 3 * np1, A.what + (int64_t)slot * K,
-                                      qk, nkap, 0.0, a1, a2);
-    const double u = __builtin_fma(-A.fs[i], a2[0], a1[0]);
-    e = live ? fabs(u - exact[(int64_t)p * kWave + lane]) : 0.0;
+    for (int k0 = 0; k0 < nt; k0 += kWave) {
+      const bool live = k0 + lane < nt;
+      const int i = sample_target(tb, nb, live ? k0 + lane : 0);
+      double a1[1] = {0.0}, a2[1] = {0.0};
+      far_cluster<TAGI_YUKAWA_SS, 1, 0>(A.xs[i], A.ys[i], A.zs[i], np1,
+                                        A.pnodes + (int64_t)slot * 3 * np1,
+                                        A.what + (int64_t)slot * K, qk, nkap, 0.0, a1, a2);
+      const double u = __builtin_fma(-A.fs[i], a2[0], a1[0]);
+      if (live) e = fmax(e, fabs(u - exact[(int64_t)p * kSampleT + k0 + lane]));
+    }
   }
   for (int off = kWave / 2; off > 0; off >>= 1) e = fmax(e, __shfl_xor(e, off));
   if (lane == 0) err[p] = slot >= 0 ? (float)e : NAN;
 }
 
-// l1 norm of each slot's proxy charges (orbital 0)
-__global__ void k_slot_l1(const double* __restrict__ qhat, int n_approx, int K,
-                          double* __restrict__ l1) {
+// l1 norm of each slot's charges (q points at one charge set, [n_approx][K]),
+// scattered to a per-node array
+__global__ void k_l1_scatter(const double* __restrict__ q, const int32_t* __restrict__ node,
+                             int K, float* __restrict__ out) {
   const int slot = blockIdx.x;
   double s = 0.0;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) s += fabs(qhat[(int64_t)slot * K + k]);
+  for (int k = threadIdx.x; k < K; k += kWave) s += fabs(q[(int64_t)slot * K + k]);
   for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  __shared__ double red[4];
-  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) l1[slot] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) out[node[slot]] = (float)s;
+}
+
+// max |f| over each batch's targets, per orbital: out[o][leaf]
+__global__ void k_leaf_fmax(const int32_t* __restrict__ leaf_node,
+                            const int32_t* __restrict__ nbeg, const int32_t* __restrict__ nend,
+                            const double* __restrict__ fs, int64_t n, int n_leaves,
+                            float* __restrict__ out) {
+  const int b = blockIdx.x, o = blockIdx.y;
+  const int c = leaf_node[b];
+  double m = 0.0;
+  for (int i = nbeg[c] + threadIdx.x; i < nend[c]; i += kWave) m = fmax(m, fabs(fs[(int64_t)o * n + i]));
+  for (int off = kWave / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if (threadIdx.x == 0) out[(int64_t)o * n_leaves + b] = (float)m;
 }
 
 InteractArgs args_of(tagi_tree* t) {
@@ -133,7 +161,11 @@ __global__ void k_dense_fwd(const float* __restrict__ X, int nin, const float* _
   H[id] = act ? tanhf(s) : s;
 }
 
-// G[b][k] = mask (out - y) / count;  loss partial per block
+// Asymmetric squared loss: residual r = out - y, weight a = 1 for r >= 0 and
+// kUnder for r < 0 (a prediction below the observed error costs kUnder times
+// more, which keeps the selector on the safe side);
+// G[b][k] = mask a r / count, loss partial per block = sum mask a r^2 / (2 count)
+constexpr float kUnder = 4.0f;
 __global__ void k_out_grad(const float* __restrict__ out, const float* __restrict__ Y,
                            const float* __restrict__ M, int64_t total, float inv_cnt,
                            float* __restrict__ G, float* __restrict__ loss_part) {
@@ -141,8 +173,9 @@ __global__ void k_out_grad(const float* __restrict__ out, const float* __restric
   float l = 0.0f;
   if (id < total) {
     const float r = (out[id] - Y[id]) * M[id];
-    G[id] = r * inv_cnt;
-    l = 0.5f * r * r * inv_cnt;
+    const float a = r < 0.0f ? kUnder : 1.0f;
+    G[id] = a * r * inv_cnt;
+    l = 0.5f * a * r * r * inv_cnt;
   }
   for (int off = kWave / 2; off > 0; off >>= 1) l += __shfl_xor(l, off);
   __shared__ float red[4];
@@ -207,6 +240,27 @@ int grid_of(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 
 int selector_param_count() {
   return (kSelIn * kSelH + kSelH) + 2 * (kSelH * kSelH + kSelH) + (kSelH * kSelOut + kSelOut);
+}
+
+int l1_to_nodes(const ProxySet& ps, int set, float* out, hipStream_t s) {
+  if (ps.n_approx == 0) return TAGI_OK;
+  const int np1 = ps.degree + 1;
+  const int64_t K = (int64_t)np1 * np1 * np1;
+  const double* q = set < ps.n_orb ? ps.qhat.as<double>() + (int64_t)set * ps.n_approx * K
+                                   : ps.what.as<double>();
+  hipLaunchKernelGGL(k_l1_scatter, dim3(ps.n_approx), dim3(kWave), 0, s, q,
+                     ps.node.as<int32_t>(), (int)K, out);
+  TAGI_HIP(hipGetLastError());
+  return TAGI_OK;
+}
+
+int leaf_fmax(tagi_tree* t, float* out, hipStream_t s) {
+  const int nl = (int)t->leaves.size();
+  hipLaunchKernelGGL(k_leaf_fmax, dim3(nl, t->n_orb), dim3(kWave), 0, s, t->leaf_node.as<int32_t>(),
+                     t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(), t->fs.as<double>(), t->n,
+                     nl, out);
+  TAGI_HIP(hipGetLastError());
+  return TAGI_OK;
 }
 
 // Forward, loss gradient and backward of one mini-batch; fills grads (same layout
@@ -364,18 +418,25 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
   std::vector<int32_t> fid(std::max<int64_t>(t->n_far, 1));
   if (t->n_far)
     TAGI_HIP(hipMemcpyAsync(fid.data(), t->far_id.p, t->n_far * 4, hipMemcpyDeviceToHost, s));
-  // per-slot l1 norms of the degree-4 proxy charges
-  const int K4 = (d0 + 1) * (d0 + 1) * (d0 + 1);
-  std::vector<double> l1(std::max(t->px.n_approx, 1));
-  std::vector<int32_t> slot4 = t->px.h_slot_of;
-  if (t->px.n_approx > 0) {
-    double* dl1;
-    TAGI_HIP(hipMallocAsync((void**)&dl1, t->px.n_approx * sizeof(double), s));
-    hipLaunchKernelGGL(k_slot_l1, dim3(t->px.n_approx), dim3(256), 0, s, t->px.qhat.as<double>(),
-                       t->px.n_approx, K4, dl1);
-    TAGI_HIP(hipMemcpyAsync(l1.data(), dl1, t->px.n_approx * sizeof(double), hipMemcpyDeviceToHost, s));
-    TAGI_HIP(hipFreeAsync(dl1, s));
+  // l1 norms of the degree-4 proxy charges of f w and of w per node, and max |f|
+  // per batch: the pair's feature is ||q^||_1 + max_B |f| ||w^||_1, which bounds
+  // the l1 norm of the subtracted charges q^ - f_i w^ seen by any target of B
+  const int nn = (int)t->nodes.size();
+  std::vector<float> l1f(nn, 0.0f), l1w(nn, 0.0f), fmaxb(nl, 0.0f);
+  {
+    float* dbuf;
+    TAGI_HIP(hipMallocAsync((void**)&dbuf, (size_t)(2 * nn + nl) * sizeof(float), s));
+    TAGI_HIP(hipMemsetAsync(dbuf, 0, (size_t)(2 * nn + nl) * sizeof(float), s));
+    TAGI_TRY(l1_to_nodes(t->px, 0, dbuf, s));
+    TAGI_TRY(l1_to_nodes(t->px, 1, dbuf + nn, s));
+    TAGI_TRY(leaf_fmax(t, dbuf + 2 * nn, s));
+    TAGI_HIP(hipMemcpyAsync(l1f.data(), dbuf, nn * sizeof(float), hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipMemcpyAsync(l1w.data(), dbuf + nn, nn * sizeof(float), hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipMemcpyAsync(fmaxb.data(), dbuf + 2 * nn, nl * sizeof(float), hipMemcpyDeviceToHost, s));
+    TAGI_HIP(hipFreeAsync(dbuf, s));
   }
+  std::vector<int32_t> leaf_index(nn, -1);
+  for (int b = 0; b < nl; ++b) leaf_index[t->leaves[b]] = b;
   TAGI_HIP(hipStreamSynchronize(s));
   // evenly strided subset of the far pairs, in list order
   std::vector<int2> pairs;
@@ -407,12 +468,12 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
     const double rc = std::sqrt(hc[0] * hc[0] + hc[1] * hc[1] + hc[2] * hc[2]);
     const double R = std::sqrt((cb[0] - cc[0]) * (cb[0] - cc[0]) + (cb[1] - cc[1]) * (cb[1] - cc[1]) +
                                (cb[2] - cc[2]) * (cb[2] - cc[2]));
-    const int sl = slot4[pairs[p].y];
+    const int Cn = pairs[p].y;
     feat[p * 5 + 0] = (float)rc;
     feat[p * 5 + 1] = (float)(R - rb);
     feat[p * 5 + 2] = (float)kappa;
     feat[p * 5 + 3] = (float)(C.end - C.begin);
-    feat[p * 5 + 4] = (float)(sl >= 0 ? l1[sl] : 0.0);
+    feat[p * 5 + 4] = l1f[Cn] + fmaxb[leaf_index[pairs[p].x]] * l1w[Cn];
     if (pair_ids) {
       pair_ids[2 * p] = pairs[p].x;
       pair_ids[2 * p + 1] = pairs[p].y;
@@ -422,7 +483,7 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
   double* exact;
   float* derr;
   TAGI_HIP(hipMallocAsync((void**)&dp, np * sizeof(int2), s));
-  TAGI_HIP(hipMallocAsync((void**)&exact, (size_t)np * kWave * sizeof(double), s));
+  TAGI_HIP(hipMallocAsync((void**)&exact, (size_t)np * kSampleT * sizeof(double), s));
   TAGI_HIP(hipMallocAsync((void**)&derr, (size_t)np * sizeof(float), s));
   TAGI_HIP(hipMemcpyAsync(dp, pairs.data(), np * sizeof(int2), hipMemcpyHostToDevice, s));
   InteractArgs A = args_of(t);

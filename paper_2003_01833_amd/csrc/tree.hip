@@ -1,4 +1,4 @@
-// Algorithm 3, line 1 (Section 6.1): source clusters and target batches.
+// Algorithm 3, tree step (Section 6.1): source clusters and target batches.
 //
 // The tree is built level by level on the GPU. At each level, every cluster with
 // more than N_L sources is bisected at the midpoint of its box in the dimensions

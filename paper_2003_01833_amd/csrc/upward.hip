@@ -1,4 +1,4 @@
-// Algorithm 3, line 2 (Section 6.2): proxy charges of every source cluster that
+// Algorithm 3, proxy-charge step (Section 6.2): proxy charges of every source cluster that
 // can be approximated ((n+1)^3 < N_S, Eq. MAC), by Eq.
 // particle-cluster-approx-rearranged:
 //

@@ -8,9 +8,16 @@ on the GPU through tagi_selector_train. tagi_convolve_learned then picks, per
 pair, the lowest degree whose predicted error fits the pair's error budget.
 
 Feature transform (both here and in the list kernel): x_k = (ln raw_k - shift_k)
-* scale_k with raw = (r_C, R - r_B, kappa, N_S, l1 norm of the degree-4 proxy
-charges); shift/scale standardise the training set; lo/hi are the training range
-of ln raw, outside which the list kernel falls back to the fixed MAC.
+* scale_k with raw = (r_C, R - r_B, kappa, N_S, l1) where l1 bounds the l1 norm
+of the subtracted degree-4 charges q^_k - f_i w^_k over the batch's targets
+(l1(q^) + max_B |f| l1(w^)); shift/scale standardise the training set; lo/hi are
+the training range of ln raw, outside which the list kernel falls back to the
+fixed MAC.
+
+Target: the network learns the residual log10(error) - s with the pair scale
+s = log10(l1) - kappa d log10(e) - log10(d), d = R - r_B, i.e. the error relative
+to the size l1 exp(-kappa d) / d of the far field the pair contributes; the list
+kernel adds s back before comparing with the budget.
 """
 from __future__ import annotations
 
@@ -58,6 +65,14 @@ def log_features(raw: np.ndarray) -> np.ndarray:
     r[:, 1] = np.maximum(r[:, 1], 1e-12)
     r[:, 4] = np.maximum(r[:, 4], 1e-30)
     return np.log(r).astype(np.float32)
+
+
+def pair_scale(raw: np.ndarray) -> np.ndarray:
+    """log10 of l1 exp(-kappa d) / d, d = R - r_B, per sample (floored as in log_features)."""
+    d = np.maximum(np.asarray(raw[:, 1], dtype=np.float64), 1e-12)
+    l1 = np.maximum(np.asarray(raw[:, 4], dtype=np.float64), 1e-30)
+    kappa = np.asarray(raw[:, 2], dtype=np.float64)
+    return np.log10(l1) - kappa * d * np.log10(np.e) - np.log10(d)
 
 
 def init_params(n_params: int, seed: int) -> np.ndarray:
@@ -110,17 +125,54 @@ def make_samples(tagi, torch, seeds=(1, 2, 3, 4, 5), kappas_per_seed: int = 4,
 
 
 def prepare(raw: np.ndarray, errors: np.ndarray):
-    """(X, Y, M, norm): standardised log features, log10 errors, mask of existing labels."""
+    """(X, Y, M, norm): standardised log features, residual log10 errors (over
+    pair_scale), mask of the labels that exist and are nonzero."""
     L = log_features(raw)
     shift = L.mean(axis=0)
     scale = 1.0 / np.maximum(L.std(axis=0), 1e-6)
     lo, hi = L.min(axis=0), L.max(axis=0)
     X = ((L - shift) * scale).astype(np.float32)
-    M = np.isfinite(errors).astype(np.float32)
-    Y = np.where(M > 0, np.log10(np.maximum(np.nan_to_num(errors, nan=1.0), 1e-30)), 0.0)
-    Y = np.maximum(Y, LOG_FLOOR).astype(np.float32)
+    err = np.nan_to_num(np.asarray(errors, dtype=np.float64), nan=0.0)
+    M = (np.isfinite(errors) & (err > 0.0)).astype(np.float32)
+    Y = np.log10(np.maximum(err, 1e-300)) - pair_scale(raw)[:, None]
+    Y = np.where(M > 0, np.maximum(Y, LOG_FLOOR), 0.0).astype(np.float32)
     norm = np.concatenate([shift, scale, lo, hi]).astype(np.float32)
     return X, Y, M, norm
+
+
+def predict_log_error(sel: "Selector", raw: np.ndarray) -> np.ndarray:
+    """log10 error the list kernel would predict at degrees 4..12 for raw features
+    (network output plus pair_scale), evaluated in FP64 on the host; for reports."""
+    n_in = N_IN
+    norm = sel.norm.astype(np.float64)
+    h = (log_features(raw).astype(np.float64) - norm[:n_in]) * norm[n_in:2 * n_in]
+    p = sel.params.astype(np.float64)
+    off = 0
+    sizes = (N_IN, 64, 64, 64, N_OUT)
+    for li, (a, b) in enumerate(zip(sizes[:-1], sizes[1:])):
+        W = p[off:off + a * b].reshape(b, a)
+        off += a * b
+        bias = p[off:off + b]
+        off += b
+        h = h @ W.T + bias
+        if li < len(sizes) - 2:
+            h = np.tanh(h)
+    return h + pair_scale(raw)[:, None]
+
+
+def heldout_report(sel: "Selector", raw: np.ndarray, errors: np.ndarray) -> dict:
+    """How the predicted log10 error compares with the observed one on held-out pairs:
+    quantiles of predicted - observed, and the fraction under-predicted by more
+    than 2x and 10x."""
+    pred = predict_log_error(sel, raw)
+    err = np.nan_to_num(np.asarray(errors, dtype=np.float64), nan=0.0)
+    ok = np.isfinite(errors) & (err > 0.0)
+    d = (pred - np.log10(np.maximum(err, 1e-300)))[ok]
+    q = np.quantile(d, [0.001, 0.01, 0.1, 0.5, 0.9]) if d.size else np.zeros(5)
+    return {"labels": int(d.size), "q0.001": float(q[0]), "q0.01": float(q[1]),
+            "q0.1": float(q[2]), "median": float(q[3]), "q0.9": float(q[4]),
+            "under_2x": float(np.mean(d < -np.log10(2.0))) if d.size else 0.0,
+            "under_10x": float(np.mean(d < -1.0)) if d.size else 0.0}
 
 
 def train(tagi, torch, X, Y, M, norm, epochs: int = 30, batch: int = 4096, lr: float = 2e-3,

@@ -36,7 +36,8 @@ def _log(msg):
 
 
 def calibrate(tagi, torch, sel, mesh, seed: int = 6, kappas=(0.6, 1.5, 4.0), leaf: int = 500,
-              samples: int = 1000, etas=(1.0, 0.3, 0.1, 0.03, 0.01, 0.003), target: float = 1e-6):
+              samples: int = 1000, etas=(1.0, 0.3, 0.1, 0.03, 0.01, 0.003, 0.001, 3e-4),
+              target: float = 1e-6):
     from paper_2003_01833_amd.selector import slater_field
     from workloads.configs import DOMAIN, sample_targets
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
@@ -63,9 +64,10 @@ def calibrate(tagi, torch, sel, mesh, seed: int = 6, kappas=(0.6, 1.5, 4.0), lea
             worst = max(worst, float(torch.linalg.norm(e - refs[o]) / torch.linalg.norm(refs[o])),
                         float((e - refs[o]).abs().max() / refs[o].abs().max()))
         st = t.learned_stats()
-        log.append({"eta": eta, "worst_rel_err": worst,
-                    "evaluations": st["far_interactions"] + st["near_interactions"]})
-        _log(f"calibration: eta {eta}: worst rel err {worst:.3e}")
+        ev = st["far_interactions"] + st["near_interactions"]
+        log.append({"eta": eta, "worst_rel_err": worst, "evaluations": ev})
+        _log(f"calibration: eta {eta}: worst rel err {worst:.3e}, {ev:.4g} evaluations, "
+             f"far pairs by degree {st['far_pairs_by_degree']}")
         if worst <= target and chosen is None:
             chosen = eta
     t.close()
@@ -99,8 +101,13 @@ def main():
     sel = S.train(tagi, torch, X, Y, M, norm, epochs=args.epochs, batch=args.batch, lr=args.lr,
                   log=_log)
     t2 = time.perf_counter()
+    raw_h, err_h = S.make_samples(tagi, torch, seeds=(6,), kappas_per_seed=2, pairs=args.pairs,
+                                  mesh=mesh, log=_log)
+    rep = S.heldout_report(sel, raw_h, err_h)
+    _log("held-out pairs (seed 6): predicted - observed log10 error: " +
+         ", ".join(f"{k} {v:.3g}" for k, v in rep.items()))
     eta, cal = calibrate(tagi, torch, sel, mesh)
-    sel.meta.update({"eta": eta, "calibration": cal, "n_labels": int(M.sum()),
+    sel.meta.update({"eta": eta, "calibration": cal, "n_labels": int(M.sum()), "heldout": rep,
                      "sample_seconds": t1 - t0, "train_seconds": t2 - t1,
                      "training_data": "Be-like atom mesh (1,007,616 points), seeds 1-5, "
                                       f"{args.kappas_per_seed} kappas per seed, "

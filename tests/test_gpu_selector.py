@@ -95,9 +95,11 @@ def test_selector_samples_match_oracle(case):
     F, W = case["f"][perm], case["w"][perm]
     for p in range(0, 40, 7):
         B, C = ids[p]
-        b0, b1 = ref.begin[B], min(ref.end[B], ref.begin[B] + 64)
+        nb = ref.end[B] - ref.begin[B]
+        nt = min(nb, 256)
+        ti = ref.begin[B] + (np.arange(nt) * nb) // nt  # the sampled targets
         c0, c1 = ref.begin[C], ref.end[C]
-        tx, ty, tz, tf = X[b0:b1], Y[b0:b1], Z[b0:b1], F[b0:b1]
+        tx, ty, tz, tf = X[ti], Y[ti], Z[ti], F[ti]
         # exact pair contribution (subtracted Yukawa, no analytic term)
         ex = direct_sum("yukawa_ss", X[c0:c1], Y[c0:c1], Z[c0:c1], F[c0:c1], W[c0:c1], tx, ty, tz,
                         tf, kappa=kappa) - 4 * np.pi * tf / kappa ** 2
@@ -121,6 +123,13 @@ def test_selector_samples_match_oracle(case):
         cc, rc = 0.5 * (ref.lo[C] + ref.hi[C]), 0.5 * np.linalg.norm(ref.hi[C] - ref.lo[C])
         np.testing.assert_allclose(feat[p, :4], [rc, np.linalg.norm(cb - cc) - rb, kappa, c1 - c0],
                                    rtol=1e-6)
+        # l1 bound of the subtracted degree-4 charges
+        _, ch4 = bltc.proxy_charges(X[c0:c1], Y[c0:c1], Z[c0:c1],
+                                    np.vstack([F[c0:c1] * W[c0:c1], W[c0:c1]]),
+                                    ref.lo[C], ref.hi[C], 4)
+        fmax_b = np.abs(F[ref.begin[B]:ref.end[B]]).max()
+        l1 = np.abs(ch4[0]).sum() + fmax_b * np.abs(ch4[1]).sum()
+        np.testing.assert_allclose(feat[p, 4], l1, rtol=1e-5)
 
 
 def _selector(bias, lo=-1e30, hi=1e30):
