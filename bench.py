@@ -8,9 +8,10 @@ upward pass, interaction lists and schedule, far and near fields, combine, for
 every convolution the workload holds. The default workload is the single-atom
 adaptive mesh (Be-like Z = 4 in [-20, 20]^3, 1,007,616 Fejer points): a Yukawa
 convolution (kappa = sqrt(0.4)) of psi_1s + psi_2s and a Coulomb (Hartree)
-convolution of rho = 2 psi_1s^2 + 2 psi_2s^2, both singularity-subtracted, timed
-at theta = 0.8, degree 9, N_L = 2000 (the cheapest setting found that holds both
-to 1e-6; the accuracy of theta = 0.8, degree 8, N_L = 500 is reported beside it).
+convolution of rho = 2 psi_1s^2 + 2 psi_2s^2, both singularity-subtracted, on one
+tree with N_L = 2000, each at the cheapest (theta, degree) found that holds it to
+1e-6 (Yukawa 0.75, 8; Coulomb 0.8, 8); the accuracy of theta = 0.8, degree 8,
+N_L = 500 is reported beside it.
 Inputs are resident in HBM before timing.
 
 Printed: one JSON line with the throughput (batch-cluster kernel evaluations
@@ -44,11 +45,14 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 # for particle sources; 3 for proxy sources, whose tensor grid gives d^2 with one
 # subtraction and one multiply-add per pair), reciprocal square root (seed plus
 # refinement, 9), exp by Cody-Waite reduction and a degree-11 polynomial (31),
-# the products forming the kernel value, and two multiply-adds (4).
+# the products forming the kernel value, and two multiply-adds (4). The far
+# field of the Gaussian-subtracted Coulomb kernel takes the Gaussian as the
+# product of per-dimension factors: two multiplies per evaluation, and 3 (n+1)
+# exponentials per target and cluster that are not counted.
 FLOPS = {
     ("yukawa_ss", "far"): 3 + 9 + 1 + 1 + 31 + 1 + 4,
     ("yukawa_ss", "near"): 8 + 9 + 1 + 1 + 31 + 1 + 4,
-    ("coulomb_ss", "far"): 3 + 9 + 1 + 31 + 1 + 2 + 2,
+    ("coulomb_ss", "far"): 3 + 9 + 2 + 4,
     ("coulomb_ss", "near"): 8 + 9 + 1 + 31 + 1 + 2 + 2,
 }
 
@@ -71,6 +75,13 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
+def workload_key(config: dict) -> str:
+    """One line naming the workload and every convolution's setting."""
+    convs = " ".join(f"{k} theta {v['theta']} degree {v['degree']}"
+                     for k, v in config["settings"].items())
+    return f"{config['workload']} {convs} leaf {config['leaf_size']}"
+
+
 def counter_traffic(config: dict):
     """HBM bytes per interaction-kernel launch (FETCH_SIZE and WRITE_SIZE, each
     scaled by its reading for a copy of known size) from the committed profile, or
@@ -81,8 +92,7 @@ def counter_traffic(config: dict):
             kv = dict(re.findall(r"^- `(\w+)`: `([^`]*)`", fh.read(), re.M))
     except OSError:
         return None
-    want = (f"{config['workload']} theta {config['theta']} degree {config['degree']} "
-            f"leaf {config['leaf_size']}")
+    want = workload_key(config)
     if kv.get("workload") != want or kv.get("source_sha256") != kernel_source_digest():
         return None
     return float(kv["traffic_bytes_per_launch"])
@@ -92,16 +102,19 @@ def make_workload(name: str):
     from workloads.configs import DOMAIN, atom_mesh, uniform_cube
     if name == "atom":
         d = atom_mesh()
-        convs = [("yukawa_ss", d["psi"], float(d["kappa"])), ("coulomb_ss", d["rho"], 0.0)]
-        # timed at the cheapest (theta, degree, N_L) of the parameter sweep that meets
-        # 1e-6 relative L2 and max error for both kernels; the workload's stated
-        # setting (theta 0.8, degree 8, N_L 500) is run once for its error
+        # each convolution at the cheapest (theta, degree) of the parameter sweep
+        # that meets 1e-6 relative L2 and max error on one tree (N_L = 2000); the
+        # workload's stated setting (theta 0.8, degree 8, N_L 500) is run once for
+        # its error
+        convs = [dict(kernel="yukawa_ss", f=d["psi"], kappa=float(d["kappa"]), theta=0.75,
+                      degree=8),
+                 dict(kernel="coulomb_ss", f=d["rho"], kappa=0.0, theta=0.8, degree=8)]
         return dict(name="atom_mesh_Z4", x=d["x"], y=d["y"], z=d["z"], w=d["w"], convs=convs,
-                    theta=0.8, degree=9, leaf=2000, stated=(0.8, 8, 500),
-                    box=(*DOMAIN[0], *DOMAIN[1]))
+                    leaf=2000, stated=(0.8, 8, 500), box=(*DOMAIN[0], *DOMAIN[1]))
     x, y, z, f, w = uniform_cube(32768, seed=1)
-    return dict(name="uniform_cube_32768", x=x, y=y, z=z, w=w, convs=[("yukawa_ss", f, 1.0)],
-                theta=0.7, degree=6, leaf=500, box=None)
+    return dict(name="uniform_cube_32768", x=x, y=y, z=z, w=w,
+                convs=[dict(kernel="yukawa_ss", f=f, kappa=1.0, theta=0.7, degree=6)],
+                leaf=500, box=None)
 
 
 def cpu_baseline(wl, seconds: float):
@@ -114,9 +127,11 @@ def cpu_baseline(wl, seconds: float):
     def run(k):
         idx = sample_targets(n, k, seed=4)
         t0 = time.perf_counter()
-        for kernel, f, kappa in wl["convs"]:
-            direct_sum(kernel, wl["x"], wl["y"], wl["z"], f, wl["w"], wl["x"][idx], wl["y"][idx],
-                       wl["z"][idx], f[idx], kappa=kappa if kappa else 1.0, threads=threads)
+        for c in wl["convs"]:
+            f = c["f"]
+            direct_sum(c["kernel"], wl["x"], wl["y"], wl["z"], f, wl["w"], wl["x"][idx],
+                       wl["y"][idx], wl["z"][idx], f[idx], kappa=c["kappa"] or 1.0,
+                       threads=threads)
         return time.perf_counter() - t0
 
     probe = max(threads, 16)
@@ -129,12 +144,16 @@ def cpu_baseline(wl, seconds: float):
                       f"{len(wl['convs'])} kernel(s), {dt:.1f} s"}
 
 
-def compare_batched(tagi, torch, theta=0.8, degree=9, leaf=2000, samples=1000, reps=1):
+def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samples=1000,
+                    reps=1):
     """The benzene workload (4,143,104 points, 21 orbitals, one kappa each): the
-    per-orbital FP64 loop, one batched FP64 launch sequence, and batched with the
-    mixed-precision far field. Times exclude the tree build and include upward,
-    lists (cached after the first call) and the convolution; errors are per
-    orbital against the GPU direct sum at sampled targets."""
+    per-orbital FP64 loop and one batched FP64 launch sequence at the cheapest
+    FP64 (theta, degree) found that meets 1e-6, batched with the mixed-precision
+    far field at the cheapest such setting for it, and the learned selector.
+    Times exclude the tree build and include upward, lists (cached after the
+    first call) and the convolution; errors are per orbital against the GPU
+    direct sum at sampled targets."""
+    theta, degree = fp64
     from workloads.configs import DOMAIN, benzene_mesh, benzene_orbitals, sample_targets
     _log("compare: building the benzene mesh and 21 orbitals")
     m = benzene_mesh()
@@ -177,25 +196,29 @@ def compare_batched(tagi, torch, theta=0.8, degree=9, leaf=2000, samples=1000, r
             t.convolve("yukawa_ss", float(kap[o]), theta, degree, out=U_plain[o:o + 1])
         return U_plain
 
-    res = {"workload": "benzene_mesh_21_orbitals", "n_points": n, "n_orb": n_orb, "theta": theta,
-           "degree": degree, "leaf_size": leaf}
+    res = {"workload": "benzene_mesh_21_orbitals", "n_points": n, "n_orb": n_orb,
+           "leaf_size": leaf, "fp64_setting": {"theta": theta, "degree": degree},
+           "mixed_setting": {"theta": mixed[0], "degree": mixed[1]}}
     _log("compare: plain per-orbital loop")
     U, ms = timed(plain)
     res["plain_fp64"] = {"ms": ms, **errors(U)}
 
-    def batched(precision):
+    def batched(precision, th, deg):
         def run():
-            t.upward(F, w, degree)
-            return t.convolve("yukawa_ss", kap, theta, degree, precision=precision)
+            t.upward(F, w, deg)
+            return t.convolve("yukawa_ss", kap, th, deg, precision=precision)
         return run
 
     _log("compare: batched FP64")
-    U, ms = timed(batched("fp64"))
-    res["batched_fp64"] = {"ms": ms, **errors(U)}
-    _log("compare: batched mixed")
-    U, ms = timed(batched("mixed"))
-    res["batched_mixed"] = {"ms": ms, **errors(U)}
+    U, ms = timed(batched("fp64", theta, degree))
     st = t.stats()
+    res["batched_fp64"] = {"ms": ms, **errors(U),
+                           "interactions_per_orbital": st["far_interactions"] + st["near_interactions"]}
+    _log("compare: batched mixed")
+    U, ms = timed(batched("mixed", *mixed))
+    st_m = t.stats()
+    res["batched_mixed"] = {"ms": ms, **errors(U), "interactions_per_orbital":
+                            st_m["far_interactions"] + st_m["near_interactions"]}
     weights = os.path.join(ROOT, "paper_2003_01833_amd", "selector_weights.npz")
     if os.path.exists(weights):
         from paper_2003_01833_amd.selector import Selector
@@ -203,11 +226,13 @@ def compare_batched(tagi, torch, theta=0.8, degree=9, leaf=2000, samples=1000, r
         eta = float(sel.meta.get("eta", 0.01))
         # per-orbital pair budget from the FP64 result's magnitude (in a Green
         # iteration: the previous iterate's)
-        U64 = batched("fp64")()
+        U64 = batched("fp64", theta, degree)()
         tol = eta * 1e-6 * U64.abs().amax(dim=1).cpu().numpy()
         for prec in ("fp64", "mixed"):
             def learned(prec=prec):
-                t.upward(F, w, degree)
+                # the learned path forms its own per-degree proxy charges; the
+                # upward pass only has to stage f and w (lowest degree)
+                t.upward(F, w, 1)
                 return t.convolve_learned("yukawa_ss", kap, sel, tol, precision=prec)
             _log(f"compare: batched {prec} + learned selector")
             t0 = time.perf_counter()
@@ -220,7 +245,6 @@ def compare_batched(tagi, torch, theta=0.8, degree=9, leaf=2000, samples=1000, r
                 "ms": ms, "first_call_ms_with_lists": first_ms, "eta": eta, **errors(U),
                 "interactions_per_orbital": ls["far_interactions"] + ls["near_interactions"],
                 "far_pairs_by_degree": ls["far_pairs_by_degree"]}
-    res["interactions_per_orbital"] = st["far_interactions"] + st["near_interactions"]
     res["speedup_batched_vs_plain"] = res["plain_fp64"]["ms"] / res["batched_fp64"]["ms"]
     res["speedup_mixed_vs_plain"] = res["plain_fp64"]["ms"] / res["batched_mixed"]["ms"]
     if "batched_mixed_learned" in res:
@@ -272,9 +296,9 @@ def main():
     n = wl["x"].size
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
     x, y, z, w = dev(wl["x"]), dev(wl["y"]), dev(wl["z"]), dev(wl["w"])
-    fields = [(k, dev(f), kap) for k, f, kap in wl["convs"]]
+    fields = [dict(c, f=dev(c["f"])) for c in wl["convs"]]
     outs = [torch.empty((1, n), dtype=torch.float64, device="cuda") for _ in fields]
-    theta, degree, leaf = wl["theta"], wl["degree"], wl["leaf"]
+    leaf = wl["leaf"]
     torch.cuda.synchronize()
 
     records = []
@@ -282,10 +306,13 @@ def main():
     def step():
         t = tagi.Tree(x, y, z, leaf, wl["box"])
         t.set_timing(True)
-        for (kernel, f, kap), out in zip(fields, outs):
-            t.upward(f, w, degree)
-            t.convolve(kernel, kap if kap else 1.0, theta, degree, alpha=1.0, out=out)
-        records.append((t.timing(), t.stats()))
+        stats = []
+        for c, out in zip(fields, outs):
+            t.upward(c["f"], w, c["degree"])
+            t.convolve(c["kernel"], c["kappa"] or 1.0, c["theta"], c["degree"], alpha=1.0,
+                       out=out)
+            stats.append(t.stats())
+        records.append((t.timing(), stats))
         t.close()
 
     for i in range(args.warmup):
@@ -301,40 +328,42 @@ def main():
     _log(f"bench: {args.steps} timed steps in {elapsed:.3f} s")
     ms_per_step = 1e3 * elapsed / args.steps
 
-    st = records[-1][1]
-    inter_per_conv = st["far_interactions"] + st["near_interactions"]
-    interactions = inter_per_conv * len(fields)
+    sts = records[-1][1]
+    interactions = sum(st["far_interactions"] + st["near_interactions"] for st in sts)
     value = interactions / (ms_per_step / 1e3)
     phases = {k: float(np.mean([r[0][k] for r in records])) for k in
               ("build_ms", "upward_ms", "lists_ms", "interact_ms", "combine_ms")}
-    flops = sum(st["far_interactions"] * FLOPS[(k, "far")] + st["near_interactions"] * FLOPS[(k, "near")]
-                for k, _, _ in fields)
+    flops = sum(st["far_interactions"] * FLOPS[(c["kernel"], "far")] +
+                st["near_interactions"] * FLOPS[(c["kernel"], "near")]
+                for c, st in zip(fields, sts))
     interact_s = phases["interact_ms"] / 1e3
     achieved = flops / interact_s / 1e12
     launches = records[-1][0]["interact_launches"]
 
     # accuracy of the last step's outputs against the GPU direct sum at sampled targets
     idx = torch.from_numpy(sample_targets(n, min(args.samples, n), seed=4)).cuda()
-    acc = {}
-    for (kernel, f, kap), out in zip(fields, outs):
-        ref = tagi.direct(kernel, x, y, z, f, w, x[idx].contiguous(), y[idx].contiguous(),
-                          z[idx].contiguous(), f[idx].contiguous(), kappa=kap if kap else 1.0)
+    acc, refs = {}, {}
+    for c, out in zip(fields, outs):
+        f = c["f"]
+        ref = tagi.direct(c["kernel"], x, y, z, f, w, x[idx].contiguous(), y[idx].contiguous(),
+                          z[idx].contiguous(), f[idx].contiguous(), kappa=c["kappa"] or 1.0)
+        refs[c["kernel"]] = ref
         u = out[0, idx]
-        acc[kernel] = {"rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
-                       "rel_max": float((u - ref).abs().max() / ref.abs().max())}
+        acc[c["kernel"]] = {"rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
+                            "rel_max": float((u - ref).abs().max() / ref.abs().max())}
 
     stated = None
     if wl.get("stated"):
         th_s, deg_s, leaf_s = wl["stated"]
         t = tagi.Tree(x, y, z, leaf_s, wl["box"])
         stated = {"theta": th_s, "degree": deg_s, "leaf_size": leaf_s}
-        for kernel, f, kap in fields:
-            t.upward(f, w, deg_s)
-            u = t.convolve(kernel, kap if kap else 1.0, th_s, deg_s)[0, idx]
-            ref = tagi.direct(kernel, x, y, z, f, w, x[idx].contiguous(), y[idx].contiguous(),
-                              z[idx].contiguous(), f[idx].contiguous(), kappa=kap if kap else 1.0)
-            stated[kernel] = {"rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
-                              "rel_max": float((u - ref).abs().max() / ref.abs().max())}
+        for c in fields:
+            t.upward(c["f"], w, deg_s)
+            u = t.convolve(c["kernel"], c["kappa"] or 1.0, th_s, deg_s)[0, idx]
+            ref = refs[c["kernel"]]
+            stated[c["kernel"]] = {
+                "rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
+                "rel_max": float((u - ref).abs().max() / ref.abs().max())}
         t.close()
 
     comparison = None
@@ -351,11 +380,12 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl["name"], "n_points": n, "theta": theta, "degree": degree,
-                   "leaf_size": leaf, "convolutions": [k for k, _, _ in fields],
-                   "n_leaves": st["n_leaves"], "far_pairs": st["n_far_pairs"],
-                   "near_pairs": st["n_near_pairs"],
-                   "interactions_per_step": interactions},
+        "config": {"workload": wl["name"], "n_points": n, "leaf_size": leaf,
+                   "settings": {c["kernel"]: {"theta": c["theta"], "degree": c["degree"],
+                                              "far_pairs": st["n_far_pairs"],
+                                              "near_pairs": st["n_near_pairs"]}
+                                for c, st in zip(fields, sts)},
+                   "n_leaves": sts[0]["n_leaves"], "interactions_per_step": interactions},
         "roofline": {"bound": "alu", "kernel": "k_interact", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,

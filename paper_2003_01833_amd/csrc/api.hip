@@ -479,7 +479,7 @@ int tagi_tree_destroy(tagi_tree* t) {
   DBuf* bufs[] = {&t->perm, &t->xs, &t->ys, &t->zs, &t->leaf_of_pos, &t->nd_begin, &t->nd_end,
                   &t->nd_first_child, &t->nd_n_child, &t->nd_geom, &t->nd_box, &t->leaf_node,
                   &t->ws, &t->fs, &t->qs, &t->far_off, &t->near_off, &t->far_id, &t->near_id,
-                  &t->chunks, &t->items, &t->group_first_item, &t->batch_group_base,
+                  &t->chunks, &t->items, &t->item_order, &t->group_first_item, &t->batch_group_base,
                   &t->batch_chunks, &t->partial, &t->kappa_dev};
   for (DBuf* b : bufs) b->release();
   t->px.release();

@@ -162,6 +162,7 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   A.qhat = t->px.qhat.as<double>();
   A.what = t->px.what.as<double>();
   A.geom = t->nd_geom.as<double>();
+  A.box = t->nd_box.as<double>();
   A.pnodes32 = t->px.pnodes32.as<float>();
   A.qhat32 = t->px.qhat32.as<float>();
   A.what32 = t->px.what32.as<float>();
@@ -171,6 +172,8 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   A.degree = t->degree;
   A.ia2 = ia2;
   A.partial = t->partial.as<double>();
+  A.item_list = t->item_order.as<int32_t>();
+  A.n_list = t->n_items;
   if (t->n_items > 0) {
     phase_begin(t, kPhaseInteract, s);
     ++t->interact_launches;

@@ -73,6 +73,13 @@ struct Pair {
   }
 };
 
+// Proxy charges of a grid row arrive through scalar loads, (OB + 1) doubles per
+// proxy point. A row is taken in steps of kRowStep points, with a scheduling
+// barrier between steps, so that the loaded charges stay within the scalar
+// register file instead of spilling into vector lanes.
+template <int OB>
+constexpr int kRowStep = 24 / (OB + 1) > 2 ? 24 / (OB + 1) : 2;
+
 // Far pairs of one cluster: proxy points s_k on the tensor grid px x py x pz
 // (NP1 = degree + 1 points per dimension; NP1 == 0 means a run-time degree).
 template <int KER, int OB, int NP1>
@@ -84,6 +91,48 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
   const int np1 = NP1 ? NP1 : np1_rt;
   const double* py = px + np1;
   const double* pz = py + np1;
+  if constexpr (KER == TAGI_COULOMB_SS && NP1 > 0) {
+    // The Gaussian of K2 separates over the tensor grid,
+    //   exp(-d^2/a^2) = exp(-dx^2/a^2) exp(-dy^2/a^2) exp(-dz^2/a^2),
+    // so the cluster needs 3 (n+1) exponentials per target instead of (n+1)^3.
+    double dz[NP1], gz[NP1], gy[NP1];
+#pragma unroll
+    for (int k3 = 0; k3 < NP1; ++k3) {
+      dz[k3] = zi - pz[k3];
+      gz[k3] = exp_nonpos(dz[k3] * dz[k3] * nia2);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < NP1; ++k2) {
+      const double dy = yi - py[k2];
+      gy[k2] = exp_nonpos(dy * dy * nia2);
+    }
+    int k = 0;
+    for (int k1 = 0; k1 < NP1; ++k1) {
+      const double dx = xi - px[k1];
+      const double dx2 = dx * dx;
+      const double gx = exp_nonpos(dx2 * nia2);
+#pragma unroll
+      for (int k2 = 0; k2 < NP1; ++k2) {
+        const double dy = yi - py[k2];
+        const double dxy = __builtin_fma(dy, dy, dx2);
+        const double gxy = gx * gy[k2];
+#pragma unroll
+        for (int h = 0; h < NP1; h += kRowStep<OB>) {
+#pragma unroll
+          for (int k3 = h; k3 < (h + kRowStep<OB> < NP1 ? h + kRowStep<OB> : NP1); ++k3) {
+            const double r2 = __builtin_fma(dz[k3], dz[k3], dxy);
+            const double rinv = rsqrt_pos(r2);
+            a2[0] = __builtin_fma(gxy * gz[k3] * rinv, wk[k + k3], a2[0]);
+#pragma unroll
+            for (int o = 0; o < OB; ++o) a1[o] = __builtin_fma(rinv, qk[o][k + k3], a1[o]);
+          }
+          if constexpr (kRowStep<OB> < NP1) __builtin_amdgcn_sched_barrier(0);
+        }
+        k += NP1;
+      }
+    }
+    return;
+  }
   int k = 0;
   for (int k1 = 0; k1 < np1; ++k1) {
     const double dx = xi - px[k1];
@@ -93,13 +142,17 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
       const double dxy = __builtin_fma(dy, dy, dx2);
       if constexpr (NP1 > 0) {
 #pragma unroll
-        for (int k3 = 0; k3 < NP1; ++k3) {
-          const double dz = zi - pz[k3];
-          const double r2 = __builtin_fma(dz, dz, dxy);
-          double c[OB];
+        for (int h = 0; h < NP1; h += kRowStep<OB>) {
 #pragma unroll
-          for (int o = 0; o < OB; ++o) c[o] = qk[o][k + k3];
-          Pair<KER>::template add<OB>(r2, rsqrt_pos(r2), c, wk[k + k3], nkap, nia2, a1, a2);
+          for (int k3 = h; k3 < (h + kRowStep<OB> < NP1 ? h + kRowStep<OB> : NP1); ++k3) {
+            const double dz = zi - pz[k3];
+            const double r2 = __builtin_fma(dz, dz, dxy);
+            double c[OB];
+#pragma unroll
+            for (int o = 0; o < OB; ++o) c[o] = qk[o][k + k3];
+            Pair<KER>::template add<OB>(r2, rsqrt_pos(r2), c, wk[k + k3], nkap, nia2, a1, a2);
+          }
+          if constexpr (kRowStep<OB> < NP1) __builtin_amdgcn_sched_barrier(0);
         }
         k += NP1;
       } else {
@@ -142,6 +195,47 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
   float b1[OB], b2[OB];
 #pragma unroll
   for (int o = 0; o < OB; ++o) b1[o] = b2[o] = 0.0f;
+  if constexpr (KER == TAGI_COULOMB_SS && NP1 > 0) {
+    // separable Gaussian, as in the FP64 far field
+    float dz[NP1], gz[NP1], gy[NP1];
+#pragma unroll
+    for (int k3 = 0; k3 < NP1; ++k3) {
+      dz[k3] = oz - pz[k3];
+      gz[k3] = __builtin_amdgcn_exp2f(dz[k3] * dz[k3] * nial2);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < NP1; ++k2) {
+      const float dy = oy - py[k2];
+      gy[k2] = __builtin_amdgcn_exp2f(dy * dy * nial2);
+    }
+    int k = 0;
+    for (int k1 = 0; k1 < NP1; ++k1) {
+      const float dx = ox - px[k1];
+      const float dx2 = dx * dx;
+      const float gx = __builtin_amdgcn_exp2f(dx2 * nial2);
+#pragma unroll
+      for (int k2 = 0; k2 < NP1; ++k2) {
+        const float dy = oy - py[k2];
+        const float dxy = __builtin_fmaf(dy, dy, dx2);
+        const float gxy = gx * gy[k2];
+#pragma unroll
+        for (int k3 = 0; k3 < NP1; ++k3) {
+          const float r2 = __builtin_fmaf(dz[k3], dz[k3], dxy);
+          const float rinv = __builtin_amdgcn_rsqf(r2);
+          b2[0] = __builtin_fmaf(gxy * gz[k3] * rinv, wk[k + k3], b2[0]);
+#pragma unroll
+          for (int o = 0; o < OB; ++o) b1[o] = __builtin_fmaf(rinv, qk[o][k + k3], b1[o]);
+        }
+        k += NP1;
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < OB; ++o) {
+      a1[o] += (double)b1[o];
+      a2[o] += (double)b2[o];
+    }
+    return;
+  }
   int k = 0;
   for (int k1 = 0; k1 < np1; ++k1) {
     const float dx = ox - px[k1];
@@ -184,8 +278,10 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
   }
 }
 
-// Near pairs with the particles [j0, j1): coincident points are masked out.
-template <int KER, int OB>
+// Near pairs with the particles [j0, j1): coincident points are masked out
+// (MASK), or, where the caller has shown that no source coincides with a target
+// of the wave, summed without the test.
+template <int KER, int OB, bool MASK = true>
 __device__ __forceinline__ void near_range(double xi, double yi, double zi, int j0, int j1,
                                            const double* __restrict__ xs,
                                            const double* __restrict__ ys,
@@ -193,7 +289,10 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
                                            const double* __restrict__ ws,
                                            const double* const* qr, const double* nkap,
                                            double nia2, double* a1, double* a2) {
-  constexpr int U = 4;
+  // 4 sources per step; the masked form (rare: only where a target may coincide
+  // with a source) takes 2, which keeps the kernel's scalar registers from
+  // spilling into the unmasked loop
+  constexpr int U = MASK ? 2 : 4;
   int j = j0;
   for (; j + U <= j1; j += U) {
 #pragma unroll
@@ -202,7 +301,7 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
       const double dy = yi - ys[j + u];
       const double dz = zi - zs[j + u];
       const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-      const double rinv = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+      const double rinv = !MASK || r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
       double c[OB];
 #pragma unroll
       for (int o = 0; o < OB; ++o) c[o] = qr[o][j + u];
@@ -214,7 +313,7 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
     const double dy = yi - ys[j];
     const double dz = zi - zs[j];
     const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-    const double rinv = r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+    const double rinv = !MASK || r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
     double c[OB];
 #pragma unroll
     for (int o = 0; o < OB; ++o) c[o] = qr[o][j];
@@ -230,6 +329,7 @@ struct InteractArgs {
   const int32_t *leaf_node, *nbeg, *nend, *far_id, *near_id, *slot_of;
   const double *xs, *ys, *zs, *qs, *ws, *fs;
   const double *pnodes, *qhat, *what, *geom;
+  const double* box;  // optional: node bounding boxes [n_nodes][6] (lo xyz, hi xyz)
   const float *pnodes32, *qhat32, *what32;
   int64_t n;
   int n_orb, n_approx, degree;
@@ -239,10 +339,22 @@ struct InteractArgs {
   int64_t n_list;
 };
 
+// Workgroups are handed to the 8 XCDs of the chip round-robin by their index, and
+// every XCD has its own L2. Renumbering the workgroups so that each XCD runs one
+// contiguous range of the launch order keeps items that read the same clusters
+// (the groups of one chunk, neighbouring batches) on one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds;
+  return x * q + min(x, r) + b / kXcds;
+}
+
 template <int KER, int OB, int NP1, bool MIX>
 __global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb) {
   const int lane = threadIdx.x % kWave;
-  const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kWavesPerBlock + threadIdx.x / kWave));
+  const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int wv = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (int)(threadIdx.x / kWave));
   if (A.item_list ? wv >= A.n_list : wv >= A.n_items) return;
   const int it = A.item_list ? __builtin_amdgcn_readfirstlane(A.item_list[wv]) : wv;
   const int4 item = A.items[it];
@@ -311,8 +423,21 @@ __global__ __launch_bounds__(kBlock) void k_interact(InteractArgs A, OrbArg orb)
     for (int o = 0; o < OB; ++o) qr[o] = A.qs + (int64_t)orb_row[o] * A.n;
     for (int e = ch.e0; e < ch.e1; ++e) {
       const int C = A.near_id[e];
-      near_range<KER, OB>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws, qr, nkap,
-                          nia2, a1, a2);
+      // A source can only coincide with a target inside the cluster's (closed)
+      // bounding box; the coincidence test is needed only when some lane's target
+      // lies in it.
+      bool inside = true;
+      if (A.box) {
+        const double* bx = A.box + (int64_t)C * 6;
+        inside = xi >= bx[0] && xi <= bx[3] && yi >= bx[1] && yi <= bx[4] && zi >= bx[2] &&
+                 zi <= bx[5];
+      }
+      if (__builtin_amdgcn_ballot_w64(inside))
+        near_range<KER, OB, true>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws, qr,
+                                  nkap, nia2, a1, a2);
+      else
+        near_range<KER, OB, false>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws,
+                                   qr, nkap, nia2, a1, a2);
     }
   }
   double* out = A.partial + (int64_t)it * OB * 2 * kWave;

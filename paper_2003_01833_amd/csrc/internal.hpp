@@ -151,6 +151,8 @@ struct tagi_tree {
   int items_n_orb = 0;
   tagi::DBuf chunks;                // int4 {kind, e0, e1, cost}
   tagi::DBuf items;                 // int4 {batch, group, oblock, chunk}
+  tagi::DBuf item_order;            // int32 [n_items] launch order: per batch and orbital
+                                    // block, chunk-major (the groups of a chunk adjacent)
   tagi::DBuf group_first_item;      // int32 per (batch, group)
   tagi::DBuf batch_group_base;      // int32 [n_leaves] first (batch, group) index
   tagi::DBuf batch_chunks;          // int2 [n_leaves] {first chunk, n chunks}

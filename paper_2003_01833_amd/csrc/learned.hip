@@ -465,6 +465,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     A.ws = t->ws.as<double>();
     A.fs = t->fs.as<double>();
     A.geom = t->nd_geom.as<double>();
+    A.box = t->nd_box.as<double>();
     A.n = t->n;
     A.n_orb = n_orb;
     A.partial = S.partial.as<double>();

@@ -262,7 +262,22 @@ int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
     set_error("compute schedule exceeds 2^31 work items");
     return TAGI_E_UNSUPPORTED;
   }
+  // launch order: the waves of one chunk (same sources, different target groups)
+  // run side by side
+  std::vector<int32_t> order;
+  order.reserve((size_t)t->n_items);
+  for (int b = 0; b < nl; ++b) {
+    const HostNode& q = t->nodes[t->leaves[b]];
+    const int ng = (q.end - q.begin + kWave - 1) / kWave;
+    for (int ob = 0; ob < n_ob; ++ob)
+      for (int c = 0; c < hn[b]; ++c)
+        for (int g = 0; g < ng; ++g)
+          order.push_back(group_first[group_base[b] + g] + ob * hn[b] + c);
+  }
   TAGI_TRY(t->items.ensure(std::max<size_t>(items.size(), 4) * 4));
+  TAGI_TRY(t->item_order.ensure(std::max<size_t>(order.size(), 1) * 4));
+  if (!order.empty())
+    TAGI_HIP(hipMemcpyAsync(t->item_order.p, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
   TAGI_TRY(t->group_first_item.ensure(std::max<size_t>(group_first.size(), 1) * 4));
   TAGI_TRY(t->batch_group_base.ensure((size_t)nl * 4));
   TAGI_TRY(t->batch_chunks.ensure((size_t)nl * 8));
