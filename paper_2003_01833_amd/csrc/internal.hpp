@@ -86,7 +86,9 @@ struct LearnedState {
   DBuf l1n;                         // float l1 norms of those charges: [n_orb][n_nodes] of f w,
                                     // [n_nodes] of w, then [n_orb][n_leaves] max |f| per batch
   DBuf params;                      // float network parameters
-  DBuf cnt;                         // int64 [n_leaves][kDegSlots] counts, then offsets
+  DBuf cnt;                         // int64 [n_leaves][kDegSlots] counts, offsets; [n_leaves] log sizes
+  DBuf log;                         // int32 [n_leaves][log_cap] traversal logs
+  int64_t log_cap = 0;
   DBuf far_id, near_id;             // int32 lists (far grouped by degree within a batch)
   DBuf chunks, items, group_first, group_base, batch_chunks, partial, item_lists;
   std::vector<int32_t> h_items, h_chunks, h_group_first, h_group_base, h_batch_chunks, h_lists;
@@ -98,11 +100,12 @@ struct LearnedState {
   int64_t far_by_degree[kMaxDegree + 1] = {};
   void release() {
     l1set.release();
-    for (DBuf* b : {&l1n, &params, &cnt, &far_id, &near_id, &chunks, &items, &group_first,
+    for (DBuf* b : {&l1n, &params, &cnt, &log, &far_id, &near_id, &chunks, &items, &group_first,
                     &group_base, &batch_chunks, &partial, &item_lists})
       b->release();
     key.clear();
     n_items = 0;
+    log_cap = 0;
   }
 };
 

@@ -51,12 +51,11 @@ struct LearnArgs {
   float shift[kIn], scale[kIn], lo[kIn], hi[kIn];
   float logk[kMaxOrb];
   float kap[kMaxOrb];
-  int fill;
-  int64_t* cnt;        // count pass: [n_leaves][kSlots]
-  const int64_t* off;  // fill pass: [n_leaves][kSlots] start offsets
-  int32_t* far_id;
-  int32_t* near_id;
-  int32_t* overflow;
+  int64_t* cnt;        // [n_leaves][kSlots] entries per slot
+  int64_t* nlog;       // [n_leaves] entries visited (may exceed cap)
+  int32_t* log;        // [n_leaves][cap] (C << 4) | slot in traversal order
+  int64_t cap;
+  int32_t* overflow;   // traversal stack overflow
 };
 
 // network forward for one lane; hA, hB are this block's [64][64] LDS buffers
@@ -98,24 +97,32 @@ __device__ void mlp_forward(const float* P, const float* x, float* hA, float* hB
   }
 }
 
-// one wave per block of 64 batches
+constexpr int kStack = 512;  // traversal stack entries
+
+// One wave per batch: the ComputePotential traversal is wave-uniform; at a
+// candidate pair lane o evaluates the network for orbital o. Every visited
+// pair's outcome goes to the batch's log in traversal order as (C << 4) | slot
+// (slot 0..8: far at degree 4 + slot, 9: near); entries beyond `cap` are counted
+// but not written.
 __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
   __shared__ float sP[kNParam];
   __shared__ float hbuf[2][kH * kWave];
+  __shared__ int stk[kStack];
   for (int i = threadIdx.x; i < kNParam; i += blockDim.x) sP[i] = L.params[i];
-  __syncthreads();
   const int lane = threadIdx.x;
-  const int b = blockIdx.x * blockDim.x + lane;
-  if (b >= L.n_leaves) return;
+  const int b = blockIdx.x;
   const int B = L.leaf_node[b];
   const double rB = L.geom[B * 4 + 3];
+  int32_t* log = L.log + (int64_t)b * L.cap;
   int64_t c[kSlots];
   for (int k = 0; k < kSlots; ++k) c[k] = 0;
-  int stack[512];
-  int sp = 0;
-  stack[sp++] = 0;
+  int64_t nlog = 0;
+  if (lane == 0) stk[0] = 0;
+  int sp = 1;
+  bool over = false;
   while (sp > 0) {
-    const int C = stack[--sp];
+    __syncthreads();
+    const int C = stk[--sp];
     const int cnt = L.nend[C] - L.nbeg[C];
     const bool leaf = L.n_child[C] == 0;
     double R, rC;
@@ -134,9 +141,10 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
     } else if (cnt <= (kDegMin + 1) * (kDegMin + 1) * (kDegMin + 1)) {
       kind = 1;  // too few sources for any degree: direct, as a size-rejected pair
     } else {
-      bool fallback = false, ok = true;
-      int dmax = kDegMin;
-      for (int o = 0; o < L.n_orb && ok && !fallback; ++o) {
+      bool fb = false;
+      int d_o = 0;  // this lane's orbital: lowest acceptable degree, -1 if none
+      if (lane < L.n_orb) {
+        const int o = lane;
         float raw[kIn];
         raw[0] = logf((float)rC);
         raw[1] = logf((float)fmax(R - rB, 1e-12));
@@ -149,27 +157,30 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
         raw[4] = logf(l1);
         float x[kIn];
         for (int k = 0; k < kIn; ++k) {
-          if (!(raw[k] >= L.lo[k] && raw[k] <= L.hi[k])) fallback = true;
+          if (!(raw[k] >= L.lo[k] && raw[k] <= L.hi[k])) fb = true;
           x[k] = (raw[k] - L.shift[k]) * L.scale[k];
         }
-        if (fallback) break;
-        float pred[kOut];
-        mlp_forward(sP, x, hbuf[0], hbuf[1], lane, pred);
-        // the network predicts the error relative to the magnitude scale
-        // l1 exp(-kappa d) / d of the pair, d = R - r_B
-        const float dd = (float)fmax(R - rB, 1e-12);
-        const float scl = log10f(l1) - 0.43429448f * L.kap[o] * dd - log10f(dd);
-        int d_o = -1;
-        for (int d = kDegMin; d <= kDegMax; ++d) {
-          if ((d + 1) * (d + 1) * (d + 1) >= cnt) break;
-          if (pred[d - kDegMin] + scl <= L.log_tol[o]) {
-            d_o = d;
-            break;
+        if (!fb) {
+          float pred[kOut];
+          mlp_forward(sP, x, hbuf[0], hbuf[1], lane, pred);
+          // the network predicts the error relative to the magnitude scale
+          // l1 exp(-kappa d) / d of the pair, d = R - r_B
+          const float dd = (float)fmax(R - rB, 1e-12);
+          const float scl = log10f(l1) - 0.43429448f * L.kap[o] * dd - log10f(dd);
+          d_o = -1;
+          for (int d = kDegMin; d <= kDegMax; ++d) {
+            if ((d + 1) * (d + 1) * (d + 1) >= cnt) break;
+            if (pred[d - kDegMin] + scl <= L.log_tol[o]) {
+              d_o = d;
+              break;
+            }
           }
         }
-        if (d_o < 0) ok = false;
-        else dmax = max(dmax, d_o);
       }
+      const bool fallback = __builtin_amdgcn_ballot_w64(fb) != 0;
+      const bool ok = __builtin_amdgcn_ballot_w64(d_o < 0) == 0;
+      int dmax = d_o;
+      for (int off = kWave / 2; off > 0; off >>= 1) dmax = max(dmax, __shfl_xor(dmax, off));
       if (fallback) {
         const int nf = L.degree_fb + 1;
         const bool dist = (rB + rC) < L.theta_fb * R;
@@ -183,29 +194,52 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
         }
       } else if (ok) {
         kind = 0;
-        deg = dmax;
+        deg = max(dmax, kDegMin);
       } else {
         kind = leaf ? 1 : 2;
       }
     }
-    if (kind == 0) {
-      const int slot = deg - kDegMin;
-      if (L.fill) L.far_id[L.off[(int64_t)b * kSlots + slot] + c[slot]] = C;
-      ++c[slot];
-    } else if (kind == 1) {
-      if (L.fill) L.near_id[L.off[(int64_t)b * kSlots + kNDeg] + c[kNDeg]] = C;
-      ++c[kNDeg];
-    } else {
+    kind = __builtin_amdgcn_readfirstlane(kind);
+    deg = __builtin_amdgcn_readfirstlane(deg);
+    if (kind == 2) {
       const int fc = L.first_child[C], nc = L.n_child[C];
-      if (sp + nc > 512) {
-        atomicExch(L.overflow, 1);
-        return;
+      if (sp + nc > kStack) {
+        over = true;
+        break;
       }
-      for (int k = nc - 1; k >= 0; --k) stack[sp++] = fc + k;
+      __syncthreads();  // every lane has read stk[sp] before it is overwritten
+      if (lane < nc) stk[sp + nc - 1 - lane] = fc + lane;
+      sp += nc;
+    } else {
+      const int slot = kind == 0 ? deg - kDegMin : kNDeg;
+      if (lane == 0 && nlog < L.cap) log[nlog] = (C << 4) | slot;
+      ++nlog;
+      ++c[slot];
     }
   }
-  if (!L.fill)
+  if (lane == 0) {
     for (int k = 0; k < kSlots; ++k) L.cnt[(int64_t)b * kSlots + k] = c[k];
+    L.nlog[b] = nlog;
+    if (over) atomicExch(L.overflow, 1);
+  }
+}
+
+// Scatters each batch's log into the far list (grouped by degree, traversal
+// order within a degree) and the near list, at the host-computed offsets.
+__global__ void k_lists_scatter(int n_leaves, int64_t cap, const int32_t* __restrict__ log,
+                                const int64_t* __restrict__ nlog, const int64_t* __restrict__ off,
+                                int32_t* __restrict__ far_id, int32_t* __restrict__ near_id) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_leaves) return;
+  int64_t pos[kSlots];
+  for (int k = 0; k < kSlots; ++k) pos[k] = off[(int64_t)b * kSlots + k];
+  const int32_t* lg = log + (int64_t)b * cap;
+  for (int64_t i = 0; i < nlog[b]; ++i) {
+    const int32_t e = lg[i];
+    const int slot = e & 15, C = e >> 4;
+    if (slot < kNDeg) far_id[pos[slot]++] = C;
+    else near_id[pos[kNDeg]++] = C;
+  }
 }
 
 }  // namespace
@@ -274,26 +308,42 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       L.logk[o] = (float)std::log(kappa[o]);
       L.kap[o] = (float)kappa[o];
     }
-    TAGI_TRY(S.cnt.ensure((size_t)nl * kSlots * 2 * sizeof(int64_t) + 4));
+    // one wave per batch; the per-batch logs are scattered into grouped lists
+    TAGI_TRY(S.cnt.ensure((size_t)nl * (2 * kSlots + 1) * sizeof(int64_t) + 4));
     int64_t* d_cnt = S.cnt.as<int64_t>();
     int64_t* d_off = d_cnt + (size_t)nl * kSlots;
-    int32_t* d_over = reinterpret_cast<int32_t*>(d_off + (size_t)nl * kSlots);
-    TAGI_HIP(hipMemsetAsync(d_over, 0, 4, s));
+    int64_t* d_nlog = d_off + (size_t)nl * kSlots;
+    int32_t* d_over = reinterpret_cast<int32_t*>(d_nlog + nl);
     L.cnt = d_cnt;
+    L.nlog = d_nlog;
     L.overflow = d_over;
-    L.fill = 0;
-    const int grid = (nl + 63) / 64;
-    hipLaunchKernelGGL(k_lists_learned, dim3(grid), dim3(64), 0, s, L);
-    TAGI_HIP(hipGetLastError());
-    std::vector<int64_t> h((size_t)nl * kSlots);
-    int32_t over = 0;
-    TAGI_HIP(hipMemcpyAsync(h.data(), d_cnt, h.size() * 8, hipMemcpyDeviceToHost, s));
-    TAGI_HIP(hipMemcpyAsync(&over, d_over, 4, hipMemcpyDeviceToHost, s));
-    TAGI_HIP(hipStreamSynchronize(s));
-    if (over) {
-      set_error("learned lists: traversal stack overflow");
-      return TAGI_E_UNSUPPORTED;
+    std::vector<int64_t> h((size_t)nl * kSlots), hlog(nl);
+    int64_t cap = std::max<int64_t>(S.log_cap, 2048);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      TAGI_TRY(S.log.ensure((size_t)nl * cap * sizeof(int32_t)));
+      TAGI_HIP(hipMemsetAsync(d_over, 0, 4, s));
+      L.log = S.log.as<int32_t>();
+      L.cap = cap;
+      hipLaunchKernelGGL(k_lists_learned, dim3(nl), dim3(64), 0, s, L);
+      TAGI_HIP(hipGetLastError());
+      int32_t over = 0;
+      TAGI_HIP(hipMemcpyAsync(h.data(), d_cnt, h.size() * 8, hipMemcpyDeviceToHost, s));
+      TAGI_HIP(hipMemcpyAsync(hlog.data(), d_nlog, hlog.size() * 8, hipMemcpyDeviceToHost, s));
+      TAGI_HIP(hipMemcpyAsync(&over, d_over, 4, hipMemcpyDeviceToHost, s));
+      TAGI_HIP(hipStreamSynchronize(s));
+      if (over) {
+        set_error("learned lists: traversal stack overflow");
+        return TAGI_E_UNSUPPORTED;
+      }
+      const int64_t need = *std::max_element(hlog.begin(), hlog.end());
+      if (need <= cap) break;
+      if (attempt == 1 || need >= INT32_MAX / 16) {
+        set_error("learned lists: per-batch log of %lld entries", (long long)need);
+        return TAGI_E_UNSUPPORTED;
+      }
+      cap = need;  // a second traversal with room for every batch
     }
+    S.log_cap = cap;
     std::vector<int64_t> off(h.size());
     int64_t nf = 0, nnear = 0;
     for (int b = 0; b < nl; ++b) {
@@ -313,11 +363,9 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     TAGI_TRY(S.far_id.ensure(std::max<int64_t>(nf, 1) * 4));
     TAGI_TRY(S.near_id.ensure(std::max<int64_t>(nnear, 1) * 4));
     TAGI_HIP(hipMemcpyAsync(d_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
-    L.fill = 1;
-    L.off = d_off;
-    L.far_id = S.far_id.as<int32_t>();
-    L.near_id = S.near_id.as<int32_t>();
-    hipLaunchKernelGGL(k_lists_learned, dim3(grid), dim3(64), 0, s, L);
+    hipLaunchKernelGGL(k_lists_scatter, dim3((nl + 127) / 128), dim3(128), 0, s, nl, cap,
+                       S.log.as<int32_t>(), d_nlog, d_off, S.far_id.as<int32_t>(),
+                       S.near_id.as<int32_t>());
     TAGI_HIP(hipGetLastError());
     std::vector<int32_t> fid(std::max<int64_t>(nf, 1)), nid(std::max<int64_t>(nnear, 1));
     if (nf) TAGI_HIP(hipMemcpyAsync(fid.data(), S.far_id.p, nf * 4, hipMemcpyDeviceToHost, s));
@@ -355,7 +403,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       for (int64_t e = off[(size_t)b * kSlots + kNDeg]; e < off[(size_t)b * kSlots + kNDeg] + h[(size_t)b * kSlots + kNDeg]; ++e)
         S.near_inter += nb * (t->nodes[nid[e]].end - t->nodes[nid[e]].begin);
     }
-    const int64_t cap = std::max<int64_t>((total + S.near_inter / std::max<int64_t>(1, t->n / nl)) / 16384, 4096);
+    const int64_t ccap = std::max<int64_t>((total + S.near_inter / std::max<int64_t>(1, t->n / nl)) / 16384, 4096);
     for (int b = 0; b < nl; ++b) {
       bfirst[b] = (int32_t)(S.h_chunks.size() / 4);
       for (int k = 0; k <= kNDeg; ++k) {
@@ -365,7 +413,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
         for (int64_t e = e0; e < e1; ++e) {
           const int64_t cst = k < kNDeg ? (int64_t)(kDegMin + k + 1) * (kDegMin + k + 1) * (kDegMin + k + 1)
                                         : (int64_t)(t->nodes[nid[e]].end - t->nodes[nid[e]].begin);
-          if (cost > 0 && cost + cst > cap) {
+          if (cost > 0 && cost + cst > ccap) {
             S.h_chunks.insert(S.h_chunks.end(), {kindv, (int32_t)start, (int32_t)e, (int32_t)std::min<int64_t>(cost, INT32_MAX)});
             start = e;
             cost = 0;
@@ -393,14 +441,18 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       for (int g = 0; g < ng; ++g) {
         S.h_group_first.push_back((int32_t)(S.h_items.size() / 4));
         for (int o = 0; o < n_ob; ++o)
-          for (int cidx = 0; cidx < bcount[b]; ++cidx) {
-            const int ch = bfirst[b] + cidx;
-            const int kindv = S.h_chunks[(size_t)ch * 4];
-            const int slot = kindv == 1 ? kNDeg : kindv - 16 - kDegMin;
-            per[slot].push_back((int32_t)(S.h_items.size() / 4));
-            S.h_items.insert(S.h_items.end(), {b, g, o, ch});
-          }
+          for (int cidx = 0; cidx < bcount[b]; ++cidx)
+            S.h_items.insert(S.h_items.end(), {b, g, o, bfirst[b] + cidx});
       }
+      // launch order within the batch: chunk-major, the target groups that read
+      // the same sources side by side
+      for (int o = 0; o < n_ob; ++o)
+        for (int cidx = 0; cidx < bcount[b]; ++cidx) {
+          const int kindv = S.h_chunks[(size_t)(bfirst[b] + cidx) * 4];
+          const int slot = kindv == 1 ? kNDeg : kindv - 16 - kDegMin;
+          for (int g = 0; g < ng; ++g)
+            per[slot].push_back(S.h_group_first[S.h_group_base[b] + g] + o * bcount[b] + cidx);
+        }
     }
     S.n_items = (int64_t)S.h_items.size() / 4;
     S.h_lists.clear();

@@ -9,8 +9,10 @@
 2. Training: tagi_selector_train (FP32 Adam, mini-batches of 4096).
 3. Calibration: on a held-out seed (6), the per-pair budget is
    tol_o = eta * 1e-6 * max|u_o| with u_o the FP64 fixed-MAC result; eta is the
-   largest of a decreasing ladder for which the learned result stays within 1e-6
-   (relative L2 and max) of the direct sum at sampled targets.
+   largest of a decreasing ladder for which the learned result stays within
+   1e-6 / margin (relative L2 and max, margin 2) of the direct sum at sampled
+   targets; the margin covers workloads with more pairs per target than the
+   single atom.
 Writes selector_weights.npz and selector_weights.json (loss history, sample
 count, eta, timings).
 """
@@ -37,7 +39,7 @@ def _log(msg):
 
 def calibrate(tagi, torch, sel, mesh, seed: int = 6, kappas=(0.6, 1.5, 4.0), leaf: int = 500,
               samples: int = 1000, etas=(1.0, 0.3, 0.1, 0.03, 0.01, 0.003, 0.001, 3e-4),
-              target: float = 1e-6):
+              target: float = 1e-6, margin: float = 2.0):
     from paper_2003_01833_amd.selector import slater_field
     from workloads.configs import DOMAIN, sample_targets
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
@@ -68,7 +70,7 @@ def calibrate(tagi, torch, sel, mesh, seed: int = 6, kappas=(0.6, 1.5, 4.0), lea
         log.append({"eta": eta, "worst_rel_err": worst, "evaluations": ev})
         _log(f"calibration: eta {eta}: worst rel err {worst:.3e}, {ev:.4g} evaluations, "
              f"far pairs by degree {st['far_pairs_by_degree']}")
-        if worst <= target and chosen is None:
+        if worst <= target / margin and chosen is None:
             chosen = eta
     t.close()
     return chosen if chosen is not None else etas[-1], log
