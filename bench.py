@@ -139,9 +139,20 @@ def cpu_baseline(wl, seconds: float):
     k = int(min(n, max(probe, probe * seconds / max(dt, 1e-6))))
     dt = run(k)
     pairs = k * n * len(wl["convs"])
+    # one thread, for the per-core rate (a tenth of the time)
+    k1 = max(1, int(k * 0.1 / max(threads, 1)))
+    idx1 = sample_targets(n, k1, seed=5)
+    t0 = time.perf_counter()
+    for c in wl["convs"]:
+        f = c["f"]
+        direct_sum(c["kernel"], wl["x"], wl["y"], wl["z"], f, wl["w"], wl["x"][idx1],
+                   wl["y"][idx1], wl["z"][idx1], f[idx1], kappa=c["kappa"] or 1.0, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"direct sum at {k} seeded targets x {n} sources for "
-                      f"{len(wl['convs'])} kernel(s), {dt:.1f} s"}
+                      f"{len(wl['convs'])} kernel(s), {dt:.1f} s",
+            "per_core_value": k1 * n * len(wl["convs"]) / dt1,
+            "per_core_sample": f"{k1} targets on 1 thread, {dt1:.1f} s"}
 
 
 def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samples=1000,
@@ -214,6 +225,35 @@ def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samp
     st = t.stats()
     res["batched_fp64"] = {"ms": ms, **errors(U),
                            "interactions_per_orbital": st["far_interactions"] + st["near_interactions"]}
+    # the same step captured as a HIP graph (upward + convolve), replayed
+    Ug = torch.empty((n_orb, n), dtype=torch.float64, device="cuda")
+    g = t.graph(F, w, degree, "yukawa_ss", kap, theta, out=Ug)
+    _, ms_g = timed(lambda: g.launch())
+    res["batched_fp64"]["graph_replay_ms"] = ms_g
+    res["batched_fp64"]["graph_equals_eager"] = bool(torch.equal(Ug, U))
+    g.close()
+    # autotuned leaf size and orbital block (timed on the first four orbitals),
+    # then the batched FP64 step with the pick on all orbitals
+    _log("compare: autotuning N_L and the orbital block")
+    cand_leaf, cand_ob = (1000, 2000, 4000), (2, 4)
+    (leaf_t, ob_t), times = tagi.autotune(x, y, z, F[:4].contiguous(), w, "yukawa_ss", kap[:4],
+                                          theta, degree, leaf_sizes=cand_leaf, obs=cand_ob,
+                                          box=(*DOMAIN[0], *DOMAIN[1]))
+    tt = t if leaf_t == leaf else tagi.Tree(x, y, z, leaf_t, (*DOMAIN[0], *DOMAIN[1]))
+    tt.set_orbital_block(ob_t)
+
+    def tuned():
+        tt.upward(F, w, degree)
+        return tt.convolve("yukawa_ss", kap, theta, degree)
+    U, ms = timed(tuned)
+    res["batched_fp64_autotuned"] = {
+        "ms": ms, **errors(U), "leaf_size": leaf_t, "orbital_block": ob_t,
+        "tuning_ms_per_step_4_orbitals": {f"N_L {a} OB {b}": float(times[i, j])
+                                          for i, a in enumerate(cand_leaf)
+                                          for j, b in enumerate(cand_ob)}}
+    tt.set_orbital_block(0)
+    if tt is not t:
+        tt.close()
     _log("compare: batched mixed")
     U, ms = timed(batched("mixed", *mixed))
     st_m = t.stats()
@@ -247,6 +287,8 @@ def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samp
                 "far_pairs_by_degree": ls["far_pairs_by_degree"]}
     res["speedup_batched_vs_plain"] = res["plain_fp64"]["ms"] / res["batched_fp64"]["ms"]
     res["speedup_mixed_vs_plain"] = res["plain_fp64"]["ms"] / res["batched_mixed"]["ms"]
+    res["speedup_autotuned_vs_plain"] = (res["plain_fp64"]["ms"] /
+                                         res["batched_fp64_autotuned"]["ms"])
     if "batched_mixed_learned" in res:
         res["speedup_mixed_learned_vs_plain"] = (res["plain_fp64"]["ms"] /
                                                  res["batched_mixed_learned"]["ms"])

@@ -232,6 +232,43 @@ int tagi_graph_launch(tagi_graph* graph, void* stream);
 int tagi_graph_destroy(tagi_graph* graph);
 
 /*
+ * Orbital block of the batched launch (a project addition on the per-orbital
+ * loop of Algorithm 2): the interaction kernel evaluates the geometry of a pair
+ * once for `ob` orbitals. ob = 1, 2, 4 or 8 fixes the width for every later
+ * tagi_convolve / tagi_convolve_learned on the tree (the schedule is rebuilt on
+ * the next call); ob = 0 restores the automatic choice (Yukawa kernels: 4 from
+ * four orbitals up; Coulomb kernels: 8 from eight up; else the largest power
+ * of two not above n_orb). Results do not depend on ob.
+ * Errors: TAGI_E_ARG.
+ */
+int tagi_tree_set_orbital_block(tagi_tree* tree, int ob);
+
+/*
+ * Autotuner for the batched launch (a project addition): picks the leaf size
+ * N_L (Section 6.1; batches are leaves, so it sets both N_L and N_B) and the
+ * orbital block width for one convolution by timing the candidates on the
+ * caller's data. For every leaf size it builds a tree, and for every orbital
+ * block it runs tagi_upward + tagi_convolve once untimed (plans, lists and
+ * schedule), then `reps` times between HIP events on `stream`.
+ *   x, y, z, w   DEVICE double [n] sources; f DEVICE double [n_orb][n]
+ *   box          HOST double[6] root box or NULL, as tagi_tree_build
+ *   kernel, kappa (HOST [n_orb]), alpha, theta, degree, precision: as tagi_convolve
+ *   leaf_sizes   HOST int [n_leaf] candidates (>= 1)
+ *   obs          HOST int [n_ob] candidates (0, 1, 2, 4 or 8)
+ *   best         HOST int [2] receives {leaf size, orbital block} of the fastest
+ *   times        HOST double [n_leaf][n_ob] mean ms per step (may be NULL)
+ * The accuracy at a fixed (theta, degree) changes slightly with N_L; checking
+ * it is the caller's. Synchronises the stream; allocates and frees its own
+ * scratch (one output array and the candidate trees).
+ * Errors: as tagi_tree_build, tagi_upward and tagi_convolve; TAGI_E_ARG.
+ */
+int tagi_autotune(const double* x, const double* y, const double* z, const double* w, int64_t n,
+                  const double* box, const double* f, int n_orb, int kernel, const double* kappa,
+                  double alpha, double theta, int degree, int precision, const int* leaf_sizes,
+                  int n_leaf, const int* obs, int n_ob, int reps, int* best, double* times,
+                  void* stream);
+
+/*
  * Learned degree/MAC selector (a project addition on top of Section 6.2-6.3).
  *
  * Network: 5 inputs -> 3 hidden tanh layers of 64 -> 9 linear outputs, FP32.

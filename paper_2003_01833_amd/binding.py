@@ -30,7 +30,8 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct", "t
             "tagi_tree_timing", "tagi_graph_create", "tagi_graph_launch", "tagi_graph_destroy",
             "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
             "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
-            "tagi_tree_destroy", "tagi_last_error"]
+            "tagi_tree_set_orbital_block", "tagi_autotune", "tagi_tree_destroy",
+            "tagi_last_error"]
 
 
 class TagiError(RuntimeError):
@@ -82,6 +83,9 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_upward_export.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.tagi_tree_destroy.argtypes = [vp]
     lib.tagi_tree_set_timing.argtypes = [vp, i32]
+    lib.tagi_tree_set_orbital_block.argtypes = [vp, i32]
+    lib.tagi_autotune.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, vp, dbl, dbl, i32, i32,
+                                  vp, i32, vp, i32, i32, vp, vp, vp]
     lib.tagi_graph_create.argtypes = [vp, vp, vp, i32, i32, i32, vp, dbl, dbl, i32, vp, vp,
                                       ctypes.POINTER(vp)]
     lib.tagi_graph_launch.argtypes = [vp, vp]
@@ -245,6 +249,10 @@ class Tree:
             return feat[:k].copy(), err[:k].copy(), ids[:k].copy()
         return feat[:k].copy(), err[:k].copy()
 
+    def set_orbital_block(self, ob: int = 0):
+        """tagi_tree_set_orbital_block: 1, 2, 4 or 8 orbitals per wave; 0 = automatic."""
+        _check(load_library().tagi_tree_set_orbital_block(self._h, int(ob)))
+
     def set_timing(self, enable: bool = True):
         _check(load_library().tagi_tree_set_timing(self._h, int(bool(enable))))
 
@@ -367,6 +375,26 @@ class GreenStep:
             self.close()
         except Exception:
             pass
+
+
+def autotune(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_sizes,
+             obs=(0,), alpha: float = 1.0, precision: str = "fp64", reps: int = 1, box=None):
+    """tagi_autotune: ((best leaf size, best orbital block), times ms [n_leaf][n_ob])."""
+    n = x.numel()
+    n_orb = 1 if f.dim() == 1 else f.shape[0]
+    kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64), (n_orb,)))
+    ls = np.ascontiguousarray(leaf_sizes, dtype=np.int32)
+    ob = np.ascontiguousarray(obs, dtype=np.int32)
+    bx = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
+    best = np.zeros(2, np.int32)
+    times = np.zeros((ls.size, ob.size), np.float64)
+    _check(load_library().tagi_autotune(_dptr(x, "x", n), _dptr(y, "y", n), _dptr(z, "z", n),
+                                        _dptr(w, "w", n), n, None if bx is None else _hptr(bx),
+                                        _dptr(f, "f", n_orb * n), n_orb, KERNELS[kernel],
+                                        _hptr(kap), float(alpha), float(theta), int(degree),
+                                        PRECISIONS[precision], _hptr(ls), ls.size, _hptr(ob),
+                                        ob.size, int(reps), _hptr(best), _hptr(times), _stream()))
+    return (int(best[0]), int(best[1])), times
 
 
 def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_size: int,

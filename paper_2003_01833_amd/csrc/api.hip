@@ -150,7 +150,7 @@ int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* k
   if (kernel == TAGI_COULOMB_SS)
     REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_convolve: alpha = %g must be > 0", alpha);
   hipStream_t s = (hipStream_t)stream;
-  const int ob = orbital_block(kernel, t->n_orb);
+  const int ob = orbital_block_of(t, kernel);
   const bool rebuild = !(t->list_theta == theta && t->list_degree == degree) ||
                        !(t->items_orb_block == ob && t->items_n_orb == t->n_orb && t->n_items > 0);
   if (rebuild) {
@@ -470,6 +470,91 @@ int tagi_tree_timing(tagi_tree* t, tagi_timing* o) {
   o->combine_ms = t->phase_ms[kPhaseCombine];
   o->interact_launches = t->interact_launches;
   return TAGI_OK;
+}
+
+int tagi_tree_set_orbital_block(tagi_tree* t, int ob) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_tree_set_orbital_block: tree is NULL");
+  REQUIRE(ob == 0 || ob == 1 || ob == 2 || ob == 4 || ob == 8,
+          "tagi_tree_set_orbital_block: ob = %d must be 0, 1, 2, 4 or 8", ob);
+  t->ob_override = ob;
+  return TAGI_OK;
+}
+
+int tagi_autotune(const double* x, const double* y, const double* z, const double* w, int64_t n,
+                  const double* box, const double* f, int n_orb, int kernel, const double* kappa,
+                  double alpha, double theta, int degree, int precision, const int* leaf_sizes,
+                  int n_leaf, const int* obs, int n_ob, int reps, int* best, double* times,
+                  void* stream) {
+  g_err[0] = 0;
+  REQUIRE(x && y && z && w && f, "tagi_autotune: null input array");
+  REQUIRE(leaf_sizes && n_leaf >= 1, "tagi_autotune: no leaf size candidates");
+  REQUIRE(obs && n_ob >= 1, "tagi_autotune: no orbital block candidates");
+  REQUIRE(best, "tagi_autotune: best is NULL");
+  REQUIRE(reps >= 1 && reps <= 1000, "tagi_autotune: reps = %d out of range [1, 1000]", reps);
+  REQUIRE(n >= 1 && n < (int64_t)INT32_MAX, "tagi_autotune: n = %lld out of range", (long long)n);
+  REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb, "tagi_autotune: n_orb = %d out of range", n_orb);
+  for (int i = 0; i < n_leaf; ++i)
+    REQUIRE(leaf_sizes[i] >= 1, "tagi_autotune: leaf_sizes[%d] = %d must be >= 1", i,
+            leaf_sizes[i]);
+  for (int i = 0; i < n_ob; ++i)
+    REQUIRE(obs[i] == 0 || obs[i] == 1 || obs[i] == 2 || obs[i] == 4 || obs[i] == 8,
+            "tagi_autotune: obs[%d] = %d must be 0, 1, 2, 4 or 8", i, obs[i]);
+  hipStream_t s = (hipStream_t)stream;
+  double* out = nullptr;
+  TAGI_HIP(hipMallocAsync((void**)&out, (size_t)n_orb * n * sizeof(double), s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = TAGI_OK;
+  double best_ms = INFINITY;
+  best[0] = best[1] = 0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_error("tagi_autotune: hipEventCreate failed");
+    st = TAGI_E_HIP;
+  }
+  for (int li = 0; li < n_leaf && st == TAGI_OK; ++li) {
+    tagi_tree* t = nullptr;
+    st = tagi_tree_build(x, y, z, n, box, leaf_sizes[li], stream, &t);
+    for (int oi = 0; oi < n_ob && st == TAGI_OK; ++oi) {
+      t->ob_override = obs[oi];
+      auto step = [&]() {
+        int r = tagi_upward(t, f, w, n_orb, degree, stream);
+        if (r == TAGI_OK)
+          r = tagi_convolve(t, nullptr, kernel, kappa, alpha, theta, degree, precision, out,
+                            stream);
+        return r;
+      };
+      st = step();
+      if (st != TAGI_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) st = TAGI_E_HIP;
+      for (int r = 0; r < reps && st == TAGI_OK; ++r) st = step();
+      if (st != TAGI_OK) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        set_error("tagi_autotune: event timing failed");
+        st = TAGI_E_HIP;
+        break;
+      }
+      const double per = (double)ms / reps;
+      if (times) times[(size_t)li * n_ob + oi] = per;
+      if (per < best_ms) {
+        best_ms = per;
+        best[0] = leaf_sizes[li];
+        best[1] = obs[oi];
+      }
+    }
+    if (t) {
+      char keep[1024];
+      std::memcpy(keep, g_err, sizeof(keep));
+      tagi_tree_destroy(t);
+      std::memcpy(g_err, keep, sizeof(keep));
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFreeAsync(out, s);
+  (void)hipStreamSynchronize(s);
+  return st;
 }
 
 int tagi_tree_destroy(tagi_tree* t) {

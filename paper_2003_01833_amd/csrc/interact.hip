@@ -115,7 +115,7 @@ __global__ void k_direct_combine(int64_t nt, int n_sc, int ss, double self,
 int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
              double* out, hipStream_t s) {
   const int n_orb = t->n_orb;
-  const int ob = orbital_block(kernel, n_orb);
+  const int ob = orbital_block_of(t, kernel);
   if (t->items_orb_block != ob || t->items_n_orb != n_orb || t->n_items == 0) {
     set_error("convolve: the compute schedule was not prepared");
     return TAGI_E_STATE;
@@ -231,6 +231,10 @@ OrbArg make_orb(int kernel, int n_orb, const double* kappa, double alpha) {
 }
 
 }  // namespace ik
+
+int orbital_block_of(const tagi_tree* t, int kernel) {
+  return t->ob_override ? t->ob_override : orbital_block(kernel, t->n_orb);
+}
 
 int orbital_block(int kernel, int n_orb) {
   // Coulomb kernels share all geometry across orbitals, so wider blocks pay off

@@ -151,6 +151,7 @@ struct tagi_tree {
   // schedule: chunks of (kind, begin, end) per batch, items, group table
   int64_t n_items = 0;
   int items_orb_block = 0;
+  int ob_override = 0;              // orbital block set by the caller (0 = automatic)
   int items_n_orb = 0;
   tagi::DBuf chunks;                // int4 {kind, e0, e1, cost}
   tagi::DBuf items;                 // int4 {batch, group, oblock, chunk}
@@ -202,6 +203,8 @@ int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s);
 int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s);
 int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s);
 int orbital_block(int kernel, int n_orb);
+// the tree's orbital block for a kernel: its override if set, else the default
+int orbital_block_of(const tagi_tree* t, int kernel);
 int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
              double* out, hipStream_t s);
 int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,

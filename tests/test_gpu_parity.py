@@ -171,6 +171,29 @@ def test_treecode_matches_oracle_treecode(ragged_tree, kernel):
         assert np.all(np.abs(u[o] - ref[o]) <= 1e-12 * S), (o, np.max(np.abs(u[o] - ref[o]) / S))
 
 
+@pytest.mark.parametrize("kernel,n_orb,degree,theta", [
+    ("coulomb_ss", 9, 8, 0.8),   # orbital blocks of 8 and a ragged last block; separable Gaussian
+    ("yukawa_ss", 5, 9, 0.8),    # blocks of 4 and 1; proxy rows taken in steps
+    ("coulomb_ss", 2, 11, 0.9),  # a degree without a compiled loop (run-time trip counts)
+    ("yukawa", 3, 4, 0.6),
+])
+def test_treecode_orbital_blocks_and_degrees(ragged_tree, kernel, n_orb, degree, theta):
+    c = ragged_tree
+    t = c["t"]
+    g = SplitMix64(90 + n_orb)
+    F = np.stack([g.uniform(c["f"].size, -1, 1) for _ in range(n_orb)])
+    kap = np.array([0.5 + 0.4 * o for o in range(n_orb)])
+    dF, dw = _dev(F, c["w"])
+    t.upward(dF, dw, degree)
+    u = t.convolve(kernel, kap, theta, degree).cpu().numpy()
+    assert t.stats()["n_far_pairs"] > 0
+    ref = bltc.treecode(c["x"], c["y"], c["z"], F, c["w"], kernel, kap, theta, degree, 200,
+                        tree=c["ref"])
+    for o in range(n_orb):
+        S = _scale(kernel, c["x"], c["y"], c["z"], F[o], c["w"], kap[o])
+        assert np.all(np.abs(u[o] - ref[o]) <= 1e-12 * S), (o, np.max(np.abs(u[o] - ref[o]) / S))
+
+
 def test_theta_zero_equals_direct_and_is_repeatable(ragged_tree):
     c = ragged_tree
     tagi, t = c["tagi"], c["t"]
