@@ -12,8 +12,8 @@ It takes the steps of the paper's Algorithm 3 (Section 6.3) in the paper's order
    Eq. MAC, evaluating accepted batch-cluster pairs by the approximation and the
    others by the direct sum of Eq. direct-sum_2.
 
-Singularity subtraction (Section 4.3) enters by linearity (the paper says it is
-"easily accommodated" but gives no detail): each cluster carries two charge sets,
+Singularity subtraction (Section 4.3) enters by linearity (the paper states that
+the treecode takes it in without giving the details): each cluster carries two charge sets,
 f^_k from q_j = f_j w_j and w^_k from q_j = w_j. For Yukawa the approximated pair
 sum is sum_k G(|r_i - s_k|) (f^_k - f_i w^_k); for Coulomb it is
 sum_k [f^_k - f_i exp(-|r_i - s_k|^2/a^2) w^_k] / |r_i - s_k|. Near pairs use the

@@ -11,6 +11,9 @@ to within the mesh's discretization error.
       u(r) = 4 pi e^{-a r} / D + 8 pi a (e^{-k r} - e^{-a r}) / (D^2 r),  D = k^2 - a^2,
   u(0) = 4 pi / (a + k)^2.
 * Yukawa convolution of r exp(-a r): minus the a-derivative of the previous one.
+* Yukawa convolution of exp(-a r) / r: from the radial formula below,
+      u(r) = 4 pi (e^{-a r} - e^{-k r}) / (r (k^2 - a^2)),
+  with the limit 2 pi e^{-a r} / a at k = a and 4 pi / (a + k) at r = 0.
 * ``radial_convolution``: any radial f by the one-dimensional formulas
       Yukawa:  u(r) = 4 pi / (k r) [e^{-k r} int_0^r sinh(k s) f(s) s ds
                                       + sinh(k r) int_r^inf e^{-k s} f(s) s ds]
@@ -51,6 +54,18 @@ def yukawa_of_r_exp(r, a, k):
     d_t2 = 8.0 * np.pi * ((ek - ea) / (D * D * r) + a * ea / (D * D)
                           + a * (ek - ea) * 4.0 * a / (D ** 3 * r))
     return -(d_t1 + d_t2)
+
+
+def yukawa_of_exp_over_r(r, a, k):
+    """Yukawa convolution of exp(-a r) / r."""
+    r = np.asarray(r, dtype=np.float64)
+    small = r < 1e-8
+    rs = np.where(small, 1.0, r)
+    if abs(k - a) < 1e-12 * max(a, k):
+        u = 2.0 * np.pi * np.exp(-a * rs) / a
+    else:
+        u = 4.0 * np.pi * (np.exp(-a * rs) - np.exp(-k * rs)) / (rs * (k * k - a * a))
+    return np.where(small, 4.0 * np.pi / (a + k), u)
 
 
 def radial_convolution(f, r, kernel: str, k: float = 0.0, rmax: float = 60.0):

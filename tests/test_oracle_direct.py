@@ -107,6 +107,10 @@ def test_closed_forms_against_radial_quadrature():
     for r in (0.02, 0.3, 1.0, 4.0):
         assert cf.yukawa_of_r_exp(np.array([r]), 2.0, k)[0] == pytest.approx(
             cf.radial_convolution(lambda s: s * np.exp(-2.0 * s), r, "yukawa", k), rel=1e-10)
+    for a, kk in ((3.0, k), (2.0, 2.0)):
+        for r in (0.0, 0.02, 0.3, 1.0, 4.0):
+            assert cf.yukawa_of_exp_over_r(np.array([r]), a, kk)[0] == pytest.approx(
+                cf.radial_convolution(lambda s: np.exp(-a * s) / s, r, "yukawa", kk), rel=1e-9)
 
 
 @pytest.fixture(scope="module")
