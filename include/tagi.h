@@ -232,6 +232,35 @@ int tagi_graph_launch(tagi_graph* graph, void* stream);
 int tagi_graph_destroy(tagi_graph* graph);
 
 /*
+ * One block step of Green Iteration (the iteration body of Algorithm 2, applied
+ * to every wavefunction of the block at once) around the batched convolution:
+ *   1. f_o = V_eff psi_o and psi'_o = G(eps_o) psi_o (Eqs. integral_operator,
+ *      Hemlholtz_Greens_Function): -1/(2 pi) times the subtracted Yukawa sum
+ *      (Section 4.3) of f_o with kappa_o = sqrt(-2 eps_o), by the treecode at
+ *      (theta, degree) on the tree's points with quadrature weights w;
+ *   2. the gradient-free eigenvalue update (Eq. gradient-free),
+ *      eps'_o = eps_o - <V_eff psi_o, psi_o - psi'_o> / <psi'_o, psi'_o>,
+ *      with psi'_o before orthogonalization;
+ *   3. psi'_o orthogonalized against psi'_j, j < o (classical Gram-Schmidt,
+ *      twice), in block order, then normalized;
+ *   4. resid_o = ||psi'_o - psi_o||.
+ * Inner products are sum_j w_j a_j b_j (the mesh quadrature).
+ *   psi      DEVICE double [n_orb][n] current wavefunctions, caller order
+ *   veff, w  DEVICE double [n] effective potential and quadrature weights
+ *   eps      HOST double [n_orb] eigenvalues (< 0), replaced by the update
+ *   psi_out  DEVICE double [n_orb][n] new wavefunctions (must not alias psi)
+ *   resid    HOST double [n_orb] or NULL
+ * Runs tagi_upward on the tree (its previous upward state is replaced).
+ * Reductions are block sums added on the host in a fixed order: the step is
+ * bitwise repeatable. Synchronises the stream.
+ * Errors: TAGI_E_ARG (bad arguments, a wavefunction that vanishes or becomes
+ * linearly dependent), TAGI_E_OOM, TAGI_E_HIP.
+ */
+int tagi_green_step(tagi_tree* tree, const double* psi, const double* veff, const double* w,
+                    int n_orb, double* eps, double theta, int degree, int precision,
+                    double* psi_out, double* resid, void* stream);
+
+/*
  * Orbital block of the batched launch (a project addition on the per-orbital
  * loop of Algorithm 2): the interaction kernel evaluates the geometry of a pair
  * once for `ob` orbitals. ob = 1, 2, 4 or 8 fixes the width for every later

@@ -30,7 +30,7 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct", "t
             "tagi_tree_timing", "tagi_graph_create", "tagi_graph_launch", "tagi_graph_destroy",
             "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
             "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
-            "tagi_tree_set_orbital_block", "tagi_autotune", "tagi_tree_destroy",
+            "tagi_tree_set_orbital_block", "tagi_autotune", "tagi_green_step", "tagi_tree_destroy",
             "tagi_last_error"]
 
 
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_tree_destroy.argtypes = [vp]
     lib.tagi_tree_set_timing.argtypes = [vp, i32]
     lib.tagi_tree_set_orbital_block.argtypes = [vp, i32]
+    lib.tagi_green_step.argtypes = [vp, vp, vp, vp, i32, vp, dbl, i32, i32, vp, vp, vp]
     lib.tagi_autotune.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, vp, dbl, dbl, i32, i32,
                                   vp, i32, vp, i32, i32, vp, vp, vp]
     lib.tagi_graph_create.argtypes = [vp, vp, vp, i32, i32, i32, vp, dbl, dbl, i32, vp, vp,
@@ -248,6 +249,24 @@ class Tree:
         if with_ids:
             return feat[:k].copy(), err[:k].copy(), ids[:k].copy()
         return feat[:k].copy(), err[:k].copy()
+
+    def green_step(self, psi: torch.Tensor, veff: torch.Tensor, w: torch.Tensor, eps,
+                   theta: float, degree: int, precision: str = "fp64",
+                   out: torch.Tensor | None = None):
+        """tagi_green_step: (psi' (n_orb, n), eps' numpy, residual numpy)."""
+        n_orb = 1 if psi.dim() == 1 else psi.shape[0]
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (n_orb,))).copy()
+        res = np.zeros(n_orb, np.float64)
+        if out is None:
+            out = torch.empty((n_orb, self.n), dtype=torch.float64, device="cuda")
+        _check(load_library().tagi_green_step(self._h, _dptr(psi, "psi", n_orb * self.n),
+                                              _dptr(veff, "veff", self.n), _dptr(w, "w", self.n),
+                                              n_orb, _hptr(e), float(theta), int(degree),
+                                              PRECISIONS[precision],
+                                              _dptr(out, "out", n_orb * self.n), _hptr(res),
+                                              _stream()))
+        self.n_orb, self.degree = n_orb, int(degree)
+        return out, e, res
 
     def set_orbital_block(self, ob: int = 0):
         """tagi_tree_set_orbital_block: 1, 2, 4 or 8 orbitals per wave; 0 = automatic."""

@@ -472,6 +472,27 @@ int tagi_tree_timing(tagi_tree* t, tagi_timing* o) {
   return TAGI_OK;
 }
 
+int tagi_green_step(tagi_tree* t, const double* psi, const double* veff, const double* w,
+                    int n_orb, double* eps, double theta, int degree, int precision,
+                    double* psi_out, double* resid, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_green_step: tree is NULL");
+  REQUIRE(psi && veff && w && psi_out && eps, "tagi_green_step: null argument");
+  REQUIRE(psi_out != psi, "tagi_green_step: psi_out must not alias psi");
+  REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb, "tagi_green_step: n_orb = %d out of range [1, %d]",
+          n_orb, kMaxOrb);
+  for (int o = 0; o < n_orb; ++o)
+    REQUIRE(std::isfinite(eps[o]) && eps[o] < 0.0,
+            "tagi_green_step: eps[%d] = %g must be finite and < 0", o, eps[o]);
+  REQUIRE(theta >= 0.0 && theta < 1.0, "tagi_green_step: theta = %g out of range [0, 1)", theta);
+  REQUIRE(degree >= 1 && degree <= kMaxDegree, "tagi_green_step: degree = %d out of range",
+          degree);
+  REQUIRE(precision == TAGI_FP64 || precision == TAGI_MIXED,
+          "tagi_green_step: unknown precision %d", precision);
+  return green_step(t, psi, veff, w, n_orb, eps, theta, degree, precision, psi_out, resid,
+                    (hipStream_t)stream);
+}
+
 int tagi_tree_set_orbital_block(tagi_tree* t, int ob) {
   g_err[0] = 0;
   REQUIRE(t, "tagi_tree_set_orbital_block: tree is NULL");
@@ -565,7 +586,8 @@ int tagi_tree_destroy(tagi_tree* t) {
                   &t->nd_first_child, &t->nd_n_child, &t->nd_geom, &t->nd_box, &t->leaf_node,
                   &t->ws, &t->fs, &t->qs, &t->far_off, &t->near_off, &t->far_id, &t->near_id,
                   &t->chunks, &t->items, &t->item_order, &t->group_first_item, &t->batch_group_base,
-                  &t->batch_chunks, &t->partial, &t->kappa_dev};
+                  &t->batch_chunks, &t->partial, &t->kappa_dev, &t->green_f, &t->green_phi,
+                  &t->green_part};
   for (DBuf* b : bufs) b->release();
   t->px.release();
   for (ProxySet& ps : t->lx) ps.release();

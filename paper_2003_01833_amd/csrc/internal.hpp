@@ -162,6 +162,8 @@ struct tagi_tree {
   tagi::DBuf batch_chunks;          // int2 [n_leaves] {first chunk, n chunks}
   tagi::DBuf partial;               // double partial sums per item
   tagi::DBuf kappa_dev;             // double [n_orb]
+  // Green-iteration step: V psi, the convolution, reduction partials
+  tagi::DBuf green_f, green_phi, green_part;
 
   // phase timing (HIP events on the calls' stream)
   bool timing = false;
@@ -210,6 +212,9 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
 int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,
                      const float* params, const float* norm, const double* tol, double theta_max,
                      double theta_fb, int degree_fb, int precision, double* out, hipStream_t s);
+int green_step(tagi_tree* t, const double* psi, const double* veff, const double* w, int n_orb,
+               double* eps, double theta, int degree, int precision, double* psi_out,
+               double* resid, hipStream_t s);
 int selector_param_count();
 // l1 norms of one charge set of a proxy set (set < n_orb: orbital, set == n_orb:
 // the weights' charges), written to out[node] for every slot's node

@@ -78,4 +78,7 @@ def test_validation_rejects_before_any_device_work():
     assert lib.tagi_autotune(bogus, bogus, bogus, bogus, 10, None, bogus, 1, 0, bogus, 1.0, 0.5, 4,
                              0, leafs, 1, obs, 1, 1, best, None, None) == -1
     assert b"obs[0]" in lib.tagi_last_error()
+    lib.tagi_green_step.argtypes = [vp, vp, vp, vp, i32, vp, dbl, i32, i32, vp, vp, vp]
+    eps = (ctypes.c_double * 1)(-1.0)
+    assert lib.tagi_green_step(None, bogus, bogus, bogus, 1, eps, 0.7, 6, 0, bogus, None, None) == -1
     assert lib.tagi_tree_destroy(None) == 0
