@@ -368,6 +368,15 @@ int tagi_convolve_learned(tagi_tree* tree, int kernel, const double* kappa, doub
                           double theta_max, double theta_fb, int degree_fb, int precision,
                           double* out, void* stream);
 int tagi_learned_stats(const tagi_tree* tree, int64_t* out);
+/*
+ * Copies the lists of the last tagi_convolve_learned to HOST buffers:
+ *   far_off [n_leaves+1], far_id / far_degree [far pairs] (per batch, grouped by
+ *   increasing degree, traversal order within a degree), near_off [n_leaves+1],
+ *   near_id [near pairs] (traversal order); sizes from tagi_learned_stats.
+ * Errors: TAGI_E_ARG, TAGI_E_STATE (no learned lists).
+ */
+int tagi_learned_lists_export(const tagi_tree* tree, int64_t* far_off, int32_t* far_id,
+                              int32_t* far_degree, int64_t* near_off, int32_t* near_id);
 int tagi_selector_param_count(void);
 int tagi_selector_samples(tagi_tree* tree, const double* f, const double* w, double kappa,
                           double theta_max, int64_t max_pairs, float* features, float* errors,

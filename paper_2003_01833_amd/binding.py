@@ -30,7 +30,8 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct", "t
             "tagi_tree_timing", "tagi_graph_create", "tagi_graph_launch", "tagi_graph_destroy",
             "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
             "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
-            "tagi_tree_set_orbital_block", "tagi_autotune", "tagi_green_step", "tagi_tree_destroy",
+            "tagi_tree_set_orbital_block", "tagi_autotune", "tagi_green_step",
+            "tagi_learned_lists_export", "tagi_tree_destroy",
             "tagi_last_error"]
 
 
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_tree_set_timing.argtypes = [vp, i32]
     lib.tagi_tree_set_orbital_block.argtypes = [vp, i32]
     lib.tagi_green_step.argtypes = [vp, vp, vp, vp, i32, vp, dbl, i32, i32, vp, vp, vp]
+    lib.tagi_learned_lists_export.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.tagi_autotune.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, vp, dbl, dbl, i32, i32,
                                   vp, i32, vp, i32, i32, vp, vp, vp]
     lib.tagi_graph_create.argtypes = [vp, vp, vp, i32, i32, i32, vp, dbl, dbl, i32, vp, vp,
@@ -230,6 +232,20 @@ class Tree:
         return {"far_pairs": int(a[0]), "near_pairs": int(a[1]), "far_interactions": int(a[2]),
                 "near_interactions": int(a[3]),
                 "far_pairs_by_degree": {d: int(a[4 + d]) for d in range(13) if a[4 + d]}}
+
+    def learned_lists(self) -> dict:
+        """tagi_learned_lists_export: per batch (in leaf order) the far entries
+        (node id, degree) and the near entries of the last learned convolution."""
+        st = self.learned_stats()
+        nl = self.stats()["n_leaves"]
+        fo, no = np.zeros(nl + 1, np.int64), np.zeros(nl + 1, np.int64)
+        fid = np.zeros(max(st["far_pairs"], 1), np.int32)
+        fdg = np.zeros(max(st["far_pairs"], 1), np.int32)
+        nid = np.zeros(max(st["near_pairs"], 1), np.int32)
+        _check(load_library().tagi_learned_lists_export(self._h, _hptr(fo), _hptr(fid), _hptr(fdg),
+                                                        _hptr(no), _hptr(nid)))
+        return {"far_off": fo, "far_id": fid[:st["far_pairs"]], "far_degree": fdg[:st["far_pairs"]],
+                "near_off": no, "near_id": nid[:st["near_pairs"]]}
 
     def selector_samples(self, f: torch.Tensor, w: torch.Tensor, kappa: float,
                          theta_max: float = 0.9, max_pairs: int = 50000, with_ids: bool = False):

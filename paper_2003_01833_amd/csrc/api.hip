@@ -378,6 +378,36 @@ int tagi_learned_stats(const tagi_tree* t, int64_t* o) {
   return TAGI_OK;
 }
 
+int tagi_learned_lists_export(const tagi_tree* t, int64_t* far_off, int32_t* far_id,
+                              int32_t* far_degree, int64_t* near_off, int32_t* near_id) {
+  g_err[0] = 0;
+  REQUIRE(t && far_off && near_off, "tagi_learned_lists_export: null argument");
+  const LearnedState& S = t->learned;
+  if (S.key.empty()) {
+    set_error("tagi_learned_lists_export: no learned lists on this tree");
+    return TAGI_E_STATE;
+  }
+  REQUIRE((far_id && far_degree) || S.n_far == 0, "tagi_learned_lists_export: null far arrays");
+  REQUIRE(near_id || S.n_near == 0, "tagi_learned_lists_export: null near array");
+  const int nl = (int)t->leaves.size();
+  constexpr int kDegMin = kLearnDegMin, kNDeg = kLearnDegMax - kLearnDegMin + 1;
+  constexpr int kSlots = kNDeg + 1;
+  int64_t f = 0, nn = 0;
+  for (int b = 0; b < nl; ++b) {
+    far_off[b] = f;
+    near_off[b] = nn;
+    for (int k = 0; k < kNDeg; ++k)
+      for (int64_t e = 0; e < S.h_cnt[(size_t)b * kSlots + k]; ++e, ++f) {
+        far_id[f] = S.h_fid[f];
+        far_degree[f] = kDegMin + k;
+      }
+    for (int64_t e = 0; e < S.h_cnt[(size_t)b * kSlots + kNDeg]; ++e, ++nn) near_id[nn] = S.h_nid[nn];
+  }
+  far_off[nl] = f;
+  near_off[nl] = nn;
+  return TAGI_OK;
+}
+
 int tagi_selector_param_count(void) { return selector_param_count(); }
 
 int tagi_selector_samples(tagi_tree* t, const double* f, const double* w, double kappa,

@@ -49,6 +49,7 @@ struct DBuf {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxDegree = 16;
 constexpr int kMaxOrb = 64;
+constexpr int kLearnDegMin = 4, kLearnDegMax = 12;  // degrees the learned selector chooses from
 
 struct HostNode {
   int32_t begin, end, parent, level, first_child, n_child;
@@ -92,6 +93,8 @@ struct LearnedState {
   DBuf far_id, near_id;             // int32 lists (far grouped by degree within a batch)
   DBuf chunks, items, group_first, group_base, batch_chunks, partial, item_lists;
   std::vector<int32_t> h_items, h_chunks, h_group_first, h_group_base, h_batch_chunks, h_lists;
+  std::vector<int64_t> h_cnt;       // host copies of the lists: [n_leaves][kDegSlots] counts,
+  std::vector<int32_t> h_fid, h_nid;  // far ids (grouped by degree per batch), near ids
   std::vector<int64_t> list_begin;  // per launch: offset into item_lists
   std::vector<int> list_degree;     // per launch: degree (0 = near items)
   int64_t n_items = 0;

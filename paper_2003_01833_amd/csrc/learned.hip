@@ -32,7 +32,7 @@ extern template void launch_interact_ob<TAGI_YUKAWA>(int, tagi_tree*, bool, cons
 namespace {
 using namespace ik;
 
-constexpr int kDegMin = 4, kDegMax = 12, kNDeg = kDegMax - kDegMin + 1;
+constexpr int kDegMin = kLearnDegMin, kDegMax = kLearnDegMax, kNDeg = kDegMax - kDegMin + 1;
 constexpr int kSlots = kNDeg + 1;  // per batch: far entries per degree, then near entries
 constexpr int kH = 64, kIn = 5, kOut = 9;
 constexpr int kNParam = (kIn * kH + kH) + 2 * (kH * kH + kH) + (kH * kOut + kOut);
@@ -367,7 +367,11 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
                        S.log.as<int32_t>(), d_nlog, d_off, S.far_id.as<int32_t>(),
                        S.near_id.as<int32_t>());
     TAGI_HIP(hipGetLastError());
-    std::vector<int32_t> fid(std::max<int64_t>(nf, 1)), nid(std::max<int64_t>(nnear, 1));
+    std::vector<int32_t>& fid = S.h_fid;
+    std::vector<int32_t>& nid = S.h_nid;
+    fid.assign(std::max<int64_t>(nf, 1), 0);
+    nid.assign(std::max<int64_t>(nnear, 1), 0);
+    S.h_cnt = h;
     if (nf) TAGI_HIP(hipMemcpyAsync(fid.data(), S.far_id.p, nf * 4, hipMemcpyDeviceToHost, s));
     if (nnear) TAGI_HIP(hipMemcpyAsync(nid.data(), S.near_id.p, nnear * 4, hipMemcpyDeviceToHost, s));
     TAGI_HIP(hipStreamSynchronize(s));
