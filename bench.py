@@ -232,11 +232,11 @@ def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samp
     res["batched_fp64"]["graph_replay_ms"] = ms_g
     res["batched_fp64"]["graph_equals_eager"] = bool(torch.equal(Ug, U))
     g.close()
-    # autotuned leaf size and orbital block (timed on the first four orbitals),
+    # autotuned leaf size and orbital block (timed on the first eight orbitals),
     # then the batched FP64 step with the pick on all orbitals
     _log("compare: autotuning N_L and the orbital block")
-    cand_leaf, cand_ob = (1000, 2000, 4000), (2, 4)
-    (leaf_t, ob_t), times = tagi.autotune(x, y, z, F[:4].contiguous(), w, "yukawa_ss", kap[:4],
+    cand_leaf, cand_ob = (2000, 4000), (4, 8)
+    (leaf_t, ob_t), times = tagi.autotune(x, y, z, F[:8].contiguous(), w, "yukawa_ss", kap[:8],
                                           theta, degree, leaf_sizes=cand_leaf, obs=cand_ob,
                                           box=(*DOMAIN[0], *DOMAIN[1]))
     tt = t if leaf_t == leaf else tagi.Tree(x, y, z, leaf_t, (*DOMAIN[0], *DOMAIN[1]))
@@ -248,7 +248,7 @@ def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samp
     U, ms = timed(tuned)
     res["batched_fp64_autotuned"] = {
         "ms": ms, **errors(U), "leaf_size": leaf_t, "orbital_block": ob_t,
-        "tuning_ms_per_step_4_orbitals": {f"N_L {a} OB {b}": float(times[i, j])
+        "tuning_ms_per_step_8_orbitals": {f"N_L {a} OB {b}": float(times[i, j])
                                           for i, a in enumerate(cand_leaf)
                                           for j, b in enumerate(cand_ob)}}
     tt.set_orbital_block(0)

@@ -265,9 +265,9 @@ int tagi_green_step(tagi_tree* tree, const double* psi, const double* veff, cons
  * loop of Algorithm 2): the interaction kernel evaluates the geometry of a pair
  * once for `ob` orbitals. ob = 1, 2, 4 or 8 fixes the width for every later
  * tagi_convolve / tagi_convolve_learned on the tree (the schedule is rebuilt on
- * the next call); ob = 0 restores the automatic choice (Yukawa kernels: 4 from
- * four orbitals up; Coulomb kernels: 8 from eight up; else the largest power
- * of two not above n_orb). Results do not depend on ob.
+ * the next call); ob = 0 restores the automatic choice: the largest power of
+ * two not above n_orb, capped at 4 for Yukawa kernels in mixed precision and at
+ * 8 otherwise. Results do not depend on ob.
  * Errors: TAGI_E_ARG.
  */
 int tagi_tree_set_orbital_block(tagi_tree* tree, int ob);

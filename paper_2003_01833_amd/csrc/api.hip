@@ -150,7 +150,7 @@ int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* k
   if (kernel == TAGI_COULOMB_SS)
     REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_convolve: alpha = %g must be > 0", alpha);
   hipStream_t s = (hipStream_t)stream;
-  const int ob = orbital_block_of(t, kernel);
+  const int ob = orbital_block_of(t, kernel, precision);
   const bool rebuild = !(t->list_theta == theta && t->list_degree == degree) ||
                        !(t->items_orb_block == ob && t->items_n_orb == t->n_orb && t->n_items > 0);
   if (rebuild) {

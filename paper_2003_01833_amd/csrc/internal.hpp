@@ -207,9 +207,9 @@ int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& node
 int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s);
 int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s);
 int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s);
-int orbital_block(int kernel, int n_orb);
+int orbital_block(int kernel, int n_orb, int precision);
 // the tree's orbital block for a kernel: its override if set, else the default
-int orbital_block_of(const tagi_tree* t, int kernel);
+int orbital_block_of(const tagi_tree* t, int kernel, int precision);
 int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
              double* out, hipStream_t s);
 int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,

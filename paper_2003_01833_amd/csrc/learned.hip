@@ -258,7 +258,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
   for (int o = 0; o < n_orb; ++o) key.push_back(tol[o]);
   for (int k = 0; k < 4 * kIn; ++k) key.push_back(norm[k]);
   for (int k = 0; k < kNParam; ++k) key.push_back(params[k]);
-  const int ob = orbital_block_of(t, kernel);
+  const int ob = orbital_block_of(t, kernel, precision);
   if (key != S.key) {
     phase_begin(t, kPhaseLists, s);
     S.key.clear();
@@ -429,33 +429,50 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       }
       bcount[b] = (int32_t)(S.h_chunks.size() / 4) - bfirst[b];
     }
+    S.h_batch_chunks.assign(2 * (size_t)nl, 0);
+    for (int b = 0; b < nl; ++b) {
+      S.h_batch_chunks[2 * b] = bfirst[b];
+      S.h_batch_chunks[2 * b + 1] = bcount[b];
+    }
+    auto up = [&](DBuf& buf, const std::vector<int32_t>& v) -> int {
+      TAGI_TRY(buf.ensure(std::max<size_t>(v.size(), 1) * 4));
+      if (!v.empty()) TAGI_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+      return TAGI_OK;
+    };
+    TAGI_TRY(up(S.chunks, S.h_chunks));
+    TAGI_TRY(up(S.batch_chunks, S.h_batch_chunks));
+    TAGI_HIP(hipStreamSynchronize(s));
+    S.key = key;
+    S.ob = 0;  // the items below depend on the orbital block
+    phase_end(t, kPhaseLists, s);
+  }
+  if (S.ob != ob) {
     // items (batch, group, orbital block, chunk); launch lists per degree and near
     const int n_ob = (n_orb + ob - 1) / ob;
     S.h_items.clear();
     S.h_group_first.clear();
     S.h_group_base.assign(nl, 0);
-    S.h_batch_chunks.assign(2 * (size_t)nl, 0);
     std::vector<std::vector<int32_t>> per(kNDeg + 1);
     for (int b = 0; b < nl; ++b) {
       const HostNode& q = t->nodes[t->leaves[b]];
       const int ng = (q.end - q.begin + kWave - 1) / kWave;
+      const int32_t* bch = S.h_batch_chunks.data();  // {first chunk, n chunks} per batch
       S.h_group_base[b] = (int32_t)S.h_group_first.size();
-      S.h_batch_chunks[2 * b] = bfirst[b];
-      S.h_batch_chunks[2 * b + 1] = bcount[b];
+      const int bf = bch[2 * b], bc = bch[2 * b + 1];
       for (int g = 0; g < ng; ++g) {
         S.h_group_first.push_back((int32_t)(S.h_items.size() / 4));
         for (int o = 0; o < n_ob; ++o)
-          for (int cidx = 0; cidx < bcount[b]; ++cidx)
-            S.h_items.insert(S.h_items.end(), {b, g, o, bfirst[b] + cidx});
+          for (int cidx = 0; cidx < bc; ++cidx)
+            S.h_items.insert(S.h_items.end(), {b, g, o, bf + cidx});
       }
       // launch order within the batch: chunk-major, the target groups that read
       // the same sources side by side
       for (int o = 0; o < n_ob; ++o)
-        for (int cidx = 0; cidx < bcount[b]; ++cidx) {
-          const int kindv = S.h_chunks[(size_t)(bfirst[b] + cidx) * 4];
+        for (int cidx = 0; cidx < bc; ++cidx) {
+          const int kindv = S.h_chunks[(size_t)(bf + cidx) * 4];
           const int slot = kindv == 1 ? kNDeg : kindv - 16 - kDegMin;
           for (int g = 0; g < ng; ++g)
-            per[slot].push_back(S.h_group_first[S.h_group_base[b] + g] + o * bcount[b] + cidx);
+            per[slot].push_back(S.h_group_first[S.h_group_base[b] + g] + o * bc + cidx);
         }
     }
     S.n_items = (int64_t)S.h_items.size() / 4;
@@ -474,17 +491,13 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       if (!v.empty()) TAGI_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
       return TAGI_OK;
     };
-    TAGI_TRY(up(S.chunks, S.h_chunks));
     TAGI_TRY(up(S.items, S.h_items));
     TAGI_TRY(up(S.group_first, S.h_group_first));
     TAGI_TRY(up(S.group_base, S.h_group_base));
-    TAGI_TRY(up(S.batch_chunks, S.h_batch_chunks));
     TAGI_TRY(up(S.item_lists, S.h_lists));
     TAGI_TRY(S.partial.ensure(std::max<int64_t>(S.n_items, 1) * ob * 2 * kWave * sizeof(double)));
     TAGI_HIP(hipStreamSynchronize(s));
     S.ob = ob;
-    S.key = key;
-    phase_end(t, kPhaseLists, s);
   }
   // proxy charges at every degree in use, from the current tree-ordered values
   const bool mix = precision == TAGI_MIXED;

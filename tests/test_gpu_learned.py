@@ -74,3 +74,30 @@ def test_learned_lists_match_oracle_traversal():
         degrees.update(dg for _, dg in of)
     assert len(degrees) >= 3, degrees  # the selection is not degenerate
     t.close()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector weights")
+def test_learned_precisions_share_lists_and_agree():
+    # FP64 and mixed calls on one tree use different orbital blocks (8 and 4 for
+    # nine orbitals): each call must run on a schedule built for its own block
+    import paper_2003_01833_amd as tagi
+    from paper_2003_01833_amd.selector import Selector
+    sel = Selector.load(WEIGHTS)
+    d = atom_mesh(tol_m=1e-5, p=5, uniform_levels=2)
+    x, y, z, w = d["x"], d["y"], d["z"], d["w"]
+    r = np.sqrt(x * x + y * y + z * z)
+    F = np.stack([_slater(r, 60 + o) for o in range(9)])
+    kap = np.linspace(0.7, 3.5, 9)
+    tol = 3e-9 * 4 * np.pi / kap ** 2 * np.abs(F).max(axis=1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    t = tagi.Tree(dev(x), dev(y), dev(z), 300)
+    t.upward(dev(F), dev(w), 1)
+    u64 = t.convolve_learned("yukawa_ss", kap, sel, tol).clone()
+    u32 = t.convolve_learned("yukawa_ss", kap, sel, tol, precision="mixed").clone()
+    u64b = t.convolve_learned("yukawa_ss", kap, sel, tol)
+    assert torch.equal(u64, u64b)
+    # a stale schedule gives errors of order one; the FP32 far field alone stays
+    # far below 1e-4 of max|u| here
+    err = ((u32 - u64).abs().amax(dim=1) / u64.abs().amax(dim=1)).cpu().numpy()
+    assert err.max() < 1e-4, err
+    t.close()
