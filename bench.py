@@ -441,6 +441,23 @@ def main():
         "batched_mixed_vs_plain": comparison,
     }
     line["roofline"]["traffic"] = counter_traffic(line["config"])
+    # the upward pass (proxy charges), against both the FP64 and the HBM roofline.
+    # Per (source, approximable cluster) pair: barycentric basis values in three
+    # dimensions, 4 flops per node (difference, divide, sum, normalise), the
+    # (n+1)^2 products L_k1 L_k2, and one multiply-add per coefficient and charge
+    # set; bytes: the source's coordinates and charges read once per cluster it
+    # belongs to, and the proxy charges written once.
+    up_flops = up_bytes = 0.0
+    for c, st in zip(fields, sts):
+        p1 = c["degree"] + 1
+        sets = 2  # f w and w
+        up_flops += st["upward_points"] * (12 * p1 + p1 * p1 + 2 * sets * p1 ** 3)
+        up_bytes += st["upward_points"] * 8 * (3 + sets) + st["n_approx"] * 8 * sets * p1 ** 3
+    up_s = phases["upward_ms"] / 1e3
+    line["upward"] = {"ms_per_step": phases["upward_ms"],
+                      "tflops": up_flops / up_s / 1e12,
+                      "frac_fp64": up_flops / up_s / 1e12 / FP64_PEAK_TFLOPS,
+                      "gbs": up_bytes / up_s / 1e9, "frac_hbm": up_bytes / up_s / 1e9 / 8000.0}
     print(json.dumps(line), flush=True)
 
 

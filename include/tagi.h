@@ -89,6 +89,8 @@ typedef struct {
   int64_t far_interactions;  /* sum over far pairs of |B| (n+1)^3, one orbital */
   int64_t near_interactions; /* sum over near pairs of |B| N_S, one orbital */
   int64_t n_work_items;  /* compute work items of the cached schedule */
+  int64_t upward_points; /* sum of N_S over the clusters holding proxy charges: the
+                            (source, cluster) pairs of the last tagi_upward */
 } tagi_stats;
 
 /*

@@ -48,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("n_orb", ctypes.c_int32), ("n_approx", ctypes.c_int32),
                 ("theta", ctypes.c_double), ("n_far_pairs", ctypes.c_int64),
                 ("n_near_pairs", ctypes.c_int64), ("far_interactions", ctypes.c_int64),
-                ("near_interactions", ctypes.c_int64), ("n_work_items", ctypes.c_int64)]
+                ("near_interactions", ctypes.c_int64), ("n_work_items", ctypes.c_int64),
+                ("upward_points", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

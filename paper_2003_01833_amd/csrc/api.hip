@@ -201,6 +201,7 @@ int tagi_tree_stats(const tagi_tree* t, tagi_stats* o) {
   o->far_interactions = t->list_degree >= 0 ? t->far_inter : 0;
   o->near_interactions = t->list_degree >= 0 ? t->near_inter : 0;
   o->n_work_items = t->n_items;
+  for (int32_t c : t->px.nodes) o->upward_points += t->nodes[c].end - t->nodes[c].begin;
   return TAGI_OK;
 }
 

@@ -142,6 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_upward(
       }
     }
     __syncthreads();
+#pragma unroll 4
     for (int p = 0; p < cnt; ++p) {
       const int64_t j = p0 + p;
       double q[MB];
@@ -193,10 +194,31 @@ void launch_upward(hipStream_t s, tagi_tree* t, ProxySet& ps, int m0, int n_sets
                      ps.pnodes32.as<float>());
 }
 
+// charge sets per pass that R coefficient rounds leave registers for
+constexpr int max_sets(int R) { return R <= 3 ? 8 : (R <= 6 ? 4 : (R <= 10 ? 2 : 1)); }
+
 int charge_blocking(int K, int* R_out) {
   const int R = (K + kThreads - 1) / kThreads;
   *R_out = R;
-  return R <= 3 ? 8 : (R <= 6 ? 4 : (R <= 10 ? 2 : 1));
+  return max_sets(R);
+}
+
+// charge sets per pass for n_sets sets in all: no wider than the sets present
+int charge_block(int K, int n_sets, int* R_out) {
+  int mb = charge_blocking(K, R_out);
+  while (mb > 1 && mb / 2 >= n_sets) mb /= 2;
+  return mb;
+}
+
+template <int R>
+void launch_upward_r(int MB, hipStream_t s, tagi_tree* t, ProxySet& ps, int m0, int n_sets) {
+  if constexpr (max_sets(R) >= 8)
+    if (MB == 8) return launch_upward<R, 8>(s, t, ps, m0, n_sets);
+  if constexpr (max_sets(R) >= 4)
+    if (MB == 4) return launch_upward<R, 4>(s, t, ps, m0, n_sets);
+  if constexpr (max_sets(R) >= 2)
+    if (MB == 2) return launch_upward<R, 2>(s, t, ps, m0, n_sets);
+  launch_upward<R, 1>(s, t, ps, m0, n_sets);
 }
 
 }  // namespace
@@ -263,23 +285,23 @@ int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s) {
   const int K = np1 * np1 * np1;
   const int n_sets_total = ps.n_orb + 1;
   int R;
-  const int MB = charge_blocking(K, &R);
+  const int MB = charge_block(K, n_sets_total, &R);
   const int32_t* d_slot_first =
       reinterpret_cast<const int32_t*>(ps.items.as<char>() + (size_t)ps.n_items * sizeof(UpItem));
   for (int m0 = 0; m0 < n_sets_total; m0 += MB) {
     const int n_sets = std::min(MB, n_sets_total - m0);
     switch (R) {
-      case 1: launch_upward<1, 8>(s, t, ps, m0, n_sets); break;
-      case 2: launch_upward<2, 8>(s, t, ps, m0, n_sets); break;
-      case 3: launch_upward<3, 8>(s, t, ps, m0, n_sets); break;
-      case 4: launch_upward<4, 4>(s, t, ps, m0, n_sets); break;
-      case 5: launch_upward<5, 4>(s, t, ps, m0, n_sets); break;
-      case 6: launch_upward<6, 4>(s, t, ps, m0, n_sets); break;
-      case 7: launch_upward<7, 2>(s, t, ps, m0, n_sets); break;
-      case 8: launch_upward<8, 2>(s, t, ps, m0, n_sets); break;
-      case 9: launch_upward<9, 2>(s, t, ps, m0, n_sets); break;
-      case 10: launch_upward<10, 2>(s, t, ps, m0, n_sets); break;
-      default: launch_upward<20, 1>(s, t, ps, m0, n_sets); break;
+      case 1: launch_upward_r<1>(MB, s, t, ps, m0, n_sets); break;
+      case 2: launch_upward_r<2>(MB, s, t, ps, m0, n_sets); break;
+      case 3: launch_upward_r<3>(MB, s, t, ps, m0, n_sets); break;
+      case 4: launch_upward_r<4>(MB, s, t, ps, m0, n_sets); break;
+      case 5: launch_upward_r<5>(MB, s, t, ps, m0, n_sets); break;
+      case 6: launch_upward_r<6>(MB, s, t, ps, m0, n_sets); break;
+      case 7: launch_upward_r<7>(MB, s, t, ps, m0, n_sets); break;
+      case 8: launch_upward_r<8>(MB, s, t, ps, m0, n_sets); break;
+      case 9: launch_upward_r<9>(MB, s, t, ps, m0, n_sets); break;
+      case 10: launch_upward_r<10>(MB, s, t, ps, m0, n_sets); break;
+      default: launch_upward_r<20>(MB, s, t, ps, m0, n_sets); break;
     }
     TAGI_HIP(hipGetLastError());
     const int64_t tot = (int64_t)n_sets * K;
