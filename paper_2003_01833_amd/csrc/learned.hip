@@ -398,16 +398,22 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       }
     }
     // chunks (host): far segments per degree, then the near list, each cut by cost
-    const int64_t total = S.far_inter + 1;
+    // (kernel evaluations per target lane), at most 1/16384 of the whole
     S.h_chunks.clear();
     std::vector<int32_t> bfirst(nl), bcount(nl);
+    int64_t lane_cost = 0;
     for (int b = 0; b < nl; ++b) {
       const HostNode& q = t->nodes[t->leaves[b]];
       const int64_t nb = q.end - q.begin;
-      for (int64_t e = off[(size_t)b * kSlots + kNDeg]; e < off[(size_t)b * kSlots + kNDeg] + h[(size_t)b * kSlots + kNDeg]; ++e)
-        S.near_inter += nb * (t->nodes[nid[e]].end - t->nodes[nid[e]].begin);
+      for (int k = 0; k < kNDeg; ++k)
+        lane_cost += h[(size_t)b * kSlots + k] * (kDegMin + k + 1) * (kDegMin + k + 1) * (kDegMin + k + 1);
+      for (int64_t e = off[(size_t)b * kSlots + kNDeg]; e < off[(size_t)b * kSlots + kNDeg] + h[(size_t)b * kSlots + kNDeg]; ++e) {
+        const int64_t ns = t->nodes[nid[e]].end - t->nodes[nid[e]].begin;
+        S.near_inter += nb * ns;
+        lane_cost += ns;
+      }
     }
-    const int64_t ccap = std::max<int64_t>((total + S.near_inter / std::max<int64_t>(1, t->n / nl)) / 16384, 4096);
+    const int64_t ccap = std::max<int64_t>(lane_cost / 16384, 4096);
     for (int b = 0; b < nl; ++b) {
       bfirst[b] = (int32_t)(S.h_chunks.size() / 4);
       for (int k = 0; k <= kNDeg; ++k) {
