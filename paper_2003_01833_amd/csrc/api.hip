@@ -553,8 +553,9 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
     REQUIRE(obs[i] == 0 || obs[i] == 1 || obs[i] == 2 || obs[i] == 4 || obs[i] == 8,
             "tagi_autotune: obs[%d] = %d must be 0, 1, 2, 4 or 8", i, obs[i]);
   hipStream_t s = (hipStream_t)stream;
+  StreamScratch scratch(s);
   double* out = nullptr;
-  TAGI_HIP(hipMallocAsync((void**)&out, (size_t)n_orb * n * sizeof(double), s));
+  TAGI_TRY(scratch.alloc(&out, (size_t)n_orb * n));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int st = TAGI_OK;
   double best_ms = INFINITY;
@@ -604,7 +605,6 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  (void)hipFreeAsync(out, s);
   (void)hipStreamSynchronize(s);
   return st;
 }

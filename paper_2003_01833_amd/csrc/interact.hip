@@ -258,10 +258,11 @@ int direct(const double* sx, const double* sy, const double* sz, const double* s
   const int64_t sc_len = (ns + n_sc - 1) / n_sc;
   n_sc = (ns + sc_len - 1) / sc_len;
   // stream-ordered scratch: allocated and freed on `s`, so no host synchronisation
+  StreamScratch scratch(s);
   double* part = nullptr;
   double* q = nullptr;
-  TAGI_HIP(hipMallocAsync((void**)&part, (size_t)n_groups * n_sc * 2 * kWave * sizeof(double), s));
-  TAGI_HIP(hipMallocAsync((void**)&q, (size_t)ns * sizeof(double), s));
+  TAGI_TRY(scratch.alloc(&part, (size_t)n_groups * n_sc * 2 * kWave));
+  TAGI_TRY(scratch.alloc(&q, (size_t)ns));
   hipLaunchKernelGGL(k_charge, dim3((ns + 255) / 256), dim3(256), 0, s, sf, sw, ns, q);
   const double ia2 = kernel == TAGI_COULOMB_SS ? 1.0 / (alpha * alpha) : 0.0;
   const int64_t waves = n_groups * n_sc;
@@ -283,8 +284,6 @@ int direct(const double* sx, const double* sy, const double* sz, const double* s
   hipLaunchKernelGGL(k_direct_combine, dim3((nt + 255) / 256), dim3(256), 0, s, nt, (int)n_sc, ss,
                      self, tf, part, out);
   TAGI_HIP(hipGetLastError());
-  TAGI_HIP(hipFreeAsync(q, s));
-  TAGI_HIP(hipFreeAsync(part, s));
   return TAGI_OK;
 }
 

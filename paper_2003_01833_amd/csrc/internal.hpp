@@ -44,6 +44,37 @@ struct DBuf {
 };
 
 // ---------------------------------------------------------------------------
+// stream-ordered device scratch: allocated with hipMallocAsync and freed on the
+// same stream when the holder goes out of scope, early error returns included
+
+class StreamScratch {
+ public:
+  explicit StreamScratch(hipStream_t s) : s_(s) {}
+  StreamScratch(const StreamScratch&) = delete;
+  StreamScratch& operator=(const StreamScratch&) = delete;
+  ~StreamScratch() {
+    for (void* p : ptrs_) (void)hipFreeAsync(p, s_);
+  }
+  template <class T>
+  int alloc(T** out, size_t count) {
+    void* p = nullptr;
+    const hipError_t e = hipMallocAsync(&p, count * sizeof(T) + (count == 0 ? 8 : 0), s_);
+    if (e != hipSuccess) {
+      set_error("hipMallocAsync(%zu bytes) failed: %s", count * sizeof(T), hipGetErrorString(e));
+      (void)hipGetLastError();
+      return e == hipErrorOutOfMemory ? TAGI_E_OOM : TAGI_E_HIP;
+    }
+    ptrs_.push_back(p);
+    *out = static_cast<T*>(p);
+    return TAGI_OK;
+  }
+
+ private:
+  hipStream_t s_;
+  std::vector<void*> ptrs_;
+};
+
+// ---------------------------------------------------------------------------
 // tree handle
 
 constexpr int kWave = 64;          // CDNA wavefront width

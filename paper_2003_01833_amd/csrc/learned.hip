@@ -113,7 +113,7 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
   const int b = blockIdx.x;
   const int B = L.leaf_node[b];
   const double rB = L.geom[B * 4 + 3];
-  int32_t* log = L.log + (int64_t)b * L.cap;
+  int32_t* blog = L.log + (int64_t)b * L.cap;
   int64_t c[kSlots];
   for (int k = 0; k < kSlots; ++k) c[k] = 0;
   int64_t nlog = 0;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
       sp += nc;
     } else {
       const int slot = kind == 0 ? deg - kDegMin : kNDeg;
-      if (lane == 0 && nlog < L.cap) log[nlog] = (C << 4) | slot;
+      if (lane == 0 && nlog < L.cap) blog[nlog] = (C << 4) | slot;
       ++nlog;
       ++c[slot];
     }

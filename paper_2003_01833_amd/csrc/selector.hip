@@ -310,10 +310,11 @@ static int mlp_batch_grad(const float* params, const float* X, const float* Y, c
 
 int selector_grad(const float* params, const float* X, const float* Y, const float* M, int64_t m,
                   float* grads, float* loss, hipStream_t s) {
+  StreamScratch scratch(s);
   float *acts = nullptr, *gbuf = nullptr, *lp = nullptr;
-  TAGI_HIP(hipMallocAsync((void**)&acts, (size_t)4 * m * kSelH * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&gbuf, (size_t)2 * m * kSelH * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&lp, (size_t)grid_of(m * kSelOut) * sizeof(float), s));
+  TAGI_TRY(scratch.alloc(&acts, (size_t)4 * m * kSelH));
+  TAGI_TRY(scratch.alloc(&gbuf, (size_t)2 * m * kSelH));
+  TAGI_TRY(scratch.alloc(&lp, (size_t)grid_of(m * kSelOut)));
   std::vector<float> hm(m * kSelOut);
   TAGI_HIP(hipMemcpyAsync(hm.data(), M, hm.size() * sizeof(float), hipMemcpyDeviceToHost, s));
   TAGI_HIP(hipStreamSynchronize(s));
@@ -330,9 +331,6 @@ int selector_grad(const float* params, const float* X, const float* Y, const flo
     for (float v : h) l += v;
     *loss = (float)l;
   }
-  TAGI_HIP(hipFreeAsync(acts, s));
-  TAGI_HIP(hipFreeAsync(gbuf, s));
-  TAGI_HIP(hipFreeAsync(lp, s));
   return st;
 }
 
@@ -344,18 +342,19 @@ int selector_train(float* params, const float* X, const float* Y, const float* M
     return TAGI_E_ARG;
   }
   const int np = selector_param_count();
+  StreamScratch scratch(s);
   float *acts, *gbuf, *lp, *grads, *mom, *vel, *bx, *by, *bm;
   int32_t* didx;
-  TAGI_HIP(hipMallocAsync((void**)&acts, (size_t)4 * batch * kSelH * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&gbuf, (size_t)2 * batch * kSelH * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&lp, (size_t)grid_of((int64_t)batch * kSelOut) * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&grads, np * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&mom, np * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&vel, np * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&bx, (size_t)batch * kSelIn * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&by, (size_t)batch * kSelOut * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&bm, (size_t)batch * kSelOut * sizeof(float), s));
-  TAGI_HIP(hipMallocAsync((void**)&didx, (size_t)(m + batch) * sizeof(int32_t), s));
+  TAGI_TRY(scratch.alloc(&acts, (size_t)4 * batch * kSelH));
+  TAGI_TRY(scratch.alloc(&gbuf, (size_t)2 * batch * kSelH));
+  TAGI_TRY(scratch.alloc(&lp, (size_t)grid_of((int64_t)batch * kSelOut)));
+  TAGI_TRY(scratch.alloc(&grads, (size_t)np));
+  TAGI_TRY(scratch.alloc(&mom, (size_t)np));
+  TAGI_TRY(scratch.alloc(&vel, (size_t)np));
+  TAGI_TRY(scratch.alloc(&bx, (size_t)batch * kSelIn));
+  TAGI_TRY(scratch.alloc(&by, (size_t)batch * kSelOut));
+  TAGI_TRY(scratch.alloc(&bm, (size_t)batch * kSelOut));
+  TAGI_TRY(scratch.alloc(&didx, (size_t)(m + batch)));
   TAGI_HIP(hipMemsetAsync(mom, 0, np * sizeof(float), s));
   TAGI_HIP(hipMemsetAsync(vel, 0, np * sizeof(float), s));
   // the order, followed by its first `batch` entries, so any window of `batch`
@@ -400,9 +399,6 @@ int selector_train(float* params, const float* X, const float* Y, const float* M
     if (loss_hist) loss_hist[ep] = (float)(ep_loss / std::max<int64_t>(nb, 1));
   }
   TAGI_HIP(hipGetLastError());
-  for (void* p : {(void*)acts, (void*)gbuf, (void*)lp, (void*)grads, (void*)mom, (void*)vel,
-                  (void*)bx, (void*)by, (void*)bm, (void*)didx})
-    TAGI_HIP(hipFreeAsync(p, s));
   TAGI_HIP(hipStreamSynchronize(s));
   return st;
 }
@@ -424,8 +420,9 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
   const int nn = (int)t->nodes.size();
   std::vector<float> l1f(nn, 0.0f), l1w(nn, 0.0f), fmaxb(nl, 0.0f);
   {
+    StreamScratch scratch(s);
     float* dbuf;
-    TAGI_HIP(hipMallocAsync((void**)&dbuf, (size_t)(2 * nn + nl) * sizeof(float), s));
+    TAGI_TRY(scratch.alloc(&dbuf, (size_t)(2 * nn + nl)));
     TAGI_HIP(hipMemsetAsync(dbuf, 0, (size_t)(2 * nn + nl) * sizeof(float), s));
     TAGI_TRY(l1_to_nodes(t->px, 0, dbuf, s));
     TAGI_TRY(l1_to_nodes(t->px, 1, dbuf + nn, s));
@@ -433,7 +430,7 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
     TAGI_HIP(hipMemcpyAsync(l1f.data(), dbuf, nn * sizeof(float), hipMemcpyDeviceToHost, s));
     TAGI_HIP(hipMemcpyAsync(l1w.data(), dbuf + nn, nn * sizeof(float), hipMemcpyDeviceToHost, s));
     TAGI_HIP(hipMemcpyAsync(fmaxb.data(), dbuf + 2 * nn, nl * sizeof(float), hipMemcpyDeviceToHost, s));
-    TAGI_HIP(hipFreeAsync(dbuf, s));
+    TAGI_HIP(hipStreamSynchronize(s));
   }
   std::vector<int32_t> leaf_index(nn, -1);
   for (int b = 0; b < nl; ++b) leaf_index[t->leaves[b]] = b;
@@ -479,18 +476,19 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
       pair_ids[2 * p + 1] = pairs[p].y;
     }
   }
+  StreamScratch scratch(s);
   int2* dp;
   double* exact;
   float* derr;
-  TAGI_HIP(hipMallocAsync((void**)&dp, np * sizeof(int2), s));
-  TAGI_HIP(hipMallocAsync((void**)&exact, (size_t)np * kSampleT * sizeof(double), s));
-  TAGI_HIP(hipMallocAsync((void**)&derr, (size_t)np * sizeof(float), s));
+  TAGI_TRY(scratch.alloc(&dp, (size_t)np));
+  TAGI_TRY(scratch.alloc(&exact, (size_t)np * kSampleT));
+  TAGI_TRY(scratch.alloc(&derr, (size_t)np));
   TAGI_HIP(hipMemcpyAsync(dp, pairs.data(), np * sizeof(int2), hipMemcpyHostToDevice, s));
   InteractArgs A = args_of(t);
   hipLaunchKernelGGL(k_pair_exact, dim3((np + 3) / 4), dim3(256), 0, s, dp, np, A, kappa, exact);
   TAGI_HIP(hipGetLastError());
   std::vector<float> e(np);
-  for (int d = 4; d <= 12 && true; ++d) {
+  for (int d = 4; d <= 12; ++d) {
     TAGI_TRY(upward(t, f, w, 1, d, s));
     A = args_of(t);
     hipLaunchKernelGGL(k_pair_approx, dim3((np + 3) / 4), dim3(256), 0, s, dp, np, A, kappa,
@@ -500,10 +498,6 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
     TAGI_HIP(hipStreamSynchronize(s));
     for (int p = 0; p < np; ++p) err[p * 9 + (d - 4)] = e[p];
   }
-  TAGI_HIP(hipFreeAsync(dp, s));
-  TAGI_HIP(hipFreeAsync(exact, s));
-  TAGI_HIP(hipFreeAsync(derr, s));
-  TAGI_HIP(hipStreamSynchronize(s));
   (void)nl;
   return TAGI_OK;
 }
