@@ -167,10 +167,28 @@ def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samp
     theta, degree = fp64
     from workloads.configs import DOMAIN, benzene_mesh, benzene_orbitals, sample_targets
     _log("compare: building the benzene mesh and 21 orbitals")
+    t0 = time.perf_counter()
     m = benzene_mesh()
+    cpu_mesh_ms = 1e3 * (time.perf_counter() - t0)
     orb = benzene_orbitals(m["x"], m["y"], m["z"])
     n = m["x"].size
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    # the same mesh built on the GPU (adaptive refinement and the quadrature points)
+    from workloads.configs import benzene_atoms
+    atoms = [(tuple(R), Z) for R, Z in benzene_atoms()]
+    gpu_mesh = lambda: tagi.mesh(DOMAIN[0], DOMAIN[1], 7, 5e-4, 4, atoms=atoms,  # noqa: E731
+                                 test="root_density_vext")
+    gpu_mesh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gx, gy, gz, gw, glo, _ = gpu_mesh()
+    torch.cuda.synchronize()
+    mesh_info = {"cells": int(glo.shape[0]), "points": int(gx.numel()),
+                 "gpu_ms": 1e3 * (time.perf_counter() - t0),
+                 "cpu_input_generator_ms": cpu_mesh_ms,
+                 "same_points_as_cpu": bool(np.array_equal(gx.cpu().numpy(), m["x"]) and
+                                            np.array_equal(gw.cpu().numpy(), m["w"]))}
+    del gx, gy, gz, gw
     x, y, z, w = dev(m["x"]), dev(m["y"]), dev(m["z"]), dev(m["w"])
     F = dev(orb["psi"])
     kap = orb["kappa"]
@@ -209,6 +227,7 @@ def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samp
         return U_plain
 
     res = {"workload": "benzene_mesh_21_orbitals", "n_points": n, "n_orb": n_orb,
+           "mesh_build": mesh_info,
            "leaf_size": leaf, "fp64_setting": {"theta": theta, "degree": degree},
            "mixed_setting": {"theta": mixed[0], "degree": mixed[1]}}
     _log("compare: plain per-orbital loop")

@@ -234,6 +234,42 @@ int tagi_graph_launch(tagi_graph* graph, void* stream);
 int tagi_graph_destroy(tagi_graph* graph);
 
 /*
+ * Adaptive cuboid mesh with tensor Fejer quadrature (Section 4.2), built on the
+ * GPU. From the domain box [lo3, hi3], `uniform_levels` rounds bisect every cell
+ * into eight; then each round replaces a cell C by its eight children C_i iff
+ * |int_C t - sum_i int_{C_i} t| >= tol_m (Eq. refinement_criterion), both by the
+ * Fejer rule on (p+1)^3 Chebyshev points of the first kind (Eq.
+ * Chebyshev_points), until no cell splits or `max_level` is reached. Cells that
+ * hold an atom strictly inside along some dimension are split there (atoms on
+ * vertices), cells with longest/shortest side > max_aspect are halved along the
+ * longest side, and the cells are sorted by (lo x, lo y, lo z, hi x, hi y, hi z).
+ *   atoms    HOST double [n_atoms][4] = x, y, z, Z (0 <= n_atoms <= 64)
+ *   test_fn  TAGI_TEST_DENSITY: t = sum_a Z_a^3/pi exp(-2 Z_a d_a) (hydrogenic
+ *            1s densities); TAGI_TEST_ROOT_DENSITY_VEXT: Eq. test_function,
+ *            t = sqrt(rho0) V_ext with that rho0 and V_ext = -sum_a Z_a / d_a
+ *   1 <= p <= 15, tol_m > 0, 0 <= uniform_levels <= 6,
+ *   uniform_levels <= max_level <= 40, max_aspect >= 1.
+ * Synchronises the stream. Points of a cell are c + h s_i per dimension
+ * (c, h: centre and half-width, s_i = cos((2i+1) pi / (2p+2))) with weights the
+ * products of h v_i (Fejer's first rule, Waldvogel 2006), x index slowest; cells
+ * in order. Errors: TAGI_E_ARG, TAGI_E_OOM, TAGI_E_HIP, TAGI_E_UNSUPPORTED
+ * (more than 2^31 points).
+ */
+typedef struct tagi_mesh tagi_mesh;
+enum tagi_mesh_test { TAGI_TEST_DENSITY = 0, TAGI_TEST_ROOT_DENSITY_VEXT = 1 };
+int tagi_mesh_build(const double* lo3, const double* hi3, int p, double tol_m,
+                    int uniform_levels, int max_level, const double* atoms, int n_atoms,
+                    int test_fn, double max_aspect, void* stream, tagi_mesh** out);
+/* HOST outputs: cells and points ((p+1)^3 per cell). */
+int tagi_mesh_info(const tagi_mesh* mesh, int64_t* n_cells, int64_t* n_points);
+/* HOST double [n_cells][3] each (NULL skips). */
+int tagi_mesh_cells(const tagi_mesh* mesh, double* lo, double* hi);
+/* DEVICE double [n_points] each: quadrature points and weights. */
+int tagi_mesh_points(const tagi_mesh* mesh, double* x, double* y, double* z, double* w,
+                     void* stream);
+int tagi_mesh_destroy(tagi_mesh* mesh);
+
+/*
  * One block step of Green Iteration (the iteration body of Algorithm 2, applied
  * to every wavefunction of the block at once) around the batched convolution:
  *   1. f_o = V_eff psi_o and psi'_o = G(eps_o) psi_o (Eqs. integral_operator,

@@ -31,7 +31,8 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct", "t
             "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
             "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
             "tagi_tree_set_orbital_block", "tagi_autotune", "tagi_green_step",
-            "tagi_learned_lists_export", "tagi_tree_destroy",
+            "tagi_learned_lists_export", "tagi_mesh_build", "tagi_mesh_info",
+            "tagi_mesh_cells", "tagi_mesh_points", "tagi_mesh_destroy", "tagi_tree_destroy",
             "tagi_last_error"]
 
 
@@ -88,6 +89,12 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_tree_set_orbital_block.argtypes = [vp, i32]
     lib.tagi_green_step.argtypes = [vp, vp, vp, vp, i32, vp, dbl, i32, i32, vp, vp, vp]
     lib.tagi_learned_lists_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tagi_mesh_build.argtypes = [vp, vp, i32, dbl, i32, i32, vp, i32, i32, dbl, vp,
+                                    ctypes.POINTER(vp)]
+    lib.tagi_mesh_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.tagi_mesh_cells.argtypes = [vp, vp, vp]
+    lib.tagi_mesh_points.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tagi_mesh_destroy.argtypes = [vp]
     lib.tagi_autotune.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, vp, dbl, dbl, i32, i32,
                                   vp, i32, vp, i32, i32, vp, vp, vp]
     lib.tagi_graph_create.argtypes = [vp, vp, vp, i32, i32, i32, vp, dbl, dbl, i32, vp, vp,
@@ -411,6 +418,34 @@ class GreenStep:
             self.close()
         except Exception:
             pass
+
+
+MESH_TESTS = {"density": 0, "root_density_vext": 1}
+
+
+def mesh(domain_lo, domain_hi, p: int, tol_m: float, uniform_levels: int = 3,
+         max_level: int = 40, atoms=(), test: str = "density", max_aspect: float = 2.0):
+    """tagi_mesh_build + tagi_mesh_points: (x, y, z, w) float64 CUDA tensors and
+    the cells (lo, hi) as numpy (n_cells, 3) arrays. atoms: ((x, y, z), Z) pairs."""
+    lib = load_library()
+    lo3 = np.ascontiguousarray(domain_lo, dtype=np.float64)
+    hi3 = np.ascontiguousarray(domain_hi, dtype=np.float64)
+    at = np.ascontiguousarray([[*a, Z] for a, Z in atoms], dtype=np.float64).reshape(-1, 4)
+    h = ctypes.c_void_p()
+    _check(lib.tagi_mesh_build(_hptr(lo3), _hptr(hi3), int(p), float(tol_m), int(uniform_levels),
+                               int(max_level), _hptr(at) if at.size else None, at.shape[0],
+                               MESH_TESTS[test], float(max_aspect), _stream(), ctypes.byref(h)))
+    try:
+        nc, npt = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.tagi_mesh_info(h, ctypes.byref(nc), ctypes.byref(npt)))
+        lo = np.empty((nc.value, 3))
+        hi = np.empty((nc.value, 3))
+        _check(lib.tagi_mesh_cells(h, _hptr(lo), _hptr(hi)))
+        out = [torch.empty(npt.value, dtype=torch.float64, device="cuda") for _ in range(4)]
+        _check(lib.tagi_mesh_points(h, *(_dptr(t, "out", npt.value) for t in out), _stream()))
+    finally:
+        lib.tagi_mesh_destroy(h)
+    return (*out, lo, hi)
 
 
 def autotune(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_sizes,

@@ -524,6 +524,74 @@ int tagi_green_step(tagi_tree* t, const double* psi, const double* veff, const d
                     (hipStream_t)stream);
 }
 
+int tagi_mesh_build(const double* lo3, const double* hi3, int p, double tol_m,
+                    int uniform_levels, int max_level, const double* atoms, int n_atoms,
+                    int test_fn, double max_aspect, void* stream, tagi_mesh** out) {
+  g_err[0] = 0;
+  REQUIRE(out, "tagi_mesh_build: out is NULL");
+  *out = nullptr;
+  REQUIRE(lo3 && hi3, "tagi_mesh_build: null domain");
+  for (int d = 0; d < 3; ++d)
+    REQUIRE(std::isfinite(lo3[d]) && std::isfinite(hi3[d]) && lo3[d] < hi3[d],
+            "tagi_mesh_build: domain dimension %d is empty or not finite", d);
+  REQUIRE(p >= 1 && p <= kMeshMaxP, "tagi_mesh_build: p = %d out of range [1, %d]", p, kMeshMaxP);
+  REQUIRE(std::isfinite(tol_m) && tol_m > 0.0, "tagi_mesh_build: tol_m = %g must be > 0", tol_m);
+  REQUIRE(uniform_levels >= 0 && uniform_levels <= 6,
+          "tagi_mesh_build: uniform_levels = %d out of range [0, 6]", uniform_levels);
+  REQUIRE(max_level >= uniform_levels && max_level <= 40,
+          "tagi_mesh_build: max_level = %d out of range [uniform_levels, 40]", max_level);
+  REQUIRE(n_atoms >= 0 && n_atoms <= 64, "tagi_mesh_build: n_atoms = %d out of range [0, 64]",
+          n_atoms);
+  REQUIRE(n_atoms == 0 || atoms, "tagi_mesh_build: atoms is NULL");
+  for (int a = 0; a < n_atoms; ++a)
+    for (int k = 0; k < 4; ++k)
+      REQUIRE(std::isfinite(atoms[4 * a + k]), "tagi_mesh_build: atom %d is not finite", a);
+  REQUIRE(test_fn == TAGI_TEST_DENSITY || test_fn == TAGI_TEST_ROOT_DENSITY_VEXT,
+          "tagi_mesh_build: unknown test function %d", test_fn);
+  REQUIRE(max_aspect >= 1.0, "tagi_mesh_build: max_aspect = %g must be >= 1", max_aspect);
+  tagi_mesh* m = nullptr;
+  const int st = mesh_build(lo3, hi3, p, tol_m, uniform_levels, max_level, atoms, n_atoms,
+                            test_fn, max_aspect, (hipStream_t)stream, &m);
+  if (st != TAGI_OK) return st;
+  const int64_t q = p + 1;
+  if ((int64_t)(m->lo.size() / 3) * q * q * q >= (int64_t)INT32_MAX) {
+    delete m;
+    set_error("tagi_mesh_build: the mesh has 2^31 points or more");
+    return TAGI_E_UNSUPPORTED;
+  }
+  *out = m;
+  return TAGI_OK;
+}
+
+int tagi_mesh_info(const tagi_mesh* m, int64_t* n_cells, int64_t* n_points) {
+  g_err[0] = 0;
+  REQUIRE(m && n_cells && n_points, "tagi_mesh_info: null argument");
+  const int64_t q = m->p + 1;
+  *n_cells = (int64_t)m->lo.size() / 3;
+  *n_points = *n_cells * q * q * q;
+  return TAGI_OK;
+}
+
+int tagi_mesh_cells(const tagi_mesh* m, double* lo, double* hi) {
+  g_err[0] = 0;
+  REQUIRE(m, "tagi_mesh_cells: mesh is NULL");
+  if (lo) std::memcpy(lo, m->lo.data(), m->lo.size() * sizeof(double));
+  if (hi) std::memcpy(hi, m->hi.data(), m->hi.size() * sizeof(double));
+  return TAGI_OK;
+}
+
+int tagi_mesh_points(const tagi_mesh* m, double* x, double* y, double* z, double* w,
+                     void* stream) {
+  g_err[0] = 0;
+  REQUIRE(m && x && y && z && w, "tagi_mesh_points: null argument");
+  return mesh_points(m, x, y, z, w, (hipStream_t)stream);
+}
+
+int tagi_mesh_destroy(tagi_mesh* m) {
+  delete m;
+  return TAGI_OK;
+}
+
 int tagi_tree_set_orbital_block(tagi_tree* t, int ob) {
   g_err[0] = 0;
   REQUIRE(t, "tagi_tree_set_orbital_block: tree is NULL");

@@ -81,6 +81,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxDegree = 16;
 constexpr int kMaxOrb = 64;
 constexpr int kLearnDegMin = 4, kLearnDegMax = 12;  // degrees the learned selector chooses from
+constexpr int kMeshMaxP = 15;                        // largest Fejer order of a mesh cell
 
 struct HostNode {
   int32_t begin, end, parent, level, first_child, n_child;
@@ -207,6 +208,14 @@ struct tagi_tree {
   int64_t interact_launches = 0;
 };
 
+// adaptive mesh: cells and the one-dimensional Fejer rule on [-1, 1]
+struct tagi_mesh {
+  int p = 0;
+  std::vector<double> lo, hi;  // [n_cells][3]
+  double nodes[tagi::kMeshMaxP + 1] = {};
+  double weights[tagi::kMeshMaxP + 1] = {};
+};
+
 namespace tagi {
 
 enum Phase { kPhaseUpward = 0, kPhaseLists = 1, kPhaseInteract = 2, kPhaseCombine = 3 };
@@ -246,6 +255,10 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
 int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,
                      const float* params, const float* norm, const double* tol, double theta_max,
                      double theta_fb, int degree_fb, int precision, double* out, hipStream_t s);
+int mesh_build(const double* lo, const double* hi, int p, double tol, int uniform_levels,
+               int max_level, const double* atoms, int n_atoms, int kind, double max_aspect,
+               hipStream_t s, tagi_mesh** out);
+int mesh_points(const tagi_mesh* m, double* x, double* y, double* z, double* w, hipStream_t s);
 int green_step(tagi_tree* t, const double* psi, const double* veff, const double* w, int n_orb,
                double* eps, double theta, int degree, int precision, double* psi_out,
                double* resid, hipStream_t s);
