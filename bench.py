@@ -187,7 +187,8 @@ def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samp
                  "gpu_ms": 1e3 * (time.perf_counter() - t0),
                  "cpu_input_generator_ms": cpu_mesh_ms,
                  "same_points_as_cpu": bool(np.array_equal(gx.cpu().numpy(), m["x"]) and
-                                            np.array_equal(gw.cpu().numpy(), m["w"]))}
+                                            np.allclose(gw.cpu().numpy(), m["w"], rtol=1e-15,
+                                                        atol=0))}
     del gx, gy, gz, gw
     x, y, z, w = dev(m["x"]), dev(m["y"]), dev(m["z"]), dev(m["w"])
     F = dev(orb["psi"])

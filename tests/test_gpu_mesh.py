@@ -39,6 +39,10 @@ def test_benzene_mesh_matches_oracle():
     got = tagi.mesh(DOMAIN[0], DOMAIN[1], 7, 5e-4, 4, atoms=atoms, test="root_density_vext")
     assert len(cells) == 8092
     _compare(cells, got, 7)
+    # the weights tile the domain: their sum is its volume, 40^3
+    w = got[3].cpu().numpy()
+    assert abs(w.sum() / 64000.0 - 1.0) < 1e-12
+    assert (w > 0).all()
 
 
 def test_small_mesh_and_argument_checks():
