@@ -132,6 +132,28 @@ int tagi_upward(tagi_tree* tree, const double* f, const double* w, int n_orb, in
                 void* stream);
 
 /*
+ * Hermite proxy charges, for the barycentric Hermite treecode that the paper's
+ * conclusions (Section 7) propose for the high-accuracy regime: the same
+ * clusters, points and charge sets as tagi_upward, but per dimension the
+ * interpolant matches values and first derivatives at the n+1 points, with
+ * A_k(t) = (1 - 2 c_k (t - s_k)) L_k(t)^2, B_k(t) = (t - s_k) L_k(t)^2 and
+ * c_k = sum_{m != k} 1/(s_k - s_m). Per point k and derivative pattern
+ * beta in {0,1}^3 (bit 0: x, bit 1: y, bit 2: z)
+ *     q^_{k,beta} = sum_{j in C} prod_d H^{beta_d}_{k_d}(y_{j,d}) q_j,  H^0 = A, H^1 = B,
+ * which interpolates the kernel to degree 2n+1 per dimension. A following
+ * tagi_convolve evaluates the far field as
+ *     sum_k sum_beta d^beta_y G(|y - x_i|) at y = s_k, times q^_{k,beta}
+ * (FP64 only: precision TAGI_MIXED then fails with TAGI_E_UNSUPPORTED), with the
+ * same lists, near field and subtraction as the Lagrange form. The next
+ * tagi_upward returns the tree to Lagrange charges.
+ *   f, w, n_orb  as for tagi_upward.
+ *   degree       1 <= n <= 7.
+ * Errors: TAGI_E_ARG, TAGI_E_OOM, TAGI_E_HIP.
+ */
+int tagi_upward_hermite(tagi_tree* tree, const double* f, const double* w, int n_orb, int degree,
+                        void* stream);
+
+/*
  * Algorithm 3, ComputePotential step (Section 6.3): for every target batch, ComputePotential
  * from the root with the MAC of Eq. MAC, (r_B + r_C) < theta R and
  * (n+1)^3 < N_S (r = half the diagonal of a shrunk box, R = distance between box
@@ -201,11 +223,13 @@ int tagi_lists_export(tagi_tree* tree, double theta, int degree, int64_t* far_of
                       int64_t* n_near, void* stream);
 
 /*
- * Copies the proxy data of the last tagi_upward to HOST buffers (NULL skips):
+ * Copies the proxy data of the last tagi_upward or tagi_upward_hermite to HOST
+ * buffers (NULL skips):
  *   cluster  int32 [n_approx]                     node id of each approximable cluster
  *   nodes    double [n_approx][3][degree+1]       Chebyshev points per dimension
- *   qhat     double [n_orb][n_approx][(degree+1)^3] proxy charges of f w (k1 slowest)
- *   what     double [n_approx][(degree+1)^3]      proxy charges of w
+ *   qhat     double [n_orb][n_approx][(degree+1)^3] proxy charges of f w (k1 slowest);
+ *            Hermite: [n_orb][n_approx][(degree+1)^3][8], pattern beta fastest
+ *   what     double [n_approx][(degree+1)^3]      proxy charges of w; Hermite: [..][8]
  * Errors: TAGI_E_ARG, TAGI_E_STATE, TAGI_E_HIP.
  */
 int tagi_upward_export(const tagi_tree* tree, int32_t* cluster, double* nodes, double* qhat,

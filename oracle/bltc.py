@@ -210,11 +210,14 @@ def proxy_charges(px, py, pz, q, lo, hi, n):
 # ----------------------------------------------------------------------------------
 # Section 6.3: Algorithm 3
 
-def interaction_lists(tree: Tree, theta: float, n: int):
+def interaction_lists(tree: Tree, theta: float, n: int, ncoef: int | None = None):
     """Per batch (leaf, in node order): (far clusters, near clusters) from
-    ComputePotential(B, root). Returns (batches, far, near)."""
+    ComputePotential(B, root). `ncoef` is the size part of the MAC (a cluster is
+    approximated only if ncoef < N_S), (n+1)^3 unless given. Returns (batches,
+    far, near)."""
     cen, rad = geometry(tree)
-    ncoef = (n + 1) ** 3
+    if ncoef is None:
+        ncoef = (n + 1) ** 3
     batches = tree.leaves()
     far, near = [], []
     for B in batches:

@@ -25,8 +25,10 @@ Algorithm 3 (tree, MAC, near field, subtraction by linearity):
       D_0 = g,  D_{m+1}(r) = (1/r) dD_m/dr.
   `radial_derivatives` holds D_0..D_3 of e^{-k r}/r, 1/r and e^{-r^2/a^2}/r,
   obtained by applying that recursion by hand.
-* The size part of the MAC stays (n+1)^3 < N_S: the approximation costs (n+1)^3
-  kernel evaluations (each with its derivatives), as in Algorithm 3.
+* The size part of the MAC counts charges: a cluster is approximated only if
+  8 (n+1)^3 < N_S, so that the approximation never carries more charges than the
+  direct sum has sources (Algorithm 3 compares the (n+1)^3 Lagrange charges with
+  N_S the same way).
 
 Here the Lagrange basis is the product formula prod_{m != k} (t - s_m)/(s_k - s_m)
 (the plain definition; the GPU uses the barycentric form), and the proxy charges
@@ -145,7 +147,7 @@ def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
     X, Y, Zs, W = x[perm], y[perm], z[perm], w[perm]
     F = f[:, perm]
     Q = F * W[None, :]
-    ncoef = (degree + 1) ** 3
+    ncoef = 8 * (degree + 1) ** 3
     nodes, fhat, what = {}, {}, {}
     for c in range(tree.n_nodes):
         if tree.count(c) > ncoef:
@@ -155,7 +157,7 @@ def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
             nodes[c] = nd
             fhat[c] = ch[:n_orb].reshape(n_orb, -1, 8)
             what[c] = ch[n_orb].reshape(-1, 8)
-    batches, far, near = bltc.interaction_lists(tree, theta, degree)
+    batches, far, near = bltc.interaction_lists(tree, theta, degree, ncoef)
     U = np.zeros((n_orb, N))
     for B, fl, nl in zip(batches, far, near):
         b0, b1 = tree.begin[B], tree.end[B]

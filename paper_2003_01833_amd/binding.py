@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 STATUS = {0: "TAGI_OK", -1: "TAGI_E_ARG", -2: "TAGI_E_STATE", -3: "TAGI_E_OOM",
           -4: "TAGI_E_HIP", -5: "TAGI_E_UNSUPPORTED"}
 
-EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_convolve", "tagi_direct", "tagi_tree_stats",
+EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_upward_hermite", "tagi_convolve", "tagi_direct", "tagi_tree_stats",
             "tagi_tree_export", "tagi_lists_export", "tagi_upward_export", "tagi_tree_set_timing",
             "tagi_tree_timing", "tagi_graph_create", "tagi_graph_launch", "tagi_graph_destroy",
             "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     lib.tagi_tree_build.argtypes = [vp, vp, vp, i64, vp, i32, vp, ctypes.POINTER(vp)]
     lib.tagi_upward.argtypes = [vp, vp, vp, i32, i32, vp]
+    lib.tagi_upward_hermite.argtypes = [vp, vp, vp, i32, i32, vp]
     lib.tagi_convolve.argtypes = [vp, vp, i32, vp, dbl, dbl, i32, i32, vp, vp]
     lib.tagi_direct.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, i64, i32, dbl, dbl, vp, vp]
     lib.tagi_tree_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -174,6 +175,7 @@ class Tree:
         self._h = h
         self.n_orb = 0
         self.degree = 0
+        self.interpolation = "lagrange"
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -186,12 +188,19 @@ class Tree:
         except Exception:
             pass
 
-    def upward(self, f: torch.Tensor, w: torch.Tensor, degree: int):
-        """Algorithm 3, proxy-charge step: proxy charges; f is (n,) or (n_orb, n)."""
+    def upward(self, f: torch.Tensor, w: torch.Tensor, degree: int,
+               interpolation: str = "lagrange"):
+        """Algorithm 3, proxy-charge step: proxy charges; f is (n,) or (n_orb, n).
+        interpolation "hermite" takes tagi_upward_hermite (values and derivatives)."""
         n_orb = 1 if f.dim() == 1 else f.shape[0]
-        _check(load_library().tagi_upward(self._h, _dptr(f, "f", n_orb * self.n),
-                                          _dptr(w, "w", self.n), n_orb, int(degree), _stream()))
+        if interpolation not in ("lagrange", "hermite"):
+            raise ValueError(f"unknown interpolation {interpolation!r}")
+        fn = load_library().tagi_upward if interpolation == "lagrange" else \
+            load_library().tagi_upward_hermite
+        _check(fn(self._h, _dptr(f, "f", n_orb * self.n), _dptr(w, "w", self.n), n_orb,
+                  int(degree), _stream()))
         self.n_orb, self.degree = n_orb, int(degree)
+        self.interpolation = interpolation
 
     def convolve(self, kernel: str, kappa, theta: float, degree: int | None = None,
                  alpha: float = 1.0, precision: str = "fp64", out: torch.Tensor | None = None):
@@ -269,6 +278,7 @@ class Tree:
                                                     _hptr(err), _hptr(ids), ctypes.byref(m),
                                                     _stream()))
         self.n_orb, self.degree = 1, 12
+        self.interpolation = "lagrange"
         k = m.value
         if with_ids:
             return feat[:k].copy(), err[:k].copy(), ids[:k].copy()
@@ -290,6 +300,7 @@ class Tree:
                                               _dptr(out, "out", n_orb * self.n), _hptr(res),
                                               _stream()))
         self.n_orb, self.degree = n_orb, int(degree)
+        self.interpolation = "lagrange"
         return out, e, res
 
     def set_orbital_block(self, ob: int = 0):
@@ -342,8 +353,9 @@ class Tree:
         na, p1 = st["n_approx"], st["degree"] + 1
         cl = np.empty(max(na, 1), np.int32)
         nodes = np.empty((max(na, 1), 3, p1))
-        qh = np.empty((st["n_orb"], max(na, 1), p1 ** 3))
-        wh = np.empty((max(na, 1), p1 ** 3))
+        npat = 8 if getattr(self, "interpolation", "lagrange") == "hermite" else 1
+        qh = np.empty((st["n_orb"], max(na, 1), p1 ** 3 * npat))
+        wh = np.empty((max(na, 1), p1 ** 3 * npat))
         _check(load_library().tagi_upward_export(self._h, _hptr(cl), _hptr(nodes), _hptr(qh),
                                                  _hptr(wh), _stream()))
         return dict(cluster=cl[:na], nodes=nodes[:na], qhat=qh[:, :na], what=wh[:na])

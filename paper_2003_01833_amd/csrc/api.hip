@@ -118,6 +118,18 @@ int tagi_upward(tagi_tree* t, const double* f, const double* w, int n_orb, int d
   return upward(t, f, w, n_orb, degree, (hipStream_t)stream);
 }
 
+int tagi_upward_hermite(tagi_tree* t, const double* f, const double* w, int n_orb, int degree,
+                        void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_upward_hermite: tree is NULL");
+  REQUIRE(f && w, "tagi_upward_hermite: null f or w");
+  REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb, "tagi_upward_hermite: n_orb = %d out of range [1, %d]",
+          n_orb, kMaxOrb);
+  REQUIRE(degree >= 1 && degree <= kMaxHermDegree,
+          "tagi_upward_hermite: degree = %d out of range [1, %d]", degree, kMaxHermDegree);
+  return upward(t, f, w, n_orb, degree, (hipStream_t)stream, true);
+}
+
 int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* kappa,
                   double alpha, double theta, int degree, int precision, double* out,
                   void* stream) {
@@ -151,7 +163,7 @@ int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* k
     REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_convolve: alpha = %g must be > 0", alpha);
   hipStream_t s = (hipStream_t)stream;
   const int ob = orbital_block_of(t, kernel, precision);
-  const bool rebuild = !(t->list_theta == theta && t->list_degree == degree) ||
+  const bool rebuild = !lists_current(t, theta, degree) ||
                        !(t->items_orb_block == ob && t->items_n_orb == t->n_orb && t->n_items > 0);
   if (rebuild) {
     phase_begin(t, kPhaseLists, s);
@@ -262,7 +274,8 @@ int tagi_upward_export(const tagi_tree* t, int32_t* cluster, double* nodes, doub
     return TAGI_E_STATE;
   }
   hipStream_t s = (hipStream_t)stream;
-  const size_t na = t->px.n_approx, np1 = t->degree + 1, K = np1 * np1 * np1;
+  const size_t na = t->px.n_approx, np1 = t->degree + 1;
+  const size_t K = (t->px.herm ? kHermPatterns : 1) * np1 * np1 * np1;
   if (cluster && na) std::memcpy(cluster, t->px.nodes.data(), na * 4);
   if (nodes && na)
     TAGI_HIP(hipMemcpyAsync(nodes, t->px.pnodes.p, na * 3 * np1 * 8, hipMemcpyDeviceToHost, s));

@@ -159,7 +159,7 @@ int green_step(tagi_tree* t, const double* psi, const double* veff, const double
   for (int o = 0; o < n_orb; ++o) kappa[o] = std::sqrt(-2.0 * eps[o]);
   TAGI_TRY(upward(t, f, w, n_orb, degree, s));
   const int ob = orbital_block_of(t, TAGI_YUKAWA_SS, precision);
-  if (!(t->list_theta == theta && t->list_degree == degree) ||
+  if (!lists_current(t, theta, degree) ||
       !(t->items_orb_block == ob && t->items_n_orb == n_orb && t->n_items > 0)) {
     phase_begin(t, kPhaseLists, s);
     int st = ensure_lists(t, theta, degree, s);

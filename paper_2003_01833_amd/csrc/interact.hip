@@ -15,6 +15,10 @@ extern template void launch_interact_ob<TAGI_YUKAWA_SS>(int, tagi_tree*, bool, c
 extern template void launch_interact_ob<TAGI_COULOMB_SS>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
 extern template void launch_interact_ob<TAGI_YUKAWA>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
 extern template void launch_interact_ob<TAGI_COULOMB>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_herm_ob<TAGI_YUKAWA_SS>(int, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_herm_ob<TAGI_COULOMB_SS>(int, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_herm_ob<TAGI_YUKAWA>(int, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_herm_ob<TAGI_COULOMB>(int, const InteractArgs&, const OrbArg&, hipStream_t);
 }  // namespace ik
 
 namespace {
@@ -129,6 +133,10 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   }
   const double ia2 = kernel == TAGI_COULOMB_SS ? 1.0 / (alpha * alpha) : 0.0;
   const bool mix = precision == TAGI_MIXED;
+  if (mix && t->px.herm) {
+    set_error("convolve: the mixed-precision far field takes Lagrange charges (tagi_upward)");
+    return TAGI_E_UNSUPPORTED;
+  }
   const int np1 = t->degree + 1;
   const int64_t K = (int64_t)np1 * np1 * np1;
   if (mix && t->px.n_approx > 0) {
@@ -177,11 +185,20 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   if (t->n_items > 0) {
     phase_begin(t, kPhaseInteract, s);
     ++t->interact_launches;
-    switch (kernel) {
-      case TAGI_YUKAWA_SS: launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, s); break;
-      case TAGI_COULOMB_SS: launch_interact_ob<TAGI_COULOMB_SS>(ob, t, mix, A, orb, s); break;
-      case TAGI_YUKAWA: launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, s); break;
-      default: launch_interact_ob<TAGI_COULOMB>(ob, t, mix, A, orb, s); break;
+    if (t->px.herm) {
+      switch (kernel) {
+        case TAGI_YUKAWA_SS: launch_interact_herm_ob<TAGI_YUKAWA_SS>(ob, A, orb, s); break;
+        case TAGI_COULOMB_SS: launch_interact_herm_ob<TAGI_COULOMB_SS>(ob, A, orb, s); break;
+        case TAGI_YUKAWA: launch_interact_herm_ob<TAGI_YUKAWA>(ob, A, orb, s); break;
+        default: launch_interact_herm_ob<TAGI_COULOMB>(ob, A, orb, s); break;
+      }
+    } else {
+      switch (kernel) {
+        case TAGI_YUKAWA_SS: launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, s); break;
+        case TAGI_COULOMB_SS: launch_interact_ob<TAGI_COULOMB_SS>(ob, t, mix, A, orb, s); break;
+        case TAGI_YUKAWA: launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, s); break;
+        default: launch_interact_ob<TAGI_COULOMB>(ob, t, mix, A, orb, s); break;
+      }
     }
     phase_end(t, kPhaseInteract, s);
     TAGI_HIP(hipGetLastError());
@@ -233,7 +250,9 @@ OrbArg make_orb(int kernel, int n_orb, const double* kappa, double alpha) {
 }  // namespace ik
 
 int orbital_block_of(const tagi_tree* t, int kernel, int precision) {
-  return t->ob_override ? t->ob_override : orbital_block(kernel, t->n_orb, precision);
+  const int ob = t->ob_override ? t->ob_override : orbital_block(kernel, t->n_orb, precision);
+  // the Hermite far field reads 8 charges per proxy point and set: at most 4 orbitals
+  return t->px.herm ? std::min(ob, 4) : ob;
 }
 
 int orbital_block(int kernel, int n_orb, int precision) {

@@ -321,6 +321,127 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
   }
 }
 
+// Far pairs of one cluster by Hermite interpolation (the Hermite treecode variant
+// of the conclusions, Section 7): per proxy point s_k eight charges, one per
+// derivative pattern beta of the source point, and
+//     sum_k sum_beta d^beta_y G(|y - x_i|)|_{y = s_k} q^_{k,beta}.
+// For a radial G and distinct coordinates d^beta_y G = D_|beta|(r) prod (s - x)_d
+// with D_0 = G and D_{m+1} = (1/r) dD_m/dr:
+//   e^{-k r}/r:     D_m = (-1)^m P_m(k r) e^{-k r} / r^{2m+1}, P_0 = 1, P_1 = 1 + p,
+//                   P_2 = 3 + 3p + p^2, P_3 = 15 + 15p + 6p^2 + p^3;
+//   1/r:            D_1 = -1/r^3, D_2 = 3/r^5, D_3 = -15/r^7;
+//   e^{-b r^2}/r:   D_1 = -E (1/r^3 + 2b/r), D_2 = E (3/r^5 + 4b/r^3 + 4b^2/r),
+//                   D_3 = -E (15/r^7 + 18b/r^5 + 12b^2/r^3 + 8b^3/r), b = 1/a^2.
+// The charges of one proxy point, taken with the geometric factors of their
+// patterns, reduce to four sums S_m (m = |beta|), so a set costs four FMAs with
+// the D_m per pair.
+template <int OB>
+constexpr int kHermStep = 1;
+
+struct HermGeo {
+  double g1, g2, g4, g3, g5, g6, g7;  // factors of the patterns x, y, z, xy, xz, yz, xyz
+};
+
+__device__ __forceinline__ void herm_sums(const HermGeo& g, const double* __restrict__ c,
+                                          double* S) {
+  S[0] = c[0];
+  S[1] = __builtin_fma(g.g1, c[1], __builtin_fma(g.g2, c[2], g.g4 * c[4]));
+  S[2] = __builtin_fma(g.g3, c[3], __builtin_fma(g.g5, c[5], g.g6 * c[6]));
+  S[3] = g.g7 * c[7];
+}
+
+__device__ __forceinline__ double herm_dot(const double* D, const double* S, double acc) {
+  return __builtin_fma(D[0], S[0],
+                       __builtin_fma(D[1], S[1], __builtin_fma(D[2], S[2], __builtin_fma(D[3], S[3], acc))));
+}
+
+template <int KER, int OB>
+__device__ __forceinline__ void herm_point(const HermGeo& g, double r2, const double* __restrict__ m8,
+                                           const double* const* q8, const double* nkap, double nia2,
+                                           double* a1, double* a2) {
+  const double rinv = rsqrt_pos(r2);
+  const double ri2 = rinv * rinv;
+  constexpr bool SS = KER == TAGI_YUKAWA_SS || KER == TAGI_COULOMB_SS;
+  double W[4] = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (SS) herm_sums(g, m8, W);
+  if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
+    const double r = r2 * rinv;
+#pragma unroll
+    for (int o = 0; o < OB; ++o) {
+      const double x = nkap[o] * r;  // -k r
+      const double p = -x;
+      double D[4];
+      D[0] = exp_nonpos(x) * rinv;
+      const double t1 = D[0] * ri2;
+      D[1] = -(p + 1.0) * t1;
+      const double t2 = t1 * ri2;
+      D[2] = __builtin_fma(p, p + 3.0, 3.0) * t2;
+      D[3] = -__builtin_fma(__builtin_fma(p + 6.0, p, 15.0), p, 15.0) * (t2 * ri2);
+      double S[4];
+      herm_sums(g, q8[o], S);
+      a1[o] = herm_dot(D, S, a1[o]);
+      if constexpr (SS) a2[o] = herm_dot(D, W, a2[o]);
+    }
+  } else {
+    const double t1 = rinv * ri2, t2 = t1 * ri2, t3 = t2 * ri2;
+    const double D[4] = {rinv, -t1, 3.0 * t2, -15.0 * t3};
+#pragma unroll
+    for (int o = 0; o < OB; ++o) {
+      double S[4];
+      herm_sums(g, q8[o], S);
+      a1[o] = herm_dot(D, S, a1[o]);
+    }
+    if constexpr (KER == TAGI_COULOMB_SS) {
+      const double b = -nia2;
+      const double E = exp_nonpos(r2 * nia2);
+      const double b2 = b * b;
+      double G[4];
+      G[0] = E * rinv;
+      G[1] = -E * __builtin_fma(2.0 * b, rinv, t1);
+      G[2] = E * __builtin_fma(3.0, t2, __builtin_fma(4.0 * b, t1, 4.0 * b2 * rinv));
+      G[3] = -E * __builtin_fma(15.0, t3, __builtin_fma(18.0 * b, t2,
+                                __builtin_fma(12.0 * b2, t1, 8.0 * b2 * b * rinv)));
+      a2[0] = herm_dot(G, W, a2[0]);
+    }
+  }
+}
+
+template <int KER, int OB, int NP1>
+__device__ __forceinline__ void far_cluster_herm(double xi, double yi, double zi, int np1_rt,
+                                                 const double* __restrict__ px,
+                                                 const double* __restrict__ wk,
+                                                 const double* const* qk, const double* nkap,
+                                                 double nia2, double* a1, double* a2) {
+  const int np1 = NP1 ? NP1 : np1_rt;
+  const double* py = px + np1;
+  const double* pz = py + np1;
+  int k = 0;
+  for (int k1 = 0; k1 < np1; ++k1) {
+    const double dx = px[k1] - xi;
+    for (int k2 = 0; k2 < np1; ++k2) {
+      const double dy = py[k2] - yi;
+      const double dxy2 = __builtin_fma(dy, dy, dx * dx);
+      const double pxy = dx * dy;
+      for (int h = 0; h < np1; h += kHermStep<OB>) {
+#pragma unroll
+        for (int u = 0; u < kHermStep<OB>; ++u) {
+          const int k3 = h + u;
+          if (kHermStep<OB> > 1 && k3 >= np1) break;
+          const double dz = pz[k3] - zi;
+          const HermGeo g{dx, dy, dz, pxy, dx * dz, dy * dz, pxy * dz};
+          const int kk = (k + k3) * kHermPatterns;
+          const double* q8[OB];
+#pragma unroll
+          for (int o = 0; o < OB; ++o) q8[o] = qk[o] + kk;
+          herm_point<KER, OB>(g, __builtin_fma(dz, dz, dxy2), wk + kk, q8, nkap, nia2, a1, a2);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      k += np1;
+    }
+  }
+}
+
 // Everything the interaction kernel reads, passed by value.
 struct InteractArgs {
   const int4* items;
@@ -350,16 +471,22 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * q + min(x, r) + b / kXcds;
 }
 
+// Far-field forms of the interaction kernel
+constexpr int kModeFp64 = 0, kModeMixed = 1, kModeHermite = 2;
+
 // Register budget in waves per SIMD: at least 5 for FP64 tiles and 6 for mixed
 // ones (measured 1-7% faster than the compiler's own allocation, which held 4).
-// The FP64 Coulomb far field (per-dimension Gaussian factors held in registers)
-// and blocks of 8 orbitals keep the compiler's allocation (1 = no bound), which
-// does not spill.
-template <int KER, int OB, bool MIX>
-constexpr int kWavesPerEu = (OB >= 8 || (KER == TAGI_COULOMB_SS && !MIX)) ? 1 : (MIX ? 6 : 5);
+// The FP64 Coulomb far field (per-dimension Gaussian factors held in registers),
+// blocks of 8 orbitals and the Hermite far field keep the compiler's allocation
+// (1 = no bound).
+template <int KER, int OB, int MODE>
+constexpr int kWavesPerEu =
+    (OB >= 8 || MODE == kModeHermite || (KER == TAGI_COULOMB_SS && MODE == kModeFp64))
+        ? 1
+        : (MODE == kModeMixed ? 6 : 5);
 
-template <int KER, int OB, int NP1, bool MIX>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<KER, OB, MIX>)))
+template <int KER, int OB, int NP1, int MODE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<KER, OB, MODE>)))
 void k_interact(InteractArgs A, OrbArg orb) {
   const int lane = threadIdx.x % kWave;
   const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
@@ -384,7 +511,7 @@ void k_interact(InteractArgs A, OrbArg orb) {
   double fi[OB];  // target values, for the FP64 subtracted charges of mixed tiles
 #pragma unroll
   for (int o = 0; o < OB; ++o) {
-    if constexpr (MIX && KER == TAGI_YUKAWA_SS)
+    if constexpr (MODE == kModeMixed && KER == TAGI_YUKAWA_SS)
       fi[o] = A.fs[(int64_t)orb_row[o] * A.n + i];
     else
       fi[o] = 0.0;
@@ -395,12 +522,12 @@ void k_interact(InteractArgs A, OrbArg orb) {
   const Chunk ch = A.chunks[item.w];
   if (ch.kind != 1) {  // far chunk (kind 0, or 16 + degree in learned lists)
     const int np1 = A.degree + 1;
-    const int K = np1 * np1 * np1;
+    const int K = (MODE == kModeHermite ? kHermPatterns : 1) * np1 * np1 * np1;
     for (int e = ch.e0; e < ch.e1; ++e) {
       const int C = A.far_id[e];
       const int slot = A.slot_of[C];
       if (slot < 0) continue;  // never taken: far clusters always hold proxy charges
-      if constexpr (MIX) {
+      if constexpr (MODE == kModeMixed) {
         constexpr double kLog2e = 0x1.71547652b82fep+0;
         float nkl2[OB];
         const float* qk[OB];
@@ -422,8 +549,12 @@ void k_interact(InteractArgs A, OrbArg orb) {
         const double* qk[OB];
 #pragma unroll
         for (int o = 0; o < OB; ++o) qk[o] = A.qhat + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
-        far_cluster<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
-                                  A.what + (int64_t)slot * K, qk, nkap, nia2, a1, a2);
+        if constexpr (MODE == kModeHermite)
+          far_cluster_herm<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
+                                         A.what + (int64_t)slot * K, qk, nkap, nia2, a1, a2);
+        else
+          far_cluster<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
+                                    A.what + (int64_t)slot * K, qk, nkap, nia2, a1, a2);
       }
     }
   } else {
@@ -464,9 +595,41 @@ void launch_interact(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg
   const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return;
   if (mix)
-    hipLaunchKernelGGL((k_interact<KER, OB, NP1, true>), dim3(blocks), dim3(kBlock), 0, s, A, orb);
+    hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeMixed>), dim3(blocks), dim3(kBlock), 0, s, A,
+                       orb);
   else
-    hipLaunchKernelGGL((k_interact<KER, OB, NP1, false>), dim3(blocks), dim3(kBlock), 0, s, A, orb);
+    hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeFp64>), dim3(blocks), dim3(kBlock), 0, s, A,
+                       orb);
+}
+
+// Hermite far field: degrees 1 .. kMaxHermDegree
+template <int KER, int OB, int NP1>
+void launch_interact_herm(const InteractArgs& A, const OrbArg& orb, hipStream_t s) {
+  const int64_t waves = A.item_list ? A.n_list : A.n_items;
+  const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeHermite>), dim3(blocks), dim3(kBlock), 0, s, A,
+                     orb);
+}
+
+template <int KER, int OB>
+void launch_interact_herm_np(const InteractArgs& A, const OrbArg& orb, hipStream_t s) {
+  switch (A.degree + 1) {
+    case 3: launch_interact_herm<KER, OB, 3>(A, orb, s); break;
+    case 4: launch_interact_herm<KER, OB, 4>(A, orb, s); break;
+    case 5: launch_interact_herm<KER, OB, 5>(A, orb, s); break;
+    case 6: launch_interact_herm<KER, OB, 6>(A, orb, s); break;
+    default: launch_interact_herm<KER, OB, 0>(A, orb, s); break;
+  }
+}
+
+template <int KER>
+void launch_interact_herm_ob(int ob, const InteractArgs& A, const OrbArg& orb, hipStream_t s) {
+  switch (ob) {
+    case 1: launch_interact_herm_np<KER, 1>(A, orb, s); break;
+    case 2: launch_interact_herm_np<KER, 2>(A, orb, s); break;
+    default: launch_interact_herm_np<KER, 4>(A, orb, s); break;
+  }
 }
 
 template <int KER, int OB>

@@ -82,6 +82,10 @@ constexpr int kMaxDegree = 16;
 constexpr int kMaxOrb = 64;
 constexpr int kLearnDegMin = 4, kLearnDegMax = 12;  // degrees the learned selector chooses from
 constexpr int kMeshMaxP = 15;                        // largest Fejer order of a mesh cell
+// Hermite proxy charges: per proxy point one charge per derivative pattern
+// beta in {0,1}^3 (bit 0: d/dx, bit 1: d/dy, bit 2: d/dz of the source point)
+constexpr int kHermPatterns = 8;
+constexpr int kMaxHermDegree = 7;
 
 struct HostNode {
   int32_t begin, end, parent, level, first_child, n_child;
@@ -94,14 +98,15 @@ struct ProxySet {
   int n_orb = 0;
   int n_approx = 0;                 // clusters ("slots") in the set
   int n_items = 0;                  // upward work items
+  bool herm = false;                // Hermite charges: 8 per proxy point (see kHermPatterns)
   std::vector<int32_t> nodes;       // host: node id per slot
   std::vector<int32_t> h_slot_of, h_items, h_slot_first;  // host staging for uploads
   DBuf slot_of;                     // int32 [n_nodes], -1 if the node has no slot
   DBuf node;                        // int32 [n_approx]
   DBuf pnodes;                      // double [n_approx][3][degree+1]
   DBuf pnodes32;                    // float [n_approx][3][degree+1], offsets from the cluster centre
-  DBuf qhat;                        // double [n_orb][n_approx][(degree+1)^3]
-  DBuf what;                        // double [n_approx][(degree+1)^3]
+  DBuf qhat;                        // double [n_orb][n_approx][(degree+1)^3], Hermite: [..][(degree+1)^3][8]
+  DBuf what;                        // double [n_approx][(degree+1)^3], Hermite: [..][(degree+1)^3][8]
   DBuf qhat32, what32;              // FP32 copies for mixed-precision tiles
   DBuf items, partial;              // upward work items (+ slot_first) and partial charges
   void release() {
@@ -109,6 +114,7 @@ struct ProxySet {
                     &partial})
       b->release();
     degree = n_orb = n_approx = n_items = 0;
+    herm = false;
   }
 };
 
@@ -178,6 +184,7 @@ struct tagi_tree {
   // cached interaction lists and compute schedule
   double list_theta = -1.0;
   int list_degree = -1;
+  bool list_herm = false;  // lists built with the Hermite size test 8 (n+1)^3 < N_S
   int64_t n_far = 0, n_near = 0;
   int64_t far_inter = 0, near_inter = 0;
   tagi::DBuf far_off, near_off;     // int64 [n_leaves+1]
@@ -218,6 +225,12 @@ struct tagi_mesh {
 
 namespace tagi {
 
+// the cached interaction lists serve (theta, degree) with the size test of the
+// current proxy charges
+inline bool lists_current(const tagi_tree* t, double theta, int degree) {
+  return t->list_theta == theta && t->list_degree == degree && t->list_herm == t->px.herm;
+}
+
 enum Phase { kPhaseUpward = 0, kPhaseLists = 1, kPhaseInteract = 2, kPhaseCombine = 3 };
 
 inline void phase_begin(tagi_tree* t, int ph, hipStream_t s) {
@@ -239,10 +252,11 @@ inline void phase_end(tagi_tree* t, int ph, hipStream_t s) {
 
 int build_tree(tagi_tree* t, const double* x, const double* y, const double* z,
                const double* box, hipStream_t s);
-int upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree, hipStream_t s);
+int upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree, hipStream_t s,
+           bool herm = false);
 // plan (host lists, uploads, buffers) of proxy charges at `degree` for `nodes`
 int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& nodes, int degree,
-                    int n_orb, hipStream_t s);
+                    int n_orb, hipStream_t s, bool herm = false);
 // proxy charges of the planned set from the tree-ordered q = f w and w
 int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s);
 int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s);

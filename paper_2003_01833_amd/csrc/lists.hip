@@ -127,7 +127,7 @@ __global__ void k_chunks(int n_leaves, const int32_t* __restrict__ nbeg,
 }  // namespace
 
 int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
-  if (t->list_theta == theta && t->list_degree == degree) return TAGI_OK;
+  if (lists_current(t, theta, degree)) return TAGI_OK;
   t->list_theta = -1.0;
   t->list_degree = -1;
   t->items_orb_block = 0;
@@ -135,6 +135,9 @@ int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
   const int nl = (int)t->leaves.size();
   const int np1 = degree + 1;
   const int K = np1 * np1 * np1;
+  // size part of the MAC: charges per approximated cluster, 8 per point for Hermite
+  const bool herm = t->px.herm;
+  const int K_mac = (herm ? kHermPatterns : 1) * K;
   DBuf cnt;
   TAGI_TRY(cnt.ensure((size_t)nl * 3 * sizeof(int64_t) + sizeof(int32_t)));
   int64_t* d_far_cnt = cnt.as<int64_t>();
@@ -145,7 +148,7 @@ int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
   const int blk = 128, grid = (nl + blk - 1) / blk;
   hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, t->leaf_node.as<int32_t>(),
                      t->nd_geom.as<double>(), t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(),
-                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K, 0,
+                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K_mac, 0,
                      d_far_cnt, d_near_cnt, d_near_src, nullptr, nullptr, nullptr, nullptr,
                      d_over);
   TAGI_HIP(hipGetLastError());
@@ -187,7 +190,7 @@ int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
                           hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, t->leaf_node.as<int32_t>(),
                      t->nd_geom.as<double>(), t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(),
-                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K, 1,
+                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K_mac, 1,
                      nullptr, nullptr, nullptr, t->far_off.as<int64_t>(),
                      t->near_off.as<int64_t>(), t->far_id.as<int32_t>(),
                      t->near_id.as<int32_t>(), d_over);
@@ -196,6 +199,7 @@ int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
   cnt.release();
   t->list_theta = theta;
   t->list_degree = degree;
+  t->list_herm = herm;
   return TAGI_OK;
 }
 
@@ -206,7 +210,8 @@ int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
   t->n_items = 0;
   const int nl = (int)t->leaves.size();
   const int np1 = t->list_degree + 1;
-  const int K = np1 * np1 * np1;
+  // kernel evaluations per far pair and target; a Hermite point costs about two
+  const int K = (t->list_herm ? 2 : 1) * np1 * np1 * np1;
   // cost cap per chunk (kernel evaluations per target lane): small enough to give
   // every SIMD several items, large enough to amortise the per-item overhead
   const int64_t total = (t->n_far * (int64_t)K) + t->near_inter / std::max<int64_t>(1, t->n / nl);

@@ -14,6 +14,15 @@
 // Charge sets: q_j = f_j w_j for every orbital, plus q_j = w_j (orbital
 // independent), which carries the singularity subtraction through the far field.
 //
+// Hermite charges (the Hermite treecode variant of the conclusions, Section 7):
+// per dimension the interpolant matches values and first derivatives at the same
+// nodes, with the basis A_k(t) = (1 - 2 c_k (t - s_k)) L_k(t)^2 for values and
+// B_k(t) = (t - s_k) L_k(t)^2 for derivatives, c_k = L_k'(s_k) =
+// sum_{m != k} 1/(s_k - s_m); the charge of node k and derivative pattern beta is
+// q^_{k,beta} = sum_j prod_d H^{beta_d}_{k_d}(y_{j,d}) q_j (H^0 = A, H^1 = B),
+// stored with the 8 patterns of one node adjacent. A source on a node has
+// A_k = delta, B_k = 0; a zero-extent dimension puts all mass on A_0.
+//
 // GPU mapping: a work item is (cluster, range of at most kItemPts sources,
 // block of charge sets). The block stages the basis values of 64 sources at a
 // time in LDS; each thread owns up to R coefficients and MB charge sets in
@@ -64,8 +73,9 @@ __device__ void cheb_nodes(double lo, double hi, int n, double* s) {
   s[n] = lo;
 }
 
-// R: coefficient rounds per thread (K <= R * kThreads); MB: charge sets per pass
-template <int R, int MB>
+// R: coefficient rounds per thread (K <= R * kThreads); MB: charge sets per pass;
+// HERM: Hermite charges (K = 8 (n+1)^3 coefficients, index 8 k + beta)
+template <int R, int MB, bool HERM>
 __global__ __launch_bounds__(kThreads) void k_upward(
     const UpItem* __restrict__ items, const int32_t* __restrict__ approx_node,
     const double* __restrict__ box, const double* __restrict__ xs,
@@ -74,11 +84,14 @@ __global__ __launch_bounds__(kThreads) void k_upward(
     int m0, int n_sets, int degree, double* __restrict__ partial,
     double* __restrict__ pnodes, float* __restrict__ pnodes32) {
   const UpItem it = items[blockIdx.x];
+  constexpr int NB = HERM ? 2 : 1;  // basis families per dimension (values, derivatives)
+  constexpr int kLd = kMaxDegree + 1;
   const int np1 = degree + 1;
-  const int K = np1 * np1 * np1;
-  __shared__ double s_nodes[3][kMaxDegree + 1];
-  __shared__ double s_b[kMaxDegree + 1];
-  __shared__ double s_L[3][kStage][kMaxDegree + 1];
+  const int K = (HERM ? kHermPatterns : 1) * np1 * np1 * np1;
+  __shared__ double s_nodes[3][kLd];
+  __shared__ double s_b[kLd];
+  __shared__ double s_c[3][kLd];  // Hermite: L_k'(s_k)
+  __shared__ double s_L[3][kStage][NB * kLd];
   const int c = approx_node[it.slot];
   if (threadIdx.x < 3) {
     const int d = threadIdx.x;
@@ -90,6 +103,16 @@ __global__ __launch_bounds__(kThreads) void k_upward(
     s_b[threadIdx.x] = b;
   }
   __syncthreads();
+  if (HERM && threadIdx.x < 3 * np1) {
+    const int d = threadIdx.x / np1, k = threadIdx.x % np1;
+    const double* s = s_nodes[d];
+    double ck = 0.0;
+    if (s[0] != s[degree])
+      for (int m = 0; m <= degree; ++m)
+        if (m != k) ck += 1.0 / (s[k] - s[m]);
+    s_c[d][k] = ck;
+  }
+  __syncthreads();
   // the first item of each cluster publishes the node coordinates
   if (m0 == 0 && it.part == it.slot && threadIdx.x < 3 * np1) {
     const int d = threadIdx.x / np1, k = threadIdx.x % np1;
@@ -98,13 +121,16 @@ __global__ __launch_bounds__(kThreads) void k_upward(
     const double ctr = 0.5 * (box[c * 6 + d] + box[c * 6 + 3 + d]);
     pnodes32[((int64_t)it.slot * 3 + d) * np1 + k] = (float)(v - ctr);
   }
+  // per coefficient: offsets of its three basis values within a staged row
   int k1[R], k2[R], k3[R];
   for (int r = 0; r < R; ++r) {
     const int k = threadIdx.x + r * kThreads;
-    const int kk = k < K ? k : 0;
-    k1[r] = kk / (np1 * np1);
-    k2[r] = (kk / np1) % np1;
-    k3[r] = kk % np1;
+    const int kc = k < K ? k : 0;
+    const int kk = HERM ? kc / kHermPatterns : kc;
+    const int beta = HERM ? kc % kHermPatterns : 0;
+    k1[r] = kk / (np1 * np1) + ((beta >> 0) & 1) * kLd;
+    k2[r] = (kk / np1) % np1 + ((beta >> 1) & 1) * kLd;
+    k3[r] = kk % np1 + ((beta >> 2) & 1) * kLd;
   }
   double acc[R][MB];
   for (int r = 0; r < R; ++r)
@@ -119,6 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_upward(
         const double* cp = d == 0 ? xs : (d == 1 ? ys : zs);
         const double t = cp[p0 + p];
         const double* s = s_nodes[d];
+        bool exact = true;  // Kronecker values, no derivative part
         if (s[0] == s[degree]) {  // zero-extent dimension
           for (int k = 0; k <= degree; ++k) L[k] = k == 0 ? 1.0 : 0.0;
         } else {
@@ -128,6 +155,7 @@ __global__ __launch_bounds__(kThreads) void k_upward(
           if (hit >= 0) {
             for (int k = 0; k <= degree; ++k) L[k] = k == hit ? 1.0 : 0.0;
           } else {
+            exact = false;
             double sum = 0.0;
             for (int k = 0; k <= degree; ++k) {
               const double a = s_b[k] / (t - s[k]);
@@ -137,8 +165,22 @@ __global__ __launch_bounds__(kThreads) void k_upward(
             for (int k = 0; k <= degree; ++k) L[k] = L[k] / sum;
           }
         }
+        if (HERM) {
+          for (int k = 0; k <= degree; ++k) {
+            if (exact) {
+              L[kLd + k] = 0.0;
+            } else {
+              const double dt = t - s[k];
+              const double l2 = L[k] * L[k];
+              L[kLd + k] = dt * l2;
+              L[k] = (1.0 - 2.0 * s_c[d][k] * dt) * l2;
+            }
+          }
+        }
       } else {
         for (int k = 0; k <= degree; ++k) L[k] = 0.0;
+        if (HERM)
+          for (int k = 0; k <= degree; ++k) L[kLd + k] = 0.0;
       }
     }
     __syncthreads();
@@ -186,7 +228,8 @@ __global__ void k_upward_reduce(const int32_t* __restrict__ slot_first,
 
 template <int R, int MB>
 void launch_upward(hipStream_t s, tagi_tree* t, ProxySet& ps, int m0, int n_sets) {
-  hipLaunchKernelGGL((k_upward<R, MB>), dim3(ps.n_items), dim3(kThreads), 0, s,
+  auto kern = ps.herm ? k_upward<R, MB, true> : k_upward<R, MB, false>;
+  hipLaunchKernelGGL(kern, dim3(ps.n_items), dim3(kThreads), 0, s,
                      ps.items.as<UpItem>(), ps.node.as<int32_t>(), t->nd_box.as<double>(),
                      t->xs.as<double>(), t->ys.as<double>(), t->zs.as<double>(),
                      t->qs.as<double>(), t->ws.as<double>(), t->n, ps.n_orb, m0, n_sets,
@@ -227,10 +270,10 @@ void launch_upward_r(int MB, hipStream_t s, tagi_tree* t, ProxySet& ps, int m0, 
 // device buffers. Built once per (set, degree, n_orb) and reused, so a repeated
 // upward pass only launches kernels (and can be captured in a HIP graph).
 int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& nodes, int degree,
-                    int n_orb, hipStream_t s) {
+                    int n_orb, hipStream_t s, bool herm) {
   ps.degree = ps.n_orb = 0;
   const int np1 = degree + 1;
-  const int K = np1 * np1 * np1;
+  const int K = (herm ? kHermPatterns : 1) * np1 * np1 * np1;
   ps.nodes = nodes;
   ps.h_slot_of.assign(t->nodes.size(), -1);
   for (size_t sl = 0; sl < nodes.size(); ++sl) ps.h_slot_of[nodes[sl]] = (int32_t)sl;
@@ -275,6 +318,7 @@ int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& node
   }
   ps.degree = degree;
   ps.n_orb = n_orb;
+  ps.herm = herm;
   return TAGI_OK;
 }
 
@@ -282,7 +326,7 @@ int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s) {
   const int na = ps.n_approx;
   if (na == 0) return TAGI_OK;
   const int np1 = ps.degree + 1;
-  const int K = np1 * np1 * np1;
+  const int K = (ps.herm ? kHermPatterns : 1) * np1 * np1 * np1;
   const int n_sets_total = ps.n_orb + 1;
   int R;
   const int MB = charge_block(K, n_sets_total, &R);
@@ -314,21 +358,22 @@ int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s) {
 }
 
 int upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree,
-           hipStream_t s) {
+           hipStream_t s, bool herm) {
   const int64_t n = t->n;
   t->degree = 0;  // invalid until complete
   phase_begin(t, kPhaseUpward, s);
-  if (!(t->px.degree == degree && t->px.n_orb == n_orb)) {
+  if (!(t->px.degree == degree && t->px.n_orb == n_orb && t->px.herm == herm)) {
     TAGI_TRY(t->ws.ensure(n * sizeof(double)));
     TAGI_TRY(t->fs.ensure((size_t)n_orb * n * sizeof(double)));
     TAGI_TRY(t->qs.ensure((size_t)n_orb * n * sizeof(double)));
-    // approximable clusters: more than (n+1)^3 sources; the root is skipped because
-    // every batch centre lies inside it, so the distance test can never accept it
-    const int K = (degree + 1) * (degree + 1) * (degree + 1);
+    // approximable clusters: more sources than charges ((n+1)^3, Hermite 8 (n+1)^3);
+    // the root is skipped because every batch centre lies inside it, so the
+    // distance test can never accept it
+    const int K = (herm ? kHermPatterns : 1) * (degree + 1) * (degree + 1) * (degree + 1);
     std::vector<int32_t> nodes;
     for (size_t c = 1; c < t->nodes.size(); ++c)
       if (t->nodes[c].end - t->nodes[c].begin > K) nodes.push_back((int32_t)c);
-    TAGI_TRY(prepare_proxies(t, t->px, nodes, degree, n_orb, s));
+    TAGI_TRY(prepare_proxies(t, t->px, nodes, degree, n_orb, s, herm));
   }
   hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, t->perm.as<int32_t>(), f,
                      w, n, n_orb, t->fs.as<double>(), t->qs.as<double>(), t->ws.as<double>());

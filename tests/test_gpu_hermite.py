@@ -1,0 +1,180 @@
+"""The Hermite treecode variant on the GPU (tagi_upward_hermite + tagi_convolve)
+against the oracle's Hermite treecode on the same tree, element by element.
+
+Tolerance. As for the Lagrange form, the scale is S_i, what the terms of the
+subtracted sum can cancel down from. The Hermite far field adds, per proxy
+point, eight products of charges and kernel derivatives whose magnitudes exceed
+the kernel value times the charge by up to the Hermite basis's amplification
+(|A_k| + |B_k| |g'/g| summed over the nodes, below 10 at the degrees tested), so
+the bound is 1e-11 S_i instead of 1e-12 S_i.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bltc, hermite
+from oracle.direct import direct_sum
+from workloads.configs import atom_mesh, sample_targets, uniform_cube
+from workloads.rng import SplitMix64
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(*arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def _scale(kernel, x, y, z, f, w, kappa, alpha=1.0):
+    fi = np.abs(f)
+    if kernel.startswith("yukawa"):
+        s = direct_sum("yukawa", x, y, z, np.abs(f), w, kappa=kappa)
+        if kernel == "yukawa_ss":
+            s = s + fi * direct_sum("yukawa", x, y, z, np.ones_like(f), w, kappa=kappa)
+            s = s + 4 * np.pi / kappa ** 2 * fi
+        return s
+    s = direct_sum("coulomb", x, y, z, np.abs(f), w)
+    if kernel == "coulomb_ss":
+        s = s + fi * direct_sum("coulomb", x, y, z, np.ones_like(f), w) + 2 * np.pi * alpha ** 2 * fi
+    return s
+
+
+def _make_case(n, seed):
+    import paper_2003_01833_amd as tagi
+    x, y, z, f, w = uniform_cube(n, seed=seed)
+    # a third of the points squeezed toward a corner: uneven leaves and deep branches
+    sq = np.arange(n) % 3 == 0
+    x = np.where(sq, -1.0 + 0.05 * (x + 1.0), x)
+    y = np.where(sq, -1.0 + 0.05 * (y + 1.0), y)
+    t = tagi.Tree(*_dev(x, y, z), leaf_size=150)
+    ref = bltc.build_tree(x, y, z, 150)
+    return dict(tagi=tagi, x=x, y=y, z=z, f=f, w=w, t=t, ref=ref)
+
+
+@pytest.fixture(scope="module")
+def case():
+    return _make_case(6007, 41)
+
+
+@pytest.fixture(scope="module")
+def big_case():
+    # enough sources that clusters pass the Hermite size test 8 (n+1)^3 < N_S at n = 5, 7
+    return _make_case(20000, 42)
+
+
+def test_hermite_upward_matches_oracle(case):
+    c = case
+    t, ref = c["t"], c["ref"]
+    g = SplitMix64(51)
+    F = np.stack([c["f"], g.uniform(c["f"].size, -2, 1)])
+    dF, dw = _dev(F, c["w"])
+    deg = 2
+    t.upward(dF, dw, deg, interpolation="hermite")
+    P = t.proxies()
+    perm = ref.perm
+    X, Y, Z, W = c["x"][perm], c["y"][perm], c["z"][perm], c["w"][perm]
+    Q = F[:, perm] * W[None, :]
+    # clusters with more sources than Hermite charges, 8 (n+1)^3
+    K = 8 * (deg + 1) ** 3
+    approx = [cl for cl in range(1, ref.n_nodes) if ref.count(cl) > K]
+    assert list(P["cluster"]) == approx and len(approx) > 10
+    for s, cl in enumerate(approx):
+        b, e = ref.begin[cl], ref.end[cl]
+        nodes, ch = hermite.proxy_charges(X[b:e], Y[b:e], Z[b:e],
+                                          np.vstack([Q[:, b:e], W[None, b:e]]),
+                                          ref.lo[cl], ref.hi[cl], deg)
+        np.testing.assert_allclose(P["nodes"][s], nodes, rtol=0, atol=1e-15 * np.abs(nodes).max())
+        h = np.max(ref.hi[cl] - ref.lo[cl])
+        for o in range(2):
+            scale = np.abs(Q[o, b:e]).sum() * max(1.0, h)
+            assert np.abs(P["qhat"][o, s] - ch[o].reshape(-1)).max() <= 1e-13 * scale
+        assert np.abs(P["what"][s] - ch[2].reshape(-1)).max() <= 1e-13 * W[b:e].sum() * max(1.0, h)
+
+
+@pytest.mark.parametrize("kernel", ["yukawa_ss", "coulomb_ss", "yukawa", "coulomb"])
+def test_hermite_treecode_matches_oracle(case, kernel):
+    c = case
+    t = c["t"]
+    g = SplitMix64(52)
+    F = np.stack([c["f"], g.uniform(c["f"].size, -1, 1), g.uniform(c["f"].size, 0, 3)])
+    kap = np.array([0.6, 1.3, 3.1])
+    deg, theta = 3, 0.65
+    dF, dw = _dev(F, c["w"])
+    t.upward(dF, dw, deg, interpolation="hermite")
+    u = t.convolve(kernel, kap, theta, deg).cpu().numpy()
+    assert t.stats()["n_far_pairs"] > 0
+    ref = hermite.treecode(c["x"], c["y"], c["z"], F, c["w"], kernel, kap, theta, deg, 150,
+                           tree=c["ref"])
+    for o in range(3):
+        S = _scale(kernel, c["x"], c["y"], c["z"], F[o], c["w"], kap[o])
+        r = np.max(np.abs(u[o] - ref[o]) / S)
+        assert r <= 1e-11, (o, r)
+
+
+@pytest.mark.parametrize("kernel,n_orb,degree,theta,big", [
+    ("yukawa", 5, 5, 0.7, True),       # orbital blocks of 4 and 1
+    ("coulomb_ss", 2, 7, 0.8, True),   # degree 7: run-time trip counts
+    ("coulomb", 3, 2, 0.5, False),     # blocks of 2 and 1
+    ("yukawa_ss", 1, 1, 0.6, False),   # degree 1: two points per dimension, run-time trip counts
+    ("yukawa_ss", 2, 4, 0.9, False),
+])
+def test_hermite_orbital_blocks_and_degrees(request, kernel, n_orb, degree, theta, big):
+    c = request.getfixturevalue("big_case" if big else "case")
+    t = c["t"]
+    g = SplitMix64(60 + n_orb)
+    F = np.stack([g.uniform(c["f"].size, -1, 1) for _ in range(n_orb)])
+    kap = np.array([0.5 + 0.4 * o for o in range(n_orb)])
+    dF, dw = _dev(F, c["w"])
+    t.upward(dF, dw, degree, interpolation="hermite")
+    u = t.convolve(kernel, kap, theta, degree).cpu().numpy()
+    assert t.stats()["n_far_pairs"] > 0
+    ref = hermite.treecode(c["x"], c["y"], c["z"], F, c["w"], kernel, kap, theta, degree, 150,
+                           tree=c["ref"])
+    L = t.lists(theta, degree)
+    _, far, near = bltc.interaction_lists(c["ref"], theta, degree, 8 * (degree + 1) ** 3)
+    assert L["far_id"].tolist() == [C for fl in far for C in fl]
+    assert L["near_id"].tolist() == [C for nl in near for C in nl]
+    for o in range(n_orb):
+        S = _scale(kernel, c["x"], c["y"], c["z"], F[o], c["w"], kap[o])
+        r = np.max(np.abs(u[o] - ref[o]) / S)
+        assert r <= 1e-11, (o, r)
+
+
+def test_hermite_state_and_argument_checks(case):
+    c = case
+    tagi, t = c["tagi"], c["t"]
+    dF, dw = _dev(c["f"], c["w"])
+    with pytest.raises(tagi.TagiError):
+        t.upward(dF, dw, 8, interpolation="hermite")  # degrees 1..7
+    t.upward(dF, dw, 4, interpolation="hermite")
+    with pytest.raises(tagi.TagiError):
+        t.convolve("yukawa_ss", 1.0, 0.7, 4, precision="mixed")
+    uh = t.convolve("yukawa_ss", 1.0, 0.7, 4).cpu().numpy()
+    # the next Lagrange upward pass returns the tree to Lagrange charges
+    t.upward(dF, dw, 4)
+    ul = t.convolve("yukawa_ss", 1.0, 0.7, 4).cpu().numpy()
+    ref = bltc.treecode(c["x"], c["y"], c["z"], c["f"], c["w"], "yukawa_ss", 1.0, 0.7, 4, 150,
+                        tree=c["ref"])[0]
+    S = _scale("yukawa_ss", c["x"], c["y"], c["z"], c["f"], c["w"], 1.0)
+    assert np.max(np.abs(ul[0] - ref) / S) <= 1e-12
+    # and Hermite is the more accurate of the two at the same (theta, n)
+    ds = direct_sum("yukawa_ss", c["x"], c["y"], c["z"], c["f"], c["w"], kappa=1.0)
+    assert np.linalg.norm(uh[0] - ds) < np.linalg.norm(ul[0] - ds)
+
+
+def test_hermite_on_the_atom_mesh_meets_1e6():
+    # the Be-like mesh (1.0M points) at the Hermite setting of the benchmark's
+    # comparison (n = 6, theta = 0.8, N_L = 2000), against the oracle's direct sum
+    # at seeded sample targets
+    import paper_2003_01833_amd as tagi
+    d = atom_mesh()
+    x, y, z, w = d["x"], d["y"], d["z"], d["w"]
+    f = d["psi"]
+    kappa = d["kappa"]
+    t = tagi.Tree(*_dev(x, y, z), leaf_size=2000, box=(-20, -20, -20, 20, 20, 20))
+    dF, dw = _dev(f, w)
+    t.upward(dF, dw, 6, interpolation="hermite")
+    u = t.convolve("yukawa_ss", kappa, 0.8, 6).cpu().numpy()[0]
+    idx = sample_targets(x.size, 400, seed=9)
+    ref = direct_sum("yukawa_ss", x, y, z, f, w, x[idx], y[idx], z[idx], f[idx], kappa=kappa)
+    err = np.abs(u[idx] - ref).max() / np.abs(ref).max()
+    assert err < 1e-6, err
