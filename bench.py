@@ -20,7 +20,10 @@ direct sum on sampled targets, the roofline position of the dominant kernel
 (the interaction kernel, timed with HIP events on its own stream; its HBM
 traffic comes from the FETCH_SIZE / WRITE_SIZE counter profile committed under
 profiles/, reported only while the kernel sources match the profiled ones) and
-the CPU oracle's rate on a bounded sample.
+the CPU oracle's rate on a bounded sample. Unless --no-compare is given, it also
+holds two comparisons: Lagrange against Hermite interpolation on the atom at
+the accuracy targets 1e-6 and 1e-9, and the plain, batched, mixed-precision and
+learned-selector variants on the 21 benzene orbitals (with the GPU mesh build).
 """
 from __future__ import annotations
 
@@ -323,6 +326,62 @@ def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samp
     return res
 
 
+# Cheapest settings of each interpolation form (N_L = 2000, the tree of the timed
+# step) reaching a maximum relative error of 1e-6 and of 1e-9 on the Be-like mesh,
+# from parameter sweeps (Lagrange degrees 8-14, Hermite degrees 4-7, theta
+# 0.5-0.9): (theta, degree).
+HERMITE_COMPARE = {
+    "yukawa_ss": {"1e-6": {"lagrange": (0.75, 8), "hermite": (0.8, 6)},
+                  "1e-9": {"lagrange": (0.7, 12), "hermite": (0.5, 6)}},
+    "coulomb_ss": {"1e-6": {"lagrange": (0.8, 8), "hermite": (0.8, 5)},
+                   "1e-9": {"lagrange": (0.7, 11), "hermite": (0.5, 6)}},
+}
+
+
+def compare_hermite(tagi, torch, x, y, z, w, fields, refs, idx, leaf, box, reps=3):
+    """Lagrange against Hermite interpolation at two accuracy targets: the median
+    of `reps` convolutions after one warm-up, and the error at the sampled
+    targets against the GPU direct sum."""
+    _log("compare: Lagrange and Hermite treecodes on the Be-like mesh")
+    t = tagi.Tree(x, y, z, leaf, box)
+    res = {}
+    for c in fields:
+        k = c["kernel"]
+        if k not in HERMITE_COMPARE:
+            continue
+        kap = c["kappa"] or 1.0
+        ref = refs[k]
+        res[k] = {}
+        for target, forms in HERMITE_COMPARE[k].items():
+            res[k][target] = {}
+            for form, (th, deg) in forms.items():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                t.upward(c["f"], w, deg, interpolation=form)
+                torch.cuda.synchronize()
+                up_ms = 1e3 * (time.perf_counter() - t0)
+                u = t.convolve(k, kap, th, deg)
+                ts = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    u = t.convolve(k, kap, th, deg)
+                    torch.cuda.synchronize()
+                    ts.append(1e3 * (time.perf_counter() - t0))
+                ui = u[0, idx]
+                st = t.stats()
+                res[k][target][form] = {
+                    "theta": th, "degree": deg, "convolve_ms": float(np.median(ts)),
+                    "upward_ms": up_ms,
+                    "rel_max": float((ui - ref).abs().max() / ref.abs().max()),
+                    "rel_l2": float(torch.linalg.norm(ui - ref) / torch.linalg.norm(ref)),
+                    "far_pairs": st["n_far_pairs"], "near_pairs": st["n_near_pairs"]}
+            r = res[k][target]
+            r["hermite_speedup"] = r["lagrange"]["convolve_ms"] / r["hermite"]["convolve_ms"]
+    t.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -438,8 +497,10 @@ def main():
                 "rel_max": float((u - ref).abs().max() / ref.abs().max())}
         t.close()
 
-    comparison = None
+    comparison = hermite = None
     if not args.no_compare:
+        if args.workload == "atom":
+            hermite = compare_hermite(tagi, torch, x, y, z, w, fields, refs, idx, leaf, wl["box"])
         comparison = compare_batched(tagi, torch)
 
     cpu = None
@@ -473,6 +534,7 @@ def main():
         "accuracy_vs_direct": acc,
         "stated_setting_accuracy": stated,
         "batched_mixed_vs_plain": comparison,
+        "hermite_vs_lagrange": hermite,
     }
     line["roofline"]["traffic"] = counter_traffic(line["config"])
     # the upward pass (proxy charges), against both the FP64 and the HBM roofline.
