@@ -1,6 +1,6 @@
 """Regenerates the polynomial coefficients of exp_nonpos in devmath.hpp.
 
-The polynomial of degree 11 that interpolates exp at the 12 Chebyshev points of
+The polynomial of degree 9 that interpolates exp at the 10 Chebyshev points of
 the first kind on [-ln 2 / 2, ln 2 / 2], in monomial form, computed in 60-digit
 arithmetic and rounded to double. Prints the coefficients (hex) and the largest
 relative error of the double-precision Horner evaluation (with fused
@@ -10,7 +10,7 @@ import mpmath as mp
 import numpy as np
 
 
-def main(degree: int = 11):
+def main(degree: int = 9):
     mp.mp.dps = 60
     a = mp.log(2) / 2
     nodes = [a * mp.cos((2 * i + 1) * mp.pi / (2 * (degree + 1))) for i in range(degree + 1)]

@@ -345,6 +345,9 @@ int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s) {
       case 8: launch_upward_r<8>(MB, s, t, ps, m0, n_sets); break;
       case 9: launch_upward_r<9>(MB, s, t, ps, m0, n_sets); break;
       case 10: launch_upward_r<10>(MB, s, t, ps, m0, n_sets); break;
+      case 11: case 12: launch_upward_r<12>(MB, s, t, ps, m0, n_sets); break;
+      case 13: case 14: launch_upward_r<14>(MB, s, t, ps, m0, n_sets); break;
+      case 15: case 16: launch_upward_r<16>(MB, s, t, ps, m0, n_sets); break;
       default: launch_upward_r<20>(MB, s, t, ps, m0, n_sets); break;
     }
     TAGI_HIP(hipGetLastError());

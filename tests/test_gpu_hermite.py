@@ -112,7 +112,8 @@ def test_hermite_treecode_matches_oracle(case, kernel):
 
 @pytest.mark.parametrize("kernel,n_orb,degree,theta,big", [
     ("yukawa", 5, 5, 0.7, True),       # orbital blocks of 4 and 1
-    ("coulomb_ss", 2, 7, 0.8, True),   # degree 7: run-time trip counts
+    ("coulomb_ss", 2, 7, 0.8, True),   # degree 7: run-time trip counts, 16 upward rounds
+    ("yukawa_ss", 2, 6, 0.8, True),    # 8 * 7^3 = 2744 charges: 12 upward rounds
     ("coulomb", 3, 2, 0.5, False),     # blocks of 2 and 1
     ("yukawa_ss", 1, 1, 0.6, False),   # degree 1: two points per dimension, run-time trip counts
     ("yukawa_ss", 2, 4, 0.9, False),
