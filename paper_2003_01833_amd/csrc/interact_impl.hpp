@@ -47,17 +47,31 @@ struct Chunk {
   int32_t kind, e0, e1, cost;
 };
 
+// 1/d and, for the Yukawa kernels, d from the squared distance r2; with MASK,
+// both are 0 for a coincident pair (r2 = 0), which then adds nothing.
+template <int KER, bool MASK>
+__device__ __forceinline__ void inv_dist(double r2, double& rinv, double& r) {
+  if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
+    rsqrt_sqrt(r2, rinv, r);
+  } else {
+    rinv = rsqrt_pos(r2);
+    r = 0.0;
+  }
+  if constexpr (MASK) {
+    if (!(r2 > 0.0)) rinv = r = 0.0;
+  }
+}
+
 // Accumulates one source with charges c[o] (per orbital) and m (orbital
-// independent) at squared distance r2 with inverse distance rinv (0 for a
-// coincident pair, which then adds nothing).
+// independent) at squared distance r2, inverse distance rinv and distance r
+// (Yukawa kernels only), as inv_dist gives them.
 template <int KER>
 struct Pair {
   template <int OB>
-  __device__ __forceinline__ static void add(double r2, double rinv, const double* c, double m,
-                                             const double* nkap, double nia2, double* a1,
-                                             double* a2) {
+  __device__ __forceinline__ static void add(double r2, double rinv, double r, const double* c,
+                                             double m, const double* nkap, double nia2,
+                                             double* a1, double* a2) {
     if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
-      const double r = r2 * rinv;
 #pragma unroll
       for (int o = 0; o < OB; ++o) {
         const double g = exp_nonpos(nkap[o] * r) * rinv;
@@ -150,7 +164,9 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
             double c[OB];
 #pragma unroll
             for (int o = 0; o < OB; ++o) c[o] = qk[o][k + k3];
-            Pair<KER>::template add<OB>(r2, rsqrt_pos(r2), c, wk[k + k3], nkap, nia2, a1, a2);
+            double rinv, r;
+            inv_dist<KER, false>(r2, rinv, r);
+            Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k + k3], nkap, nia2, a1, a2);
           }
           if constexpr (kRowStep<OB> < NP1) __builtin_amdgcn_sched_barrier(0);
         }
@@ -162,7 +178,9 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
           double c[OB];
 #pragma unroll
           for (int o = 0; o < OB; ++o) c[o] = qk[o][k];
-          Pair<KER>::template add<OB>(r2, rsqrt_pos(r2), c, wk[k], nkap, nia2, a1, a2);
+          double rinv, r;
+          inv_dist<KER, false>(r2, rinv, r);
+          Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k], nkap, nia2, a1, a2);
         }
       }
     }
@@ -301,11 +319,12 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
       const double dy = yi - ys[j + u];
       const double dz = zi - zs[j + u];
       const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-      const double rinv = !MASK || r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+      double rinv, r;
+      inv_dist<KER, MASK>(r2, rinv, r);
       double c[OB];
 #pragma unroll
       for (int o = 0; o < OB; ++o) c[o] = qr[o][j + u];
-      Pair<KER>::template add<OB>(r2, rinv, c, ws[j + u], nkap, nia2, a1, a2);
+      Pair<KER>::template add<OB>(r2, rinv, r, c, ws[j + u], nkap, nia2, a1, a2);
     }
   }
   for (; j < j1; ++j) {
@@ -313,11 +332,12 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
     const double dy = yi - ys[j];
     const double dz = zi - zs[j];
     const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-    const double rinv = !MASK || r2 > 0.0 ? rsqrt_pos(r2) : 0.0;
+    double rinv, r;
+    inv_dist<KER, MASK>(r2, rinv, r);
     double c[OB];
 #pragma unroll
     for (int o = 0; o < OB; ++o) c[o] = qr[o][j];
-    Pair<KER>::template add<OB>(r2, rinv, c, ws[j], nkap, nia2, a1, a2);
+    Pair<KER>::template add<OB>(r2, rinv, r, c, ws[j], nkap, nia2, a1, a2);
   }
 }
 
@@ -359,13 +379,13 @@ template <int KER, int OB>
 __device__ __forceinline__ void herm_point(const HermGeo& g, double r2, const double* __restrict__ m8,
                                            const double* const* q8, const double* nkap, double nia2,
                                            double* a1, double* a2) {
-  const double rinv = rsqrt_pos(r2);
+  double rinv, r;
+  inv_dist<KER, false>(r2, rinv, r);
   const double ri2 = rinv * rinv;
   constexpr bool SS = KER == TAGI_YUKAWA_SS || KER == TAGI_COULOMB_SS;
   double W[4] = {0.0, 0.0, 0.0, 0.0};
   if constexpr (SS) herm_sums(g, m8, W);
   if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
-    const double r = r2 * rinv;
 #pragma unroll
     for (int o = 0; o < OB; ++o) {
       const double x = nkap[o] * r;  // -k r
