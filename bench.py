@@ -47,17 +47,18 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
 # Algorithmic FP64 flops per kernel evaluation (FMA = 2): squared distance (8
 # for particle sources; 3 for proxy sources, whose tensor grid gives d^2 with one
 # subtraction and one multiply-add per pair), reciprocal square root (seed plus
-# one Newton step, 7; 9 when the same step also gives d), exp by Cody-Waite
-# reduction and a degree-9 polynomial (25), the products forming the kernel
-# value, and two multiply-adds (4). The far field of the Gaussian-subtracted
+# one Newton step, 7; 9 when the same step also gives d), exp as a power of two
+# whose reduced argument comes from the scaled decay constant in one multiply-add,
+# and a degree-9 polynomial (24), the products forming the kernel value, and two
+# multiply-adds (4). The far field of the Gaussian-subtracted
 # Coulomb kernel takes the Gaussian as the product of per-dimension factors: two
 # multiplies per evaluation, and 3 (n+1) exponentials per target and cluster
 # that are not counted.
 FLOPS = {
-    ("yukawa_ss", "far"): 3 + 9 + 1 + 25 + 1 + 4,
-    ("yukawa_ss", "near"): 8 + 9 + 1 + 25 + 1 + 4,
+    ("yukawa_ss", "far"): 3 + 9 + 24 + 1 + 4,
+    ("yukawa_ss", "near"): 8 + 9 + 24 + 1 + 4,
     ("coulomb_ss", "far"): 3 + 7 + 2 + 4,
-    ("coulomb_ss", "near"): 8 + 7 + 1 + 25 + 1 + 2 + 2,
+    ("coulomb_ss", "near"): 8 + 7 + 24 + 1 + 2 + 2,
 }
 
 

@@ -8,36 +8,36 @@
 
 namespace tagi {
 
-// exp(x) for finite x <= 0. Cody and Waite's additive range reduction
-// (W. J. Cody and W. Waite, Software Manual for the Elementary Functions, 1980):
-// k = nearest integer to x / ln 2, r = x - k ln 2 in one fused multiply-add with
-// ln 2 rounded to double (which adds at most |k| 2^-54 ln 2 to r: 1.6e-15 for
-// exp(x) > 1e-20, 2.6e-14 at the underflow end), |r| <= ln(2)/2; then
-// exp(r) by the degree-9 polynomial that interpolates exp at the 10 Chebyshev
-// points of [-ln 2 / 2, ln 2 / 2] (coefficients computed in 60-digit arithmetic
-// by gen_exp_coeffs.py beside this file and rounded to double; relative error of
-// the Horner evaluation at most 1.9e-14 on the interval, far below the
-// treecode's own error), and exp(x) = 2^k exp(r).
+constexpr double kLog2e = 0x1.71547652b82fep+0;  // log2(e)
+constexpr double kLn2 = 0x1.62e42fefa39efp-1;    // ln(2)
+
+// exp(v c) for finite v c <= 0, given cl2 = c log2(e) (the kernels scale their
+// decay constants once): exp(v c) = 2^(v cl2) = 2^k 2^f with k the nearest
+// integer to v cl2 and f = v cl2 - k, formed in one fused multiply-add from the
+// same product (|f| <= 1/2, rounded once); 2^f by the degree-9 polynomial that
+// interpolates 2^f at the 10 Chebyshev points of [-1/2, 1/2] (coefficients
+// computed in 60-digit arithmetic by gen_exp_coeffs.py beside this file and
+// rounded to double; relative error of the Horner evaluation at most 1.9e-14 on
+// the interval, far below the treecode's own error). Rounding cl2 adds a
+// relative error of at most |v c| 3.4e-16 (1.6e-14 for results above 1e-20).
 // The nearest integer is formed by adding 1.5 * 2^52, whose ulp is 1, so the
 // low word of the sum holds k in two's complement.
-__device__ __forceinline__ double exp_nonpos(double x) {
-  constexpr double kLog2e = 0x1.71547652b82fep+0;
+__device__ __forceinline__ double exp2_scaled(double v, double cl2) {
   constexpr double kShift = 0x1.8p52;
-  constexpr double kLn2 = 0x1.62e42fefa39efp-1;
-  const double t = __builtin_fma(x, kLog2e, kShift);
+  const double t = __builtin_fma(v, cl2, kShift);
   const double kd = t - kShift;
   const int k = (int)__double2loint(t);
-  const double r = __builtin_fma(kd, -kLn2, x);
-  double p = 0x1.72e107c874de9p-19;
-  p = __builtin_fma(p, r, 0x1.a17df0d914d6cp-16);
-  p = __builtin_fma(p, r, 0x1.a01994c849582p-13);
-  p = __builtin_fma(p, r, 0x1.6c162bb7d965cp-10);
-  p = __builtin_fma(p, r, 0x1.11111123bf154p-7);
-  p = __builtin_fma(p, r, 0x1.55555588b8403p-5);
-  p = __builtin_fma(p, r, 0x1.5555555550d88p-3);
-  p = __builtin_fma(p, r, 0x1.ffffffffe74f1p-2);
-  p = __builtin_fma(p, r, 0x1.0000000000006p+0);
-  p = __builtin_fma(p, r, 0x1.000000000003dp+0);
+  const double f = __builtin_fma(v, cl2, -kd);
+  double p = 0x1.b6571de2f2351p-24;
+  p = __builtin_fma(p, f, 0x1.63ef969a64d3cp-20);
+  p = __builtin_fma(p, f, 0x1.ffcb76789860fp-17);
+  p = __builtin_fma(p, f, 0x1.43088e257f341p-13);
+  p = __builtin_fma(p, f, 0x1.5d87fe908f88ap-10);
+  p = __builtin_fma(p, f, 0x1.3b2ab72b175eep-7);
+  p = __builtin_fma(p, f, 0x1.c6b08d7044119p-5);
+  p = __builtin_fma(p, f, 0x1.ebfbdff8149f2p-3);
+  p = __builtin_fma(p, f, 0x1.62e42fefa39f7p-1);
+  p = __builtin_fma(p, f, 0x1.000000000003dp+0);
   return __builtin_amdgcn_ldexp(p, k);
 }
 

@@ -85,9 +85,9 @@ __global__ __launch_bounds__(kBlock) void k_direct(
   const double xi = tx[t], yi = ty[t], zi = tz[t];
   const int j0 = (int)(sc * sc_len), j1 = (int)min(ns, j0 + sc_len);
   double a1[1] = {0.0}, a2[1] = {0.0};
-  const double nkap[1] = {-kappa};
+  const double kl2[1] = {-kappa * kLog2e};
   const double* qr[1] = {sq};
-  near_range<KER, 1>(xi, yi, zi, j0, j1, sx, sy, sz, sw, qr, nkap, -ia2, a1, a2);
+  near_range<KER, 1>(xi, yi, zi, j0, j1, sx, sy, sz, sw, qr, kl2, -ia2 * kLog2e, a1, a2);
   double* out = partial + (int64_t)w * 2 * kWave;
   out[lane] = a1[0];
   out[kWave + lane] = a2[0];

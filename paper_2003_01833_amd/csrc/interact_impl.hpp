@@ -64,23 +64,24 @@ __device__ __forceinline__ void inv_dist(double r2, double& rinv, double& r) {
 
 // Accumulates one source with charges c[o] (per orbital) and m (orbital
 // independent) at squared distance r2, inverse distance rinv and distance r
-// (Yukawa kernels only), as inv_dist gives them.
+// (Yukawa kernels only), as inv_dist gives them. kl2[o] = -k_o log2(e) and
+// al2 = -log2(e) / a^2 are the decay constants in base 2.
 template <int KER>
 struct Pair {
   template <int OB>
   __device__ __forceinline__ static void add(double r2, double rinv, double r, const double* c,
-                                             double m, const double* nkap, double nia2,
+                                             double m, const double* kl2, double al2,
                                              double* a1, double* a2) {
     if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
 #pragma unroll
       for (int o = 0; o < OB; ++o) {
-        const double g = exp_nonpos(nkap[o] * r) * rinv;
+        const double g = exp2_scaled(r, kl2[o]) * rinv;
         a1[o] = __builtin_fma(g, c[o], a1[o]);
         if constexpr (KER == TAGI_YUKAWA_SS) a2[o] = __builtin_fma(g, m, a2[o]);
       }
     } else {
       if constexpr (KER == TAGI_COULOMB_SS)
-        a2[0] = __builtin_fma(exp_nonpos(r2 * nia2) * rinv, m, a2[0]);
+        a2[0] = __builtin_fma(exp2_scaled(r2, al2) * rinv, m, a2[0]);
 #pragma unroll
       for (int o = 0; o < OB; ++o) a1[o] = __builtin_fma(rinv, c[o], a1[o]);
     }
@@ -100,8 +101,8 @@ template <int KER, int OB, int NP1>
 __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int np1_rt,
                                             const double* __restrict__ px,
                                             const double* __restrict__ wk,
-                                            const double* const* qk, const double* nkap,
-                                            double nia2, double* a1, double* a2) {
+                                            const double* const* qk, const double* kl2,
+                                            double al2, double* a1, double* a2) {
   const int np1 = NP1 ? NP1 : np1_rt;
   const double* py = px + np1;
   const double* pz = py + np1;
@@ -113,18 +114,18 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
 #pragma unroll
     for (int k3 = 0; k3 < NP1; ++k3) {
       dz[k3] = zi - pz[k3];
-      gz[k3] = exp_nonpos(dz[k3] * dz[k3] * nia2);
+      gz[k3] = exp2_scaled(dz[k3] * dz[k3], al2);
     }
 #pragma unroll
     for (int k2 = 0; k2 < NP1; ++k2) {
       const double dy = yi - py[k2];
-      gy[k2] = exp_nonpos(dy * dy * nia2);
+      gy[k2] = exp2_scaled(dy * dy, al2);
     }
     int k = 0;
     for (int k1 = 0; k1 < NP1; ++k1) {
       const double dx = xi - px[k1];
       const double dx2 = dx * dx;
-      const double gx = exp_nonpos(dx2 * nia2);
+      const double gx = exp2_scaled(dx2, al2);
 #pragma unroll
       for (int k2 = 0; k2 < NP1; ++k2) {
         const double dy = yi - py[k2];
@@ -166,7 +167,7 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
             for (int o = 0; o < OB; ++o) c[o] = qk[o][k + k3];
             double rinv, r;
             inv_dist<KER, false>(r2, rinv, r);
-            Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k + k3], nkap, nia2, a1, a2);
+            Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k + k3], kl2, al2, a1, a2);
           }
           if constexpr (kRowStep<OB> < NP1) __builtin_amdgcn_sched_barrier(0);
         }
@@ -180,7 +181,7 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
           for (int o = 0; o < OB; ++o) c[o] = qk[o][k];
           double rinv, r;
           inv_dist<KER, false>(r2, rinv, r);
-          Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k], nkap, nia2, a1, a2);
+          Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k], kl2, al2, a1, a2);
         }
       }
     }
@@ -305,8 +306,8 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
                                            const double* __restrict__ ys,
                                            const double* __restrict__ zs,
                                            const double* __restrict__ ws,
-                                           const double* const* qr, const double* nkap,
-                                           double nia2, double* a1, double* a2) {
+                                           const double* const* qr, const double* kl2,
+                                           double al2, double* a1, double* a2) {
   // 4 sources per step; the masked form (rare: only where a target may coincide
   // with a source) takes 2, which keeps the kernel's scalar registers from
   // spilling into the unmasked loop
@@ -324,7 +325,7 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
       double c[OB];
 #pragma unroll
       for (int o = 0; o < OB; ++o) c[o] = qr[o][j + u];
-      Pair<KER>::template add<OB>(r2, rinv, r, c, ws[j + u], nkap, nia2, a1, a2);
+      Pair<KER>::template add<OB>(r2, rinv, r, c, ws[j + u], kl2, al2, a1, a2);
     }
   }
   for (; j < j1; ++j) {
@@ -337,7 +338,7 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
     double c[OB];
 #pragma unroll
     for (int o = 0; o < OB; ++o) c[o] = qr[o][j];
-    Pair<KER>::template add<OB>(r2, rinv, r, c, ws[j], nkap, nia2, a1, a2);
+    Pair<KER>::template add<OB>(r2, rinv, r, c, ws[j], kl2, al2, a1, a2);
   }
 }
 
@@ -377,7 +378,8 @@ __device__ __forceinline__ double herm_dot(const double* D, const double* S, dou
 
 template <int KER, int OB>
 __device__ __forceinline__ void herm_point(const HermGeo& g, double r2, const double* __restrict__ m8,
-                                           const double* const* q8, const double* nkap, double nia2,
+                                           const double* const* q8, const double* kl2,
+                                           const double* kap, double al2, double b,
                                            double* a1, double* a2) {
   double rinv, r;
   inv_dist<KER, false>(r2, rinv, r);
@@ -388,10 +390,9 @@ __device__ __forceinline__ void herm_point(const HermGeo& g, double r2, const do
   if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
 #pragma unroll
     for (int o = 0; o < OB; ++o) {
-      const double x = nkap[o] * r;  // -k r
-      const double p = -x;
+      const double p = kap[o] * r;  // k r
       double D[4];
-      D[0] = exp_nonpos(x) * rinv;
+      D[0] = exp2_scaled(r, kl2[o]) * rinv;
       const double t1 = D[0] * ri2;
       D[1] = -(p + 1.0) * t1;
       const double t2 = t1 * ri2;
@@ -412,8 +413,7 @@ __device__ __forceinline__ void herm_point(const HermGeo& g, double r2, const do
       a1[o] = herm_dot(D, S, a1[o]);
     }
     if constexpr (KER == TAGI_COULOMB_SS) {
-      const double b = -nia2;
-      const double E = exp_nonpos(r2 * nia2);
+      const double E = exp2_scaled(r2, al2);
       const double b2 = b * b;
       double G[4];
       G[0] = E * rinv;
@@ -430,9 +430,14 @@ template <int KER, int OB, int NP1>
 __device__ __forceinline__ void far_cluster_herm(double xi, double yi, double zi, int np1_rt,
                                                  const double* __restrict__ px,
                                                  const double* __restrict__ wk,
-                                                 const double* const* qk, const double* nkap,
-                                                 double nia2, double* a1, double* a2) {
+                                                 const double* const* qk, const double* kl2,
+                                                 double al2, double* a1, double* a2) {
   const int np1 = NP1 ? NP1 : np1_rt;
+  // k and 1/a^2 for the derivative polynomials
+  double kap[OB];
+#pragma unroll
+  for (int o = 0; o < OB; ++o) kap[o] = -kl2[o] * kLn2;
+  const double b = -al2 * kLn2;
   const double* py = px + np1;
   const double* pz = py + np1;
   int k = 0;
@@ -453,7 +458,8 @@ __device__ __forceinline__ void far_cluster_herm(double xi, double yi, double zi
           const double* q8[OB];
 #pragma unroll
           for (int o = 0; o < OB; ++o) q8[o] = qk[o] + kk;
-          herm_point<KER, OB>(g, __builtin_fma(dz, dz, dxy2), wk + kk, q8, nkap, nia2, a1, a2);
+          herm_point<KER, OB>(g, __builtin_fma(dz, dz, dxy2), wk + kk, q8, kl2, kap, al2, b, a1,
+                              a2);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -520,14 +526,16 @@ void k_interact(InteractArgs A, OrbArg orb) {
   const int i = tb + lane < te ? tb + lane : tb;
   const double xi = A.xs[i], yi = A.ys[i], zi = A.zs[i];
   const int o0 = item.z * OB;
-  double nkap[OB];
+  double nkap[OB], kl2[OB];  // -k and -k log2(e) per orbital
   int orb_row[OB];
 #pragma unroll
   for (int o = 0; o < OB; ++o) {
     orb_row[o] = min(o0 + o, A.n_orb - 1);
     nkap[o] = -orb.kappa[orb_row[o]];
+    kl2[o] = nkap[o] * kLog2e;
   }
   const double nia2 = -A.ia2;
+  const double al2 = nia2 * kLog2e;
   double fi[OB];  // target values, for the FP64 subtracted charges of mixed tiles
 #pragma unroll
   for (int o = 0; o < OB; ++o) {
@@ -548,13 +556,12 @@ void k_interact(InteractArgs A, OrbArg orb) {
       const int slot = A.slot_of[C];
       if (slot < 0) continue;  // never taken: far clusters always hold proxy charges
       if constexpr (MODE == kModeMixed) {
-        constexpr double kLog2e = 0x1.71547652b82fep+0;
         float nkl2[OB];
         const float* qk[OB];
         const double* qk64[OB];
 #pragma unroll
         for (int o = 0; o < OB; ++o) {
-          nkl2[o] = (float)(nkap[o] * kLog2e);
+          nkl2[o] = (float)kl2[o];
           qk[o] = A.qhat32 + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
           qk64[o] = A.qhat + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
         }
@@ -563,7 +570,7 @@ void k_interact(InteractArgs A, OrbArg orb) {
         const float oz = (float)(zi - A.geom[C * 4 + 2]);
         far_cluster32<KER, OB, NP1>(ox, oy, oz, np1, A.pnodes32 + (int64_t)slot * 3 * np1,
                                     A.what32 + (int64_t)slot * K, qk, nkl2,
-                                    (float)(nia2 * kLog2e), A.what + (int64_t)slot * K, qk64,
+                                    (float)al2, A.what + (int64_t)slot * K, qk64,
                                     fi, a1, a2);
       } else {
         const double* qk[OB];
@@ -571,10 +578,10 @@ void k_interact(InteractArgs A, OrbArg orb) {
         for (int o = 0; o < OB; ++o) qk[o] = A.qhat + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
         if constexpr (MODE == kModeHermite)
           far_cluster_herm<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
-                                         A.what + (int64_t)slot * K, qk, nkap, nia2, a1, a2);
+                                         A.what + (int64_t)slot * K, qk, kl2, al2, a1, a2);
         else
           far_cluster<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
-                                    A.what + (int64_t)slot * K, qk, nkap, nia2, a1, a2);
+                                    A.what + (int64_t)slot * K, qk, kl2, al2, a1, a2);
       }
     }
   } else {
@@ -594,10 +601,10 @@ void k_interact(InteractArgs A, OrbArg orb) {
       }
       if (__builtin_amdgcn_ballot_w64(inside))
         near_range<KER, OB, true>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws, qr,
-                                  nkap, nia2, a1, a2);
+                                  kl2, al2, a1, a2);
       else
         near_range<KER, OB, false>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws,
-                                   qr, nkap, nia2, a1, a2);
+                                   qr, kl2, al2, a1, a2);
     }
   }
   double* out = A.partial + (int64_t)it * OB * 2 * kWave;

@@ -53,14 +53,14 @@ __global__ __launch_bounds__(256) void k_pair_exact(const int2* __restrict__ pai
   const int B = pr.x, C = pr.y;
   const int tb = A.nbeg[B], nb = A.nend[B] - tb;
   const int nt = min(nb, kSampleT);
-  const double nkap[1] = {-kappa};
+  const double kl2[1] = {-kappa * kLog2e};
   const double* qr[1] = {A.qs};
   for (int k0 = 0; k0 < nt; k0 += kWave) {
     const bool live = k0 + lane < nt;
     const int i = sample_target(tb, nb, live ? k0 + lane : 0);
     double a1[1] = {0.0}, a2[1] = {0.0};
     near_range<TAGI_YUKAWA_SS, 1>(A.xs[i], A.ys[i], A.zs[i], A.nbeg[C], A.nend[C], A.xs, A.ys,
-                                  A.zs, A.ws, qr, nkap, 0.0, a1, a2);
+                                  A.zs, A.ws, qr, kl2, 0.0, a1, a2);
     if (live) out[(int64_t)p * kSampleT + k0 + lane] = __builtin_fma(-A.fs[i], a2[0], a1[0]);
   }
 }
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_pair_approx(const int2* __restrict__ pa
   if (slot >= 0) {
     const int np1 = A.degree + 1;
     const int K = np1 * np1 * np1;
-    const double nkap[1] = {-kappa};
+    const double kl2[1] = {-kappa * kLog2e};
     const double* qk[1] = {A.qhat + (int64_t)slot * K};
     for (int k0 = 0; k0 < nt; k0 += kWave) {
       const bool live = k0 + lane < nt;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_pair_approx(const int2* __restrict__ pa
       double a1[1] = {0.0}, a2[1] = {0.0};
       far_cluster<TAGI_YUKAWA_SS, 1, 0>(A.xs[i], A.ys[i], A.zs[i], np1,
                                         A.pnodes + (int64_t)slot * 3 * np1,
-                                        A.what + (int64_t)slot * K, qk, nkap, 0.0, a1, a2);
+                                        A.what + (int64_t)slot * K, qk, kl2, 0.0, a1, a2);
       const double u = __builtin_fma(-A.fs[i], a2[0], a1[0]);
       if (live) e = fmax(e, fabs(u - exact[(int64_t)p * kSampleT + k0 + lane]));
     }
