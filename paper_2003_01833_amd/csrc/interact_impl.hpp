@@ -308,10 +308,11 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
                                            const double* __restrict__ ws,
                                            const double* const* qr, const double* kl2,
                                            double al2, double* a1, double* a2) {
-  // 4 sources per step; the masked form (rare: only where a target may coincide
-  // with a source) takes 2, which keeps the kernel's scalar registers from
-  // spilling into the unmasked loop
-  constexpr int U = MASK ? 2 : 4;
+  // 4 sources per step for blocks of one or two orbitals; 2 for the masked form
+  // (rare: only where a target may coincide with a source) and for blocks of 4
+  // or 8 orbitals, whose per-orbital charges of 4 sources overflow the scalar
+  // register file (spill moves were a quarter of the 8-orbital loop)
+  constexpr int U = MASK || OB >= 4 ? 2 : 4;
   int j = j0;
   for (; j + U <= j1; j += U) {
 #pragma unroll
