@@ -133,7 +133,7 @@ int tagi_upward(tagi_tree* tree, const double* f, const double* w, int n_orb, in
 
 /*
  * Hermite proxy charges, for the barycentric Hermite treecode that the paper's
- * conclusions (Section 7) propose for the high-accuracy regime: the same
+ * conclusions (Section 8) propose for the high-accuracy regime: the same
  * clusters, points and charge sets as tagi_upward, but per dimension the
  * interpolant matches values and first derivatives at the n+1 points, with
  * A_k(t) = (1 - 2 c_k (t - s_k)) L_k(t)^2, B_k(t) = (t - s_k) L_k(t)^2 and

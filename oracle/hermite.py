@@ -2,7 +2,7 @@
 
 Only tests/, the smoke check and the benchmark's CPU-baseline leg may import this.
 
-The paper's conclusions (Section 7) propose a treecode based on barycentric Hermite
+The paper's conclusions (Section 8) propose a treecode based on barycentric Hermite
 interpolation (Krasny and Wang, 2019) for the high-accuracy regime, without giving
 its form. The form taken here replaces the Lagrange interpolation of Section 6.2
 by Hermite interpolation on the same points and keeps everything else of

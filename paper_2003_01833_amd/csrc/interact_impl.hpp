@@ -344,7 +344,7 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
 }
 
 // Far pairs of one cluster by Hermite interpolation (the Hermite treecode variant
-// of the conclusions, Section 7): per proxy point s_k eight charges, one per
+// of the conclusions, Section 8): per proxy point s_k eight charges, one per
 // derivative pattern beta of the source point, and
 //     sum_k sum_beta d^beta_y G(|y - x_i|)|_{y = s_k} q^_{k,beta}.
 // For a radial G and distinct coordinates d^beta_y G = D_|beta|(r) prod (s - x)_d

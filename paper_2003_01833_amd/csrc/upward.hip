@@ -14,7 +14,7 @@
 // Charge sets: q_j = f_j w_j for every orbital, plus q_j = w_j (orbital
 // independent), which carries the singularity subtraction through the far field.
 //
-// Hermite charges (the Hermite treecode variant of the conclusions, Section 7):
+// Hermite charges (the Hermite treecode variant of the conclusions, Section 8):
 // per dimension the interpolant matches values and first derivatives at the same
 // nodes, with the basis A_k(t) = (1 - 2 c_k (t - s_k)) L_k(t)^2 for values and
 // B_k(t) = (t - s_k) L_k(t)^2 for derivatives, c_k = L_k'(s_k) =
