@@ -156,6 +156,8 @@ def cpu_baseline(wl, seconds: float):
     return {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"direct sum at {k} seeded targets x {n} sources for "
                       f"{len(wl['convs'])} kernel(s), {dt:.1f} s",
+            # the full N^2 direct sums of one step at the sampled rate
+            "extrapolated_full_direct_s": n * n * len(wl["convs"]) / (pairs / dt),
             "per_core_value": k1 * n * len(wl["convs"]) / dt1,
             "per_core_sample": f"{k1} targets on 1 thread, {dt1:.1f} s"}
 
@@ -464,6 +466,8 @@ def main():
     sts = records[-1][1]
     interactions = sum(st["far_interactions"] + st["near_interactions"] for st in sts)
     value = interactions / (ms_per_step / 1e3)
+    # the N^2 pairs that the direct sums of one step would evaluate, per second
+    direct_equivalent = n * n * len(fields) / (ms_per_step / 1e3)
     phases = {k: float(np.mean([r[0][k] for r in records])) for k in
               ("build_ms", "upward_ms", "lists_ms", "interact_ms", "combine_ms")}
     flops = sum(st["far_interactions"] * FLOPS[(c["kernel"], "far")] +
@@ -528,6 +532,7 @@ def main():
                      "launches_per_step": launches,
                      "avg_launch_ms": phases["interact_ms"] / max(launches, 1)},
         "cpu_baseline": cpu,
+        "direct_equivalent_pairs_per_s": direct_equivalent,
         "phases_ms": phases,
         "ms_per_step_median": float(np.median(step_ms)),
         # a Green-iteration step on a fixed mesh reuses the tree and the lists:
