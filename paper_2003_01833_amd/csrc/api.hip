@@ -172,6 +172,7 @@ int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* k
     phase_end(t, kPhaseLists, s);
     if (st != TAGI_OK) return st;
   }
+  TAGI_TRY(order_schedule(t, far_weight(kernel, precision, t->px.herm), s));
   return convolve(t, kernel, kappa, alpha, precision, out, s);
 }
 

@@ -167,6 +167,7 @@ int green_step(tagi_tree* t, const double* psi, const double* veff, const double
     phase_end(t, kPhaseLists, s);
     if (st != TAGI_OK) return st;
   }
+  TAGI_TRY(order_schedule(t, far_weight(TAGI_YUKAWA_SS, precision, false), s));
   TAGI_TRY(convolve(t, TAGI_YUKAWA_SS, kappa.data(), 1.0, precision, phi, s));
   // scale, and the eigenvalue update from psi' before orthogonalization
   hipLaunchKernelGGL(k_update_sums, dim3(kRedBlocks, n_orb), dim3(kRedThreads), 0, s, w, f, psi,

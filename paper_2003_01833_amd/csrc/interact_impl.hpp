@@ -498,6 +498,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * q + min(x, r) + b / kXcds;
 }
 
+// the logical blocks [b0, b1) that XCD x runs under xcd_block
+__host__ __device__ inline void xcd_range(int x, int nb, int& b0, int& b1) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  b0 = x * q + (x < r ? x : r);
+  b1 = b0 + q + (x < r ? 1 : 0);
+}
+
 // Far-field forms of the interaction kernel
 constexpr int kModeFp64 = 0, kModeMixed = 1, kModeHermite = 2;
 

@@ -193,6 +193,15 @@ struct tagi_tree {
   // schedule: chunks of (kind, begin, end) per batch, items, group table
   int64_t n_items = 0;
   int items_orb_block = 0;
+  double items_far_w = -1.0;             // far weight the launch order was sorted for
+  std::vector<int32_t> h_order_base;     // chunk-major launch order
+  std::vector<int32_t> h_order;          // the order last uploaded
+  struct Run {
+    int32_t start, len, chunk;           // waves [start, start+len) of h_order_base
+  };
+  std::vector<Run> h_runs;               // runs of one chunk's waves
+  std::vector<int32_t> h_chunk_cost;     // evaluations per target lane of each chunk
+  std::vector<uint8_t> h_chunk_far;      // 1 for far chunks
   int ob_override = 0;              // orbital block set by the caller (0 = automatic)
   int items_n_orb = 0;
   tagi::DBuf chunks;                // int4 {kind, e0, e1, cost}
@@ -261,6 +270,9 @@ int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& node
 int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s);
 int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s);
 int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s);
+// launch order of the schedule for far evaluations costing far_w near ones
+int order_schedule(tagi_tree* t, double far_w, hipStream_t s);
+double far_weight(int kernel, int precision, bool herm);
 int orbital_block(int kernel, int n_orb, int precision);
 // the tree's orbital block for a kernel: its override if set, else the default
 int orbital_block_of(const tagi_tree* t, int kernel, int precision);

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <vector>
 
+#include "interact_impl.hpp"
 #include "internal.hpp"
 
 namespace tagi {
@@ -279,6 +280,34 @@ int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
         for (int g = 0; g < ng; ++g)
           order.push_back(group_first[group_base[b] + g] + ob * hn[b] + c);
   }
+  // host copies for order_schedule: the chunk-major order as runs of one chunk's
+  // waves (start, length, chunk), and each chunk's cost and kind
+  t->h_order_base = order;
+  t->h_runs.clear();
+  for (int b = 0; b < nl; ++b) {
+    const HostNode& q = t->nodes[t->leaves[b]];
+    const int ng = (q.end - q.begin + kWave - 1) / kWave;
+    for (int ob = 0; ob < n_ob; ++ob)
+      for (int c = 0; c < hn[b]; ++c) {
+        const int32_t start = t->h_runs.empty() ? 0 : t->h_runs.back().start + t->h_runs.back().len;
+        t->h_runs.push_back({start, ng, choff[b] + c});
+      }
+  }
+  {
+    std::vector<Chunk> hch((size_t)n_chunks);
+    if (n_chunks > 0) {
+      TAGI_HIP(hipMemcpyAsync(hch.data(), t->chunks.p, hch.size() * sizeof(Chunk),
+                              hipMemcpyDeviceToHost, s));
+      TAGI_HIP(hipStreamSynchronize(s));
+    }
+    t->h_chunk_cost.resize(hch.size());
+    t->h_chunk_far.resize(hch.size());
+    for (size_t c = 0; c < hch.size(); ++c) {
+      t->h_chunk_cost[c] = hch[c].cost;
+      t->h_chunk_far[c] = hch[c].kind != 1;
+    }
+  }
+  t->items_far_w = -1.0;
   TAGI_TRY(t->items.ensure(std::max<size_t>(items.size(), 4) * 4));
   TAGI_TRY(t->item_order.ensure(std::max<size_t>(order.size(), 1) * 4));
   if (!order.empty())
@@ -300,6 +329,66 @@ int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
   t->items_orb_block = orb_block;
   t->items_n_orb = t->n_orb;
   return TAGI_OK;
+}
+
+// Launch order of the schedule for far evaluations that cost far_w near ones.
+// Within the slice of the launch order that each XCD runs (xcd_range), the most
+// expensive items go first, so that every slice ends on short items. The sort is
+// stable and moves whole runs of one chunk's waves, so those stay side by side
+// and chunks of equal cost keep their chunk-major order. far_w = 0 keeps the
+// chunk-major order. Results do not depend on the order.
+int order_schedule(tagi_tree* t, double far_w, hipStream_t s) {
+  if (t->n_items == 0 || t->items_far_w == far_w) return TAGI_OK;
+  t->h_order = t->h_order_base;
+  if (far_w != 0.0) {
+    struct Piece {
+      int32_t a, b;
+      double cost;
+    };
+    std::vector<Piece> pieces;
+    const std::vector<int32_t>& base = t->h_order_base;
+    const int nb = (int)((t->n_items + ik::kWavesPerBlock - 1) / ik::kWavesPerBlock);
+    size_t r = 0;  // first run not wholly before the slice
+    for (int x = 0; x < ik::kXcds; ++x) {
+      int b0, b1;
+      ik::xcd_range(x, nb, b0, b1);
+      const int32_t i0 = (int32_t)std::min<int64_t>(t->n_items, (int64_t)b0 * ik::kWavesPerBlock);
+      const int32_t i1 = (int32_t)std::min<int64_t>(t->n_items, (int64_t)b1 * ik::kWavesPerBlock);
+      pieces.clear();
+      while (r < t->h_runs.size() && t->h_runs[r].start + t->h_runs[r].len <= i0) ++r;
+      for (size_t k = r; k < t->h_runs.size() && t->h_runs[k].start < i1; ++k) {
+        const tagi_tree::Run& u = t->h_runs[k];
+        const double c = t->h_chunk_cost[u.chunk] * (t->h_chunk_far[u.chunk] ? far_w : 1.0);
+        pieces.push_back({std::max(u.start, i0), std::min(u.start + u.len, i1), c});
+      }
+      std::stable_sort(pieces.begin(), pieces.end(),
+                       [](const Piece& p, const Piece& q) { return p.cost > q.cost; });
+      int32_t pos = i0;
+      for (const Piece& p : pieces)
+        for (int32_t i = p.a; i < p.b; ++i) t->h_order[pos++] = base[i];
+      if (pos != i1) {
+        set_error("internal: launch order slice %d has %d of %d items", x, pos - i0, i1 - i0);
+        return TAGI_E_STATE;
+      }
+    }
+  }
+  TAGI_HIP(hipMemcpyAsync(t->item_order.p, t->h_order.data(), t->h_order.size() * 4,
+                          hipMemcpyHostToDevice, s));
+  TAGI_HIP(hipStreamSynchronize(s));  // the host order is reused by the next call
+  t->items_far_w = far_w;
+  return TAGI_OK;
+}
+
+// Far evaluation cost relative to a near one, from the instruction counts of the
+// interaction loops: FP64 Yukawa far 23 vs near 28; Coulomb-SS far 10.5 (the
+// Gaussian factors per dimension) vs 27; a Hermite point about 65. Mixed
+// precision keeps the chunk-major order (0): ordered by cost, its launches were
+// 7% slower on 8 benzene orbitals, where the FP64 ones gained 3-6%.
+double far_weight(int kernel, int precision, bool herm) {
+  const bool yuk = kernel == TAGI_YUKAWA_SS || kernel == TAGI_YUKAWA;
+  if (herm) return 2.3;
+  if (precision == TAGI_MIXED) return 0.0;
+  return yuk ? 0.8 : 0.4;
 }
 
 }  // namespace tagi
