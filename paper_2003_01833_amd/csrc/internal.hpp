@@ -272,6 +272,13 @@ int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s);
 int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s);
 // launch order of the schedule for far evaluations costing far_w near ones
 int order_schedule(tagi_tree* t, double far_w, hipStream_t s);
+// waves [start, start + len) of a launch list that read the same sources
+struct WaveRun {
+  int32_t start, len;
+  double cost;
+};
+// longest runs first within each XCD's range of the launch over `list`
+int order_runs_per_xcd(std::vector<int32_t>& list, const std::vector<WaveRun>& runs);
 double far_weight(int kernel, int precision, bool herm);
 int orbital_block(int kernel, int n_orb, int precision);
 // the tree's orbital block for a kernel: its override if set, else the default

@@ -459,6 +459,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     S.h_group_first.clear();
     S.h_group_base.assign(nl, 0);
     std::vector<std::vector<int32_t>> per(kNDeg + 1);
+    std::vector<std::vector<WaveRun>> per_runs(kNDeg + 1);
     for (int b = 0; b < nl; ++b) {
       const HostNode& q = t->nodes[t->leaves[b]];
       const int ng = (q.end - q.begin + kWave - 1) / kWave;
@@ -477,6 +478,8 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
         for (int cidx = 0; cidx < bc; ++cidx) {
           const int kindv = S.h_chunks[(size_t)(bf + cidx) * 4];
           const int slot = kindv == 1 ? kNDeg : kindv - 16 - kDegMin;
+          per_runs[slot].push_back({(int32_t)per[slot].size(), ng,
+                                    (double)S.h_chunks[(size_t)(bf + cidx) * 4 + 3]});
           for (int g = 0; g < ng; ++g)
             per[slot].push_back(S.h_group_first[S.h_group_base[b] + g] + o * bc + cidx);
         }
@@ -487,6 +490,9 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     S.list_degree.clear();
     for (int k = 0; k <= kNDeg; ++k) {
       if (per[k].empty()) continue;
+      // one launch per list: its chunks are all of one kind, so their costs
+      // compare directly
+      TAGI_TRY(order_runs_per_xcd(per[k], per_runs[k]));
       S.list_begin.push_back((int64_t)S.h_lists.size());
       S.list_degree.push_back(k < kNDeg ? kDegMin + k : 0);
       S.h_lists.insert(S.h_lists.end(), per[k].begin(), per[k].end());

@@ -331,46 +331,58 @@ int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
   return TAGI_OK;
 }
 
-// Launch order of the schedule for far evaluations that cost far_w near ones.
-// Within the slice of the launch order that each XCD runs (xcd_range), the most
-// expensive items go first, so that every slice ends on short items. The sort is
-// stable and moves whole runs of one chunk's waves, so those stay side by side
-// and chunks of equal cost keep their chunk-major order. far_w = 0 keeps the
-// chunk-major order. Results do not depend on the order.
+// Longest first within each XCD's range of one launch over list.size() waves
+// (xcd_range): runs of waves that read the same sources (start, len, cost; in
+// list order, covering the list) are stably sorted by descending cost inside each
+// range, so every XCD ends on short items, the waves of a run stay side by side
+// (a run cut by a range boundary is split) and equal-cost runs keep their order.
+int order_runs_per_xcd(std::vector<int32_t>& list, const std::vector<WaveRun>& runs) {
+  struct Piece {
+    int32_t a, b;
+    double cost;
+  };
+  const std::vector<int32_t> base = list;
+  const int64_t n = (int64_t)list.size();
+  const int nb = (int)((n + ik::kWavesPerBlock - 1) / ik::kWavesPerBlock);
+  std::vector<Piece> pieces;
+  size_t r = 0;  // first run not wholly before the range
+  for (int x = 0; x < ik::kXcds; ++x) {
+    int b0, b1;
+    ik::xcd_range(x, nb, b0, b1);
+    const int32_t i0 = (int32_t)std::min<int64_t>(n, (int64_t)b0 * ik::kWavesPerBlock);
+    const int32_t i1 = (int32_t)std::min<int64_t>(n, (int64_t)b1 * ik::kWavesPerBlock);
+    pieces.clear();
+    while (r < runs.size() && runs[r].start + runs[r].len <= i0) ++r;
+    for (size_t k = r; k < runs.size() && runs[k].start < i1; ++k)
+      pieces.push_back({std::max(runs[k].start, i0), std::min(runs[k].start + runs[k].len, i1),
+                        runs[k].cost});
+    std::stable_sort(pieces.begin(), pieces.end(),
+                     [](const Piece& p, const Piece& q) { return p.cost > q.cost; });
+    int32_t pos = i0;
+    for (const Piece& p : pieces)
+      for (int32_t i = p.a; i < p.b; ++i) list[pos++] = base[i];
+    if (pos != i1) {
+      set_error("internal: launch order range %d has %d of %d waves", x, pos - i0, i1 - i0);
+      return TAGI_E_STATE;
+    }
+  }
+  return TAGI_OK;
+}
+
+// Launch order of the schedule for far evaluations that cost far_w near ones
+// (order_runs_per_xcd over the chunk runs); far_w = 0 keeps the chunk-major
+// order. Results do not depend on the order.
 int order_schedule(tagi_tree* t, double far_w, hipStream_t s) {
   if (t->n_items == 0 || t->items_far_w == far_w) return TAGI_OK;
   t->h_order = t->h_order_base;
   if (far_w != 0.0) {
-    struct Piece {
-      int32_t a, b;
-      double cost;
-    };
-    std::vector<Piece> pieces;
-    const std::vector<int32_t>& base = t->h_order_base;
-    const int nb = (int)((t->n_items + ik::kWavesPerBlock - 1) / ik::kWavesPerBlock);
-    size_t r = 0;  // first run not wholly before the slice
-    for (int x = 0; x < ik::kXcds; ++x) {
-      int b0, b1;
-      ik::xcd_range(x, nb, b0, b1);
-      const int32_t i0 = (int32_t)std::min<int64_t>(t->n_items, (int64_t)b0 * ik::kWavesPerBlock);
-      const int32_t i1 = (int32_t)std::min<int64_t>(t->n_items, (int64_t)b1 * ik::kWavesPerBlock);
-      pieces.clear();
-      while (r < t->h_runs.size() && t->h_runs[r].start + t->h_runs[r].len <= i0) ++r;
-      for (size_t k = r; k < t->h_runs.size() && t->h_runs[k].start < i1; ++k) {
-        const tagi_tree::Run& u = t->h_runs[k];
-        const double c = t->h_chunk_cost[u.chunk] * (t->h_chunk_far[u.chunk] ? far_w : 1.0);
-        pieces.push_back({std::max(u.start, i0), std::min(u.start + u.len, i1), c});
-      }
-      std::stable_sort(pieces.begin(), pieces.end(),
-                       [](const Piece& p, const Piece& q) { return p.cost > q.cost; });
-      int32_t pos = i0;
-      for (const Piece& p : pieces)
-        for (int32_t i = p.a; i < p.b; ++i) t->h_order[pos++] = base[i];
-      if (pos != i1) {
-        set_error("internal: launch order slice %d has %d of %d items", x, pos - i0, i1 - i0);
-        return TAGI_E_STATE;
-      }
+    std::vector<WaveRun> runs(t->h_runs.size());
+    for (size_t k = 0; k < runs.size(); ++k) {
+      const tagi_tree::Run& u = t->h_runs[k];
+      runs[k] = {u.start, u.len,
+                 t->h_chunk_cost[u.chunk] * (t->h_chunk_far[u.chunk] ? far_w : 1.0)};
     }
+    TAGI_TRY(order_runs_per_xcd(t->h_order, runs));
   }
   TAGI_HIP(hipMemcpyAsync(t->item_order.p, t->h_order.data(), t->h_order.size() * 4,
                           hipMemcpyHostToDevice, s));
