@@ -139,11 +139,41 @@ struct LearnedState {
   int ob = 0;
   int64_t n_far = 0, n_near = 0, far_inter = 0, near_inter = 0;
   int64_t far_by_degree[kMaxDegree + 1] = {};
+  // streams (default priority) on which the per-degree launches run side by
+  // side, forked from and joined back to the caller's stream by events
+  static constexpr int kStreams = 4;
+  hipStream_t streams[kStreams] = {};
+  hipEvent_t fork = nullptr, join[kStreams] = {};
+  int ensure_streams() {
+    if (streams[0]) return TAGI_OK;
+    for (int k = 0; k < kStreams; ++k)
+      if (hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&join[k], hipEventDisableTiming) != hipSuccess) {
+        release_streams();
+        return TAGI_E_HIP;
+      }
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+      release_streams();
+      return TAGI_E_HIP;
+    }
+    return TAGI_OK;
+  }
+  void release_streams() {
+    for (int k = 0; k < kStreams; ++k) {
+      if (streams[k]) (void)hipStreamDestroy(streams[k]);
+      if (join[k]) (void)hipEventDestroy(join[k]);
+      streams[k] = nullptr;
+      join[k] = nullptr;
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    fork = nullptr;
+  }
   void release() {
     l1set.release();
     for (DBuf* b : {&l1n, &params, &cnt, &log, &far_id, &near_id, &chunks, &items, &group_first,
                     &group_base, &batch_chunks, &partial, &item_lists})
       b->release();
+    release_streams();
     key.clear();
     n_items = 0;
     log_cap = 0;

@@ -528,8 +528,35 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
   }
   const OrbArg orb = make_orb(kernel, n_orb, kappa, alpha);
   phase_begin(t, kPhaseInteract, s);
+  // The launches (one per degree, one for the near items) touch disjoint items
+  // and partial sums, so they run side by side on S.kStreams streams: the small
+  // high-degree launches cannot fill the GPU on their own. Largest first, each
+  // to the stream with the least work so far; all are forked from s and joined
+  // back to it.
+  const int n_launch = (int)S.list_begin.size() - 1;
+  std::vector<int> by_size(std::max(n_launch, 0));
+  for (int li = 0; li < n_launch; ++li) by_size[li] = li;
+  std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) {
+    return S.list_begin[a + 1] - S.list_begin[a] > S.list_begin[b + 1] - S.list_begin[b];
+  });
+  std::vector<int> stream_of(std::max(n_launch, 0), 0);
+  {
+    int64_t load[LearnedState::kStreams] = {};
+    for (int li : by_size) {
+      int k = 0;
+      for (int j = 1; j < LearnedState::kStreams; ++j)
+        if (load[j] < load[k]) k = j;
+      stream_of[li] = k;
+      load[k] += S.list_begin[li + 1] - S.list_begin[li];
+    }
+  }
+  TAGI_TRY(S.ensure_streams());
+  TAGI_HIP(hipEventRecord(S.fork, s));
+  for (int k = 0; k < LearnedState::kStreams; ++k)
+    TAGI_HIP(hipStreamWaitEvent(S.streams[k], S.fork, 0));
   for (size_t li = 0; li + 1 < S.list_begin.size(); ++li) {
     const int d = S.list_degree[li];
+    hipStream_t ls = S.streams[stream_of[li]];
     InteractArgs A{};
     A.items = S.items.as<int4>();
     A.n_items = S.n_items;
@@ -568,10 +595,14 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     }
     ++t->interact_launches;
     if (kernel == TAGI_YUKAWA_SS)
-      launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, s);
+      launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, ls);
     else
-      launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, s);
+      launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, ls);
     TAGI_HIP(hipGetLastError());
+  }
+  for (int k = 0; k < LearnedState::kStreams; ++k) {
+    TAGI_HIP(hipEventRecord(S.join[k], S.streams[k]));
+    TAGI_HIP(hipStreamWaitEvent(s, S.join[k], 0));
   }
   phase_end(t, kPhaseInteract, s);
   phase_begin(t, kPhaseCombine, s);
