@@ -511,28 +511,24 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     TAGI_HIP(hipStreamSynchronize(s));
     S.ob = ob;
   }
-  // proxy charges at every degree in use, from the current tree-ordered values
   const bool mix = precision == TAGI_MIXED;
-  for (size_t li = 0; li + 1 < S.list_begin.size(); ++li) {
-    const int d = S.list_degree[li];
-    if (d == 0) continue;
-    ProxySet& ps = t->lx[d];
-    TAGI_TRY(compute_proxies(t, ps, s));
-    if (mix) {
+  if (mix) {  // FP32 copies of the proxy charges (allocation before the fork)
+    for (size_t li = 0; li + 1 < S.list_begin.size(); ++li) {
+      const int d = S.list_degree[li];
+      if (d == 0) continue;
+      ProxySet& ps = t->lx[d];
       const int64_t K = (int64_t)(d + 1) * (d + 1) * (d + 1);
       TAGI_TRY(ps.qhat32.ensure((size_t)n_orb * ps.n_approx * K * sizeof(float)));
       TAGI_TRY(ps.what32.ensure((size_t)ps.n_approx * K * sizeof(float)));
-      TAGI_TRY(launch_to_f32(ps.qhat.as<double>(), ps.qhat32.as<float>(), n_orb * ps.n_approx * K, s));
-      TAGI_TRY(launch_to_f32(ps.what.as<double>(), ps.what32.as<float>(), ps.n_approx * K, s));
     }
   }
   const OrbArg orb = make_orb(kernel, n_orb, kappa, alpha);
   phase_begin(t, kPhaseInteract, s);
   // The launches (one per degree, one for the near items) touch disjoint items
-  // and partial sums, so they run side by side on S.kStreams streams: the small
-  // high-degree launches cannot fill the GPU on their own. Largest first, each
-  // to the stream with the least work so far; all are forked from s and joined
-  // back to it.
+  // and partial sums, so they run side by side on S.kStreams streams, each after
+  // its degree's proxy charges on the same stream: the small high-degree
+  // launches cannot fill the GPU on their own. Largest first, each to the stream
+  // with the least work so far; all are forked from s and joined back to it.
   const int n_launch = (int)S.list_begin.size() - 1;
   std::vector<int> by_size(std::max(n_launch, 0));
   for (int li = 0; li < n_launch; ++li) by_size[li] = li;
@@ -557,6 +553,17 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
   for (size_t li = 0; li + 1 < S.list_begin.size(); ++li) {
     const int d = S.list_degree[li];
     hipStream_t ls = S.streams[stream_of[li]];
+    if (d > 0) {
+      // this degree's proxy charges, from the current tree-ordered values, on
+      // the stream of the launch that reads them
+      ProxySet& ps = t->lx[d];
+      TAGI_TRY(compute_proxies(t, ps, ls));
+      if (mix) {
+        const int64_t K = (int64_t)(d + 1) * (d + 1) * (d + 1);
+        TAGI_TRY(launch_to_f32(ps.qhat.as<double>(), ps.qhat32.as<float>(), n_orb * ps.n_approx * K, ls));
+        TAGI_TRY(launch_to_f32(ps.what.as<double>(), ps.what32.as<float>(), ps.n_approx * K, ls));
+      }
+    }
     InteractArgs A{};
     A.items = S.items.as<int4>();
     A.n_items = S.n_items;
