@@ -43,7 +43,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kStage = 64;         // sources whose basis values sit in LDS at once
-constexpr int kItemPts = 8192;     // sources per work item
+constexpr int kItemPts = 2048;     // sources per work item
 
 struct UpItem {
   int32_t slot, p0, p1, part;  // part: index of this item's partial block
