@@ -62,6 +62,30 @@ FLOPS = {
 }
 
 
+# Coulomb-SS near pairs in clusters at least 6.12 alpha from the batch skip the
+# Gaussian term: squared distance (8), reciprocal square root (7), one
+# multiply-add (2)
+COULOMB_NEAR_1R_FLOPS = 8 + 7 + 2
+GAUSS_SKIP = 37.5  # (box gap / alpha)^2 above which the kernel skips the Gaussian
+
+
+def coulomb_gauss_skipped(tagi, x, y, z, leaf, box, theta, degree, alpha=1.0):
+    """Near evaluations of a Coulomb-SS convolution that take the 1/d-only path:
+    pairs of (batch, near cluster) whose boxes lie at least 6.12 alpha apart, by
+    the kernel's own rule applied to the exported tree and lists."""
+    t = tagi.Tree(x, y, z, leaf, box)
+    e = t.export()
+    L = t.lists(theta, degree)
+    t.close()
+    leaves = np.nonzero(e["n_child"] == 0)[0]
+    cnt = (e["end"] - e["begin"]).astype(np.int64)
+    B = np.repeat(leaves, np.diff(L["near_off"]))
+    C = L["near_id"]
+    gap = np.maximum(0.0, np.maximum(e["lo"][C] - e["hi"][B], e["lo"][B] - e["hi"][C]))
+    skip = (gap * gap).sum(axis=1) / (alpha * alpha) > GAUSS_SKIP
+    return int((cnt[B] * cnt[C])[skip].sum())
+
+
 # counter profile of the interaction kernel and the sources it was taken from
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_interact_atom_mesh_Z4.md")
 KERNEL_SOURCES = ["interact_impl.hpp", "devmath.hpp", "interact_yukawa_ss.hip",
@@ -475,6 +499,12 @@ def main():
     flops = sum(st["far_interactions"] * FLOPS[(c["kernel"], "far")] +
                 st["near_interactions"] * FLOPS[(c["kernel"], "near")]
                 for c, st in zip(fields, sts))
+    gauss_skipped = 0
+    for c in fields:
+        if c["kernel"] == "coulomb_ss":
+            gauss_skipped += coulomb_gauss_skipped(tagi, x, y, z, leaf, wl["box"], c["theta"],
+                                                   c["degree"])
+    flops -= gauss_skipped * (FLOPS[("coulomb_ss", "near")] - COULOMB_NEAR_1R_FLOPS)
     interact_s = phases["interact_ms"] / 1e3
     achieved = flops / interact_s / 1e12
     launches = records[-1][0]["interact_launches"]
@@ -526,7 +556,8 @@ def main():
                                               "far_pairs": st["n_far_pairs"],
                                               "near_pairs": st["n_near_pairs"]}
                                 for c, st in zip(fields, sts)},
-                   "n_leaves": sts[0]["n_leaves"], "interactions_per_step": interactions},
+                   "n_leaves": sts[0]["n_leaves"], "interactions_per_step": interactions,
+                   "coulomb_near_without_gaussian": gauss_skipped},
         "roofline": {"bound": "alu", "kernel": "k_interact", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,

@@ -598,6 +598,27 @@ void k_interact(InteractArgs A, OrbArg orb) {
     for (int o = 0; o < OB; ++o) qr[o] = A.qs + (int64_t)orb_row[o] * A.n;
     for (int e = ch.e0; e < ch.e1; ++e) {
       const int C = A.near_id[e];
+      if constexpr (KER == TAGI_COULOMB_SS) {
+        // If the cluster's box lies at least 6.12 a from the batch's box, every
+        // pair has exp(-d^2/a^2) < exp(-37.5) < 2^-54: its Gaussian terms are
+        // below the FP64 resolution of the subtracted sum, and only the 1/d part
+        // is summed. Such a cluster cannot hold a target either.
+        if (A.box) {
+          const double* bb = A.box + (int64_t)B * 6;
+          const double* bc = A.box + (int64_t)C * 6;
+          double g2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double gap = fmax(0.0, fmax(bc[d] - bb[3 + d], bb[d] - bc[3 + d]));
+            g2 = __builtin_fma(gap, gap, g2);
+          }
+          if (g2 * A.ia2 > 37.5) {
+            near_range<TAGI_COULOMB, OB, false>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys,
+                                                A.zs, A.ws, qr, kl2, al2, a1, a2);
+            continue;
+          }
+        }
+      }
       // A source can only coincide with a target inside the cluster's (closed)
       // bounding box; the coincidence test is needed only when some lane's target
       // lies in it.

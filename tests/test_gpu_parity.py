@@ -171,6 +171,22 @@ def test_treecode_matches_oracle_treecode(ragged_tree, kernel):
         assert np.all(np.abs(u[o] - ref[o]) <= 1e-12 * S), (o, np.max(np.abs(u[o] - ref[o]) / S))
 
 
+def test_coulomb_ss_narrow_gaussian_matches_oracle(ragged_tree):
+    # alpha = 0.1: about a third of the near work lies in clusters whose boxes are
+    # at least 6.12 alpha from the batch, where the kernel sums only the 1/d part
+    # (every Gaussian term there is below 2^-54); the oracle sums every term
+    c = ragged_tree
+    t = c["t"]
+    deg, theta, alpha = 5, 0.65, 0.1
+    dF, dw = _dev(c["f"], c["w"])
+    t.upward(dF, dw, deg)
+    u = t.convolve("coulomb_ss", 1.0, theta, deg, alpha=alpha).cpu().numpy()[0]
+    ref = bltc.treecode(c["x"], c["y"], c["z"], c["f"], c["w"], "coulomb_ss", 1.0, theta, deg,
+                        200, alpha=alpha, tree=c["ref"])[0]
+    S = _scale("coulomb_ss", c["x"], c["y"], c["z"], c["f"], c["w"], 1.0, alpha=alpha)
+    assert np.all(np.abs(u - ref) <= 1e-12 * S), np.max(np.abs(u - ref) / S)
+
+
 @pytest.mark.parametrize("kernel,n_orb,degree,theta", [
     ("coulomb_ss", 9, 8, 0.8),   # orbital blocks of 8 and a ragged last block; separable Gaussian
     ("yukawa_ss", 5, 9, 0.8),    # blocks of 4 and 1; proxy rows taken in steps
