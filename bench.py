@@ -62,28 +62,36 @@ FLOPS = {
 }
 
 
-# Coulomb-SS near pairs in clusters at least 6.12 alpha from the batch skip the
-# Gaussian term: squared distance (8), reciprocal square root (7), one
+# Coulomb-SS pairs between boxes at least 6.12 alpha apart skip the Gaussian
+# term (its value is below 2^-54): a near evaluation is then squared distance (8),
+# reciprocal square root (7) and one multiply-add (2); a far one (blocks of up to
+# 4 orbitals, FP64) squared distance (3), reciprocal square root (7) and one
 # multiply-add (2)
 COULOMB_NEAR_1R_FLOPS = 8 + 7 + 2
+COULOMB_FAR_1R_FLOPS = 3 + 7 + 2
 GAUSS_SKIP = 37.5  # (box gap / alpha)^2 above which the kernel skips the Gaussian
 
 
 def coulomb_gauss_skipped(tagi, x, y, z, leaf, box, theta, degree, alpha=1.0):
-    """Near evaluations of a Coulomb-SS convolution that take the 1/d-only path:
-    pairs of (batch, near cluster) whose boxes lie at least 6.12 alpha apart, by
-    the kernel's own rule applied to the exported tree and lists."""
+    """(near, far) evaluations of a Coulomb-SS convolution that take the 1/d-only
+    path: (batch, cluster) pairs whose boxes lie at least 6.12 alpha apart, by the
+    kernel's own rule applied to the exported tree and lists."""
     t = tagi.Tree(x, y, z, leaf, box)
     e = t.export()
     L = t.lists(theta, degree)
     t.close()
     leaves = np.nonzero(e["n_child"] == 0)[0]
     cnt = (e["end"] - e["begin"]).astype(np.int64)
-    B = np.repeat(leaves, np.diff(L["near_off"]))
-    C = L["near_id"]
-    gap = np.maximum(0.0, np.maximum(e["lo"][C] - e["hi"][B], e["lo"][B] - e["hi"][C]))
-    skip = (gap * gap).sum(axis=1) / (alpha * alpha) > GAUSS_SKIP
-    return int((cnt[B] * cnt[C])[skip].sum())
+
+    def skipped(off, ids, per_cluster):
+        B = np.repeat(leaves, np.diff(off))
+        gap = np.maximum(0.0, np.maximum(e["lo"][ids] - e["hi"][B], e["lo"][B] - e["hi"][ids]))
+        skip = (gap * gap).sum(axis=1) / (alpha * alpha) > GAUSS_SKIP
+        return int((cnt[B] * per_cluster(ids))[skip].sum())
+
+    near = skipped(L["near_off"], L["near_id"], lambda C: cnt[C])
+    far = skipped(L["far_off"], L["far_id"], lambda C: np.int64((degree + 1) ** 3))
+    return near, far
 
 
 # counter profile of the interaction kernel and the sources it was taken from
@@ -499,12 +507,14 @@ def main():
     flops = sum(st["far_interactions"] * FLOPS[(c["kernel"], "far")] +
                 st["near_interactions"] * FLOPS[(c["kernel"], "near")]
                 for c, st in zip(fields, sts))
-    gauss_skipped = 0
+    gauss_near = gauss_far = 0
     for c in fields:
         if c["kernel"] == "coulomb_ss":
-            gauss_skipped += coulomb_gauss_skipped(tagi, x, y, z, leaf, wl["box"], c["theta"],
-                                                   c["degree"])
-    flops -= gauss_skipped * (FLOPS[("coulomb_ss", "near")] - COULOMB_NEAR_1R_FLOPS)
+            sn, sf = coulomb_gauss_skipped(tagi, x, y, z, leaf, wl["box"], c["theta"], c["degree"])
+            gauss_near += sn
+            gauss_far += sf
+    flops -= gauss_near * (FLOPS[("coulomb_ss", "near")] - COULOMB_NEAR_1R_FLOPS)
+    flops -= gauss_far * (FLOPS[("coulomb_ss", "far")] - COULOMB_FAR_1R_FLOPS)
     interact_s = phases["interact_ms"] / 1e3
     achieved = flops / interact_s / 1e12
     launches = records[-1][0]["interact_launches"]
@@ -557,7 +567,8 @@ def main():
                                               "near_pairs": st["n_near_pairs"]}
                                 for c, st in zip(fields, sts)},
                    "n_leaves": sts[0]["n_leaves"], "interactions_per_step": interactions,
-                   "coulomb_near_without_gaussian": gauss_skipped},
+                   "coulomb_evaluations_without_gaussian": {"near": gauss_near,
+                                                             "far": gauss_far}},
         "roofline": {"bound": "alu", "kernel": "k_interact", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,

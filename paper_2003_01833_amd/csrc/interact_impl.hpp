@@ -505,6 +505,23 @@ __host__ __device__ inline void xcd_range(int x, int nb, int& b0, int& b1) {
   b1 = b0 + q + (x < r ? 1 : 0);
 }
 
+// The Gaussian of the Coulomb-SS kernel, exp(-d^2/a^2), is below
+// exp(-37.5) < 2^-54 for every pair between the boxes of nodes B and C when they
+// lie at least 6.12 a apart: such terms are below the FP64 resolution of the
+// subtracted sum. Proxy points lie in their cluster's box.
+__device__ __forceinline__ bool gauss_negligible(const InteractArgs& A, int B, int C) {
+  if (!A.box) return false;
+  const double* bb = A.box + (int64_t)B * 6;
+  const double* bc = A.box + (int64_t)C * 6;
+  double g2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double gap = fmax(0.0, fmax(bc[d] - bb[3 + d], bb[d] - bc[3 + d]));
+    g2 = __builtin_fma(gap, gap, g2);
+  }
+  return g2 * A.ia2 > 37.5;
+}
+
 // Far-field forms of the interaction kernel
 constexpr int kModeFp64 = 0, kModeMixed = 1, kModeHermite = 2;
 
@@ -584,12 +601,23 @@ void k_interact(InteractArgs A, OrbArg orb) {
         const double* qk[OB];
 #pragma unroll
         for (int o = 0; o < OB; ++o) qk[o] = A.qhat + ((int64_t)orb_row[o] * A.n_approx + slot) * K;
-        if constexpr (MODE == kModeHermite)
+        if constexpr (MODE == kModeHermite) {
           far_cluster_herm<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
                                          A.what + (int64_t)slot * K, qk, kl2, al2, a1, a2);
-        else
-          far_cluster<KER, OB, NP1>(xi, yi, zi, np1, A.pnodes + (int64_t)slot * 3 * np1,
-                                    A.what + (int64_t)slot * K, qk, kl2, al2, a1, a2);
+        } else {
+          const double* pn = A.pnodes + (int64_t)slot * 3 * np1;
+          const double* wk = A.what + (int64_t)slot * K;
+          if constexpr (KER == TAGI_COULOMB_SS && OB <= 4) {
+            // only the 1/d part where the Gaussian is negligible (not for blocks of
+            // 8 orbitals: the second far loop makes their near loop spill)
+            if (gauss_negligible(A, B, C))
+              far_cluster<TAGI_COULOMB, OB, NP1>(xi, yi, zi, np1, pn, wk, qk, kl2, al2, a1, a2);
+            else
+              far_cluster<KER, OB, NP1>(xi, yi, zi, np1, pn, wk, qk, kl2, al2, a1, a2);
+          } else {
+            far_cluster<KER, OB, NP1>(xi, yi, zi, np1, pn, wk, qk, kl2, al2, a1, a2);
+          }
+        }
       }
     }
   } else {
@@ -599,24 +627,12 @@ void k_interact(InteractArgs A, OrbArg orb) {
     for (int e = ch.e0; e < ch.e1; ++e) {
       const int C = A.near_id[e];
       if constexpr (KER == TAGI_COULOMB_SS) {
-        // If the cluster's box lies at least 6.12 a from the batch's box, every
-        // pair has exp(-d^2/a^2) < exp(-37.5) < 2^-54: its Gaussian terms are
-        // below the FP64 resolution of the subtracted sum, and only the 1/d part
-        // is summed. Such a cluster cannot hold a target either.
-        if (A.box) {
-          const double* bb = A.box + (int64_t)B * 6;
-          const double* bc = A.box + (int64_t)C * 6;
-          double g2 = 0.0;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const double gap = fmax(0.0, fmax(bc[d] - bb[3 + d], bb[d] - bc[3 + d]));
-            g2 = __builtin_fma(gap, gap, g2);
-          }
-          if (g2 * A.ia2 > 37.5) {
-            near_range<TAGI_COULOMB, OB, false>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys,
-                                                A.zs, A.ws, qr, kl2, al2, a1, a2);
-            continue;
-          }
+        // only the 1/d part where the Gaussian is negligible (such a cluster
+        // cannot hold a target either)
+        if (gauss_negligible(A, B, C)) {
+          near_range<TAGI_COULOMB, OB, false>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys,
+                                              A.zs, A.ws, qr, kl2, al2, a1, a2);
+          continue;
         }
       }
       // A source can only coincide with a target inside the cluster's (closed)
