@@ -25,6 +25,11 @@ namespace tagi {
 namespace {
 
 constexpr int kStack = 512;
+// One wave per block. Each lane's traversal stack lives in LDS, laid out
+// [entry][lane] (128 KB per block), so every access by a lane falls in its own
+// bank; a stack in a per-thread array with a dynamic index would go through
+// scratch memory, one memory round trip per pop.
+constexpr int kListBlock = 64;
 
 __device__ __forceinline__ bool distance_ok(const double* __restrict__ geom, int B, int C,
                                             double theta) {
@@ -38,7 +43,7 @@ __device__ __forceinline__ bool distance_ok(const double* __restrict__ geom, int
 
 // fill == 0: write counts (far pairs, near pairs, near sources) per batch;
 // fill == 1: write the ids at the given offsets.
-__global__ void k_lists(int n_leaves, const int32_t* __restrict__ leaf_node,
+__global__ __launch_bounds__(kListBlock) void k_lists(int n_leaves, const int32_t* __restrict__ leaf_node,
                         const double* __restrict__ geom, const int32_t* __restrict__ nbeg,
                         const int32_t* __restrict__ nend, const int32_t* __restrict__ first_child,
                         const int32_t* __restrict__ n_child, double theta, int K, int fill,
@@ -46,16 +51,17 @@ __global__ void k_lists(int n_leaves, const int32_t* __restrict__ leaf_node,
                         int64_t* __restrict__ near_src, const int64_t* __restrict__ far_off,
                         const int64_t* __restrict__ near_off, int32_t* __restrict__ far_id,
                         int32_t* __restrict__ near_id, int32_t* __restrict__ overflow) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ int32_t stack[kStack][kListBlock];
+  const int lane = threadIdx.x;
+  const int b = blockIdx.x * kListBlock + lane;
   if (b >= n_leaves) return;
   const int B = leaf_node[b];
-  int stack[kStack];
   int sp = 0;
-  stack[sp++] = 0;
+  stack[sp++][lane] = 0;
   int64_t nf = 0, nn = 0, ns = 0;
   int64_t fo = fill ? far_off[b] : 0, no = fill ? near_off[b] : 0;
   while (sp > 0) {
-    const int C = stack[--sp];
+    const int C = stack[--sp][lane];
     const int cnt = nend[C] - nbeg[C];
     const bool dist = distance_ok(geom, B, C, theta);
     const bool size = K < cnt;
@@ -79,7 +85,7 @@ __global__ void k_lists(int n_leaves, const int32_t* __restrict__ leaf_node,
         atomicExch(overflow, 1);
         return;
       }
-      for (int k = nc - 1; k >= 0; --k) stack[sp++] = fc + k;
+      for (int k = nc - 1; k >= 0; --k) stack[sp++][lane] = fc + k;
     }
   }
   if (!fill) {
@@ -146,7 +152,7 @@ int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
   int64_t* d_near_src = d_near_cnt + nl;
   int32_t* d_over = reinterpret_cast<int32_t*>(d_near_src + nl);
   TAGI_HIP(hipMemsetAsync(d_over, 0, sizeof(int32_t), s));
-  const int blk = 128, grid = (nl + blk - 1) / blk;
+  const int blk = kListBlock, grid = (nl + blk - 1) / blk;
   hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, t->leaf_node.as<int32_t>(),
                      t->nd_geom.as<double>(), t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(),
                      t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K_mac, 0,
