@@ -128,6 +128,28 @@ def test_lists_match_oracle_exactly(ragged_tree, theta, degree):
         assert list(L["near_id"][L["near_off"][b]:L["near_off"][b + 1]]) == near[b]
 
 
+def test_lists_on_a_deep_adaptive_mesh_match_oracle_exactly():
+    # a small Be-like mesh refined toward the nucleus (10,800 points in cells of
+    # 27) with leaves of at most 8 points: nine levels of clusters, the deepest
+    # traversals of the list tests, over a thousand batches
+    tagi = _tag()
+    d = atom_mesh(tol_m=1e-3, p=2, uniform_levels=1)
+    x, y, z = d["x"], d["y"], d["z"]
+    t = tagi.Tree(*_dev(x, y, z), leaf_size=8, box=(-20, -20, -20, 20, 20, 20))
+    ref = bltc.build_tree(x, y, z, 8, domain=((-20, -20, -20), (20, 20, 20)))
+    assert int(np.max(ref.level)) >= 9
+    e = t.export()
+    assert np.array_equal(e["begin"], ref.begin) and np.array_equal(e["end"], ref.end)
+    for theta, degree in ((0.7, 1), (0.5, 2)):
+        batches, far, near = bltc.interaction_lists(ref, theta, degree)
+        assert len(batches) > 1000
+        L = t.lists(theta, degree)
+        assert L["far_id"].tolist() == [C for fl in far for C in fl]
+        assert L["near_id"].tolist() == [C for nl in near for C in nl]
+        assert np.array_equal(L["far_off"], np.cumsum([0] + [len(fl) for fl in far]))
+        assert np.array_equal(L["near_off"], np.cumsum([0] + [len(nl) for nl in near]))
+
+
 def test_upward_matches_oracle(ragged_tree):
     c = ragged_tree
     t, ref = c["t"], c["ref"]
