@@ -210,36 +210,57 @@ def proxy_charges(px, py, pz, q, lo, hi, n):
 # ----------------------------------------------------------------------------------
 # Section 6.3: Algorithm 3
 
-def interaction_lists(tree: Tree, theta: float, n: int, ncoef: int | None = None):
-    """Per batch (leaf, in node order): (far clusters, near clusters) from
-    ComputePotential(B, root). `ncoef` is the size part of the MAC (a cluster is
+FAR, NEAR, OPEN = "far", "near", "open"
+
+
+def classify(dist_ok: bool, size_ok: bool, leaf: bool) -> str:
+    """Outcome of one batch-cluster pair under Eq. MAC (Section 6.2) and the
+    ComputePotential step of Algorithm 3 (Section 6.3).
+
+    The approximation is used only when both parts of the MAC hold: the cluster
+    is well separated from the batch (distance part) and holds more sources than
+    the approximation has proxy charges (size part). A well-separated cluster that
+    is too small is summed directly as a whole. A cluster that is not well
+    separated is resolved into its children, unless it has none, in which case
+    it is summed directly."""
+    if dist_ok:
+        return FAR if size_ok else NEAR
+    return NEAR if leaf else OPEN
+
+
+def interaction_lists(tree: Tree, theta: float, n: int, ncoef: int | None = None,
+                      batch_tree: Tree | None = None):
+    """Per target batch: (far clusters, near clusters) of the source tree, in the
+    order a depth-first visit from the root that takes children in order meets
+    them (Algorithm 3 starts that visit at the root for every batch).
+
+    Batches are the leaves of `batch_tree` (default: the source tree itself, when
+    targets are the sources). `ncoef` is the size part of the MAC (a cluster is
     approximated only if ncoef < N_S), (n+1)^3 unless given. Returns (batches,
-    far, near)."""
+    far, near) with batches the leaf ids of the batch tree in node order."""
     cen, rad = geometry(tree)
+    bt = tree if batch_tree is None else batch_tree
+    bcen, brad = geometry(bt)
     if ncoef is None:
         ncoef = (n + 1) ** 3
-    batches = tree.leaves()
+    batches = bt.leaves()
     far, near = [], []
     for B in batches:
         fl, nl = [], []
-
-        def compute_potential(C):
-            d = cen[B] - cen[C]
+        work = [0]  # clusters still to classify; the last one is taken next
+        while work:
+            C = work.pop()
+            d = bcen[B] - cen[C]
             R = np.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
-            dist_ok = (rad[B] + rad[C]) < theta * R
+            dist_ok = bool((brad[B] + rad[C]) < theta * R)
             size_ok = ncoef < tree.count(C)
-            if dist_ok and size_ok:
+            kind = classify(dist_ok, size_ok, tree.is_leaf(C))
+            if kind == FAR:
                 fl.append(C)
-            elif not dist_ok:
-                if tree.is_leaf(C):
-                    nl.append(C)
-                else:
-                    for ch in tree.children[C]:
-                        compute_potential(ch)
-            else:
+            elif kind == NEAR:
                 nl.append(C)
-
-        compute_potential(0)
+            else:
+                work.extend(reversed(tree.children[C]))
         far.append(fl)
         near.append(nl)
     return batches, far, near
@@ -258,9 +279,18 @@ def _pair_kernel(kernel, d, d2, kappa, alpha):
 
 
 def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_size: int,
-             alpha: float = 1.0, domain=None, tree: Tree | None = None, return_parts=False):
-    """u (n_orb, N) in the caller's order. f may be (N,) or (n_orb, N); kappa a
-    scalar or per-orbital sequence (Yukawa only)."""
+             alpha: float = 1.0, domain=None, tree: Tree | None = None, return_parts=False,
+             targets=None):
+    """u (n_orb, N_t) in the caller's target order. f may be (N,) or (n_orb, N);
+    kappa a scalar or per-orbital sequence (Yukawa only).
+
+    targets: None (the targets are the sources: batches are the source tree's
+    leaves), or (tx, ty, tz, tf) with tf of shape (N_t,) or (n_orb, N_t) (the
+    values f_i of the subtracted kernels; may be None for the plain ones). The
+    target batches are then the leaves of a tree built on the targets by the same
+    rule (Section 6.1), with N_B = N_L and the root box the targets' bounding box.
+    Pairs at distance exactly zero are skipped, so targets that coincide with
+    sources are well defined."""
     x = np.asarray(x, np.float64)
     y = np.asarray(y, np.float64)
     z = np.asarray(z, np.float64)
@@ -275,6 +305,19 @@ def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
     X, Y, Zs, W = x[perm], y[perm], z[perm], w[perm]
     F = f[:, perm]
     Q = F * W[None, :]
+    if targets is None:
+        btree = tree
+        TX, TY, TZ, TF = X, Y, Zs, F
+        n_t = N
+    else:
+        tx, ty, tz = (np.asarray(a, np.float64) for a in targets[:3])
+        n_t = tx.size
+        tf = targets[3]
+        tf = (np.zeros((n_orb, n_t)) if tf is None
+              else np.broadcast_to(np.atleast_2d(np.asarray(tf, np.float64)), (n_orb, n_t)))
+        btree = build_tree(tx, ty, tz, leaf_size)
+        tp = btree.perm
+        TX, TY, TZ, TF = tx[tp], ty[tp], tz[tp], tf[:, tp]
     ncoef = (degree + 1) ** 3
     # proxy charges of every cluster that can ever be approximated
     nodes, fhat, what = {}, {}, {}
@@ -287,20 +330,21 @@ def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
             fhat[c] = ch[:n_orb].reshape(n_orb, -1)
             what[c] = ch[n_orb].reshape(-1)
     # batch-cluster interactions
-    batches, far, near = interaction_lists(tree, theta, degree)
-    U = np.zeros((n_orb, N))
+    batches, far, near = interaction_lists(tree, theta, degree,
+                                           batch_tree=None if targets is None else btree)
+    U = np.zeros((n_orb, n_t))
     for B, fl, nl in zip(batches, far, near):
-        b0, b1 = tree.begin[B], tree.end[B]
-        tx, ty, tz = X[b0:b1, None], Y[b0:b1, None], Zs[b0:b1, None]
+        b0, b1 = btree.begin[B], btree.end[B]
+        tx_, ty_, tz_ = TX[b0:b1, None], TY[b0:b1, None], TZ[b0:b1, None]
         for o in range(n_orb):
             acc = np.zeros(b1 - b0)
-            fi = F[o, b0:b1]
+            fi = TF[o, b0:b1]
             for C in fl:
                 sx, sy, sz = nodes[C]
                 gx, gy, gz = np.meshgrid(sx, sy, sz, indexing="ij")
-                dx = tx - gx.reshape(1, -1)
-                dy = ty - gy.reshape(1, -1)
-                dz = tz - gz.reshape(1, -1)
+                dx = tx_ - gx.reshape(1, -1)
+                dy = ty_ - gy.reshape(1, -1)
+                dz = tz_ - gz.reshape(1, -1)
                 d2 = dx * dx + dy * dy + dz * dz
                 d = np.sqrt(d2)
                 k1, k2 = _pair_kernel(kernel, d, d2, kap[o], alpha)
@@ -309,9 +353,9 @@ def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
                     acc -= fi * (k2 @ what[C])
             for C in nl:
                 s0, s1 = tree.begin[C], tree.end[C]
-                dx = tx - X[None, s0:s1]
-                dy = ty - Y[None, s0:s1]
-                dz = tz - Zs[None, s0:s1]
+                dx = tx_ - X[None, s0:s1]
+                dy = ty_ - Y[None, s0:s1]
+                dz = tz_ - Zs[None, s0:s1]
                 d2 = dx * dx + dy * dy + dz * dz
                 d = np.sqrt(d2)
                 zero = d == 0.0
@@ -328,8 +372,8 @@ def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
                 acc += 2.0 * np.pi * alpha * alpha * fi
             U[o, b0:b1] = acc
     out = np.empty_like(U)
-    out[:, perm] = U
+    out[:, btree.perm] = U
     if return_parts:
-        return out, dict(tree=tree, batches=batches, far=far, near=near, fhat=fhat, what=what,
-                         nodes=nodes)
+        return out, dict(tree=tree, batch_tree=btree, batches=batches, far=far, near=near,
+                         fhat=fhat, what=what, nodes=nodes)
     return out

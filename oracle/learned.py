@@ -1,25 +1,41 @@
 """ORACLE (test infrastructure only): the learned degree/MAC selection of the
-interaction lists, in plain numpy FP64.
+interaction lists, and the treecode sum over such lists, in plain numpy FP64.
 
 Only tests/, the smoke check and the benchmark's CPU-baseline leg may import this.
 
-The selection is a project addition on Algorithm 3 (Section 6.3): the
-ComputePotential traversal of every target batch from the root, where a pair
-that passes the permissive test (r_B + r_C) < theta_max R and holds more than
-(4+1)^3 sources is approximated at the lowest degree n in 4..12 with
-(n+1)^3 < N_S whose predicted error meets every orbital's budget, else opened
-(a leaf, or a pair failing theta_max at a leaf, is summed directly; a pair with
-at most 125 sources is summed directly). Per orbital, the network (oracle/mlp.py)
-sees the log-features (r_C, R - r_B, kappa, N_S, l1), standardised, with
-l1 = |q^|_1 + max_B |f| |w^|_1 from the cluster's degree-4 proxy charges of f w
-and of w (Section 6.2), and predicts log10 error minus the pair scale
-log10(l1) - kappa (R - r_B) log10(e) - log10(R - r_B). If any orbital's raw
-log-feature lies outside the training range [lo, hi], the pair takes the fixed
-MAC (theta_fb, degree_fb) of Algorithm 3 instead.
+The selection is a project addition on Algorithm 3 (Section 6.3). Every target
+batch B visits the source tree depth first from the root, children in order. A
+cluster C that fails the permissive distance test (r_B + r_C) < theta_max R is
+resolved into its children (a leaf is summed directly), as Algorithm 3 does. A
+cluster that passes it and holds at most (4+1)^3 sources is summed directly (no
+degree has fewer charges than sources). Otherwise, per orbital o, the network
+(oracle/mlp.py) sees the log-features
 
-The GPU evaluates the network in FP32; decisions whose margin (distance of a
-compared quantity from its threshold, in log units) is below `tie` can
-legitimately differ, and `learned_lists` reports them as ties.
+    (r_C, d = R - r_B, c_o, N_S, l1_o),   standardised as (ln raw - shift) * scale,
+
+with c_o = kappa_o for the Yukawa kernels, the Gaussian width alpha for the
+subtracted Coulomb kernel and 1 for the plain one, and
+l1_o = |q^_o|_1 + max_B |f_o| |w^|_1 from C's degree-4 proxy charges of f w and
+of w (Section 6.2), a bound on the l1 norm of the subtracted charges
+q^ - f_i w^. It predicts, for degrees 4..12, log10 of the pair's largest error
+minus the pair scale s_o = log10(l1_o) - kappa_o d log10(e) - log10(d) (kappa_o = 0
+for the Coulomb kernels: s_o is log10 of the size of the pair's far field). The
+pair is approximated at the lowest degree n with (n+1)^3 < N_S whose predicted
+error meets the batch's budget for every orbital (the largest such degree over
+the orbitals is used), and resolved into its children otherwise (a leaf is
+summed directly). If any orbital's log-feature lies outside the training range
+[lo, hi], the pair takes the fixed MAC (theta_fb, degree_fb) of Algorithm 3.
+
+Budget of a batch: a batch's error is a sum over its far pairs, so the per-pair
+budget shrinks with their number. With tol_o the caller's absolute budget for
+orbital o and M_B the number of far pairs of B in the fixed-MAC lists at
+(theta_max, degree 4), the pair budget is tol_o / sqrt(max(M_B, 1)) (errors of
+independent signs add in quadrature).
+
+The GPU evaluates the network in FP32, so a decision whose margin (distance of a
+compared log quantity from its threshold) is below `tie` may legitimately come
+out the other way there. `learned_lists` reports such decisions; it never takes
+another implementation's decision.
 """
 from __future__ import annotations
 
@@ -30,6 +46,7 @@ from oracle.mlp import forward
 
 DEG_MIN, DEG_MAX = 4, 12
 LOG10E = np.log10(np.e)
+YUKAWA_KERNELS = ("yukawa_ss", "yukawa")
 
 
 def split_params(flat, sizes=(5, 64, 64, 64, 9)):
@@ -51,24 +68,60 @@ def cluster_l1(tree, x, y, z, F, W, C, degree=DEG_MIN):
     return np.array([np.abs(c).sum() for c in ch])
 
 
-def learned_lists(tree, x, y, z, F, W, kappa, params, norm, log_tol, theta_max, theta_fb,
-                  degree_fb, reference=None, tie=2e-4):
-    """Per batch (leaf order): far [(C, degree)] and near [C] in traversal order.
-    x, y, z, F (n_orb, N), W are in the tree's order. `reference` (optional):
-    per batch a dict C -> ("far", degree) or ("near",) of another implementation;
-    where it differs from this one at a tie the traversal follows the reference.
-    Returns (far, near, ties, mismatches)."""
+def third_feature(kernel, kappa_o, alpha):
+    """The network's third input: kappa for Yukawa, the Gaussian width for the
+    subtracted Coulomb kernel, 1 for the plain Coulomb kernel."""
+    if kernel in YUKAWA_KERNELS:
+        return kappa_o
+    return alpha if kernel == "coulomb_ss" else 1.0
+
+
+def pair_scale(l1, d, kernel, kappa_o):
+    """log10 of the size of a pair's far field, l1 exp(-kappa d) / d (kappa = 0 for
+    the Coulomb kernels)."""
+    k = kappa_o if kernel in YUKAWA_KERNELS else 0.0
+    return np.log10(l1) - LOG10E * k * d - np.log10(d)
+
+
+def lowest_degree(pred, scale, log_tol, cnt):
+    """Lowest degree n in 4..12 with (n+1)^3 < cnt and pred[n-4] + scale <= log_tol,
+    or -1; and the smallest distance of a compared value from the threshold."""
+    margin = np.inf
+    for deg in range(DEG_MIN, DEG_MAX + 1):
+        if (deg + 1) ** 3 >= cnt:
+            break
+        v = pred[deg - DEG_MIN] + scale - log_tol
+        margin = min(margin, abs(v))
+        if v <= 0:
+            return deg, margin
+    return -1, margin
+
+
+def candidate_counts(tree, theta_max):
+    """M_B per batch: far pairs of the fixed-MAC lists at (theta_max, degree 4)."""
+    _, far, _ = bltc.interaction_lists(tree, theta_max, DEG_MIN)
+    return np.array([len(fl) for fl in far], dtype=np.int64)
+
+
+def learned_lists(tree, x, y, z, F, W, kernel, kappa, alpha, params, norm, log_tol, theta_max,
+                  theta_fb, degree_fb, tie=2e-4):
+    """Per batch (leaf order): far [(C, degree)] and near [C] in visiting order,
+    and the decisions within `tie` of a threshold as (batch index, C, margin).
+    x, y, z, F (n_orb, N), W are in the tree's order; log_tol (n_orb,) is log10 of
+    the caller's absolute budget per orbital. Returns (far, near, ties)."""
     P = split_params(params)
     nrm = np.asarray(norm, np.float64)
     shift, scale, lo, hi = nrm[0:5], nrm[5:10], nrm[10:15], nrm[15:20]
-    kappa = np.asarray(kappa, np.float64)
     n_orb = F.shape[0]
+    kappa = np.broadcast_to(np.asarray(kappa, np.float64), (n_orb,))
+    log_tol = np.asarray(log_tol, np.float64)
     cen, rad = bltc.geometry(tree)
+    m_b = candidate_counts(tree, theta_max)
     l1_cache = {}
-    far_all, near_all, ties, mism = [], [], [], []
+    far_all, near_all, ties = [], [], []
     for bi, B in enumerate(tree.leaves()):
         fmax = np.abs(F[:, tree.begin[B]:tree.end[B]]).max(axis=1)
-        ref = reference[bi] if reference is not None else None
+        budget = log_tol - 0.5 * np.log10(max(int(m_b[bi]), 1))
         far, near = [], []
 
         def decide(C, cnt, R, rC):
@@ -79,62 +132,100 @@ def learned_lists(tree, x, y, z, F, W, kappa, params, norm, log_tol, theta_max, 
             fallback, margin, degs = False, np.inf, []
             for o in range(n_orb):
                 l1 = max(l1s[o] + fmax[o] * l1s[n_orb], 1e-30)
-                raw = np.log(np.array([rC, d, kappa[o], cnt, l1]))
+                raw = np.log(np.array([rC, d, third_feature(kernel, kappa[o], alpha), cnt, l1]))
                 margin = min(margin, np.min(np.abs(raw - lo)), np.min(np.abs(raw - hi)))
                 if np.any(raw < lo) or np.any(raw > hi):
                     fallback = True
                     continue
                 pred = forward(P, ((raw - shift) * scale)[None])[0][0]
-                scl = np.log10(l1) - LOG10E * kappa[o] * d - np.log10(d)
-                d_o = -1
-                for deg in range(DEG_MIN, DEG_MAX + 1):
-                    if (deg + 1) ** 3 >= cnt:
-                        break
-                    v = pred[deg - DEG_MIN] + scl - log_tol[o]
-                    margin = min(margin, abs(v))
-                    if v <= 0:
-                        d_o = deg
-                        break
+                d_o, m_o = lowest_degree(pred, pair_scale(l1, d, kernel, kappa[o]), budget[o], cnt)
+                margin = min(margin, m_o)
                 degs.append(d_o)
             if fallback:
-                nf = degree_fb + 1
                 dist = (rad[B] + rC) < theta_fb * R
-                if dist and nf ** 3 < cnt:
-                    return ("far", degree_fb), margin
-                return (("open",) if not dist else ("near",)), margin
+                return bltc.classify(dist, (degree_fb + 1) ** 3 < cnt, False), degree_fb, margin
             if min(degs) >= 0:
-                return ("far", max(degs)), margin
-            return ("open",), margin
+                return bltc.FAR, max(degs), margin
+            return bltc.OPEN, 0, margin
 
-        def visit(C):
+        work = [0]
+        while work:
+            C = work.pop()
             dv = cen[B] - cen[C]
             R = np.sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2])
             rC = rad[C]
             cnt = tree.count(C)
-            leaf = tree.is_leaf(C)
+            deg = 0
             if not ((rad[B] + rC) < theta_max * R):
-                dec = ("near",) if leaf else ("open",)
+                kind = bltc.OPEN
             elif cnt <= (DEG_MIN + 1) ** 3:
-                dec = ("near",)
+                kind = bltc.NEAR
             else:
-                dec, margin = decide(C, cnt, R, rC)
-                if dec == ("open",) and leaf:
-                    dec = ("near",)
-                if ref is not None:
-                    other = ref.get(C, ("open",))
-                    if other != dec:
-                        (ties if margin < tie else mism).append((bi, C, dec, other, margin))
-                        if margin < tie:
-                            dec = other
-            if dec[0] == "far":
-                far.append((C, dec[1]))
-            elif dec[0] == "near":
+                kind, deg, margin = decide(C, cnt, R, rC)
+                if margin < tie:
+                    ties.append((bi, C, margin))
+            if kind == bltc.OPEN and tree.is_leaf(C):
+                kind = bltc.NEAR
+            if kind == bltc.FAR:
+                far.append((C, deg))
+            elif kind == bltc.NEAR:
                 near.append(C)
             else:
-                for ch in tree.children[C]:
-                    visit(ch)
-
-        visit(0)
+                work.extend(reversed(tree.children[C]))
         far_all.append(far)
         near_all.append(near)
-    return far_all, near_all, ties, mism
+    return far_all, near_all, ties
+
+
+def lists_treecode(tree, x, y, z, F, W, kernel, kappa, far, near, alpha=1.0):
+    """The treecode sum over given lists (per batch, far [(C, degree)] and near [C]),
+    with proxy charges of each far cluster at its own degree (Eq.
+    particle-cluster-approx-rearranged) and the subtracted pair sums and analytic
+    term of Section 4.3, as in oracle/bltc.py. x, y, z, F (n_orb, N), W are in
+    the tree's order; returns U (n_orb, N) in the tree's order."""
+    n_orb, N = F.shape
+    kap = np.broadcast_to(np.asarray(kappa, np.float64), (n_orb,))
+    ss = kernel in ("yukawa_ss", "coulomb_ss")
+    Q = F * W[None, :]
+    charges = {}
+    U = np.zeros((n_orb, N))
+    for B, fl, nl in zip(tree.leaves(), far, near):
+        b0, b1 = tree.begin[B], tree.end[B]
+        tx, ty, tz = x[b0:b1, None], y[b0:b1, None], z[b0:b1, None]
+        for o in range(n_orb):
+            acc = np.zeros(b1 - b0)
+            fi = F[o, b0:b1]
+            for C, deg in fl:
+                if (C, deg) not in charges:
+                    s0, s1 = tree.begin[C], tree.end[C]
+                    charges[(C, deg)] = bltc.proxy_charges(
+                        x[s0:s1], y[s0:s1], z[s0:s1], np.vstack([Q[:, s0:s1], W[None, s0:s1]]),
+                        tree.lo[C], tree.hi[C], deg)
+                (sx, sy, sz), ch = charges[(C, deg)]
+                gx, gy, gz = np.meshgrid(sx, sy, sz, indexing="ij")
+                dx = tx - gx.reshape(1, -1)
+                dy = ty - gy.reshape(1, -1)
+                dz = tz - gz.reshape(1, -1)
+                d2 = dx * dx + dy * dy + dz * dz
+                k1, k2 = bltc._pair_kernel(kernel, np.sqrt(d2), d2, kap[o], alpha)
+                acc += k1 @ ch[o].reshape(-1)
+                if ss:
+                    acc -= fi * (k2 @ ch[n_orb].reshape(-1))
+            for C in nl:
+                s0, s1 = tree.begin[C], tree.end[C]
+                dx = tx - x[None, s0:s1]
+                dy = ty - y[None, s0:s1]
+                dz = tz - z[None, s0:s1]
+                d2 = dx * dx + dy * dy + dz * dz
+                d = np.sqrt(d2)
+                zero = d == 0.0
+                k1, k2 = bltc._pair_kernel(kernel, np.where(zero, 1.0, d), d2, kap[o], alpha)
+                acc += np.where(zero, 0.0, k1) @ Q[o, s0:s1]
+                if ss:
+                    acc -= fi * (np.where(zero, 0.0, k2) @ W[s0:s1])
+            if kernel == "yukawa_ss":
+                acc += 4.0 * np.pi * fi / (kap[o] * kap[o])
+            elif kernel == "coulomb_ss":
+                acc += 2.0 * np.pi * alpha * alpha * fi
+            U[o, b0:b1] = acc
+    return U

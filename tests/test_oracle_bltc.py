@@ -172,3 +172,127 @@ def test_batched_orbitals_equal_separate_calls():
     for o in range(3):
         u = bltc.treecode(x, y, z, F[o], w, "yukawa_ss", kap[o], 0.7, 5, 200)[0]
         np.testing.assert_allclose(U[o], u, rtol=0, atol=1e-14 * np.abs(u).max())
+
+
+def _independent_geometry(t, x, y, z):
+    """Centre and radius of every cluster computed from its points directly
+    (midpoint and half-diagonal of their bounding box), not by the oracle."""
+    P = np.stack([x, y, z], axis=1)
+    cen = np.empty((t.n_nodes, 3))
+    rad = np.empty(t.n_nodes)
+    for c in range(t.n_nodes):
+        q = P[t.perm[t.begin[c]:t.end[c]]]
+        lo, hi = q.min(axis=0), q.max(axis=0)
+        cen[c] = 0.5 * (lo + hi)
+        rad[c] = 0.5 * np.sqrt(np.sum((hi - lo) ** 2))
+    return cen, rad
+
+
+@pytest.mark.parametrize("theta,deg", [(0.6, 4), (0.8, 2), (0.3, 1), (0.7, 6)])
+def test_lists_are_maximal_every_opened_ancestor_failed_the_distance_test(theta, deg):
+    # Algorithm 3 descends into a cluster only when the distance part of Eq. MAC
+    # fails for it: every proper ancestor of a listed cluster must fail it, and a
+    # listed non-leaf must have passed it (far, or near because it was too small)
+    x, y, z, f, w, t = _tree_case(n=5000, leaf=120)
+    cen, rad = _independent_geometry(t, x, y, z)
+    K = (deg + 1) ** 3
+    batches, far, near = bltc.interaction_lists(t, theta, deg)
+
+    def dist_ok(B, C):
+        return rad[B] + rad[C] < theta * np.linalg.norm(cen[B] - cen[C])
+
+    n_far = n_small = 0
+    for B, fl, nl in zip(batches, far, near):
+        for kind, lst in (("far", fl), ("near", nl)):
+            for C in lst:
+                A = t.parent[C]
+                while A >= 0:
+                    assert not dist_ok(B, A), (B, C, A)
+                    A = t.parent[A]
+                if kind == "far":
+                    assert dist_ok(B, C) and K < t.count(C)
+                    n_far += 1
+                elif t.children[C]:
+                    assert dist_ok(B, C) and K >= t.count(C)
+                    n_small += 1
+                else:
+                    assert not dist_ok(B, C) or K >= t.count(C)
+    assert n_far > 0
+    if deg == 6:  # (n+1)^3 = 343 exceeds N_L: some separated non-leaves are too small
+        assert n_small > 0
+
+
+def test_lists_visit_clusters_depth_first_in_child_order():
+    # the far and near entries of a batch, merged in visiting order, follow the
+    # tree's depth-first order (a recursive visit from the root, children in order)
+    x, y, z, f, w, t = _tree_case(n=4000, leaf=100)
+    order = []
+
+    def dfs(c):
+        order.append(c)
+        for ch in t.children[c]:
+            dfs(ch)
+
+    dfs(0)
+    rank = {c: i for i, c in enumerate(order)}
+    batches, far, near = bltc.interaction_lists(t, 0.7, 3)
+    for fl, nl in zip(far, near):
+        for lst in (fl, nl):
+            assert all(rank[a] < rank[b] for a, b in zip(lst[:-1], lst[1:]))
+        # ranges of the listed clusters tile the sources in increasing order
+        merged = sorted(fl + nl, key=rank.get)
+        assert t.begin[merged[0]] == 0 and t.end[merged[-1]] == x.size
+        for a, b in zip(merged[:-1], merged[1:]):
+            assert t.end[a] == t.begin[b]
+
+
+def _targets_case(n_t=700, seed=5):
+    g = SplitMix64(seed)
+    x, y, z, f, w = uniform_cube(3000, seed=31)
+    tx, ty, tz = g.uniform(n_t, -1.2, 1.2), g.uniform(n_t, -1.2, 1.2), g.uniform(n_t, -1.2, 1.2)
+    tf = g.uniform(n_t, -1, 1)
+    tx[:40], ty[:40], tz[:40] = x[:40], y[:40], z[:40]  # targets on sources
+    # a cluster of targets far outside the source box: the whole source tree,
+    # root included, is well separated from their batches
+    tx[-150:] = 9.0 + 0.3 * g.uniform(150, 0, 1)
+    ty[-150:] = -7.0 + 0.3 * g.uniform(150, 0, 1)
+    tz[-150:] = 5.0 + 0.3 * g.uniform(150, 0, 1)
+    return x, y, z, f, w, tx, ty, tz, tf
+
+
+@pytest.mark.parametrize("kernel", ["yukawa_ss", "coulomb_ss", "yukawa", "coulomb"])
+def test_separate_targets_theta_zero_is_the_direct_sum(kernel):
+    x, y, z, f, w, tx, ty, tz, tf = _targets_case()
+    u = bltc.treecode(x, y, z, f, w, kernel, 1.1, 0.0, 4, 150, targets=(tx, ty, tz, tf))[0]
+    ref, ab = direct_sum(kernel, x, y, z, f, w, tx, ty, tz, tf, kappa=1.1, return_abs=True)
+    assert np.max(np.abs(u - ref) / (ab + np.abs(ref))) < 1e-13
+
+
+def test_separate_targets_equal_to_the_sources_reproduce_the_self_case():
+    # a tree built on the sources' own coordinates is the source tree, so its
+    # batches, lists and sums are the same, bit for bit
+    x, y, z, f, w = uniform_cube(2500, seed=17)
+    u0 = bltc.treecode(x, y, z, f, w, "yukawa_ss", 0.9, 0.7, 5, 200)
+    u1 = bltc.treecode(x, y, z, f, w, "yukawa_ss", 0.9, 0.7, 5, 200, targets=(x, y, z, f))
+    assert np.array_equal(u0, u1)
+
+
+@pytest.mark.parametrize("kernel", ["yukawa_ss", "coulomb_ss"])
+def test_separate_targets_meet_the_treecode_accuracy(kernel):
+    x, y, z, f, w, tx, ty, tz, tf = _targets_case()
+    u, parts = bltc.treecode(x, y, z, f, w, kernel, 1.1, 0.7, 7, 150, targets=(tx, ty, tz, tf),
+                             return_parts=True)
+    ref = direct_sum(kernel, x, y, z, f, w, tx, ty, tz, tf, kappa=1.1)
+    err = np.linalg.norm(u[0] - ref) / np.linalg.norm(ref)
+    assert err < 1e-6, err
+    # the far-away targets take the whole source tree through the root's charges
+    bt = parts["batch_tree"]
+    far_targets = [fl for B, fl in zip(parts["batches"], parts["far"]) if bt.lo[B][0] > 8.0]
+    assert far_targets and all(fl == [0] for fl in far_targets)
+    # every batch covers every source exactly once
+    t = parts["tree"]
+    for fl, nl in zip(parts["far"], parts["near"]):
+        cover = np.zeros(x.size, dtype=np.int64)
+        for C in fl + nl:
+            cover[t.begin[C]:t.end[C]] += 1
+        assert np.all(cover == 1)
