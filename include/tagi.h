@@ -74,6 +74,16 @@ enum tagi_precision {
                      added into FP64; near field, proxy charges, combine stay FP64 */
 };
 
+/* A set of evaluation points (targets) distinct from the sources. */
+typedef struct {
+  const double* x;  /* DEVICE [n] target coordinates */
+  const double* y;
+  const double* z;
+  const double* f;  /* DEVICE [n_orb][n] values f_i at the targets (the subtracted
+                       kernels need them; may be NULL for TAGI_YUKAWA, TAGI_COULOMB) */
+  int64_t n;        /* number of targets, 0 <= n < 2^31 */
+} tagi_points;
+
 typedef struct {
   int64_t n_points;      /* sources (= targets) */
   int32_t n_nodes;       /* clusters, root included */
@@ -162,7 +172,20 @@ int tagi_upward_hermite(tagi_tree* tree, const double* f, const double* w, int n
  * analytic subtraction term is added and the result is written in the caller's
  * point order. All n_orb orbitals of the last tagi_upward are evaluated in one
  * launch sequence (orbital o with kappa[o]).
- *   targets    must be NULL: the targets are the sources (batches = leaves).
+ *   targets    NULL: the targets are the sources, and the batches are the source
+ *              tree's leaves. Otherwise the evaluation points (Eq. direct-sum:
+ *              targets x_i, sources y_j): the batches are then the leaves of a
+ *              tree built on the targets by the rule of tagi_tree_build (Section
+ *              6.1) with N_B = the tree's N_L and the targets' bounding box as
+ *              root box. targets->f [n_orb][n] (caller order) gives f_i of the
+ *              subtracted kernels and is required for them. A target that
+ *              coincides with a source skips that pair (distance zero), as a
+ *              source does with itself. n = 0 returns TAGI_OK with nothing done.
+ *              The target tree, lists and schedule are rebuilt on every call
+ *              with targets (which synchronises the stream); if some batch
+ *              accepts the root cluster (targets outside the sources' box), the
+ *              root's proxy charges are added to the tree's from the values of
+ *              the last tagi_upward.
  *   kernel     enum tagi_kernel.
  *   kappa      HOST [n_orb] Yukawa decay rates, finite and > 0 (ignored for
  *              Coulomb kernels; may then be NULL).
@@ -170,13 +193,14 @@ int tagi_upward_hermite(tagi_tree* tree, const double* f, const double* w, int n
  *   theta      MAC parameter, 0 <= theta < 1 (0 gives the direct sum).
  *   degree     must equal the degree of the last tagi_upward.
  *   precision  enum tagi_precision.
- *   out        device [n_orb][n], caller's point order.
- * The interaction lists and the work schedule are cached per (theta, degree);
- * rebuilding them synchronises the stream.
- * Errors: TAGI_E_ARG, TAGI_E_STATE (no upward yet, degree mismatch),
- * TAGI_E_UNSUPPORTED (targets != NULL), TAGI_E_OOM, TAGI_E_HIP.
+ *   out        device [n_orb][n_t] (n_t = n, or targets->n), caller's target order.
+ * Without targets the interaction lists and the work schedule are cached per
+ * (theta, degree); rebuilding them synchronises the stream.
+ * Errors: TAGI_E_ARG, TAGI_E_STATE (no upward yet, degree mismatch), TAGI_E_OOM,
+ * TAGI_E_HIP, TAGI_E_UNSUPPORTED (a target tree deeper than the list traversal
+ * supports).
  */
-int tagi_convolve(tagi_tree* tree, const void* targets, int kernel, const double* kappa,
+int tagi_convolve(tagi_tree* tree, const tagi_points* targets, int kernel, const double* kappa,
                   double alpha, double theta, int degree, int precision, double* out,
                   void* stream);
 

@@ -56,6 +56,12 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Points(ctypes.Structure):
+    """tagi_points: a target set distinct from the sources."""
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("f", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
 class Timing(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("upward_ms", ctypes.c_double),
                 ("lists_ms", ctypes.c_double), ("interact_ms", ctypes.c_double),
@@ -203,19 +209,30 @@ class Tree:
         self.interpolation = interpolation
 
     def convolve(self, kernel: str, kappa, theta: float, degree: int | None = None,
-                 alpha: float = 1.0, precision: str = "fp64", out: torch.Tensor | None = None):
-        """Algorithm 3, ComputePotential step plus the subtraction term; returns (n_orb, n) in caller order."""
+                 alpha: float = 1.0, precision: str = "fp64", out: torch.Tensor | None = None,
+                 targets=None):
+        """Algorithm 3, ComputePotential step plus the subtraction term; returns
+        (n_orb, n_t) in the caller's target order. targets: None (the sources) or
+        (tx, ty, tz, tf) with tf (n_orb, n_t) or (n_t,) for one orbital (None for
+        the plain kernels)."""
         degree = self.degree if degree is None else degree
-        kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64),
-                                                   (max(self.n_orb, 1),)))
+        n_orb = max(self.n_orb, 1)
+        kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64), (n_orb,)))
         self._kap = kap
+        pts = None
+        nt = self.n
+        if targets is not None:
+            tx, ty, tz, tf = targets
+            nt = tx.numel()
+            pts = Points(_dptr(tx, "tx", nt), _dptr(ty, "ty", nt), _dptr(tz, "tz", nt),
+                         _dptr(tf, "tf", n_orb * nt), nt)
+            self._pts = pts
         if out is None:
-            out = torch.empty((max(self.n_orb, 1), self.n), dtype=torch.float64, device="cuda")
-        _check(load_library().tagi_convolve(self._h, None, KERNELS[kernel], _hptr(kap),
-                                            float(alpha), float(theta), int(degree),
-                                            PRECISIONS[precision],
-                                            _dptr(out, "out", max(self.n_orb, 1) * self.n),
-                                            _stream()))
+            out = torch.empty((n_orb, nt), dtype=torch.float64, device="cuda")
+        _check(load_library().tagi_convolve(self._h, None if pts is None else ctypes.byref(pts),
+                                            KERNELS[kernel], _hptr(kap), float(alpha),
+                                            float(theta), int(degree), PRECISIONS[precision],
+                                            _dptr(out, "out", n_orb * nt), _stream()))
         return out
 
     def graph(self, f: torch.Tensor, w: torch.Tensor, degree: int, kernel: str, kappa,

@@ -64,6 +64,54 @@ using namespace tagi;
 static bool valid_kernel(int k) { return k >= TAGI_YUKAWA_SS && k <= TAGI_COULOMB; }
 static bool is_yukawa(int k) { return k == TAGI_YUKAWA_SS || k == TAGI_YUKAWA; }
 
+// tagi_convolve at a separate target set (arguments validated): the batches are
+// the leaves of a tree on the targets (Section 6.1, N_B = N_L), kept in t->tgt
+// with that call's lists and schedule.
+static int convolve_targets(tagi_tree* t, const tagi_points* tp, int kernel, const double* kappa,
+                            double alpha, double theta, int degree, int precision, double* out,
+                            hipStream_t s) {
+  if (!t->tgt) {
+    t->tgt = new (std::nothrow) tagi_tree();
+    if (!t->tgt) {
+      set_error("tagi_convolve: host allocation failed");
+      return TAGI_E_OOM;
+    }
+  }
+  tagi_tree* bt = t->tgt;
+  bt->device = t->device;
+  bt->n = tp->n;
+  bt->leaf_size = t->leaf_size;
+  bt->list_theta = -1.0;
+  bt->list_degree = -1;
+  bt->n_items = 0;
+  bt->items_orb_block = 0;
+  bt->items_far_w = -1.0;
+  phase_begin(t, kPhaseLists, s);
+  int st = build_tree(bt, tp->x, tp->y, tp->z, nullptr, s);
+  const bool ss = kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS;
+  if (st == TAGI_OK && ss) {
+    st = t->tgt_fs.ensure((size_t)t->n_orb * tp->n * sizeof(double));
+    if (st == TAGI_OK) st = gather_values(bt, tp->f, t->n_orb, t->tgt_fs.as<double>(), s);
+  }
+  bool root_far = false;
+  if (st == TAGI_OK) st = ensure_lists(t, bt, theta, degree, s, &root_far);
+  if (st == TAGI_OK && root_far && t->px.h_slot_of[0] < 0) {
+    // some batch accepts the root (targets away from the sources' box): add its
+    // proxy charges, computed from the last upward pass's tree-ordered values
+    std::vector<int32_t> nodes(1, 0);
+    nodes.insert(nodes.end(), t->px.nodes.begin(), t->px.nodes.end());
+    st = prepare_proxies(t, t->px, nodes, degree, t->n_orb, s, t->px.herm);
+    if (st == TAGI_OK) st = compute_proxies(t, t->px, s);
+  }
+  const int ob = orbital_block_of(t, kernel, precision);
+  if (st == TAGI_OK) st = ensure_schedule(t, bt, ob, s);
+  phase_end(t, kPhaseLists, s);
+  if (st != TAGI_OK) return st;
+  TAGI_TRY(order_schedule(bt, far_weight(kernel, precision, t->px.herm), s));
+  return convolve(t, bt, ss ? t->tgt_fs.as<double>() : nullptr, kernel, kappa, alpha, precision,
+                  out, s);
+}
+
 #pragma GCC visibility push(default)
 extern "C" {
 
@@ -130,20 +178,25 @@ int tagi_upward_hermite(tagi_tree* t, const double* f, const double* w, int n_or
   return upward(t, f, w, n_orb, degree, (hipStream_t)stream, true);
 }
 
-int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* kappa,
+int tagi_convolve(tagi_tree* t, const tagi_points* targets, int kernel, const double* kappa,
                   double alpha, double theta, int degree, int precision, double* out,
                   void* stream) {
   g_err[0] = 0;
   REQUIRE(t, "tagi_convolve: tree is NULL");
-  REQUIRE(out, "tagi_convolve: out is NULL");
+  REQUIRE(out || (targets && targets->n == 0), "tagi_convolve: out is NULL");
   REQUIRE(valid_kernel(kernel), "tagi_convolve: unknown kernel %d", kernel);
   REQUIRE(precision == TAGI_FP64 || precision == TAGI_MIXED,
           "tagi_convolve: unknown precision %d", precision);
   REQUIRE(theta >= 0.0 && theta < 1.0, "tagi_convolve: theta = %g out of range [0, 1)", theta);
   REQUIRE(degree >= 1 && degree <= kMaxDegree, "tagi_convolve: degree = %d out of range", degree);
   if (targets) {
-    set_error("tagi_convolve: separate target sets are not supported (targets must be NULL)");
-    return TAGI_E_UNSUPPORTED;
+    REQUIRE(targets->n >= 0 && targets->n < (int64_t)INT32_MAX,
+            "tagi_convolve: targets->n = %lld out of range [0, 2^31)", (long long)targets->n);
+    REQUIRE(targets->n == 0 || (targets->x && targets->y && targets->z),
+            "tagi_convolve: null target coordinate array");
+    REQUIRE(targets->n == 0 || targets->f ||
+                !(kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS),
+            "tagi_convolve: targets->f is required for the subtracted kernels");
   }
   if (t->degree == 0) {
     set_error("tagi_convolve: tagi_upward has not run on this tree");
@@ -162,6 +215,10 @@ int tagi_convolve(tagi_tree* t, const void* targets, int kernel, const double* k
   if (kernel == TAGI_COULOMB_SS)
     REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_convolve: alpha = %g must be > 0", alpha);
   hipStream_t s = (hipStream_t)stream;
+  if (targets) {
+    if (targets->n == 0) return TAGI_OK;
+    return convolve_targets(t, targets, kernel, kappa, alpha, theta, degree, precision, out, s);
+  }
   const int ob = orbital_block_of(t, kernel, precision);
   const bool rebuild = !lists_current(t, theta, degree) ||
                        !(t->items_orb_block == ob && t->items_n_orb == t->n_orb && t->n_items > 0);
@@ -700,8 +757,10 @@ int tagi_tree_destroy(tagi_tree* t) {
                   &t->ws, &t->fs, &t->qs, &t->far_off, &t->near_off, &t->far_id, &t->near_id,
                   &t->chunks, &t->items, &t->item_order, &t->group_first_item, &t->batch_group_base,
                   &t->batch_chunks, &t->partial, &t->kappa_dev, &t->green_f, &t->green_phi,
-                  &t->green_part};
+                  &t->green_part, &t->tgt_fs};
   for (DBuf* b : bufs) b->release();
+  if (t->tgt) tagi_tree_destroy(t->tgt);
+  t->tgt = nullptr;
   t->px.release();
   for (ProxySet& ps : t->lx) ps.release();
   t->learned.release();

@@ -24,6 +24,14 @@ extern template void launch_interact_herm_ob<TAGI_COULOMB>(int, const InteractAr
 namespace {
 using namespace ik;
 
+// out[o][i] = f[o][perm[i]]: caller-order values into a tree's order
+__global__ void k_gather_values(const int32_t* __restrict__ perm, const double* __restrict__ f,
+                                int64_t n, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = blockIdx.y;
+  if (i < n) out[o * n + i] = f[o * n + perm[i]];
+}
+
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
@@ -116,11 +124,13 @@ __global__ void k_direct_combine(int64_t nt, int n_sc, int ss, double self,
 
 }  // namespace
 
-int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
-             double* out, hipStream_t s) {
+int convolve(tagi_tree* t, tagi_tree* bt, const double* tfs, int kernel, const double* kappa,
+             double alpha, int precision, double* out, hipStream_t s) {
+  // t: source tree (particles, proxy charges); bt: batch tree (targets, lists,
+  // schedule); bt == t when the targets are the sources
   const int n_orb = t->n_orb;
   const int ob = orbital_block_of(t, kernel, precision);
-  if (t->items_orb_block != ob || t->items_n_orb != n_orb || t->n_items == 0) {
+  if (bt->items_orb_block != ob || bt->items_n_orb != n_orb || bt->n_items == 0) {
     set_error("convolve: the compute schedule was not prepared");
     return TAGI_E_STATE;
   }
@@ -151,14 +161,14 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
     TAGI_HIP(hipGetLastError());
   }
   InteractArgs A{};
-  A.items = t->items.as<int4>();
-  A.n_items = t->n_items;
-  A.chunks = t->chunks.as<Chunk>();
-  A.leaf_node = t->leaf_node.as<int32_t>();
+  A.items = bt->items.as<int4>();
+  A.n_items = bt->n_items;
+  A.chunks = bt->chunks.as<Chunk>();
+  A.leaf_node = bt->leaf_node.as<int32_t>();
   A.nbeg = t->nd_begin.as<int32_t>();
   A.nend = t->nd_end.as<int32_t>();
-  A.far_id = t->far_id.as<int32_t>();
-  A.near_id = t->near_id.as<int32_t>();
+  A.far_id = bt->far_id.as<int32_t>();
+  A.near_id = bt->near_id.as<int32_t>();
   A.slot_of = t->px.slot_of.as<int32_t>();
   A.xs = t->xs.as<double>();
   A.ys = t->ys.as<double>();
@@ -179,10 +189,18 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   A.n_approx = t->px.n_approx;
   A.degree = t->degree;
   A.ia2 = ia2;
-  A.partial = t->partial.as<double>();
-  A.item_list = t->item_order.as<int32_t>();
-  A.n_list = t->n_items;
-  if (t->n_items > 0) {
+  A.partial = bt->partial.as<double>();
+  A.item_list = bt->item_order.as<int32_t>();
+  A.n_list = bt->n_items;
+  A.bbeg = bt->nd_begin.as<int32_t>();
+  A.bend = bt->nd_end.as<int32_t>();
+  A.bbox = bt->nd_box.as<double>();
+  A.txs = bt->xs.as<double>();
+  A.tys = bt->ys.as<double>();
+  A.tzs = bt->zs.as<double>();
+  A.tfs = tfs;
+  A.tn = bt->n;
+  if (bt->n_items > 0) {
     phase_begin(t, kPhaseInteract, s);
     ++t->interact_launches;
     if (t->px.herm) {
@@ -205,12 +223,11 @@ int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int pr
   }
   phase_begin(t, kPhaseCombine, s);
   const int ss = kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS;
-  hipLaunchKernelGGL(k_combine, dim3((t->n + 255) / 256, n_orb), dim3(256), 0, s, t->n, n_orb,
-                     ob, ss, t->perm.as<int32_t>(), t->leaf_of_pos.as<int32_t>(),
-                     t->leaf_node.as<int32_t>(), t->nd_begin.as<int32_t>(),
-                     t->batch_group_base.as<int32_t>(), t->group_first_item.as<int32_t>(),
-                     t->batch_chunks.as<int2>(), t->fs.as<double>(), t->partial.as<double>(), orb,
-                     out);
+  hipLaunchKernelGGL(k_combine, dim3((bt->n + 255) / 256, n_orb), dim3(256), 0, s, bt->n, n_orb,
+                     ob, ss, bt->perm.as<int32_t>(), bt->leaf_of_pos.as<int32_t>(),
+                     bt->leaf_node.as<int32_t>(), bt->nd_begin.as<int32_t>(),
+                     bt->batch_group_base.as<int32_t>(), bt->group_first_item.as<int32_t>(),
+                     bt->batch_chunks.as<int2>(), tfs, bt->partial.as<double>(), orb, out);
   phase_end(t, kPhaseCombine, s);
   TAGI_HIP(hipGetLastError());
   return TAGI_OK;
@@ -248,6 +265,14 @@ OrbArg make_orb(int kernel, int n_orb, const double* kappa, double alpha) {
 }
 
 }  // namespace ik
+
+int gather_values(const tagi_tree* t, const double* f, int n_orb, double* out, hipStream_t s) {
+  if (t->n == 0) return TAGI_OK;
+  hipLaunchKernelGGL(k_gather_values, dim3((t->n + 255) / 256, n_orb), dim3(256), 0, s,
+                     t->perm.as<int32_t>(), f, t->n, out);
+  TAGI_HIP(hipGetLastError());
+  return TAGI_OK;
+}
 
 int orbital_block_of(const tagi_tree* t, int kernel, int precision) {
   const int ob = t->ob_override ? t->ob_override : orbital_block(kernel, t->n_orb, precision);

@@ -469,7 +469,11 @@ __device__ __forceinline__ void far_cluster_herm(double xi, double yi, double zi
   }
 }
 
-// Everything the interaction kernel reads, passed by value.
+// Everything the interaction kernel reads, passed by value. Source side: the
+// source tree's nodes (nbeg, nend, geom, box), sorted particles and proxy data.
+// Target side: the batch tree's leaves, node ranges and boxes, and the sorted
+// targets with their values (the same arrays as the source side when the
+// targets are the sources; targets_are_sources() sets them so).
 struct InteractArgs {
   const int4* items;
   int64_t n_items;
@@ -485,7 +489,23 @@ struct InteractArgs {
   double* partial;
   const int32_t* item_list;  // optional: this launch processes items item_list[0 .. n_list)
   int64_t n_list;
+  // target side: batch-tree node ranges and boxes, targets [tn] and values [n_orb][tn]
+  const int32_t *bbeg, *bend;
+  const double* bbox;  // optional, as box
+  const double *txs, *tys, *tzs, *tfs;
+  int64_t tn;
 };
+
+inline void targets_are_sources(InteractArgs& A) {
+  A.bbeg = A.nbeg;
+  A.bend = A.nend;
+  A.bbox = A.box;
+  A.txs = A.xs;
+  A.tys = A.ys;
+  A.tzs = A.zs;
+  A.tfs = A.fs;
+  A.tn = A.n;
+}
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin by their index, and
 // every XCD has its own L2. Renumbering the workgroups so that each XCD runs one
@@ -510,8 +530,8 @@ __host__ __device__ inline void xcd_range(int x, int nb, int& b0, int& b1) {
 // lie at least 6.12 a apart: such terms are below the FP64 resolution of the
 // subtracted sum. Proxy points lie in their cluster's box.
 __device__ __forceinline__ bool gauss_negligible(const InteractArgs& A, int B, int C) {
-  if (!A.box) return false;
-  const double* bb = A.box + (int64_t)B * 6;
+  if (!A.box || !A.bbox) return false;
+  const double* bb = A.bbox + (int64_t)B * 6;
   const double* bc = A.box + (int64_t)C * 6;
   double g2 = 0.0;
 #pragma unroll
@@ -546,10 +566,10 @@ void k_interact(InteractArgs A, OrbArg orb) {
   const int it = A.item_list ? __builtin_amdgcn_readfirstlane(A.item_list[wv]) : wv;
   const int4 item = A.items[it];
   const int B = A.leaf_node[item.x];
-  const int tb = A.nbeg[B] + item.y * kWave;
-  const int te = min(A.nend[B], tb + kWave);
+  const int tb = A.bbeg[B] + item.y * kWave;
+  const int te = min(A.bend[B], tb + kWave);
   const int i = tb + lane < te ? tb + lane : tb;
-  const double xi = A.xs[i], yi = A.ys[i], zi = A.zs[i];
+  const double xi = A.txs[i], yi = A.tys[i], zi = A.tzs[i];
   const int o0 = item.z * OB;
   double nkap[OB], kl2[OB];  // -k and -k log2(e) per orbital
   int orb_row[OB];
@@ -565,7 +585,7 @@ void k_interact(InteractArgs A, OrbArg orb) {
 #pragma unroll
   for (int o = 0; o < OB; ++o) {
     if constexpr (MODE == kModeMixed && KER == TAGI_YUKAWA_SS)
-      fi[o] = A.fs[(int64_t)orb_row[o] * A.n + i];
+      fi[o] = A.tfs[(int64_t)orb_row[o] * A.tn + i];
     else
       fi[o] = 0.0;
   }

@@ -245,6 +245,11 @@ struct tagi_tree {
   tagi::DBuf kappa_dev;             // double [n_orb]
   // Green-iteration step: V psi, the convolution, reduction partials
   tagi::DBuf green_f, green_phi, green_part;
+  // separate target set of the last tagi_convolve with targets: a tree on the
+  // targets (its leaves are the batches; it also holds that call's lists and
+  // schedule) and the target values in its order, [n_orb][n_targets]
+  tagi_tree* tgt = nullptr;
+  tagi::DBuf tgt_fs;
 
   // phase timing (HIP events on the calls' stream)
   bool timing = false;
@@ -264,10 +269,13 @@ struct tagi_mesh {
 
 namespace tagi {
 
-// the cached interaction lists serve (theta, degree) with the size test of the
-// current proxy charges
+// the interaction lists cached in the batch tree `bt` serve (theta, degree) with
+// the size test of the source tree's current proxy charges
+inline bool lists_current(const tagi_tree* src, const tagi_tree* bt, double theta, int degree) {
+  return bt->list_theta == theta && bt->list_degree == degree && bt->list_herm == src->px.herm;
+}
 inline bool lists_current(const tagi_tree* t, double theta, int degree) {
-  return t->list_theta == theta && t->list_degree == degree && t->list_herm == t->px.herm;
+  return lists_current(t, t, theta, degree);
 }
 
 enum Phase { kPhaseUpward = 0, kPhaseLists = 1, kPhaseInteract = 2, kPhaseCombine = 3 };
@@ -298,8 +306,19 @@ int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& node
                     int n_orb, hipStream_t s, bool herm = false);
 // proxy charges of the planned set from the tree-ordered q = f w and w
 int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s);
-int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s);
-int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s);
+// Interaction lists of the batches (leaves) of `bt` against the clusters of the
+// source tree `src`, and their compute schedule, both kept in `bt`; bt == src
+// when the targets are the sources. `root_far` (may be NULL) receives whether
+// some batch accepted the root cluster as far.
+int ensure_lists(tagi_tree* src, tagi_tree* bt, double theta, int degree, hipStream_t s,
+                 bool* root_far = nullptr);
+int ensure_schedule(const tagi_tree* src, tagi_tree* bt, int orb_block, hipStream_t s);
+inline int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
+  return ensure_lists(t, t, theta, degree, s);
+}
+inline int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
+  return ensure_schedule(t, t, orb_block, s);
+}
 // launch order of the schedule for far evaluations costing far_w near ones
 int order_schedule(tagi_tree* t, double far_w, hipStream_t s);
 // waves [start, start + len) of a launch list that read the same sources
@@ -313,8 +332,18 @@ double far_weight(int kernel, int precision, bool herm);
 int orbital_block(int kernel, int n_orb, int precision);
 // the tree's orbital block for a kernel: its override if set, else the default
 int orbital_block_of(const tagi_tree* t, int kernel, int precision);
-int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
-             double* out, hipStream_t s);
+// The far and near sums of the batches of `bt` (lists and schedule prepared in
+// it) against the source tree `src`, the combine and the scatter to the caller's
+// target order; tfs = target values in bt's order, [n_orb][bt->n] (bt == src:
+// the source tree's own values).
+int convolve(tagi_tree* src, tagi_tree* bt, const double* tfs, int kernel, const double* kappa,
+             double alpha, int precision, double* out, hipStream_t s);
+inline int convolve(tagi_tree* t, int kernel, const double* kappa, double alpha, int precision,
+                    double* out, hipStream_t s) {
+  return convolve(t, t, t->fs.as<double>(), kernel, kappa, alpha, precision, out, s);
+}
+// gathers caller-order values [n_orb][n] into the order of tree t
+int gather_values(const tagi_tree* t, const double* f, int n_orb, double* out, hipStream_t s);
 int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,
                      const float* params, const float* norm, const double* tol, double theta_max,
                      double theta_fb, int degree_fb, int precision, double* out, hipStream_t s);

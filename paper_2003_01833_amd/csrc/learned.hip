@@ -586,6 +586,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     A.partial = S.partial.as<double>();
     A.item_list = S.item_lists.as<int32_t>() + S.list_begin[li];
     A.n_list = S.list_begin[li + 1] - S.list_begin[li];
+    targets_are_sources(A);
     if (d > 0) {
       const ProxySet& ps = t->lx[d];
       A.slot_of = ps.slot_of.as<int32_t>();

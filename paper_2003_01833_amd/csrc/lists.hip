@@ -31,26 +31,32 @@ constexpr int kStack = 512;
 // scratch memory, one memory round trip per pop.
 constexpr int kListBlock = 64;
 
-__device__ __forceinline__ bool distance_ok(const double* __restrict__ geom, int B, int C,
+// distance part of Eq. MAC for batch B (geometry bgeom) and cluster C (geom)
+__device__ __forceinline__ bool distance_ok(const double* __restrict__ bgeom,
+                                            const double* __restrict__ geom, int B, int C,
                                             double theta) {
 #pragma clang fp contract(off)
-  const double dx = geom[B * 4 + 0] - geom[C * 4 + 0];
-  const double dy = geom[B * 4 + 1] - geom[C * 4 + 1];
-  const double dz = geom[B * 4 + 2] - geom[C * 4 + 2];
+  const double dx = bgeom[B * 4 + 0] - geom[C * 4 + 0];
+  const double dy = bgeom[B * 4 + 1] - geom[C * 4 + 1];
+  const double dz = bgeom[B * 4 + 2] - geom[C * 4 + 2];
   const double R = sqrt(dx * dx + dy * dy + dz * dz);
-  return (geom[B * 4 + 3] + geom[C * 4 + 3]) < theta * R;
+  return (bgeom[B * 4 + 3] + geom[C * 4 + 3]) < theta * R;
 }
 
 // fill == 0: write counts (far pairs, near pairs, near sources) per batch;
-// fill == 1: write the ids at the given offsets.
+// fill == 1: write the ids at the given offsets. Batches are the leaves
+// leaf_node[] of the batch tree (geometry bgeom); clusters are nodes of the
+// source tree (geom, nbeg, ...).
 __global__ __launch_bounds__(kListBlock) void k_lists(int n_leaves, const int32_t* __restrict__ leaf_node,
+                        const double* __restrict__ bgeom,
                         const double* __restrict__ geom, const int32_t* __restrict__ nbeg,
                         const int32_t* __restrict__ nend, const int32_t* __restrict__ first_child,
                         const int32_t* __restrict__ n_child, double theta, int K, int fill,
                         int64_t* __restrict__ far_cnt, int64_t* __restrict__ near_cnt,
                         int64_t* __restrict__ near_src, const int64_t* __restrict__ far_off,
                         const int64_t* __restrict__ near_off, int32_t* __restrict__ far_id,
-                        int32_t* __restrict__ near_id, int32_t* __restrict__ overflow) {
+                        int32_t* __restrict__ near_id, int32_t* __restrict__ overflow,
+                        int32_t* __restrict__ root_far) {
   __shared__ int32_t stack[kStack][kListBlock];
   const int lane = threadIdx.x;
   const int b = blockIdx.x * kListBlock + lane;
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists(int n_leaves, const int32_
   while (sp > 0) {
     const int C = stack[--sp][lane];
     const int cnt = nend[C] - nbeg[C];
-    const bool dist = distance_ok(geom, B, C, theta);
+    const bool dist = distance_ok(bgeom, geom, B, C, theta);
     const bool size = K < cnt;
     int kind;  // 0 far, 1 near, 2 open
     if (dist && size)
@@ -74,6 +80,7 @@ __global__ __launch_bounds__(kListBlock) void k_lists(int n_leaves, const int32_
       kind = 1;
     if (kind == 0) {
       if (fill) far_id[fo + nf] = C;
+      if (C == 0 && root_far) *root_far = 1;
       ++nf;
     } else if (kind == 1) {
       if (fill) near_id[no + nn] = C;
@@ -133,85 +140,92 @@ __global__ void k_chunks(int n_leaves, const int32_t* __restrict__ nbeg,
 
 }  // namespace
 
-int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
-  if (lists_current(t, theta, degree)) return TAGI_OK;
-  t->list_theta = -1.0;
-  t->list_degree = -1;
-  t->items_orb_block = 0;
-  t->n_items = 0;
-  const int nl = (int)t->leaves.size();
+int ensure_lists(tagi_tree* src, tagi_tree* bt, double theta, int degree, hipStream_t s,
+                 bool* root_far) {
+  if (root_far) *root_far = false;
+  if (lists_current(src, bt, theta, degree) && !root_far) return TAGI_OK;
+  bt->list_theta = -1.0;
+  bt->list_degree = -1;
+  bt->items_orb_block = 0;
+  bt->n_items = 0;
+  const int nl = (int)bt->leaves.size();
   const int np1 = degree + 1;
   const int K = np1 * np1 * np1;
   // size part of the MAC: charges per approximated cluster, 8 per point for Hermite
-  const bool herm = t->px.herm;
+  const bool herm = src->px.herm;
   const int K_mac = (herm ? kHermPatterns : 1) * K;
   DBuf cnt;
-  TAGI_TRY(cnt.ensure((size_t)nl * 3 * sizeof(int64_t) + sizeof(int32_t)));
+  TAGI_TRY(cnt.ensure((size_t)nl * 3 * sizeof(int64_t) + 2 * sizeof(int32_t)));
   int64_t* d_far_cnt = cnt.as<int64_t>();
   int64_t* d_near_cnt = d_far_cnt + nl;
   int64_t* d_near_src = d_near_cnt + nl;
   int32_t* d_over = reinterpret_cast<int32_t*>(d_near_src + nl);
-  TAGI_HIP(hipMemsetAsync(d_over, 0, sizeof(int32_t), s));
+  int32_t* d_root = d_over + 1;
+  TAGI_HIP(hipMemsetAsync(d_over, 0, 2 * sizeof(int32_t), s));
   const int blk = kListBlock, grid = (nl + blk - 1) / blk;
-  hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, t->leaf_node.as<int32_t>(),
-                     t->nd_geom.as<double>(), t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(),
-                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K_mac, 0,
-                     d_far_cnt, d_near_cnt, d_near_src, nullptr, nullptr, nullptr, nullptr,
-                     d_over);
+  hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, bt->leaf_node.as<int32_t>(),
+                     bt->nd_geom.as<double>(), src->nd_geom.as<double>(),
+                     src->nd_begin.as<int32_t>(), src->nd_end.as<int32_t>(),
+                     src->nd_first_child.as<int32_t>(), src->nd_n_child.as<int32_t>(), theta,
+                     K_mac, 0, d_far_cnt, d_near_cnt, d_near_src, nullptr, nullptr, nullptr,
+                     nullptr, d_over, d_root);
   TAGI_HIP(hipGetLastError());
   std::vector<int64_t> h(3 * (size_t)nl);
-  int32_t over = 0;
+  int32_t flags[2] = {0, 0};
   TAGI_HIP(hipMemcpyAsync(h.data(), d_far_cnt, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  TAGI_HIP(hipMemcpyAsync(&over, d_over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipMemcpyAsync(flags, d_over, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   TAGI_HIP(hipStreamSynchronize(s));
-  if (over) {
+  if (flags[0]) {
     cnt.release();
     set_error("interaction-list traversal stack overflow (tree deeper than supported)");
     return TAGI_E_UNSUPPORTED;
   }
-  t->h_far_off.assign(nl + 1, 0);
-  t->h_near_off.assign(nl + 1, 0);
-  t->far_inter = t->near_inter = 0;
+  if (root_far) *root_far = flags[1] != 0;
+  bt->h_far_off.assign(nl + 1, 0);
+  bt->h_near_off.assign(nl + 1, 0);
+  bt->far_inter = bt->near_inter = 0;
   for (int b = 0; b < nl; ++b) {
-    t->h_far_off[b + 1] = t->h_far_off[b] + h[b];
-    t->h_near_off[b + 1] = t->h_near_off[b] + h[nl + b];
-    const HostNode& q = t->nodes[t->leaves[b]];
+    bt->h_far_off[b + 1] = bt->h_far_off[b] + h[b];
+    bt->h_near_off[b + 1] = bt->h_near_off[b] + h[nl + b];
+    const HostNode& q = bt->nodes[bt->leaves[b]];
     const int64_t nb = q.end - q.begin;
-    t->far_inter += nb * h[b] * K;
-    t->near_inter += nb * h[2 * (size_t)nl + b];
+    bt->far_inter += nb * h[b] * K;
+    bt->near_inter += nb * h[2 * (size_t)nl + b];
   }
-  t->n_far = t->h_far_off[nl];
-  t->n_near = t->h_near_off[nl];
-  if (t->n_far >= INT32_MAX || t->n_near >= INT32_MAX) {
+  bt->n_far = bt->h_far_off[nl];
+  bt->n_near = bt->h_near_off[nl];
+  if (bt->n_far >= INT32_MAX || bt->n_near >= INT32_MAX) {
     cnt.release();
     set_error("interaction lists exceed 2^31 entries");
     return TAGI_E_UNSUPPORTED;
   }
-  TAGI_TRY(t->far_off.ensure((nl + 1) * sizeof(int64_t)));
-  TAGI_TRY(t->near_off.ensure((nl + 1) * sizeof(int64_t)));
-  TAGI_TRY(t->far_id.ensure(std::max<int64_t>(t->n_far, 1) * 4));
-  TAGI_TRY(t->near_id.ensure(std::max<int64_t>(t->n_near, 1) * 4));
-  TAGI_HIP(hipMemcpyAsync(t->far_off.p, t->h_far_off.data(), (nl + 1) * sizeof(int64_t),
+  TAGI_TRY(bt->far_off.ensure((nl + 1) * sizeof(int64_t)));
+  TAGI_TRY(bt->near_off.ensure((nl + 1) * sizeof(int64_t)));
+  TAGI_TRY(bt->far_id.ensure(std::max<int64_t>(bt->n_far, 1) * 4));
+  TAGI_TRY(bt->near_id.ensure(std::max<int64_t>(bt->n_near, 1) * 4));
+  TAGI_HIP(hipMemcpyAsync(bt->far_off.p, bt->h_far_off.data(), (nl + 1) * sizeof(int64_t),
                           hipMemcpyHostToDevice, s));
-  TAGI_HIP(hipMemcpyAsync(t->near_off.p, t->h_near_off.data(), (nl + 1) * sizeof(int64_t),
+  TAGI_HIP(hipMemcpyAsync(bt->near_off.p, bt->h_near_off.data(), (nl + 1) * sizeof(int64_t),
                           hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, t->leaf_node.as<int32_t>(),
-                     t->nd_geom.as<double>(), t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(),
-                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K_mac, 1,
-                     nullptr, nullptr, nullptr, t->far_off.as<int64_t>(),
-                     t->near_off.as<int64_t>(), t->far_id.as<int32_t>(),
-                     t->near_id.as<int32_t>(), d_over);
+  hipLaunchKernelGGL(k_lists, dim3(grid), dim3(blk), 0, s, nl, bt->leaf_node.as<int32_t>(),
+                     bt->nd_geom.as<double>(), src->nd_geom.as<double>(),
+                     src->nd_begin.as<int32_t>(), src->nd_end.as<int32_t>(),
+                     src->nd_first_child.as<int32_t>(), src->nd_n_child.as<int32_t>(), theta,
+                     K_mac, 1, nullptr, nullptr, nullptr, bt->far_off.as<int64_t>(),
+                     bt->near_off.as<int64_t>(), bt->far_id.as<int32_t>(),
+                     bt->near_id.as<int32_t>(), d_over, nullptr);
   TAGI_HIP(hipGetLastError());
   TAGI_HIP(hipStreamSynchronize(s));
   cnt.release();
-  t->list_theta = theta;
-  t->list_degree = degree;
-  t->list_herm = herm;
+  bt->list_theta = theta;
+  bt->list_degree = degree;
+  bt->list_herm = herm;
   return TAGI_OK;
 }
 
-int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
-  if (t->items_orb_block == orb_block && t->items_n_orb == t->n_orb && t->n_items > 0)
+int ensure_schedule(const tagi_tree* src, tagi_tree* t, int orb_block, hipStream_t s) {
+  // t: the batch tree, which holds the lists and receives the schedule
+  if (t->items_orb_block == orb_block && t->items_n_orb == src->n_orb && t->n_items > 0)
     return TAGI_OK;
   t->items_orb_block = 0;
   t->n_items = 0;
@@ -229,8 +243,8 @@ int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
   int32_t* d_nch = nch.as<int32_t>();
   int32_t* d_choff = d_nch + nl + 1;
   const int blk = 128, grid = (nl + blk - 1) / blk;
-  hipLaunchKernelGGL(k_chunks, dim3(grid), dim3(blk), 0, s, nl, t->nd_begin.as<int32_t>(),
-                     t->nd_end.as<int32_t>(), t->far_off.as<int64_t>(), t->near_off.as<int64_t>(),
+  hipLaunchKernelGGL(k_chunks, dim3(grid), dim3(blk), 0, s, nl, src->nd_begin.as<int32_t>(),
+                     src->nd_end.as<int32_t>(), t->far_off.as<int64_t>(), t->near_off.as<int64_t>(),
                      t->near_id.as<int32_t>(), K, cap, 0, d_nch, nullptr, nullptr);
   TAGI_HIP(hipGetLastError());
   std::vector<int32_t> hn(nl);
@@ -241,12 +255,12 @@ int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
   const int64_t n_chunks = choff[nl];
   TAGI_TRY(t->chunks.ensure(std::max<int64_t>(n_chunks, 1) * sizeof(Chunk)));
   TAGI_HIP(hipMemcpyAsync(d_choff, choff.data(), nl * 4, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_chunks, dim3(grid), dim3(blk), 0, s, nl, t->nd_begin.as<int32_t>(),
-                     t->nd_end.as<int32_t>(), t->far_off.as<int64_t>(), t->near_off.as<int64_t>(),
+  hipLaunchKernelGGL(k_chunks, dim3(grid), dim3(blk), 0, s, nl, src->nd_begin.as<int32_t>(),
+                     src->nd_end.as<int32_t>(), t->far_off.as<int64_t>(), t->near_off.as<int64_t>(),
                      t->near_id.as<int32_t>(), K, cap, 1, d_nch, d_choff, t->chunks.as<Chunk>());
   TAGI_HIP(hipGetLastError());
   // items in (batch, group, orbital block, chunk) order
-  const int n_ob = (t->n_orb + orb_block - 1) / orb_block;
+  const int n_ob = (src->n_orb + orb_block - 1) / orb_block;
   std::vector<int32_t> items;
   std::vector<int32_t> group_first;
   std::vector<int32_t> group_base(nl);
@@ -333,7 +347,7 @@ int ensure_schedule(tagi_tree* t, int orb_block, hipStream_t s) {
   TAGI_HIP(hipStreamSynchronize(s));
   nch.release();
   t->items_orb_block = orb_block;
-  t->items_n_orb = t->n_orb;
+  t->items_n_orb = src->n_orb;
   return TAGI_OK;
 }
 

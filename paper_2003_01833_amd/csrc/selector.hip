@@ -143,6 +143,7 @@ InteractArgs args_of(tagi_tree* t) {
   A.n_orb = t->n_orb;
   A.n_approx = t->px.n_approx;
   A.degree = t->degree;
+  targets_are_sources(A);
   return A;
 }
 
