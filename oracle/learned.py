@@ -11,15 +11,17 @@ cluster that passes it and holds at most (4+1)^3 sources is summed directly (no
 degree has fewer charges than sources). Otherwise, per orbital o, the network
 (oracle/mlp.py) sees the log-features
 
-    (r_C, d = R - r_B, c_o, N_S, l1_o),   standardised as (ln raw - shift) * scale,
+    (r_C, d = R - r_B, c_o, N_S, l1_o),
+    standardised as (ln(raw + offset) - shift) * scale,
 
-with c_o = kappa_o for the Yukawa kernels, the Gaussian width alpha for the
-subtracted Coulomb kernel and 1 for the plain one, and
+with the decay rate c_o = kappa_o for the Yukawa kernels and 0 for the Coulomb
+kernels (the kappa -> 0 limit of exp(-kappa r)/r is 1/r), offset 0.25 on c and 0
+on the others (so that c = 0 maps to a finite value), and
 l1_o = |q^_o|_1 + max_B |f_o| |w^|_1 from C's degree-4 proxy charges of f w and
 of w (Section 6.2), a bound on the l1 norm of the subtracted charges
 q^ - f_i w^. It predicts, for degrees 4..12, log10 of the pair's largest error
-minus the pair scale s_o = log10(l1_o) - kappa_o d log10(e) - log10(d) (kappa_o = 0
-for the Coulomb kernels: s_o is log10 of the size of the pair's far field). The
+minus the pair scale s_o = log10(l1_o) - c_o d log10(e) - log10(d) (log10 of the
+size of the pair's far field). The
 pair is approximated at the lowest degree n with (n+1)^3 < N_S whose predicted
 error meets the batch's budget for every orbital (the largest such degree over
 the orbitals is used), and resolved into its children otherwise (a leaf is
@@ -47,6 +49,9 @@ from oracle.mlp import forward
 DEG_MIN, DEG_MAX = 4, 12
 LOG10E = np.log10(np.e)
 YUKAWA_KERNELS = ("yukawa_ss", "yukawa")
+# added to the raw features before the logarithm: only the decay rate, which is
+# 0 for the Coulomb kernels
+LOG_OFFSET = np.array([0.0, 0.0, 0.25, 0.0, 0.0])
 
 
 def split_params(flat, sizes=(5, 64, 64, 64, 9)):
@@ -68,19 +73,15 @@ def cluster_l1(tree, x, y, z, F, W, C, degree=DEG_MIN):
     return np.array([np.abs(c).sum() for c in ch])
 
 
-def third_feature(kernel, kappa_o, alpha):
-    """The network's third input: kappa for Yukawa, the Gaussian width for the
-    subtracted Coulomb kernel, 1 for the plain Coulomb kernel."""
-    if kernel in YUKAWA_KERNELS:
-        return kappa_o
-    return alpha if kernel == "coulomb_ss" else 1.0
+def decay(kernel, kappa_o):
+    """The network's third raw input: the kernel's decay rate, kappa for the
+    Yukawa kernels, 0 for the Coulomb kernels."""
+    return kappa_o if kernel in YUKAWA_KERNELS else 0.0
 
 
-def pair_scale(l1, d, kernel, kappa_o):
-    """log10 of the size of a pair's far field, l1 exp(-kappa d) / d (kappa = 0 for
-    the Coulomb kernels)."""
-    k = kappa_o if kernel in YUKAWA_KERNELS else 0.0
-    return np.log10(l1) - LOG10E * k * d - np.log10(d)
+def pair_scale(l1, d, c):
+    """log10 of the size of a pair's far field, l1 exp(-c d) / d, c the decay rate."""
+    return np.log10(l1) - LOG10E * c * d - np.log10(d)
 
 
 def lowest_degree(pred, scale, log_tol, cnt):
@@ -103,7 +104,7 @@ def candidate_counts(tree, theta_max):
     return np.array([len(fl) for fl in far], dtype=np.int64)
 
 
-def learned_lists(tree, x, y, z, F, W, kernel, kappa, alpha, params, norm, log_tol, theta_max,
+def learned_lists(tree, x, y, z, F, W, kernel, kappa, params, norm, log_tol, theta_max,
                   theta_fb, degree_fb, tie=2e-4):
     """Per batch (leaf order): far [(C, degree)] and near [C] in visiting order,
     and the decisions within `tie` of a threshold as (batch index, C, margin).
@@ -132,13 +133,14 @@ def learned_lists(tree, x, y, z, F, W, kernel, kappa, alpha, params, norm, log_t
             fallback, margin, degs = False, np.inf, []
             for o in range(n_orb):
                 l1 = max(l1s[o] + fmax[o] * l1s[n_orb], 1e-30)
-                raw = np.log(np.array([rC, d, third_feature(kernel, kappa[o], alpha), cnt, l1]))
+                c = decay(kernel, kappa[o])
+                raw = np.log(np.array([rC, d, c, cnt, l1]) + LOG_OFFSET)
                 margin = min(margin, np.min(np.abs(raw - lo)), np.min(np.abs(raw - hi)))
                 if np.any(raw < lo) or np.any(raw > hi):
                     fallback = True
                     continue
                 pred = forward(P, ((raw - shift) * scale)[None])[0][0]
-                d_o, m_o = lowest_degree(pred, pair_scale(l1, d, kernel, kappa[o]), budget[o], cnt)
+                d_o, m_o = lowest_degree(pred, pair_scale(l1, d, c), budget[o], cnt)
                 margin = min(margin, m_o)
                 degs.append(d_o)
             if fallback:

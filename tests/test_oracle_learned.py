@@ -38,7 +38,7 @@ def _case(n=3000, leaf=150, seed=7):
 
 def _run(t, X, Y, Z, F, W, params, norm, kernel="yukawa_ss", kappa=(0.8, 2.0), log_tol=(-6, -6),
          theta_max=0.8, theta_fb=0.6, degree_fb=8):
-    return learned.learned_lists(t, X, Y, Z, F, W, kernel, np.array(kappa), 1.0, params, norm,
+    return learned.learned_lists(t, X, Y, Z, F, W, kernel, np.array(kappa), params, norm,
                                  np.array(log_tol, float), theta_max, theta_fb, degree_fb)
 
 
@@ -108,8 +108,9 @@ def _four_cluster_case():
     return P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), f, w
 
 
+@pytest.mark.parametrize("kernel", ["yukawa_ss", "coulomb_ss"])
 @pytest.mark.parametrize("shift", [-0.5, -0.2, -0.05, 0.05, 0.2, 0.5, 1.05])
-def test_hand_computed_decisions_with_the_batch_budget(shift):
+def test_hand_computed_decisions_with_the_batch_budget(shift, kernel):
     x, y, z, f, w = _four_cluster_case()
     t = bltc.build_tree(x, y, z, 250)
     # root -> (grid clusters' parent, batch); parent -> the four grid clusters
@@ -119,6 +120,8 @@ def test_hand_computed_decisions_with_the_batch_budget(shift):
     B = t.children[0][1]
     grids = t.children[t.children[0][0]]
     kappa, theta_max = 0.7, 0.15
+    # decay rate of the pair scale: kappa for Yukawa, 0 for Coulomb (1/r)
+    c = kappa if kernel == "yukawa_ss" else 0.0
     b = np.array([-5.0, -6.0, -7.0, -8.0, -9.0, -10.0, -11.0, -12.0, -13.0])
     # by hand: batch geometry, and per grid cluster the features of the decision
     Pb = np.stack([x, y, z], axis=1)[p[t.begin[B]:t.end[B]]]
@@ -139,7 +142,7 @@ def test_hand_computed_decisions_with_the_batch_budget(shift):
         d = R - rb
         # points on the proxy nodes and positive f, w: l1 = sum q + max|f| sum w
         l1 = np.sum(F[0, s0:s1] * W[s0:s1]) + fmax * np.sum(W[s0:s1])
-        s = np.log10(l1) - kappa * d / np.log(10.0) - np.log10(d)
+        s = np.log10(l1) - c * d / np.log(10.0) - np.log10(d)
         if budget is None:
             # straddle the first cluster's degree-5 threshold (shift 0) and degree-4
             # threshold (shift 1) after the budget's 1/sqrt(M_B) factor
@@ -148,13 +151,24 @@ def test_hand_computed_decisions_with_the_batch_budget(shift):
         # degrees with (n+1)^3 < 250: 4 and 5
         deg = 4 if b[0] + s <= pair_budget else (5 if b[1] + s <= pair_budget else None)
         expected.append((C, deg))
-    far, near, ties = learned.learned_lists(t, X, Y, Z, F, W, "yukawa_ss", [kappa], 1.0,
+    far, near, ties = learned.learned_lists(t, X, Y, Z, F, W, kernel, [kappa],
                                             bias_network(b), OPEN_RANGE, [budget], theta_max,
                                             0.1, 8)
     bi = t.leaves().index(B)
     assert far[bi] == [(C, d) for C, d in expected if d is not None]
     assert near[bi] == [C for C, d in expected if d is None] + [B]
     assert expected[0][1] == (None if shift < 0 else (5 if shift < 1 else 4))
+
+
+def test_decay_feature_is_finite_for_coulomb_and_continuous_in_kappa():
+    # the third log-feature ln(c + 0.25): Coulomb (c = 0) is the kappa -> 0 end
+    # of the Yukawa values
+    assert learned.decay("coulomb_ss", 3.0) == 0.0 and learned.decay("coulomb", 3.0) == 0.0
+    assert learned.decay("yukawa_ss", 3.0) == 3.0
+    f0 = np.log(learned.decay("coulomb_ss", 1.0) + learned.LOG_OFFSET[2])
+    f1 = np.log(learned.decay("yukawa_ss", 1e-9) + learned.LOG_OFFSET[2])
+    assert np.isfinite(f0) and abs(f0 - f1) < 1e-8
+    assert np.all(learned.LOG_OFFSET[[0, 1, 3, 4]] == 0.0)
 
 
 def test_candidate_counts_are_the_fixed_mac_far_counts():
