@@ -17,9 +17,14 @@ degree has fewer charges than sources). Otherwise, per orbital o, the network
 with the decay rate c_o = kappa_o for the Yukawa kernels and 0 for the Coulomb
 kernels (the kappa -> 0 limit of exp(-kappa r)/r is 1/r), offset 0.25 on c and 0
 on the others (so that c = 0 maps to a finite value), and
-l1_o = |q^_o|_1 + max_B |f_o| |w^|_1 from C's degree-4 proxy charges of f w and
-of w (Section 6.2), a bound on the l1 norm of the subtracted charges
-q^ - f_i w^. It predicts, for degrees 4..12, log10 of the pair's largest error
+l1_o = |q^_o|_1 + g max_B |f_o| |w^|_1 from C's degree-4 proxy charges of f w and
+of w (Section 6.2): the size of the charges the pair's far field carries. The
+subtracted charges -f_i w^ enter with the ratio g of their kernel to the first
+one's: g = 1 for the subtracted Yukawa kernel (both terms carry
+exp(-kappa r)/r); for the subtracted Coulomb kernel the Gaussian
+exp(-r^2/a^2) at the least distance dm = max(R - r_B - r_C, 0) that a target of
+B and a proxy point of C can have, a bound over the pair; g = 0 for the plain
+kernels (no subtraction). It predicts, for degrees 4..12, log10 of the pair's largest error
 minus the pair scale s_o = log10(l1_o) - c_o d log10(e) - log10(d) (log10 of the
 size of the pair's far field). The
 pair is approximated at the lowest degree n with (n+1)^3 < N_S whose predicted
@@ -79,6 +84,16 @@ def decay(kernel, kappa_o):
     return kappa_o if kernel in YUKAWA_KERNELS else 0.0
 
 
+def subtracted_weight(kernel, R, rB, rC, alpha):
+    """g: the weight of the subtracted charges in the l1 feature (see above)."""
+    if kernel == "yukawa_ss":
+        return 1.0
+    if kernel == "coulomb_ss":
+        dm = max(R - rB - rC, 0.0)
+        return float(np.exp(-dm * dm / (alpha * alpha)))
+    return 0.0
+
+
 def pair_scale(l1, d, c):
     """log10 of the size of a pair's far field, l1 exp(-c d) / d, c the decay rate."""
     return np.log10(l1) - LOG10E * c * d - np.log10(d)
@@ -105,7 +120,7 @@ def candidate_counts(tree, theta_max):
 
 
 def learned_lists(tree, x, y, z, F, W, kernel, kappa, params, norm, log_tol, theta_max,
-                  theta_fb, degree_fb, tie=2e-4):
+                  theta_fb, degree_fb, alpha=1.0, tie=2e-4):
     """Per batch (leaf order): far [(C, degree)] and near [C] in visiting order,
     and the decisions within `tie` of a threshold as (batch index, C, margin).
     x, y, z, F (n_orb, N), W are in the tree's order; log_tol (n_orb,) is log10 of
@@ -131,8 +146,9 @@ def learned_lists(tree, x, y, z, F, W, kernel, kappa, params, norm, log_tol, the
                 l1_cache[C] = cluster_l1(tree, x, y, z, F, W, C)
             l1s = l1_cache[C]
             fallback, margin, degs = False, np.inf, []
+            g = subtracted_weight(kernel, R, rad[B], rC, alpha)
             for o in range(n_orb):
-                l1 = max(l1s[o] + fmax[o] * l1s[n_orb], 1e-30)
+                l1 = max(l1s[o] + g * fmax[o] * l1s[n_orb], 1e-30)
                 c = decay(kernel, kappa[o])
                 raw = np.log(np.array([rC, d, c, cnt, l1]) + LOG_OFFSET)
                 margin = min(margin, np.min(np.abs(raw - lo)), np.min(np.abs(raw - hi)))

@@ -140,8 +140,10 @@ def test_hand_computed_decisions_with_the_batch_budget(shift, kernel):
         R = np.linalg.norm(cb - cc)
         assert rb + rc < theta_max * R and rc == pytest.approx(np.sqrt(3.0), abs=1e-15)
         d = R - rb
-        # points on the proxy nodes and positive f, w: l1 = sum q + max|f| sum w
-        l1 = np.sum(F[0, s0:s1] * W[s0:s1]) + fmax * np.sum(W[s0:s1])
+        # points on the proxy nodes and positive f, w: l1 = sum q + g max|f| sum w,
+        # g = 1 for Yukawa-SS and the Gaussian at the least distance for Coulomb-SS
+        g = 1.0 if kernel == "yukawa_ss" else np.exp(-max(R - rb - rc, 0.0) ** 2)
+        l1 = np.sum(F[0, s0:s1] * W[s0:s1]) + g * fmax * np.sum(W[s0:s1])
         s = np.log10(l1) - c * d / np.log(10.0) - np.log10(d)
         if budget is None:
             # straddle the first cluster's degree-5 threshold (shift 0) and degree-4
@@ -158,6 +160,18 @@ def test_hand_computed_decisions_with_the_batch_budget(shift, kernel):
     assert far[bi] == [(C, d) for C, d in expected if d is not None]
     assert near[bi] == [C for C, d in expected if d is None] + [B]
     assert expected[0][1] == (None if shift < 0 else (5 if shift < 1 else 4))
+
+
+def test_subtracted_weight_of_the_l1_feature():
+    # the subtracted charges -f_i w^ carry the Gaussian for Coulomb-SS: bounded by
+    # its value at the least distance a target and a proxy point can have
+    assert learned.subtracted_weight("yukawa_ss", 5.0, 1.0, 1.0, 1.0) == 1.0
+    assert learned.subtracted_weight("yukawa", 5.0, 1.0, 1.0, 1.0) == 0.0
+    assert learned.subtracted_weight("coulomb", 5.0, 1.0, 1.0, 1.0) == 0.0
+    assert learned.subtracted_weight("coulomb_ss", 5.0, 1.0, 1.0, 1.0) == pytest.approx(np.exp(-9.0))
+    assert learned.subtracted_weight("coulomb_ss", 5.0, 1.0, 1.0, 2.0) == pytest.approx(np.exp(-9.0 / 4))
+    # overlapping spheres: the bound is 1
+    assert learned.subtracted_weight("coulomb_ss", 1.5, 1.0, 1.0, 1.0) == 1.0
 
 
 def test_decay_feature_is_finite_for_coulomb_and_continuous_in_kappa():
