@@ -25,10 +25,12 @@
 //
 // GPU mapping: a work item is (cluster, range of at most kItemPts sources,
 // block of charge sets). The block stages the basis values of 64 sources at a
-// time in LDS; each thread owns up to R coefficients and MB charge sets in
-// registers; the charges q_j are wave-uniform and come through scalar loads.
-// Items of one cluster write partial sums that a second kernel adds in a fixed
-// order, so the result does not depend on scheduling.
+// time in LDS. For Lagrange charges at degrees 4..12 each thread owns one
+// (k1, k2) pair and every k3 for MB charge sets (k_upward_rb); otherwise each
+// thread owns up to R coefficients and MB charge sets, with the charges q_j
+// wave-uniform through scalar loads (k_upward). Items of one cluster write
+// partial sums that a second kernel adds in a fixed order, so the result does
+// not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,6 +73,54 @@ __device__ void cheb_nodes(double lo, double hi, int n, double* s) {
   for (int k = 0; k <= n; ++k) s[k] = c + h * cos(M_PI * k / n);
   s[0] = hi;
   s[n] = lo;
+}
+
+// Barycentric basis values of one coordinate t at the nodes s[0..degree]
+// (weights b), written to L[0..degree]; HERM: Hermite value basis A_k in L[k] and
+// derivative basis B_k in L[ld + k] (c = L_k'(s_k)). A coordinate on a node takes
+// the Kronecker basis there (derivative part 0); a zero-extent dimension puts all
+// mass on node 0; live == false writes zeros (padding rows of a stage).
+template <bool HERM>
+__device__ void basis_values(bool live, double t, const double* s, const double* b,
+                             const double* c, int degree, int ld, double* L) {
+  if (!live) {
+    for (int k = 0; k <= degree; ++k) L[k] = 0.0;
+    if (HERM)
+      for (int k = 0; k <= degree; ++k) L[ld + k] = 0.0;
+    return;
+  }
+  bool exact = true;  // Kronecker values, no derivative part
+  if (s[0] == s[degree]) {  // zero-extent dimension
+    for (int k = 0; k <= degree; ++k) L[k] = k == 0 ? 1.0 : 0.0;
+  } else {
+    int hit = -1;
+    for (int k = 0; k <= degree; ++k)
+      if (t == s[k]) hit = k;
+    if (hit >= 0) {
+      for (int k = 0; k <= degree; ++k) L[k] = k == hit ? 1.0 : 0.0;
+    } else {
+      exact = false;
+      double sum = 0.0;
+      for (int k = 0; k <= degree; ++k) {
+        const double a = b[k] / (t - s[k]);
+        L[k] = a;
+        sum += a;
+      }
+      for (int k = 0; k <= degree; ++k) L[k] = L[k] / sum;
+    }
+  }
+  if (HERM) {
+    for (int k = 0; k <= degree; ++k) {
+      if (exact) {
+        L[ld + k] = 0.0;
+      } else {
+        const double dt = t - s[k];
+        const double l2 = L[k] * L[k];
+        L[ld + k] = dt * l2;
+        L[k] = (1.0 - 2.0 * c[k] * dt) * l2;
+      }
+    }
+  }
 }
 
 // R: coefficient rounds per thread (K <= R * kThreads); MB: charge sets per pass;
@@ -140,48 +190,9 @@ __global__ __launch_bounds__(kThreads) void k_upward(
     const int cnt = min(kStage, it.p1 - p0);
     if (threadIdx.x < 3 * kStage) {
       const int d = threadIdx.x / kStage, p = threadIdx.x % kStage;
-      double* L = s_L[d][p];
-      if (p < cnt) {
-        const double* cp = d == 0 ? xs : (d == 1 ? ys : zs);
-        const double t = cp[p0 + p];
-        const double* s = s_nodes[d];
-        bool exact = true;  // Kronecker values, no derivative part
-        if (s[0] == s[degree]) {  // zero-extent dimension
-          for (int k = 0; k <= degree; ++k) L[k] = k == 0 ? 1.0 : 0.0;
-        } else {
-          int hit = -1;
-          for (int k = 0; k <= degree; ++k)
-            if (t == s[k]) hit = k;
-          if (hit >= 0) {
-            for (int k = 0; k <= degree; ++k) L[k] = k == hit ? 1.0 : 0.0;
-          } else {
-            exact = false;
-            double sum = 0.0;
-            for (int k = 0; k <= degree; ++k) {
-              const double a = s_b[k] / (t - s[k]);
-              L[k] = a;
-              sum += a;
-            }
-            for (int k = 0; k <= degree; ++k) L[k] = L[k] / sum;
-          }
-        }
-        if (HERM) {
-          for (int k = 0; k <= degree; ++k) {
-            if (exact) {
-              L[kLd + k] = 0.0;
-            } else {
-              const double dt = t - s[k];
-              const double l2 = L[k] * L[k];
-              L[kLd + k] = dt * l2;
-              L[k] = (1.0 - 2.0 * s_c[d][k] * dt) * l2;
-            }
-          }
-        }
-      } else {
-        for (int k = 0; k <= degree; ++k) L[k] = 0.0;
-        if (HERM)
-          for (int k = 0; k <= degree; ++k) L[kLd + k] = 0.0;
-      }
+      const double* cp = d == 0 ? xs : (d == 1 ? ys : zs);
+      basis_values<HERM>(p < cnt, p < cnt ? cp[p0 + p] : 0.0, s_nodes[d], s_b, s_c[d], degree,
+                         kLd, s_L[d][p]);
     }
     __syncthreads();
 #pragma unroll 4
@@ -206,6 +217,121 @@ __global__ __launch_bounds__(kThreads) void k_upward(
       if (m < n_sets) partial[((int64_t)blockIdx.x * MB + m) * K + k] = acc[r][m];
   }
 }
+
+// Lagrange charges with the k3 direction in registers. Thread (k1, k2, group g)
+// holds acc[m][k3] for MB charge sets and every k3. Per staged source it forms
+// c = L_k1(x) L_k2(y) once and c q_m once per set, then (n+1) MB multiply-adds
+// with the values L_k3(z), which every thread of a group reads at one LDS address
+// (a broadcast). The G = 256 / (n+1)^2 groups of a block take interleaved sources
+// of each stage; at the end their sums are added in LDS in group order. Per
+// source and thread: 2 + (n+1) + MB LDS reads against 1 + MB + (n+1) MB VALU
+// operations (the coefficient-per-thread form above reads 3 values per 2 + MB).
+template <int NP1, int MB>
+__global__ __launch_bounds__(kThreads) void k_upward_rb(
+    const UpItem* __restrict__ items, const int32_t* __restrict__ approx_node,
+    const double* __restrict__ box, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs,
+    const double* __restrict__ qs, const double* __restrict__ ws, int64_t n, int n_orb,
+    int m0, int n_sets, double* __restrict__ partial, double* __restrict__ pnodes,
+    float* __restrict__ pnodes32) {
+  constexpr int P = NP1 * NP1;
+  static_assert(P <= kThreads, "one (k1, k2) pair per thread");
+  constexpr int G = kThreads / P;                  // source groups per block
+  constexpr int LD = NP1 % 2 ? NP1 + 1 : NP1;      // even row stride: 16-byte aligned rows
+  constexpr int K = NP1 * NP1 * NP1;
+  constexpr int degree = NP1 - 1;
+  constexpr int RED = (G - 1) * P * NP1 > 0 ? (G - 1) * P * NP1 : 1;
+  const UpItem it = items[blockIdx.x];
+  __shared__ double s_nodes[3][NP1];
+  __shared__ double s_b[NP1];
+  __shared__ __align__(16) double s_L[3][kStage][LD];
+  __shared__ double s_q[MB][kStage];
+  __shared__ double s_red[RED];
+  const int c = approx_node[it.slot];
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x;
+    cheb_nodes(box[c * 6 + d], box[c * 6 + 3 + d], degree, s_nodes[d]);
+  }
+  if (threadIdx.x <= degree) {
+    double b = (threadIdx.x & 1) ? -1.0 : 1.0;
+    if (threadIdx.x == 0 || threadIdx.x == degree) b *= 0.5;
+    s_b[threadIdx.x] = b;
+  }
+  __syncthreads();
+  if (m0 == 0 && it.part == it.slot && threadIdx.x < 3 * NP1) {
+    const int d = threadIdx.x / NP1, k = threadIdx.x % NP1;
+    const double v = s_nodes[d][k];
+    pnodes[((int64_t)it.slot * 3 + d) * NP1 + k] = v;
+    const double ctr = 0.5 * (box[c * 6 + d] + box[c * 6 + 3 + d]);
+    pnodes32[((int64_t)it.slot * 3 + d) * NP1 + k] = (float)(v - ctr);
+  }
+  const int g = threadIdx.x / P, pr = threadIdx.x % P;
+  const bool active = g < G;
+  const int k1 = pr / NP1, k2 = pr % NP1;
+  double acc[MB][NP1];
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int k = 0; k < NP1; ++k) acc[m][k] = 0.0;
+
+  for (int p0 = it.p0; p0 < it.p1; p0 += kStage) {
+    const int cnt = min(kStage, it.p1 - p0);
+    if (threadIdx.x < 3 * kStage) {
+      const int d = threadIdx.x / kStage, pp = threadIdx.x % kStage;
+      const double* cp = d == 0 ? xs : (d == 1 ? ys : zs);
+      basis_values<false>(pp < cnt, pp < cnt ? cp[p0 + pp] : 0.0, s_nodes[d], s_b, nullptr,
+                          degree, 0, s_L[d][pp]);
+    }
+    for (int e = threadIdx.x; e < MB * kStage; e += kThreads) {
+      const int m = e / kStage, pp = e % kStage;
+      const int set = m0 + m;
+      const int64_t j = p0 + pp;
+      s_q[m][pp] = pp >= cnt ? 0.0 : (set < n_orb ? qs[(int64_t)set * n + j]
+                                                   : (set == n_orb ? ws[j] : 0.0));
+    }
+    __syncthreads();
+    if (active) {
+      for (int pp = g; pp < cnt; pp += G) {
+        const double cxy = s_L[0][pp][k1] * s_L[1][pp][k2];
+        double cq[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) cq[m] = cxy * s_q[m][pp];
+#pragma unroll
+        for (int k = 0; k < NP1; ++k) {
+          const double z = s_L[2][pp][k];
+#pragma unroll
+          for (int m = 0; m < MB; ++m) acc[m][k] = fma(cq[m], z, acc[m][k]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // groups 1 .. G-1 hand their sums to group 0, one charge set at a time
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    if (G > 1) {
+      if (active && g > 0)
+#pragma unroll
+        for (int k = 0; k < NP1; ++k) s_red[((g - 1) * P + pr) * NP1 + k] = acc[m][k];
+      __syncthreads();
+      if (g == 0)
+        for (int gg = 1; gg < G; ++gg)
+#pragma unroll
+          for (int k = 0; k < NP1; ++k) acc[m][k] += s_red[((gg - 1) * P + pr) * NP1 + k];
+      __syncthreads();
+    }
+    if (g == 0 && m < n_sets) {
+      double* out = partial + ((int64_t)blockIdx.x * MB + m) * K + pr * NP1;
+#pragma unroll
+      for (int k = 0; k < NP1; ++k) out[k] = acc[m][k];
+    }
+  }
+}
+
+// charge sets per pass of k_upward_rb for n+1 = np1 (its accumulators: MB (n+1)
+// doubles per thread)
+constexpr int rb_sets(int np1) { return np1 <= 9 ? 8 : 4; }
+constexpr bool rb_supported(int np1) { return np1 >= 5 && np1 <= 13; }
 
 // sum the partial charges of each cluster's items in item order
 __global__ void k_upward_reduce(const int32_t* __restrict__ slot_first,
@@ -251,6 +377,23 @@ int charge_block(int K, int n_sets, int* R_out) {
   int mb = charge_blocking(K, R_out);
   while (mb > 1 && mb / 2 >= n_sets) mb /= 2;
   return mb;
+}
+
+template <int NP1, int MB>
+void launch_upward_rb(hipStream_t s, tagi_tree* t, ProxySet& ps, int m0, int n_sets) {
+  hipLaunchKernelGGL((k_upward_rb<NP1, MB>), dim3(ps.n_items), dim3(kThreads), 0, s,
+                     ps.items.as<UpItem>(), ps.node.as<int32_t>(), t->nd_box.as<double>(),
+                     t->xs.as<double>(), t->ys.as<double>(), t->zs.as<double>(),
+                     t->qs.as<double>(), t->ws.as<double>(), t->n, ps.n_orb, m0, n_sets,
+                     ps.partial.as<double>(), ps.pnodes.as<double>(), ps.pnodes32.as<float>());
+}
+
+template <int NP1>
+void launch_upward_rb_mb(int MB, hipStream_t s, tagi_tree* t, ProxySet& ps, int m0, int n_sets) {
+  if constexpr (rb_sets(NP1) >= 8)
+    if (MB == 8) return launch_upward_rb<NP1, 8>(s, t, ps, m0, n_sets);
+  if (MB == 4) return launch_upward_rb<NP1, 4>(s, t, ps, m0, n_sets);
+  launch_upward_rb<NP1, 2>(s, t, ps, m0, n_sets);
 }
 
 template <int R>
@@ -313,7 +456,7 @@ int prepare_proxies(tagi_tree* t, ProxySet& ps, const std::vector<int32_t>& node
     TAGI_TRY(ps.qhat.ensure((size_t)n_orb * na * K * sizeof(double)));
     TAGI_TRY(ps.what.ensure((size_t)na * K * sizeof(double)));
     int R;
-    const int MB = charge_blocking(K, &R);
+    const int MB = std::max(charge_blocking(K, &R), herm ? 1 : rb_sets(np1));
     TAGI_TRY(ps.partial.ensure((size_t)ps.n_items * MB * K * sizeof(double)));
   }
   ps.degree = degree;
@@ -328,10 +471,36 @@ int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s) {
   const int np1 = ps.degree + 1;
   const int K = (ps.herm ? kHermPatterns : 1) * np1 * np1 * np1;
   const int n_sets_total = ps.n_orb + 1;
-  int R;
-  const int MB = charge_block(K, n_sets_total, &R);
   const int32_t* d_slot_first =
       reinterpret_cast<const int32_t*>(ps.items.as<char>() + (size_t)ps.n_items * sizeof(UpItem));
+  if (!ps.herm && rb_supported(np1)) {
+    // k3 in registers: as many sets per pass as there are, up to rb_sets
+    int MB = 2;
+    while (MB < n_sets_total && MB < rb_sets(np1)) MB *= 2;
+    for (int m0 = 0; m0 < n_sets_total; m0 += MB) {
+      const int n_sets = std::min(MB, n_sets_total - m0);
+      switch (np1) {
+        case 5: launch_upward_rb_mb<5>(MB, s, t, ps, m0, n_sets); break;
+        case 6: launch_upward_rb_mb<6>(MB, s, t, ps, m0, n_sets); break;
+        case 7: launch_upward_rb_mb<7>(MB, s, t, ps, m0, n_sets); break;
+        case 8: launch_upward_rb_mb<8>(MB, s, t, ps, m0, n_sets); break;
+        case 9: launch_upward_rb_mb<9>(MB, s, t, ps, m0, n_sets); break;
+        case 10: launch_upward_rb_mb<10>(MB, s, t, ps, m0, n_sets); break;
+        case 11: launch_upward_rb_mb<11>(MB, s, t, ps, m0, n_sets); break;
+        case 12: launch_upward_rb_mb<12>(MB, s, t, ps, m0, n_sets); break;
+        default: launch_upward_rb_mb<13>(MB, s, t, ps, m0, n_sets); break;
+      }
+      TAGI_HIP(hipGetLastError());
+      const int64_t tot = (int64_t)n_sets * K;
+      hipLaunchKernelGGL(k_upward_reduce, dim3((tot + 255) / 256, na), dim3(256), 0, s,
+                         d_slot_first, ps.partial.as<double>(), na, K, MB, m0, n_sets, ps.n_orb,
+                         ps.qhat.as<double>(), ps.what.as<double>());
+      TAGI_HIP(hipGetLastError());
+    }
+    return TAGI_OK;
+  }
+  int R;
+  const int MB = charge_block(K, n_sets_total, &R);
   for (int m0 = 0; m0 < n_sets_total; m0 += MB) {
     const int n_sets = std::min(MB, n_sets_total - m0);
     switch (R) {
