@@ -36,8 +36,9 @@ summed directly). If any orbital's log-feature lies outside the training range
 Budget of a batch: a batch's error is a sum over its far pairs, so the per-pair
 budget shrinks with their number. With tol_o the caller's absolute budget for
 orbital o and M_B the number of far pairs of B in the fixed-MAC lists at
-(theta_max, degree 4), the pair budget is tol_o / sqrt(max(M_B, 1)) (errors of
-independent signs add in quadrature).
+(theta_max, degree 4), the pair budget is tol_o / max(M_B, 1): the error of a
+target's far field is at most the sum of its pairs' errors (triangle
+inequality), whatever their signs.
 
 The GPU evaluates the network in FP32, so a decision whose margin (distance of a
 compared log quantity from its threshold) is below `tie` may legitimately come
@@ -137,7 +138,7 @@ def learned_lists(tree, x, y, z, F, W, kernel, kappa, params, norm, log_tol, the
     far_all, near_all, ties = [], [], []
     for bi, B in enumerate(tree.leaves()):
         fmax = np.abs(F[:, tree.begin[B]:tree.end[B]]).max(axis=1)
-        budget = log_tol - 0.5 * np.log10(max(int(m_b[bi]), 1))
+        budget = log_tol - np.log10(max(int(m_b[bi]), 1))
         far, near = [], []
 
         def decide(C, cnt, R, rC):

@@ -147,9 +147,9 @@ def test_hand_computed_decisions_with_the_batch_budget(shift, kernel):
         s = np.log10(l1) - c * d / np.log(10.0) - np.log10(d)
         if budget is None:
             # straddle the first cluster's degree-5 threshold (shift 0) and degree-4
-            # threshold (shift 1) after the budget's 1/sqrt(M_B) factor
-            budget = b[1] + s + 0.5 * np.log10(4.0) + shift
-        pair_budget = budget - 0.5 * np.log10(4.0)
+            # threshold (shift 1) after the budget's 1/M_B factor
+            budget = b[1] + s + np.log10(4.0) + shift
+        pair_budget = budget - np.log10(4.0)
         # degrees with (n+1)^3 < 250: 4 and 5
         deg = 4 if b[0] + s <= pair_budget else (5 if b[1] + s <= pair_budget else None)
         expected.append((C, deg))
