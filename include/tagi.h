@@ -359,19 +359,35 @@ int tagi_green_step(tagi_tree* tree, const double* psi, const double* veff, cons
 int tagi_tree_set_orbital_block(tagi_tree* tree, int ob);
 
 /*
+ * Granularity of the compute schedule (a project addition): each batch's far
+ * and near lists are cut into chunks of at most E / items kernel evaluations per
+ * target lane (E = the whole convolution's), and a work item is one chunk for
+ * one 64-target group and orbital block, so a launch holds about `items` waves
+ * (more where batches hold several groups). Fewer, longer items cost less
+ * per-item overhead; more, shorter ones balance the chip's 256 CUs better.
+ * items = 0 restores the default (16384); otherwise 256 <= items <= 2^22. The
+ * next tagi_convolve / tagi_convolve_learned on the tree rebuilds its schedule.
+ * Results change only by the order of the partial sums (rounding).
+ * Errors: TAGI_E_ARG.
+ */
+int tagi_tree_set_schedule_items(tagi_tree* tree, int items);
+
+/*
  * Autotuner for the batched launch (a project addition): picks the leaf size
- * N_L (Section 6.1; batches are leaves, so it sets both N_L and N_B) and the
- * orbital block width for one convolution by timing the candidates on the
- * caller's data. For every leaf size it builds a tree, and for every orbital
- * block it runs tagi_upward + tagi_convolve once untimed (plans, lists and
- * schedule), then `reps` times between HIP events on `stream`.
+ * N_L (Section 6.1; batches are leaves, so it sets both N_L and N_B), the
+ * orbital block width and the schedule granularity for one convolution by
+ * timing the candidates on the caller's data. For every leaf size it builds a
+ * tree, and for every (orbital block, schedule items) pair it runs tagi_upward
+ * + tagi_convolve once untimed (plans, lists and schedule), then `reps` times
+ * between HIP events on `stream`.
  *   x, y, z, w   DEVICE double [n] sources; f DEVICE double [n_orb][n]
  *   box          HOST double[6] root box or NULL, as tagi_tree_build
  *   kernel, kappa (HOST [n_orb]), alpha, theta, degree, precision: as tagi_convolve
  *   leaf_sizes   HOST int [n_leaf] candidates (>= 1)
  *   obs          HOST int [n_ob] candidates (0, 1, 2, 4 or 8)
- *   best         HOST int [2] receives {leaf size, orbital block} of the fastest
- *   times        HOST double [n_leaf][n_ob] mean ms per step (may be NULL)
+ *   items        HOST int [n_items] candidates for tagi_tree_set_schedule_items
+ *   best         HOST int [3] receives {leaf size, orbital block, items} of the fastest
+ *   times        HOST double [n_leaf][n_ob][n_items] mean ms per step (may be NULL)
  * The accuracy at a fixed (theta, degree) changes slightly with N_L; checking
  * it is the caller's. Synchronises the stream; allocates and frees its own
  * scratch (one output array and the candidate trees).
@@ -380,8 +396,8 @@ int tagi_tree_set_orbital_block(tagi_tree* tree, int ob);
 int tagi_autotune(const double* x, const double* y, const double* z, const double* w, int64_t n,
                   const double* box, const double* f, int n_orb, int kernel, const double* kappa,
                   double alpha, double theta, int degree, int precision, const int* leaf_sizes,
-                  int n_leaf, const int* obs, int n_ob, int reps, int* best, double* times,
-                  void* stream);
+                  int n_leaf, const int* obs, int n_ob, const int* items, int n_items, int reps,
+                  int* best, double* times, void* stream);
 
 /*
  * Learned degree/MAC selector (a project addition on top of Section 6.2-6.3).
@@ -391,22 +407,31 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
  * (row-major) followed by its biases: 5*64+64, 64*64+64, 64*64+64, 64*9+9
  * floats (tagi_selector_param_count()). Output k predicts log10 of the largest
  * absolute error of approximating a batch-cluster pair at degree 4 + k, minus
- * the pair scale s = log10(l1) - kappa d log10(e) - log10(d), d = R - r_B,
- * l1 = feature 5 below (the error relative to the size of the pair's far field).
+ * the pair scale s = log10(l1) - c d log10(e) - log10(d), d = R - r_B,
+ * l1 = feature 5 below, c = the kernel's decay rate (kappa for the Yukawa
+ * kernels, 0 for the Coulomb kernels): the error relative to the size of the
+ * pair's far field.
  *
  * tagi_selector_samples: training data from the method itself. After an upward
  * pass at degree 4 with f (one orbital) and w, the far pairs of the lists at
  * (theta_max, degree 4) are the candidates; an evenly strided subset of at most
- * max_pairs is kept. For each pair, HOST outputs:
- *   features [m][5] = {r_C, R - r_B, kappa, N_S, l1}, radii and R as in the
- *                      MAC, l1 = |q^_C|_1 + max_B |f| |w^_C|_1 from C's degree-4
- *                      proxy charges of f w (q^) and of w (w^): a bound on the
- *                      l1 norm of the subtracted charges q^ - f_i w^;
+ * max_pairs is kept. kernel: TAGI_YUKAWA_SS (decay kappa > 0) or
+ * TAGI_COULOMB_SS (Gaussian width alpha > 0; decay 0). For each pair, HOST
+ * outputs:
+ *   features [m][5] = {r_C, R - r_B, c, N_S, l1}, radii and R as in the MAC,
+ *                      c the decay rate, l1 = |q^_C|_1 + g max_B |f| |w^_C|_1 from
+ *                      C's degree-4 proxy charges of f w (q^) and of w (w^): the
+ *                      size of the charges q^ - f_i w^ the pair's far field
+ *                      carries, with g = 1 for TAGI_YUKAWA_SS, and for
+ *                      TAGI_COULOMB_SS g = exp(-dm^2/alpha^2) at the least
+ *                      distance dm = max(R - r_B - r_C, 0) of the pair (the
+ *                      Gaussian's bound over it); tagi_convolve_learned takes
+ *                      g = 0 for the plain kernels;
  *   errors   [m][9] = max over up to 256 of the batch's targets, spread
  *                      evenly (target begin + k nb / min(nb, 256), k < min(nb, 256),
- *                      nb = batch size), of |approximated -
- *                      direct| pair contribution (Yukawa with subtraction,
- *                      Section 4.3) at degrees 4..12; NaN where the cluster holds
+ *                      nb = batch size), of |approximated - direct| pair
+ *                      contribution (with the Section 4.3 subtraction of the
+ *                      kernel) at degrees 4..12; NaN where the cluster holds
  *                      too few sources for that degree ((n+1)^3 >= N_S);
  *   pair_ids [m][2] = {batch leaf node id, cluster node id} (may be NULL).
  * *n receives m. Synchronises the stream; leaves the tree's upward state at
@@ -425,26 +450,32 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
  */
 /*
  * tagi_convolve_learned: the far/near split of Algorithm 3 with the degree and acceptance of
- * every batch-cluster pair chosen by the selector network (Yukawa kernels only;
+ * every batch-cluster pair chosen by the selector network (any kernel;
  * requires a previous tagi_upward, whose f and w are used at every degree).
  * A pair with (r_B + r_C) < theta_max R is evaluated by the network once per
- * orbital on the features above, transformed as x_k = (ln(raw_k) - shift_k) *
- * scale_k; it is approximated at the lowest degree n in 4..12 with
- * (n+1)^3 < N_S whose predicted log10 error (output + pair scale) is
- * <= log10(tol[o]) for every
- * orbital o (tol: HOST [n_orb], absolute error budget of one pair per orbital);
- * otherwise the cluster is opened (a
+ * orbital on the features above, transformed as x_k = (ln(raw_k + o_k) - shift_k) *
+ * scale_k with o = (0, 0, 0.25, 0, 0) (the decay rate may be 0); it is
+ * approximated at the lowest degree n in 4..12 with (n+1)^3 < N_S whose
+ * predicted log10 error (output + pair scale) is <= log10(tol[o] / M_B)
+ * for every orbital o, M_B = the number of far pairs of the batch in the
+ * fixed-MAC lists at (theta_max, degree 4) (tol: HOST [n_orb], absolute error
+ * budget of one target's sum per orbital; a target's far-field error is at most
+ * the sum of its pairs' errors); otherwise the cluster is opened (a
  * leaf, or a cluster of at most 125 sources, is summed directly). If any
- * ln(raw_k) lies outside [lo_k, hi_k] (the training range), the pair falls back
+ * ln(raw_k + o_k) lies outside [lo_k, hi_k] (the training range), the pair falls back
  * to the fixed MAC with (theta_fb, degree_fb). Pairs failing the theta_max test
  * are opened as in Algorithm 3.
+ *   kappa   HOST [n_orb] for the Yukawa kernels (may be NULL for Coulomb)
+ *   alpha   Gaussian width of TAGI_COULOMB_SS (> 0); it does not enter the
+ *           features (the shipped network's Coulomb-SS samples use alpha = 1)
  *   params  HOST float [tagi_selector_param_count()]
  *   norm    HOST float [20] = shift[5], scale[5], lo[5], hi[5]
  *   0 < theta_fb, theta_max < 1; 4 <= degree_fb <= 12; tol[o] > 0.
  * Lists and per-degree plans are cached per argument set (rebuilding them
  * synchronises the stream); proxy charges are recomputed on every call.
- * Errors: TAGI_E_ARG, TAGI_E_STATE (no upward), TAGI_E_UNSUPPORTED (Coulomb
- * kernels, targets), TAGI_E_OOM, TAGI_E_HIP.
+ * Errors: TAGI_E_ARG, TAGI_E_STATE (no upward), TAGI_E_OOM, TAGI_E_HIP,
+ * TAGI_E_UNSUPPORTED (lists beyond 2^31 entries, a tree deeper than the
+ * traversal supports).
  *
  * tagi_learned_stats: HOST int64 out[17] = {far pairs, near pairs, far
  * evaluations, near evaluations (one orbital), far pairs at degree 0..12}.
@@ -464,9 +495,10 @@ int tagi_learned_stats(const tagi_tree* tree, int64_t* out);
 int tagi_learned_lists_export(const tagi_tree* tree, int64_t* far_off, int32_t* far_id,
                               int32_t* far_degree, int64_t* near_off, int32_t* near_id);
 int tagi_selector_param_count(void);
-int tagi_selector_samples(tagi_tree* tree, const double* f, const double* w, double kappa,
-                          double theta_max, int64_t max_pairs, float* features, float* errors,
-                          int32_t* pair_ids, int64_t* n, void* stream);
+int tagi_selector_samples(tagi_tree* tree, const double* f, const double* w, int kernel,
+                          double kappa, double alpha, double theta_max, int64_t max_pairs,
+                          float* features, float* errors, int32_t* pair_ids, int64_t* n,
+                          void* stream);
 int tagi_selector_grad(const float* params, const float* X, const float* Y, const float* M,
                        int64_t m, float* grads, float* loss, void* stream);
 int tagi_selector_train(float* params, const float* X, const float* Y, const float* M, int64_t m,

@@ -30,7 +30,8 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_upward_hermite", "tagi_convo
             "tagi_tree_timing", "tagi_graph_create", "tagi_graph_launch", "tagi_graph_destroy",
             "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
             "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
-            "tagi_tree_set_orbital_block", "tagi_autotune", "tagi_green_step",
+            "tagi_tree_set_orbital_block", "tagi_tree_set_schedule_items", "tagi_autotune",
+            "tagi_green_step",
             "tagi_learned_lists_export", "tagi_mesh_build", "tagi_mesh_info",
             "tagi_mesh_cells", "tagi_mesh_points", "tagi_mesh_destroy", "tagi_tree_destroy",
             "tagi_last_error"]
@@ -103,14 +104,15 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_mesh_points.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.tagi_mesh_destroy.argtypes = [vp]
     lib.tagi_autotune.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, vp, dbl, dbl, i32, i32,
-                                  vp, i32, vp, i32, i32, vp, vp, vp]
+                                  vp, i32, vp, i32, vp, i32, i32, vp, vp, vp]
+    lib.tagi_tree_set_schedule_items.argtypes = [vp, i32]
     lib.tagi_graph_create.argtypes = [vp, vp, vp, i32, i32, i32, vp, dbl, dbl, i32, vp, vp,
                                       ctypes.POINTER(vp)]
     lib.tagi_graph_launch.argtypes = [vp, vp]
     lib.tagi_graph_destroy.argtypes = [vp]
     lib.tagi_tree_timing.argtypes = [vp, ctypes.POINTER(Timing)]
     lib.tagi_selector_param_count.argtypes = []
-    lib.tagi_selector_samples.argtypes = [vp, vp, vp, dbl, dbl, i64, vp, vp, vp, vp, vp]
+    lib.tagi_selector_samples.argtypes = [vp, vp, vp, i32, dbl, dbl, dbl, i64, vp, vp, vp, vp, vp]
     lib.tagi_selector_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
     lib.tagi_selector_train.argtypes = [vp, vp, vp, vp, i64, vp, i32, i32, ctypes.c_float, vp, vp]
     lib.tagi_convolve_learned.argtypes = [vp, i32, vp, dbl, vp, vp, vp, dbl, dbl, i32, i32, vp, vp]
@@ -244,12 +246,14 @@ class Tree:
                          theta_fb: float = 0.7, degree_fb: int = 8, alpha: float = 1.0,
                          precision: str = "fp64", out: torch.Tensor | None = None):
         """tagi_convolve_learned: degrees and acceptance chosen by `selector`
-        (an object with float32 `params` and `norm` arrays); tol per orbital."""
+        (selector.Selector: its network for the kernel's family); tol per orbital."""
         n_orb = max(self.n_orb, 1)
-        kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64), (n_orb,)))
+        kap = np.ascontiguousarray(np.broadcast_to(
+            np.asarray(0.0 if kappa is None else kappa, dtype=np.float64), (n_orb,)))
         tl = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (n_orb,)))
-        prm = np.ascontiguousarray(selector.params, dtype=np.float32)
-        nrm = np.ascontiguousarray(selector.norm, dtype=np.float32)
+        net = selector.net(kernel)
+        prm = np.ascontiguousarray(net.params, dtype=np.float32)
+        nrm = np.ascontiguousarray(net.norm, dtype=np.float32)
         self._keep = (kap, tl, prm, nrm)
         if out is None:
             out = torch.empty((n_orb, self.n), dtype=torch.float64, device="cuda")
@@ -282,15 +286,18 @@ class Tree:
                 "near_off": no, "near_id": nid[:st["near_pairs"]]}
 
     def selector_samples(self, f: torch.Tensor, w: torch.Tensor, kappa: float,
-                         theta_max: float = 0.9, max_pairs: int = 50000, with_ids: bool = False):
+                         theta_max: float = 0.9, max_pairs: int = 50000, with_ids: bool = False,
+                         kernel: str = "yukawa_ss", alpha: float = 1.0):
         """tagi_selector_samples: (features (m, 5), errors (m, 9)) as numpy float32,
-        and the (batch node, cluster node) ids (m, 2) when with_ids."""
+        and the (batch node, cluster node) ids (m, 2) when with_ids. kernel
+        "yukawa_ss" (decay kappa) or "coulomb_ss" (Gaussian width alpha)."""
         feat = np.empty((max_pairs, 5), np.float32)
         err = np.empty((max_pairs, 9), np.float32)
         ids = np.empty((max_pairs, 2), np.int32)
         m = ctypes.c_int64()
         _check(load_library().tagi_selector_samples(self._h, _dptr(f, "f", self.n),
-                                                    _dptr(w, "w", self.n), float(kappa),
+                                                    _dptr(w, "w", self.n), KERNELS[kernel],
+                                                    float(kappa), float(alpha),
                                                     float(theta_max), int(max_pairs), _hptr(feat),
                                                     _hptr(err), _hptr(ids), ctypes.byref(m),
                                                     _stream()))
@@ -323,6 +330,10 @@ class Tree:
     def set_orbital_block(self, ob: int = 0):
         """tagi_tree_set_orbital_block: 1, 2, 4 or 8 orbitals per wave; 0 = automatic."""
         _check(load_library().tagi_tree_set_orbital_block(self._h, int(ob)))
+
+    def set_schedule_items(self, items: int = 0):
+        """tagi_tree_set_schedule_items: work items a schedule aims at; 0 = default."""
+        _check(load_library().tagi_tree_set_schedule_items(self._h, int(items)))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().tagi_tree_set_timing(self._h, int(bool(enable))))
@@ -478,23 +489,64 @@ def mesh(domain_lo, domain_hi, p: int, tol_m: float, uniform_levels: int = 3,
 
 
 def autotune(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_sizes,
-             obs=(0,), alpha: float = 1.0, precision: str = "fp64", reps: int = 1, box=None):
-    """tagi_autotune: ((best leaf size, best orbital block), times ms [n_leaf][n_ob])."""
+             obs=(0,), items=(0,), alpha: float = 1.0, precision: str = "fp64", reps: int = 1,
+             box=None):
+    """tagi_autotune: ((best leaf size, orbital block, schedule items), times ms
+    [n_leaf][n_ob][n_items])."""
     n = x.numel()
     n_orb = 1 if f.dim() == 1 else f.shape[0]
     kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64), (n_orb,)))
     ls = np.ascontiguousarray(leaf_sizes, dtype=np.int32)
     ob = np.ascontiguousarray(obs, dtype=np.int32)
+    it = np.ascontiguousarray(items, dtype=np.int32)
     bx = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
-    best = np.zeros(2, np.int32)
-    times = np.zeros((ls.size, ob.size), np.float64)
+    best = np.zeros(3, np.int32)
+    times = np.zeros((ls.size, ob.size, it.size), np.float64)
     _check(load_library().tagi_autotune(_dptr(x, "x", n), _dptr(y, "y", n), _dptr(z, "z", n),
                                         _dptr(w, "w", n), n, None if bx is None else _hptr(bx),
                                         _dptr(f, "f", n_orb * n), n_orb, KERNELS[kernel],
                                         _hptr(kap), float(alpha), float(theta), int(degree),
                                         PRECISIONS[precision], _hptr(ls), ls.size, _hptr(ob),
-                                        ob.size, int(reps), _hptr(best), _hptr(times), _stream()))
-    return (int(best[0]), int(best[1])), times
+                                        ob.size, _hptr(it), it.size, int(reps), _hptr(best),
+                                        _hptr(times), _stream()))
+    return (int(best[0]), int(best[1]), int(best[2])), times
+
+
+def tuning_key(n: int, n_orb: int, kernel: str, precision: str, theta: float, degree: int) -> str:
+    """Key of a tuned configuration: GPU architecture, kernel, precision, (theta,
+    degree), orbital count and the power-of-two bucket of the point count."""
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+    bucket = 1 << max(int(n) - 1, 0).bit_length()
+    return f"{arch}|{kernel}|{precision}|theta={theta}|degree={degree}|n_orb={n_orb}|n<={bucket}"
+
+
+def autotune_cached(cache_path: str, x, y, z, f, w, kernel: str, kappa, theta: float,
+                    degree: int, leaf_sizes, obs=(0,), items=(0,), alpha: float = 1.0,
+                    precision: str = "fp64", reps: int = 1, box=None):
+    """tagi_autotune behind a JSON cache: a configuration (tuning_key) tuned once
+    is read back from `cache_path` afterwards. Returns ((leaf size, orbital block,
+    schedule items), from_cache)."""
+    import json
+    n_orb = 1 if f.dim() == 1 else f.shape[0]
+    key = tuning_key(x.numel(), n_orb, kernel, precision, theta, degree)
+    cache = {}
+    if os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    hit = cache.get(key)
+    if hit is not None:
+        return (int(hit["leaf_size"]), int(hit["orbital_block"]), int(hit["schedule_items"])), True
+    best, times = autotune(x, y, z, f, w, kernel, kappa, theta, degree, leaf_sizes, obs, items,
+                           alpha, precision, reps, box)
+    cache[key] = {"leaf_size": best[0], "orbital_block": best[1], "schedule_items": best[2],
+                  "candidates": {"leaf_sizes": list(map(int, leaf_sizes)), "obs": list(map(int, obs)),
+                                 "items": list(map(int, items))},
+                  "ms": times.tolist()}
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, cache_path)
+    return best, False
 
 
 def treecode(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_size: int,

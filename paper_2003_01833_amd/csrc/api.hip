@@ -416,11 +416,12 @@ int tagi_convolve_learned(tagi_tree* t, int kernel, const double* kappa, double 
                           double theta_max, double theta_fb, int degree_fb, int precision,
                           double* out, void* stream) {
   g_err[0] = 0;
-  REQUIRE(t && params && norm && out && kappa && tol, "tagi_convolve_learned: null argument");
-  if (kernel != TAGI_YUKAWA_SS && kernel != TAGI_YUKAWA) {
-    set_error("tagi_convolve_learned: the selector covers the Yukawa kernels only");
-    return TAGI_E_UNSUPPORTED;
-  }
+  REQUIRE(t && params && norm && out && tol, "tagi_convolve_learned: null argument");
+  REQUIRE(valid_kernel(kernel), "tagi_convolve_learned: unknown kernel %d", kernel);
+  REQUIRE(kappa || !is_yukawa(kernel), "tagi_convolve_learned: kappa is NULL for a Yukawa kernel");
+  if (kernel == TAGI_COULOMB_SS)
+    REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_convolve_learned: alpha = %g must be > 0",
+            alpha);
   REQUIRE(precision == TAGI_FP64 || precision == TAGI_MIXED, "tagi_convolve_learned: precision");
   REQUIRE(theta_max > 0.0 && theta_max < 1.0, "tagi_convolve_learned: theta_max out of (0, 1)");
   REQUIRE(theta_fb > 0.0 && theta_fb < 1.0, "tagi_convolve_learned: theta_fb out of (0, 1)");
@@ -429,9 +430,13 @@ int tagi_convolve_learned(tagi_tree* t, int kernel, const double* kappa, double 
     set_error("tagi_convolve_learned: tagi_upward has not run on this tree");
     return TAGI_E_STATE;
   }
-  for (int o = 0; o < t->n_orb; ++o)
-    REQUIRE(std::isfinite(kappa[o]) && kappa[o] > 0.0 && std::isfinite(tol[o]) && tol[o] > 0.0,
-            "tagi_convolve_learned: kappa[%d] or tol[%d] not finite and > 0", o, o);
+  for (int o = 0; o < t->n_orb; ++o) {
+    REQUIRE(std::isfinite(tol[o]) && tol[o] > 0.0,
+            "tagi_convolve_learned: tol[%d] = %g must be finite and > 0", o, tol[o]);
+    if (is_yukawa(kernel))
+      REQUIRE(std::isfinite(kappa[o]) && kappa[o] > 0.0,
+              "tagi_convolve_learned: kappa[%d] = %g must be finite and > 0", o, kappa[o]);
+  }
   for (int k = 0; k < selector_param_count(); ++k)
     REQUIRE(std::isfinite(params[k]), "tagi_convolve_learned: params[%d] not finite", k);
   return convolve_learned(t, kernel, kappa, alpha, params, norm, tol, theta_max, theta_fb,
@@ -482,17 +487,23 @@ int tagi_learned_lists_export(const tagi_tree* t, int64_t* far_off, int32_t* far
 
 int tagi_selector_param_count(void) { return selector_param_count(); }
 
-int tagi_selector_samples(tagi_tree* t, const double* f, const double* w, double kappa,
-                          double theta_max, int64_t max_pairs, float* features, float* errors,
-                          int32_t* pair_ids, int64_t* n, void* stream) {
+int tagi_selector_samples(tagi_tree* t, const double* f, const double* w, int kernel,
+                          double kappa, double alpha, double theta_max, int64_t max_pairs,
+                          float* features, float* errors, int32_t* pair_ids, int64_t* n,
+                          void* stream) {
   g_err[0] = 0;
   REQUIRE(t && f && w && features && errors && n, "tagi_selector_samples: null argument");
-  REQUIRE(std::isfinite(kappa) && kappa > 0.0, "tagi_selector_samples: kappa must be > 0");
+  REQUIRE(kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS,
+          "tagi_selector_samples: kernel must be TAGI_YUKAWA_SS or TAGI_COULOMB_SS");
+  if (kernel == TAGI_YUKAWA_SS)
+    REQUIRE(std::isfinite(kappa) && kappa > 0.0, "tagi_selector_samples: kappa must be > 0");
+  else
+    REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_selector_samples: alpha must be > 0");
   REQUIRE(theta_max > 0.0 && theta_max < 1.0, "tagi_selector_samples: theta_max out of (0, 1)");
   REQUIRE(max_pairs >= 1 && max_pairs < (int64_t)INT32_MAX, "tagi_selector_samples: bad max_pairs");
   *n = 0;
-  return selector_samples(t, f, w, kappa, theta_max, max_pairs, features, errors, pair_ids, n,
-                          (hipStream_t)stream);
+  return selector_samples(t, f, w, kernel, kappa, alpha, theta_max, max_pairs, features, errors,
+                          pair_ids, n, (hipStream_t)stream);
 }
 
 int tagi_selector_grad(const float* params, const float* X, const float* Y, const float* M,
@@ -663,6 +674,19 @@ int tagi_mesh_destroy(tagi_mesh* m) {
   return TAGI_OK;
 }
 
+int tagi_tree_set_schedule_items(tagi_tree* t, int items) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_tree_set_schedule_items: tree is NULL");
+  REQUIRE(items == 0 || (items >= 256 && items <= (1 << 22)),
+          "tagi_tree_set_schedule_items: items = %d must be 0 or in [256, 2^22]", items);
+  if (schedule_items(t) != (items > 0 ? items : kDefaultScheduleItems)) {
+    t->n_items = 0;  // the next convolution rebuilds the schedule
+    t->items_orb_block = 0;
+  }
+  t->sched_items = items;
+  return TAGI_OK;
+}
+
 int tagi_tree_set_orbital_block(tagi_tree* t, int ob) {
   g_err[0] = 0;
   REQUIRE(t, "tagi_tree_set_orbital_block: tree is NULL");
@@ -675,12 +699,16 @@ int tagi_tree_set_orbital_block(tagi_tree* t, int ob) {
 int tagi_autotune(const double* x, const double* y, const double* z, const double* w, int64_t n,
                   const double* box, const double* f, int n_orb, int kernel, const double* kappa,
                   double alpha, double theta, int degree, int precision, const int* leaf_sizes,
-                  int n_leaf, const int* obs, int n_ob, int reps, int* best, double* times,
-                  void* stream) {
+                  int n_leaf, const int* obs, int n_ob, const int* items, int n_items, int reps,
+                  int* best, double* times, void* stream) {
   g_err[0] = 0;
   REQUIRE(x && y && z && w && f, "tagi_autotune: null input array");
   REQUIRE(leaf_sizes && n_leaf >= 1, "tagi_autotune: no leaf size candidates");
   REQUIRE(obs && n_ob >= 1, "tagi_autotune: no orbital block candidates");
+  REQUIRE(items && n_items >= 1, "tagi_autotune: no schedule item candidates");
+  for (int i = 0; i < n_items; ++i)
+    REQUIRE(items[i] == 0 || (items[i] >= 256 && items[i] <= (1 << 22)),
+            "tagi_autotune: items[%d] = %d must be 0 or in [256, 2^22]", i, items[i]);
   REQUIRE(best, "tagi_autotune: best is NULL");
   REQUIRE(reps >= 1 && reps <= 1000, "tagi_autotune: reps = %d out of range [1, 1000]", reps);
   REQUIRE(n >= 1 && n < (int64_t)INT32_MAX, "tagi_autotune: n = %lld out of range", (long long)n);
@@ -698,7 +726,7 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int st = TAGI_OK;
   double best_ms = INFINITY;
-  best[0] = best[1] = 0;
+  best[0] = best[1] = best[2] = 0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     set_error("tagi_autotune: hipEventCreate failed");
     st = TAGI_E_HIP;
@@ -706,8 +734,11 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
   for (int li = 0; li < n_leaf && st == TAGI_OK; ++li) {
     tagi_tree* t = nullptr;
     st = tagi_tree_build(x, y, z, n, box, leaf_sizes[li], stream, &t);
-    for (int oi = 0; oi < n_ob && st == TAGI_OK; ++oi) {
+    for (int ci = 0; ci < n_ob * n_items && st == TAGI_OK; ++ci) {
+      const int oi = ci / n_items, ii = ci % n_items;
       t->ob_override = obs[oi];
+      st = tagi_tree_set_schedule_items(t, items[ii]);
+      if (st != TAGI_OK) break;
       auto step = [&]() {
         int r = tagi_upward(t, f, w, n_orb, degree, stream);
         if (r == TAGI_OK)
@@ -728,11 +759,12 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
         break;
       }
       const double per = (double)ms / reps;
-      if (times) times[(size_t)li * n_ob + oi] = per;
+      if (times) times[((size_t)li * n_ob + oi) * n_items + ii] = per;
       if (per < best_ms) {
         best_ms = per;
         best[0] = leaf_sizes[li];
         best[1] = obs[oi];
+        best[2] = items[ii];
       }
     }
     if (t) {

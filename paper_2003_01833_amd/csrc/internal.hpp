@@ -125,6 +125,7 @@ struct LearnedState {
   DBuf l1n;                         // float l1 norms of those charges: [n_orb][n_nodes] of f w,
                                     // [n_nodes] of w, then [n_orb][n_leaves] max |f| per batch
   DBuf params;                      // float network parameters
+  DBuf mb;                          // int64 [n_leaves] far pairs per batch at (theta_max, 4), + scratch
   DBuf cnt;                         // int64 [n_leaves][kDegSlots] counts, offsets; [n_leaves] log sizes
   DBuf log;                         // int32 [n_leaves][log_cap] traversal logs
   int64_t log_cap = 0;
@@ -170,7 +171,7 @@ struct LearnedState {
   }
   void release() {
     l1set.release();
-    for (DBuf* b : {&l1n, &params, &cnt, &log, &far_id, &near_id, &chunks, &items, &group_first,
+    for (DBuf* b : {&l1n, &params, &mb, &cnt, &log, &far_id, &near_id, &chunks, &items, &group_first,
                     &group_base, &batch_chunks, &partial, &item_lists})
       b->release();
     release_streams();
@@ -233,6 +234,7 @@ struct tagi_tree {
   std::vector<int32_t> h_chunk_cost;     // evaluations per target lane of each chunk
   std::vector<uint8_t> h_chunk_far;      // 1 for far chunks
   int ob_override = 0;              // orbital block set by the caller (0 = automatic)
+  int sched_items = 0;              // work items a schedule aims at (0 = kDefaultScheduleItems)
   int items_n_orb = 0;
   tagi::DBuf chunks;                // int4 {kind, e0, e1, cost}
   tagi::DBuf items;                 // int4 {batch, group, oblock, chunk}
@@ -268,6 +270,14 @@ struct tagi_mesh {
 };
 
 namespace tagi {
+
+// Work items a compute schedule aims at: each batch's lists are cut into chunks
+// of at most (total kernel evaluations per target lane) / items, so the launch
+// has about that many waves (more where batches hold several 64-target groups).
+constexpr int kDefaultScheduleItems = 16384;
+inline int64_t schedule_items(const tagi_tree* t) {
+  return t->sched_items > 0 ? t->sched_items : kDefaultScheduleItems;
+}
 
 // the interaction lists cached in the batch tree `bt` serve (theta, degree) with
 // the size test of the source tree's current proxy charges
@@ -313,6 +323,8 @@ int compute_proxies(tagi_tree* t, ProxySet& ps, hipStream_t s);
 int ensure_lists(tagi_tree* src, tagi_tree* bt, double theta, int degree, hipStream_t s,
                  bool* root_far = nullptr);
 int ensure_schedule(const tagi_tree* src, tagi_tree* bt, int orb_block, hipStream_t s);
+int count_far_pairs(tagi_tree* t, double theta, int K, int64_t* far_cnt, int64_t* scratch,
+                    hipStream_t s);
 inline int ensure_lists(tagi_tree* t, double theta, int degree, hipStream_t s) {
   return ensure_lists(t, t, theta, degree, s);
 }
@@ -360,8 +372,8 @@ int selector_param_count();
 int l1_to_nodes(const ProxySet& ps, int set, float* out, hipStream_t s);
 // max |f| over each batch's targets: out[o][leaf]
 int leaf_fmax(tagi_tree* t, float* out, hipStream_t s);
-int selector_samples(tagi_tree* t, const double* f, const double* w, double kappa,
-                     double theta_max, int64_t max_pairs, float* feat, float* err,
+int selector_samples(tagi_tree* t, const double* f, const double* w, int kernel, double kappa,
+                     double alpha, double theta_max, int64_t max_pairs, float* feat, float* err,
                      int32_t* pair_ids, int64_t* n_out, hipStream_t s);
 int selector_grad(const float* params, const float* X, const float* Y, const float* M, int64_t m,
                   float* grads, float* loss, hipStream_t s);

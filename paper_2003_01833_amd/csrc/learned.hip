@@ -2,13 +2,19 @@
 // interaction lists are built by the same per-batch ComputePotential traversal,
 // but for a pair that passes a permissive geometric test (r_B + r_C) < theta_max R
 // the selector network predicts the approximation error at every degree 4..12
-// from (r_C, R - r_B, kappa, N_S, l1 bound of the cluster's subtracted degree-4
+// from (r_C, R - r_B, c, N_S, l1 bound of the cluster's subtracted degree-4
 // proxy charges), one orbital at a time, as a residual over the scale
-// l1 exp(-kappa (R - r_B)) / (R - r_B) of the pair's far field. The pair is approximated at the lowest degree
-// whose predicted error meets the per-pair budget for every orbital (and whose
+// l1 exp(-c (R - r_B)) / (R - r_B) of the pair's far field; c is the kernel's
+// decay rate (kappa for Yukawa, 0 for Coulomb, the kappa -> 0 limit), which enters
+// the network as ln(c + 0.25). The pair is approximated at the lowest degree
+// whose predicted error meets the pair budget for every orbital (and whose
 // (n+1)^3 is below N_S); if no degree does, the cluster is opened (a leaf is
-// summed directly). Where any feature lies outside the range the network was
-// trained on, the pair falls back to the fixed MAC (theta_fb, degree_fb).
+// summed directly). The pair budget of batch B is the caller's per-target budget
+// divided by M_B, M_B = the far pairs of B in the fixed-MAC lists at
+// (theta_max, degree 4): a target's far-field error is at most the sum of its
+// pairs' errors, whatever their signs. Where any feature lies outside
+// the range the network was trained on, the pair falls back to the fixed MAC
+// (theta_fb, degree_fb).
 //
 // Far entries are written grouped by degree within each batch; every degree in
 // use gets its own proxy set (only the clusters used at that degree), and the
@@ -27,6 +33,8 @@ namespace tagi {
 namespace ik {
 extern template void launch_interact_ob<TAGI_YUKAWA_SS>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
 extern template void launch_interact_ob<TAGI_YUKAWA>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_ob<TAGI_COULOMB_SS>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
+extern template void launch_interact_ob<TAGI_COULOMB>(int, tagi_tree*, bool, const InteractArgs&, const OrbArg&, hipStream_t);
 }  // namespace ik
 
 namespace {
@@ -36,6 +44,8 @@ constexpr int kDegMin = kLearnDegMin, kDegMax = kLearnDegMax, kNDeg = kDegMax - 
 constexpr int kSlots = kNDeg + 1;  // per batch: far entries per degree, then near entries
 constexpr int kH = 64, kIn = 5, kOut = 9;
 constexpr int kNParam = (kIn * kH + kH) + 2 * (kH * kH + kH) + (kH * kOut + kOut);
+// added to the decay rate before its logarithm (c = 0 for the Coulomb kernels)
+constexpr float kDecayOffset = 0.25f;
 
 struct LearnArgs {
   int n_leaves, n_nodes, n_orb;
@@ -44,13 +54,16 @@ struct LearnArgs {
   const float* l1n;        // [n_orb][n_nodes] l1 norm of the degree-4 charges of f w
   const float* l1w;        // [n_nodes] l1 norm of the degree-4 charges of w
   const float* fmax;       // [n_orb][n_leaves] max |f| over each batch
+  const int64_t* mb;       // [n_leaves] far pairs of each batch at (theta_max, degree 4)
+  int sub_kind;            // subtracted charges in the l1 feature: 0 none, 1 Yukawa, 2 Gaussian
+  float ia2;               // 1 / alpha^2 of the Gaussian
   const float* params;
   double theta_max, theta_fb;
   int degree_fb;
-  float log_tol[kMaxOrb];  // per orbital: log10 of the pair error budget
+  float log_tol[kMaxOrb];  // per orbital: log10 of the per-target error budget
   float shift[kIn], scale[kIn], lo[kIn], hi[kIn];
-  float logk[kMaxOrb];
-  float kap[kMaxOrb];
+  float logc[kMaxOrb];     // per orbital: ln(decay rate + kDecayOffset)
+  float kap[kMaxOrb];      // per orbital: decay rate (kappa, or 0 for Coulomb)
   int64_t* cnt;        // [n_leaves][kSlots] entries per slot
   int64_t* nlog;       // [n_leaves] entries visited (may exceed cap)
   int32_t* log;        // [n_leaves][cap] (C << 4) | slot in traversal order
@@ -113,6 +126,10 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
   const int b = blockIdx.x;
   const int B = L.leaf_node[b];
   const double rB = L.geom[B * 4 + 3];
+  // this lane's orbital's pair budget: log10(tol_o / M_B)
+  const float pair_log_tol = lane < L.n_orb
+                                 ? L.log_tol[lane] - log10f((float)max(L.mb[b], (int64_t)1))
+                                 : 0.0f;
   int32_t* blog = L.log + (int64_t)b * L.cap;
   int64_t c[kSlots];
   for (int k = 0; k < kSlots; ++k) c[k] = 0;
@@ -143,16 +160,24 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
     } else {
       bool fb = false;
       int d_o = 0;  // this lane's orbital: lowest acceptable degree, -1 if none
+      // weight of the subtracted charges: 1 (Yukawa-SS), the Gaussian at the
+      // least batch-cluster distance (Coulomb-SS), 0 (plain kernels)
+      float gsub = L.sub_kind == 1 ? 1.0f : 0.0f;
+      if (L.sub_kind == 2) {
+        const float dm = (float)fmax(R - rB - rC, 0.0);
+        gsub = expf(-dm * dm * L.ia2);
+      }
       if (lane < L.n_orb) {
         const int o = lane;
         float raw[kIn];
         raw[0] = logf((float)rC);
         raw[1] = logf((float)fmax(R - rB, 1e-12));
-        raw[2] = L.logk[o];
+        raw[2] = L.logc[o];
         raw[3] = logf((float)cnt);
-        // l1 norm bound of the subtracted charges q^ - f_i w^ over the batch's targets
+        // size of the charges q^ - f_i w^ the pair's far field carries, the
+        // subtracted ones weighted by their kernel relative to the first one's
         const float l1 = fmaxf(L.l1n[(int64_t)o * L.n_nodes + C] +
-                                   L.fmax[(int64_t)o * L.n_leaves + b] * L.l1w[C],
+                                   gsub * L.fmax[(int64_t)o * L.n_leaves + b] * L.l1w[C],
                                1e-30f);
         raw[4] = logf(l1);
         float x[kIn];
@@ -164,13 +189,13 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
           float pred[kOut];
           mlp_forward(sP, x, hbuf[0], hbuf[1], lane, pred);
           // the network predicts the error relative to the magnitude scale
-          // l1 exp(-kappa d) / d of the pair, d = R - r_B
+          // l1 exp(-c d) / d of the pair, d = R - r_B
           const float dd = (float)fmax(R - rB, 1e-12);
           const float scl = log10f(l1) - 0.43429448f * L.kap[o] * dd - log10f(dd);
           d_o = -1;
           for (int d = kDegMin; d <= kDegMax; ++d) {
             if ((d + 1) * (d + 1) * (d + 1) >= cnt) break;
-            if (pred[d - kDegMin] + scl <= L.log_tol[o]) {
+            if (pred[d - kDegMin] + scl <= pair_log_tol) {
               d_o = d;
               break;
             }
@@ -253,8 +278,10 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
   const int nn = (int)t->nodes.size();
   // cache key: everything the lists depend on
   std::vector<double> key = {(double)n_orb, theta_max, theta_fb, (double)degree_fb,
-                             (double)kernel};
-  for (int o = 0; o < n_orb; ++o) key.push_back(kappa[o]);
+                             (double)kernel, kernel == TAGI_COULOMB_SS ? alpha : 0.0,
+                             (double)schedule_items(t)};
+  const bool yuk_kernel = kernel == TAGI_YUKAWA_SS || kernel == TAGI_YUKAWA;
+  for (int o = 0; o < n_orb; ++o) key.push_back(yuk_kernel ? kappa[o] : 0.0);
   for (int o = 0; o < n_orb; ++o) key.push_back(tol[o]);
   for (int k = 0; k < 4 * kIn; ++k) key.push_back(norm[k]);
   for (int k = 0; k < kNParam; ++k) key.push_back(params[k]);
@@ -279,6 +306,10 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     TAGI_TRY(leaf_fmax(t, d_fmax, s));
     TAGI_TRY(S.params.ensure(kNParam * sizeof(float)));
     TAGI_HIP(hipMemcpyAsync(S.params.p, params, kNParam * sizeof(float), hipMemcpyHostToDevice, s));
+    // M_B: far pairs per batch of the fixed-MAC lists at (theta_max, degree 4)
+    TAGI_TRY(S.mb.ensure((size_t)nl * 3 * sizeof(int64_t) + sizeof(int32_t)));
+    TAGI_TRY(count_far_pairs(t, theta_max, (kDegMin + 1) * (kDegMin + 1) * (kDegMin + 1),
+                             S.mb.as<int64_t>(), S.mb.as<int64_t>() + nl, s));
     // lists: count, offsets, fill
     LearnArgs L{};
     L.n_leaves = nl;
@@ -293,6 +324,9 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     L.l1n = S.l1n.as<float>();
     L.l1w = d_l1w;
     L.fmax = d_fmax;
+    L.mb = S.mb.as<int64_t>();
+    L.sub_kind = kernel == TAGI_YUKAWA_SS ? 1 : (kernel == TAGI_COULOMB_SS ? 2 : 0);
+    L.ia2 = kernel == TAGI_COULOMB_SS ? (float)(1.0 / (alpha * alpha)) : 0.0f;
     L.params = S.params.as<float>();
     L.theta_max = theta_max;
     L.theta_fb = theta_fb;
@@ -304,9 +338,11 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       L.lo[k] = norm[2 * kIn + k];
       L.hi[k] = norm[3 * kIn + k];
     }
+    const bool yuk = kernel == TAGI_YUKAWA_SS || kernel == TAGI_YUKAWA;
     for (int o = 0; o < n_orb; ++o) {
-      L.logk[o] = (float)std::log(kappa[o]);
-      L.kap[o] = (float)kappa[o];
+      const double c = yuk ? kappa[o] : 0.0;  // decay rate
+      L.logc[o] = (float)std::log(c + (double)kDecayOffset);
+      L.kap[o] = (float)c;
     }
     // one wave per batch; the per-batch logs are scattered into grouped lists
     TAGI_TRY(S.cnt.ensure((size_t)nl * (2 * kSlots + 1) * sizeof(int64_t) + 4));
@@ -398,7 +434,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       }
     }
     // chunks (host): far segments per degree, then the near list, each cut by cost
-    // (kernel evaluations per target lane), at most 1/16384 of the whole
+    // (kernel evaluations per target lane), at most 1/schedule_items of the whole
     S.h_chunks.clear();
     std::vector<int32_t> bfirst(nl), bcount(nl);
     int64_t lane_cost = 0;
@@ -413,7 +449,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
         lane_cost += ns;
       }
     }
-    const int64_t ccap = std::max<int64_t>(lane_cost / 16384, 4096);
+    const int64_t ccap = std::max<int64_t>(lane_cost / schedule_items(t), 4096);
     for (int b = 0; b < nl; ++b) {
       bfirst[b] = (int32_t)(S.h_chunks.size() / 4);
       for (int k = 0; k <= kNDeg; ++k) {
@@ -601,11 +637,14 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     } else {
       A.degree = 0;  // near items only: any compiled variant
     }
+    A.ia2 = kernel == TAGI_COULOMB_SS ? 1.0 / (alpha * alpha) : 0.0;
     ++t->interact_launches;
-    if (kernel == TAGI_YUKAWA_SS)
-      launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, ls);
-    else
-      launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, ls);
+    switch (kernel) {
+      case TAGI_YUKAWA_SS: launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, ls); break;
+      case TAGI_COULOMB_SS: launch_interact_ob<TAGI_COULOMB_SS>(ob, t, mix, A, orb, ls); break;
+      case TAGI_YUKAWA: launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, ls); break;
+      default: launch_interact_ob<TAGI_COULOMB>(ob, t, mix, A, orb, ls); break;
+    }
     TAGI_HIP(hipGetLastError());
   }
   for (int k = 0; k < LearnedState::kStreams; ++k) {
@@ -614,7 +653,8 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
   }
   phase_end(t, kPhaseInteract, s);
   phase_begin(t, kPhaseCombine, s);
-  TAGI_TRY(launch_combine(t, ob, kernel == TAGI_YUKAWA_SS, S.group_base.as<int32_t>(),
+  TAGI_TRY(launch_combine(t, ob, kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS,
+                          S.group_base.as<int32_t>(),
                           S.group_first.as<int32_t>(), S.batch_chunks.as<int2>(),
                           S.partial.as<double>(), orb, out, s));
   phase_end(t, kPhaseCombine, s);

@@ -140,6 +140,31 @@ __global__ void k_chunks(int n_leaves, const int32_t* __restrict__ nbeg,
 
 }  // namespace
 
+// Far-pair counts per batch of the fixed-MAC lists at (theta, size part K < N_S)
+// into far_cnt[n_leaves] (device), by the count pass of the list traversal;
+// `scratch` must hold 2 n_leaves int64 and one int32.
+int count_far_pairs(tagi_tree* t, double theta, int K, int64_t* far_cnt, int64_t* scratch,
+                    hipStream_t s) {
+  const int nl = (int)t->leaves.size();
+  int32_t* d_over = reinterpret_cast<int32_t*>(scratch + 2 * (size_t)nl);
+  TAGI_HIP(hipMemsetAsync(d_over, 0, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_lists, dim3((nl + kListBlock - 1) / kListBlock), dim3(kListBlock), 0, s,
+                     nl, t->leaf_node.as<int32_t>(), t->nd_geom.as<double>(),
+                     t->nd_geom.as<double>(), t->nd_begin.as<int32_t>(), t->nd_end.as<int32_t>(),
+                     t->nd_first_child.as<int32_t>(), t->nd_n_child.as<int32_t>(), theta, K, 0,
+                     far_cnt, scratch, scratch + nl, nullptr, nullptr, nullptr, nullptr, d_over,
+                     nullptr);
+  TAGI_HIP(hipGetLastError());
+  int32_t over = 0;
+  TAGI_HIP(hipMemcpyAsync(&over, d_over, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TAGI_HIP(hipStreamSynchronize(s));
+  if (over) {
+    set_error("interaction-list traversal stack overflow (tree deeper than supported)");
+    return TAGI_E_UNSUPPORTED;
+  }
+  return TAGI_OK;
+}
+
 int ensure_lists(tagi_tree* src, tagi_tree* bt, double theta, int degree, hipStream_t s,
                  bool* root_far) {
   if (root_far) *root_far = false;
@@ -236,7 +261,7 @@ int ensure_schedule(const tagi_tree* src, tagi_tree* t, int orb_block, hipStream
   // cost cap per chunk (kernel evaluations per target lane): small enough to give
   // every SIMD several items, large enough to amortise the per-item overhead
   const int64_t total = (t->n_far * (int64_t)K) + t->near_inter / std::max<int64_t>(1, t->n / nl);
-  int64_t cap = std::max<int64_t>(total / 16384, 16 * (int64_t)K);
+  int64_t cap = std::max<int64_t>(total / schedule_items(src), 16 * (int64_t)K);
   cap = std::max<int64_t>(cap, 4096);
   DBuf nch;
   TAGI_TRY(nch.ensure((size_t)(nl + 1) * 2 * sizeof(int32_t)));

@@ -7,9 +7,11 @@
 // particle-cluster approximation of Eq. particle-cluster-approx-rearranged against
 // the direct sum of Eq. direct-sum_2 (both with the Section 4.3 subtraction, i.e.
 // the pair's contribution a1 - f_i a2). Features: cluster radius r_C, distance
-// from the batch's bounding sphere to the cluster centre R - r_B, kappa, N_S and
-// l1 = |q^_C|_1 + max_B |f| |w^_C|_1 from the degree-4 proxy charges, a bound on
-// the l1 norm of the subtracted charges q^ - f_i w^ the pair's targets see.
+// from the batch's bounding sphere to the cluster centre R - r_B, the decay rate
+// (kappa, or 0 for Coulomb), N_S and l1 = |q^_C|_1 + g max_B |f| |w^_C|_1 from the
+// degree-4 proxy charges: the size of the charges q^ - f_i w^ the pair's far field
+// carries, the subtracted ones weighted by g = 1 (Yukawa-SS) or the Gaussian at
+// the least batch-cluster distance max(R - r_B - r_C, 0) (Coulomb-SS).
 //
 // Network (FP32): 5 inputs, three tanh layers of 64, 9 linear outputs (the
 // log10 errors at degrees 4..12). Training is mini-batch Adam with one kernel per
@@ -42,7 +44,9 @@ __device__ inline int sample_target(int tb, int nb, int k) {
   return tb + (int)(((int64_t)k * nb) / nt);
 }
 
-// exact (direct) contribution of cluster C to the sampled targets of batch B
+// exact (direct) contribution of cluster C to the sampled targets of batch B;
+// KER is TAGI_YUKAWA_SS (decay kappa) or TAGI_COULOMB_SS (Gaussian 1/a^2 = A.ia2)
+template <int KER>
 __global__ __launch_bounds__(256) void k_pair_exact(const int2* __restrict__ pairs, int n_pairs,
                                                     InteractArgs A, double kappa,
                                                     double* __restrict__ out) {
@@ -59,14 +63,15 @@ __global__ __launch_bounds__(256) void k_pair_exact(const int2* __restrict__ pai
     const bool live = k0 + lane < nt;
     const int i = sample_target(tb, nb, live ? k0 + lane : 0);
     double a1[1] = {0.0}, a2[1] = {0.0};
-    near_range<TAGI_YUKAWA_SS, 1>(A.xs[i], A.ys[i], A.zs[i], A.nbeg[C], A.nend[C], A.xs, A.ys,
-                                  A.zs, A.ws, qr, kl2, 0.0, a1, a2);
+    near_range<KER, 1>(A.xs[i], A.ys[i], A.zs[i], A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws,
+                       qr, kl2, -A.ia2 * kLog2e, a1, a2);
     if (live) out[(int64_t)p * kSampleT + k0 + lane] = __builtin_fma(-A.fs[i], a2[0], a1[0]);
   }
 }
 
 // approximated contribution at the degree of the current upward pass, its largest
 // error over the sampled targets; pairs without proxies at this degree write NaN
+template <int KER>
 __global__ __launch_bounds__(256) void k_pair_approx(const int2* __restrict__ pairs, int n_pairs,
                                                      InteractArgs A, double kappa,
                                                      const double* __restrict__ exact,
@@ -89,9 +94,8 @@ __global__ __launch_bounds__(256) void k_pair_approx(const int2* __restrict__ pa
       const bool live = k0 + lane < nt;
       const int i = sample_target(tb, nb, live ? k0 + lane : 0);
       double a1[1] = {0.0}, a2[1] = {0.0};
-      far_cluster<TAGI_YUKAWA_SS, 1, 0>(A.xs[i], A.ys[i], A.zs[i], np1,
-                                        A.pnodes + (int64_t)slot * 3 * np1,
-                                        A.what + (int64_t)slot * K, qk, kl2, 0.0, a1, a2);
+      far_cluster<KER, 1, 0>(A.xs[i], A.ys[i], A.zs[i], np1, A.pnodes + (int64_t)slot * 3 * np1,
+                             A.what + (int64_t)slot * K, qk, kl2, -A.ia2 * kLog2e, a1, a2);
       const double u = __builtin_fma(-A.fs[i], a2[0], a1[0]);
       if (live) e = fmax(e, fabs(u - exact[(int64_t)p * kSampleT + k0 + lane]));
     }
@@ -404,9 +408,11 @@ int selector_train(float* params, const float* X, const float* Y, const float* M
   return st;
 }
 
-int selector_samples(tagi_tree* t, const double* f, const double* w, double kappa,
-                     double theta_max, int64_t max_pairs, float* feat, float* err,
+int selector_samples(tagi_tree* t, const double* f, const double* w, int kernel, double kappa,
+                     double alpha, double theta_max, int64_t max_pairs, float* feat, float* err,
                      int32_t* pair_ids, int64_t* n_out, hipStream_t s) {
+  const bool coul = kernel == TAGI_COULOMB_SS;
+  if (coul) kappa = 0.0;  // the decay rate of 1/r
   // candidate pairs: the far pairs of the lists at (theta_max, degree 4)
   const int d0 = 4;
   TAGI_TRY(upward(t, f, w, 1, d0, s));
@@ -469,9 +475,17 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
     const int Cn = pairs[p].y;
     feat[p * 5 + 0] = (float)rc;
     feat[p * 5 + 1] = (float)(R - rb);
-    feat[p * 5 + 2] = (float)kappa;
+    feat[p * 5 + 2] = (float)kappa;  // decay rate: kappa, or 0 for Coulomb
     feat[p * 5 + 3] = (float)(C.end - C.begin);
-    feat[p * 5 + 4] = l1f[Cn] + fmaxb[leaf_index[pairs[p].x]] * l1w[Cn];
+    // subtracted charges weighted by their kernel relative to the first one's:
+    // 1 for Yukawa-SS, the Gaussian at the least batch-cluster distance for
+    // Coulomb-SS
+    double gsub = 1.0;
+    if (coul) {
+      const double dm = std::max(R - rb - rc, 0.0);
+      gsub = std::exp(-dm * dm / (alpha * alpha));
+    }
+    feat[p * 5 + 4] = (float)(l1f[Cn] + gsub * fmaxb[leaf_index[pairs[p].x]] * l1w[Cn]);
     if (pair_ids) {
       pair_ids[2 * p] = pairs[p].x;
       pair_ids[2 * p + 1] = pairs[p].y;
@@ -485,15 +499,27 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, double kapp
   TAGI_TRY(scratch.alloc(&exact, (size_t)np * kSampleT));
   TAGI_TRY(scratch.alloc(&derr, (size_t)np));
   TAGI_HIP(hipMemcpyAsync(dp, pairs.data(), np * sizeof(int2), hipMemcpyHostToDevice, s));
+  const double ia2 = coul ? 1.0 / (alpha * alpha) : 0.0;
   InteractArgs A = args_of(t);
-  hipLaunchKernelGGL(k_pair_exact, dim3((np + 3) / 4), dim3(256), 0, s, dp, np, A, kappa, exact);
+  A.ia2 = ia2;
+  if (coul)
+    hipLaunchKernelGGL(k_pair_exact<TAGI_COULOMB_SS>, dim3((np + 3) / 4), dim3(256), 0, s, dp, np,
+                       A, kappa, exact);
+  else
+    hipLaunchKernelGGL(k_pair_exact<TAGI_YUKAWA_SS>, dim3((np + 3) / 4), dim3(256), 0, s, dp, np,
+                       A, kappa, exact);
   TAGI_HIP(hipGetLastError());
   std::vector<float> e(np);
   for (int d = 4; d <= 12; ++d) {
     TAGI_TRY(upward(t, f, w, 1, d, s));
     A = args_of(t);
-    hipLaunchKernelGGL(k_pair_approx, dim3((np + 3) / 4), dim3(256), 0, s, dp, np, A, kappa,
-                       exact, derr);
+    A.ia2 = ia2;
+    if (coul)
+      hipLaunchKernelGGL(k_pair_approx<TAGI_COULOMB_SS>, dim3((np + 3) / 4), dim3(256), 0, s, dp,
+                         np, A, kappa, exact, derr);
+    else
+      hipLaunchKernelGGL(k_pair_approx<TAGI_YUKAWA_SS>, dim3((np + 3) / 4), dim3(256), 0, s, dp,
+                         np, A, kappa, exact, derr);
     TAGI_HIP(hipGetLastError());
     TAGI_HIP(hipMemcpyAsync(e.data(), derr, np * sizeof(float), hipMemcpyDeviceToHost, s));
     TAGI_HIP(hipStreamSynchronize(s));

@@ -46,21 +46,49 @@ def test_orbital_block_rejects_other_widths():
     t.close()
 
 
-def test_autotune_picks_a_candidate_that_reproduces_the_result():
+def test_autotune_picks_a_candidate_that_reproduces_the_result(tmp_path):
     import paper_2003_01833_amd as tagi
     dx, dy, dz, dw, dF = _case(5)
     kap = np.linspace(0.8, 2.4, 5)
-    (leaf, ob), times = tagi.autotune(dx, dy, dz, dF, dw, "yukawa_ss", kap, 0.7, 6,
-                                      leaf_sizes=(150, 400), obs=(1, 4), reps=2)
-    assert leaf in (150, 400) and ob in (1, 4)
-    assert times.shape == (2, 2) and np.all(times > 0)
-    assert times[(150, 400).index(leaf), (1, 4).index(ob)] == times.min()
+    (leaf, ob, items), times = tagi.autotune(dx, dy, dz, dF, dw, "yukawa_ss", kap, 0.7, 6,
+                                             leaf_sizes=(150, 400), obs=(1, 4),
+                                             items=(0, 1024), reps=2)
+    assert leaf in (150, 400) and ob in (1, 4) and items in (0, 1024)
+    assert times.shape == (2, 2, 2) and np.all(times > 0)
+    assert times[(150, 400).index(leaf), (1, 4).index(ob), (0, 1024).index(items)] == times.min()
     t = tagi.Tree(dx, dy, dz, leaf)
     t.set_orbital_block(ob)
+    t.set_schedule_items(items)
     t.upward(dF, dw, 6)
     u = t.convolve("yukawa_ss", kap, 0.7, 6)
     t2 = tagi.Tree(dx, dy, dz, leaf)
     t2.upward(dF, dw, 6)
-    assert torch.equal(u, t2.convolve("yukawa_ss", kap, 0.7, 6))
+    u2 = t2.convolve("yukawa_ss", kap, 0.7, 6)
+    # the schedule's granularity only regroups the partial sums
+    assert torch.allclose(u, u2, rtol=0, atol=1e-13 * float(u2.abs().max()))
     t.close()
     t2.close()
+    # the JSON cache: tuned once, read back afterwards
+    cache = str(tmp_path / "tuning.json")
+    best, hit = tagi.autotune_cached(cache, dx, dy, dz, dF, dw, "yukawa_ss", kap, 0.7, 6,
+                                     leaf_sizes=(150, 400), obs=(1, 4))
+    assert not hit and best[0] in (150, 400) and best[1] in (1, 4)
+    again, hit = tagi.autotune_cached(cache, dx, dy, dz, dF, dw, "yukawa_ss", kap, 0.7, 6,
+                                      leaf_sizes=(150, 400), obs=(1, 4))
+    assert hit and again == best
+
+
+def test_schedule_items_change_only_the_grouping_of_partial_sums():
+    import paper_2003_01833_amd as tagi
+    dx, dy, dz, dw, dF = _case(3)
+    kap = np.array([0.7, 1.5, 3.0])
+    t = tagi.Tree(dx, dy, dz, 200)
+    t.upward(dF, dw, 7)
+    ref = t.convolve("coulomb_ss", kap, 0.7, 7).clone()
+    for items in (256, 4096, 1 << 20, 0):
+        t.set_schedule_items(items)
+        u = t.convolve("coulomb_ss", kap, 0.7, 7)
+        assert torch.allclose(u, ref, rtol=0, atol=1e-13 * float(ref.abs().max())), items
+    with pytest.raises(tagi.TagiError):
+        t.set_schedule_items(100)
+    t.close()

@@ -1,7 +1,9 @@
 """Learned degree/MAC lists on the GPU against the oracle traversal with the same
-network (evaluated there in FP64): every decision must agree except ties, where
-the FP32 network on the GPU and the FP64 one may fall on either side of a
-threshold within 2e-4 (log10 units)."""
+network (evaluated there in FP64). The FP32 network on the GPU and the FP64 one
+may put a decision whose compared quantity lies within 2e-4 (log10 units) of its
+threshold on either side; the oracle reports such ties and never takes the
+GPU's decision. Every batch without a tie must have identical lists; batches
+with a tie (at most a handful) must still cover every source exactly once."""
 import os
 
 import numpy as np
@@ -29,49 +31,61 @@ def _slater(r, seed):
     return f
 
 
+def _compare(t, ref_tree, far, near, ties):
+    """GPU lists (exported) against the oracle's, batch by batch; returns the
+    degrees in use."""
+    L = t.learned_lists()
+    nl = len(ref_tree.leaves())
+    assert L["far_off"].size == nl + 1
+    tied = {b for b, _, _ in ties}
+    assert len(tied) <= 5, ties
+    degrees = set()
+    for b, B in enumerate(ref_tree.leaves()):
+        e0, e1 = L["far_off"][b], L["far_off"][b + 1]
+        n0, n1 = L["near_off"][b], L["near_off"][b + 1]
+        gfar = list(zip(L["far_id"][e0:e1].tolist(), L["far_degree"][e0:e1].tolist()))
+        gnear = L["near_id"][n0:n1].tolist()
+        degrees.update(dg for _, dg in gfar)
+        if b in tied:
+            # still a partition of the sources into the listed clusters
+            cover = np.zeros(ref_tree.end[0], np.int32)
+            for C in [c for c, _ in gfar] + gnear:
+                cover[ref_tree.begin[C]:ref_tree.end[C]] += 1
+            assert np.all(cover == 1), b
+            continue
+        # far entries grouped by degree (stable), near entries in traversal order
+        assert gfar == sorted(far[b], key=lambda e: e[1]), b
+        assert gnear == near[b], b
+    return degrees
+
+
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector weights")
-def test_learned_lists_match_oracle_traversal():
+@pytest.mark.parametrize("kernel", ["yukawa_ss", "coulomb_ss"])
+def test_learned_lists_match_oracle_traversal(kernel):
     import paper_2003_01833_amd as tagi
     from paper_2003_01833_amd.selector import Selector
     sel = Selector.load(WEIGHTS)
     d = atom_mesh(tol_m=1e-5, p=5, uniform_levels=2)
     x, y, z, w = d["x"], d["y"], d["z"], d["w"]
     r = np.sqrt(x * x + y * y + z * z)
-    F = np.stack([_slater(r, 51), _slater(r, 52)])
-    kap = np.array([0.8, 2.0])
-    tol = 3e-9 * 4 * np.pi / kap ** 2 * np.abs(F).max(axis=1)
+    if kernel == "yukawa_ss":
+        F = np.stack([_slater(r, 51), _slater(r, 52)])
+        kap = np.array([0.8, 2.0])
+        tol = 1e-8 * 4 * np.pi / kap ** 2 * np.abs(F).max(axis=1)
+    else:
+        F = np.stack([_slater(r, 53) ** 2])
+        kap = np.array([1.0])
+        tol = 1e-8 * 2 * np.pi * np.abs(F).max(axis=1)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
     t = tagi.Tree(dev(x), dev(y), dev(z), 300)
     t.upward(dev(F), dev(w), 1)
-    t.convolve_learned("yukawa_ss", kap, sel, tol, theta_max=0.9, theta_fb=0.7, degree_fb=8)
-    L = t.learned_lists()
+    t.convolve_learned(kernel, kap, sel, tol, theta_max=0.9, theta_fb=0.7, degree_fb=8)
     ref_tree = bltc.build_tree(x, y, z, 300)
-    nl = len(ref_tree.leaves())
-    assert L["far_off"].size == nl + 1
-    gpu = []
-    for b in range(nl):
-        dct = {}
-        for e in range(L["far_off"][b], L["far_off"][b + 1]):
-            dct[int(L["far_id"][e])] = ("far", int(L["far_degree"][e]))
-        for e in range(L["near_off"][b], L["near_off"][b + 1]):
-            dct[int(L["near_id"][e])] = ("near",)
-        gpu.append(dct)
     p = ref_tree.perm
-    far, near, ties, mism = learned_lists(ref_tree, x[p], y[p], z[p], F[:, p], w[p], kap,
-                                          sel.params, sel.norm, np.log10(tol), 0.9, 0.7, 8,
-                                          reference=gpu)
-    assert not mism, mism[:5]
-    assert len(ties) <= 5, ties
-    degrees = set()
-    for b in range(nl):
-        # far entries grouped by degree (stable), near in traversal order
-        of = sorted(far[b], key=lambda e: e[1])
-        e0, e1 = L["far_off"][b], L["far_off"][b + 1]
-        assert [c for c, _ in of] == list(L["far_id"][e0:e1]), b
-        assert [dg for _, dg in of] == list(L["far_degree"][e0:e1]), b
-        n0, n1 = L["near_off"][b], L["near_off"][b + 1]
-        assert near[b] == list(L["near_id"][n0:n1]), b
-        degrees.update(dg for _, dg in of)
+    far, near, ties = learned_lists(ref_tree, x[p], y[p], z[p], F[:, p], w[p], kernel, kap,
+                                    sel.net(kernel).params, sel.net(kernel).norm, np.log10(tol),
+                                    0.9, 0.7, 8)
+    degrees = _compare(t, ref_tree, far, near, ties)
     assert len(degrees) >= 3, degrees  # the selection is not degenerate
     t.close()
 

@@ -85,10 +85,13 @@ def case():
     return d
 
 
-def test_selector_samples_match_oracle(case):
+@pytest.mark.parametrize("kernel", ["yukawa_ss", "coulomb_ss"])
+def test_selector_samples_match_oracle(case, kernel):
     t, ref = case["t"], case["ref"]
-    kappa = 1.7
-    feat, err, ids = t.selector_samples(case["df"], case["dw"], kappa, 0.8, 40, with_ids=True)
+    yuk = kernel == "yukawa_ss"
+    kappa, alpha = (1.7, 1.0) if yuk else (0.0, 0.6)
+    feat, err, ids = t.selector_samples(case["df"], case["dw"], kappa, 0.8, 40, with_ids=True,
+                                        kernel=kernel, alpha=alpha)
     assert feat.shape[0] == 40
     perm = ref.perm
     X, Y, Z = case["x"][perm], case["y"][perm], case["z"][perm]
@@ -100,9 +103,10 @@ def test_selector_samples_match_oracle(case):
         ti = ref.begin[B] + (np.arange(nt) * nb) // nt  # the sampled targets
         c0, c1 = ref.begin[C], ref.end[C]
         tx, ty, tz, tf = X[ti], Y[ti], Z[ti], F[ti]
-        # exact pair contribution (subtracted Yukawa, no analytic term)
-        ex = direct_sum("yukawa_ss", X[c0:c1], Y[c0:c1], Z[c0:c1], F[c0:c1], W[c0:c1], tx, ty, tz,
-                        tf, kappa=kappa) - 4 * np.pi * tf / kappa ** 2
+        # exact pair contribution (subtracted kernel, no analytic term)
+        ex = direct_sum(kernel, X[c0:c1], Y[c0:c1], Z[c0:c1], F[c0:c1], W[c0:c1], tx, ty, tz,
+                        tf, kappa=kappa if yuk else 1.0, alpha=alpha)
+        ex = ex - (4 * np.pi * tf / kappa ** 2 if yuk else 2 * np.pi * alpha ** 2 * tf)
         for d in range(4, 13):
             if (d + 1) ** 3 >= c1 - c0:
                 assert np.isnan(err[p, d - 4])
@@ -113,14 +117,16 @@ def test_selector_samples_match_oracle(case):
             gx, gy, gz = np.meshgrid(*nodes, indexing="ij")
             dd = np.sqrt((tx[:, None] - gx.ravel()) ** 2 + (ty[:, None] - gy.ravel()) ** 2 +
                          (tz[:, None] - gz.ravel()) ** 2)
-            G = np.exp(-kappa * dd) / dd
-            ap = G @ ch[0].ravel() - tf * (G @ ch[1].ravel())
+            G1 = np.exp(-kappa * dd) / dd
+            G2 = G1 if yuk else np.exp(-dd * dd / alpha ** 2) / dd
+            ap = G1 @ ch[0].ravel() - tf * (G2 @ ch[1].ravel())
             e_ref = np.abs(ap - ex).max()
-            scale = np.abs(G @ np.abs(ch[0].ravel())).max() + np.abs(tf).max() * np.abs(G @ ch[1].ravel()).max()
+            scale = np.abs(G1 @ np.abs(ch[0].ravel())).max() + np.abs(tf).max() * np.abs(G2 @ ch[1].ravel()).max()
             assert abs(err[p, d - 4] - e_ref) <= 1e-5 * e_ref + 1e-13 * scale, (p, d)
         # features
         cb, rb = 0.5 * (ref.lo[B] + ref.hi[B]), 0.5 * np.linalg.norm(ref.hi[B] - ref.lo[B])
         cc, rc = 0.5 * (ref.lo[C] + ref.hi[C]), 0.5 * np.linalg.norm(ref.hi[C] - ref.lo[C])
+        # the third feature is the decay rate: kappa, or 0 for Coulomb
         np.testing.assert_allclose(feat[p, :4], [rc, np.linalg.norm(cb - cc) - rb, kappa, c1 - c0],
                                    rtol=1e-6)
         # l1 bound of the subtracted degree-4 charges
@@ -128,7 +134,11 @@ def test_selector_samples_match_oracle(case):
                                     np.vstack([F[c0:c1] * W[c0:c1], W[c0:c1]]),
                                     ref.lo[C], ref.hi[C], 4)
         fmax_b = np.abs(F[ref.begin[B]:ref.end[B]]).max()
-        l1 = np.abs(ch4[0]).sum() + fmax_b * np.abs(ch4[1]).sum()
+        # the subtracted charges weighted by their kernel: 1 for Yukawa-SS, the
+        # Gaussian at the least batch-cluster distance for Coulomb-SS
+        R = np.linalg.norm(cb - cc)
+        g = 1.0 if yuk else np.exp(-max(R - rb - rc, 0.0) ** 2 / alpha ** 2)
+        l1 = np.abs(ch4[0]).sum() + g * fmax_b * np.abs(ch4[1]).sum()
         np.testing.assert_allclose(feat[p, 4], l1, rtol=1e-5)
 
 
@@ -138,13 +148,14 @@ def _selector(bias, lo=-1e30, hi=1e30):
     p = np.zeros(tagi.binding.selector_param_count(), np.float32)
     p[-9:] = bias
     norm = np.concatenate([np.zeros(5), np.ones(5), np.full(5, lo), np.full(5, hi)]).astype(np.float32)
-    return Selector(p, norm)
+    return Selector.single(p, norm)
 
 
+@pytest.mark.parametrize("kernel", ["yukawa_ss", "coulomb_ss"])
 @pytest.mark.parametrize("mode", ["accept_all", "accept_none", "fallback"])
-def test_learned_lists_at_their_extremes_match_oracle(case, mode):
+def test_learned_lists_at_their_extremes_match_oracle(case, mode, kernel):
     t = case["t"]
-    kappa = [0.9, 2.2]
+    kappa = [0.9, 2.2] if kernel == "yukawa_ss" else [1.0, 1.0]
     g = SplitMix64(12)
     F = np.stack([case["f"], g.uniform(case["f"].size, -1, 1)])
     dF = torch.from_numpy(F).cuda()
@@ -156,20 +167,20 @@ def test_learned_lists_at_their_extremes_match_oracle(case, mode):
         sel = _selector(+20.0)
     else:
         sel = _selector(-20.0, lo=1.0, hi=-1.0)
-    u = t.convolve_learned("yukawa_ss", kappa, sel, tol=[1e-6, 1e-6], theta_max=theta_max,
+    u = t.convolve_learned(kernel, kappa, sel, tol=[1e-6, 1e-6], theta_max=theta_max,
                            theta_fb=0.6, degree_fb=5).cpu().numpy()
     st = t.learned_stats()
     for o in range(2):
         if mode == "accept_all":
-            ref = bltc.treecode(case["x"], case["y"], case["z"], F[o], case["w"], "yukawa_ss",
+            ref = bltc.treecode(case["x"], case["y"], case["z"], F[o], case["w"], kernel,
                                 kappa[o], theta_max, 4, 150, tree=case["ref"])[0]
             assert set(st["far_pairs_by_degree"]) == {4}
         elif mode == "accept_none":
-            ref = direct_sum("yukawa_ss", case["x"], case["y"], case["z"], F[o], case["w"],
+            ref = direct_sum(kernel, case["x"], case["y"], case["z"], F[o], case["w"],
                              kappa=kappa[o])
             assert st["far_pairs"] == 0
         else:
-            ref = bltc.treecode(case["x"], case["y"], case["z"], F[o], case["w"], "yukawa_ss",
+            ref = bltc.treecode(case["x"], case["y"], case["z"], F[o], case["w"], kernel,
                                 kappa[o], 0.6, 5, 150, tree=case["ref"])[0]
             assert set(st["far_pairs_by_degree"]) == {5}
         assert np.abs(u[o] - ref).max() <= 1e-11 * np.abs(ref).max(), (mode, o)
