@@ -220,6 +220,28 @@ int tagi_direct(const double* sx, const double* sy, const double* sz, const doub
                 const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
                 double alpha, double* out, void* stream);
 
+/*
+ * tagi_direct for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, kernels and summation order as tagi_direct, so the same results;
+ * it calls no allocating routine. Its scratch (the charges f w and the partial
+ * sums) lives in a device array of 33,554,432 bytes that the library holds on
+ * every GPU it runs on until the process ends. A call needs
+ *     ceil(8 ns / 256) * 256 + 1024 * ceil(nt / 64) * n_sc
+ * bytes of it, n_sc = the source chunks per 64-target group that tagi_direct
+ * also uses (max(1, min(16384 / ceil(nt / 64), ns / 512)), then adjusted to
+ * cover ns); calls needing more fail with TAGI_E_ARG before any work is
+ * enqueued (e.g. ns = 1,000,000 and nt = 100,000 need 24,005,120 bytes).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on one GPU
+ * (other streams, other host threads) race and give wrong results; calls in
+ * stream order on one stream are safe. Errors: as tagi_direct; TAGI_E_ARG also
+ * for sizes beyond the scratch.
+ */
+int tagi_direct_noalloc(const double* sx, const double* sy, const double* sz, const double* sf,
+                        const double* sw, int64_t ns, const double* tx, const double* ty,
+                        const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
+                        double alpha, double* out, void* stream);
+
 /* Sizes and interaction counts of the tree and its cached lists (host struct). */
 int tagi_tree_stats(const tagi_tree* tree, tagi_stats* out);
 

@@ -253,6 +253,30 @@ int tagi_direct(const double* sx, const double* sy, const double* sz, const doub
                 (hipStream_t)stream);
 }
 
+int tagi_direct_noalloc(const double* sx, const double* sy, const double* sz, const double* sf,
+                        const double* sw, int64_t ns, const double* tx, const double* ty,
+                        const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
+                        double alpha, double* out, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(valid_kernel(kernel), "tagi_direct_noalloc: unknown kernel %d", kernel);
+  REQUIRE(sx && sy && sz && sf && sw, "tagi_direct_noalloc: null source array");
+  REQUIRE(tx && ty && tz && out, "tagi_direct_noalloc: null target or output array");
+  REQUIRE(ns >= 1 && ns < (int64_t)INT32_MAX, "tagi_direct_noalloc: ns = %lld out of range",
+          (long long)ns);
+  REQUIRE(nt >= 1 && nt < (int64_t)INT32_MAX, "tagi_direct_noalloc: nt = %lld out of range",
+          (long long)nt);
+  const bool ss = kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS;
+  REQUIRE(!ss || tf, "tagi_direct_noalloc: target values tf are required for subtracted kernels");
+  if (is_yukawa(kernel))
+    REQUIRE(std::isfinite(kappa) && kappa > 0.0, "tagi_direct_noalloc: kappa = %g must be > 0",
+            kappa);
+  if (kernel == TAGI_COULOMB_SS)
+    REQUIRE(std::isfinite(alpha) && alpha > 0.0, "tagi_direct_noalloc: alpha = %g must be > 0",
+            alpha);
+  return direct_noalloc(sx, sy, sz, sf, sw, ns, tx, ty, tz, tf, nt, kernel, kappa, alpha, out,
+                        (hipStream_t)stream);
+}
+
 int tagi_tree_stats(const tagi_tree* t, tagi_stats* o) {
   g_err[0] = 0;
   REQUIRE(t && o, "tagi_tree_stats: null argument");

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "interact_impl.hpp"
 
@@ -291,22 +292,27 @@ int orbital_block(int kernel, int n_orb, int precision) {
   return ob;
 }
 
-int direct(const double* sx, const double* sy, const double* sz, const double* sf,
-           const double* sw, int64_t ns, const double* tx, const double* ty, const double* tz,
-           const double* tf, int64_t nt, int kernel, double kappa, double alpha, double* out,
-           hipStream_t s) {
+namespace {
+
+// source chunks per 64-target group of the direct sum: enough waves to fill the
+// machine, chunks of at least 512 sources
+void direct_chunks(int64_t ns, int64_t nt, int64_t* n_sc_out, int64_t* sc_len_out) {
   const int64_t n_groups = (nt + kWave - 1) / kWave;
-  // enough waves to fill the machine, chunks of at least 512 sources
   int64_t n_sc = std::max<int64_t>(1, 16384 / n_groups);
   n_sc = std::min<int64_t>(n_sc, std::max<int64_t>(1, ns / 512));
   const int64_t sc_len = (ns + n_sc - 1) / n_sc;
-  n_sc = (ns + sc_len - 1) / sc_len;
-  // stream-ordered scratch: allocated and freed on `s`, so no host synchronisation
-  StreamScratch scratch(s);
-  double* part = nullptr;
-  double* q = nullptr;
-  TAGI_TRY(scratch.alloc(&part, (size_t)n_groups * n_sc * 2 * kWave));
-  TAGI_TRY(scratch.alloc(&q, (size_t)ns));
+  *n_sc_out = (ns + sc_len - 1) / sc_len;
+  *sc_len_out = sc_len;
+}
+
+// the direct-sum kernels with the charges q [ns] and partial sums
+// part [n_groups * n_sc][2][64] in caller-provided device memory
+int direct_launch(const double* sx, const double* sy, const double* sz, const double* sf,
+                  const double* sw, int64_t ns, const double* tx, const double* ty,
+                  const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
+                  double alpha, double* out, int64_t n_sc, int64_t sc_len, double* q,
+                  double* part, hipStream_t s) {
+  const int64_t n_groups = (nt + kWave - 1) / kWave;
   hipLaunchKernelGGL(k_charge, dim3((ns + 255) / 256), dim3(256), 0, s, sf, sw, ns, q);
   const double ia2 = kernel == TAGI_COULOMB_SS ? 1.0 / (alpha * alpha) : 0.0;
   const int64_t waves = n_groups * n_sc;
@@ -329,6 +335,86 @@ int direct(const double* sx, const double* sy, const double* sz, const double* s
                      self, tf, part, out);
   TAGI_HIP(hipGetLastError());
   return TAGI_OK;
+}
+
+// Device scratch of the allocation-free direct sum (tagi_direct_noalloc): the
+// charges q and the partial sums. Every GPU the library runs on holds its own
+// copy until the process ends. In host code `scratch` names a host-side stand-in,
+// not device memory: kernels get the per-device address from
+// hipGetSymbolAddress, taken once per device.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of `scratch`
+int scratch_address(void** out) {
+  int dev = 0;
+  TAGI_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("tagi_direct_noalloc: device %d beyond the %d this library tracks", dev, kMaxDevices);
+    return TAGI_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    TAGI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TAGI_OK;
+}
+
+}  // namespace
+
+int direct(const double* sx, const double* sy, const double* sz, const double* sf,
+           const double* sw, int64_t ns, const double* tx, const double* ty, const double* tz,
+           const double* tf, int64_t nt, int kernel, double kappa, double alpha, double* out,
+           hipStream_t s) {
+  const int64_t n_groups = (nt + kWave - 1) / kWave;
+  int64_t n_sc, sc_len;
+  direct_chunks(ns, nt, &n_sc, &sc_len);
+  // stream-ordered scratch: allocated and freed on `s`, so no host synchronisation
+  StreamScratch scr(s);
+  double* part = nullptr;
+  double* q = nullptr;
+  TAGI_TRY(scr.alloc(&part, (size_t)n_groups * n_sc * 2 * kWave));
+  TAGI_TRY(scr.alloc(&q, (size_t)ns));
+  return direct_launch(sx, sy, sz, sf, sw, ns, tx, ty, tz, tf, nt, kernel, kappa, alpha, out,
+                       n_sc, sc_len, q, part, s);
+}
+
+size_t direct_noalloc_bytes(int64_t ns, int64_t nt) {
+  const int64_t n_groups = (nt + kWave - 1) / kWave;
+  int64_t n_sc, sc_len;
+  direct_chunks(ns, nt, &n_sc, &sc_len);
+  const size_t q_bytes = ((size_t)ns * sizeof(double) + 255) / 256 * 256;
+  return q_bytes + (size_t)n_groups * n_sc * 2 * kWave * sizeof(double);
+}
+
+size_t direct_noalloc_limit() { return kScratchBytes; }
+
+int direct_noalloc(const double* sx, const double* sy, const double* sz, const double* sf,
+                   const double* sw, int64_t ns, const double* tx, const double* ty,
+                   const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
+                   double alpha, double* out, hipStream_t s) {
+  if (direct_noalloc_bytes(ns, nt) > kScratchBytes) {
+    set_error("tagi_direct_noalloc: ns = %lld and nt = %lld need %zu bytes of scratch, more than "
+              "its %zu",
+              (long long)ns, (long long)nt, direct_noalloc_bytes(ns, nt), kScratchBytes);
+    return TAGI_E_ARG;
+  }
+  void* base = nullptr;
+  TAGI_TRY(scratch_address(&base));
+  int64_t n_sc, sc_len;
+  direct_chunks(ns, nt, &n_sc, &sc_len);
+  double* q = static_cast<double*>(base);
+  double* part = reinterpret_cast<double*>(static_cast<unsigned char*>(base) +
+                                           ((size_t)ns * sizeof(double) + 255) / 256 * 256);
+  return direct_launch(sx, sy, sz, sf, sw, ns, tx, ty, tz, tf, nt, kernel, kappa, alpha, out,
+                       n_sc, sc_len, q, part, s);
 }
 
 }  // namespace tagi

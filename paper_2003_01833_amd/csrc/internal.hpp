@@ -384,5 +384,13 @@ int direct(const double* sx, const double* sy, const double* sz, const double* s
            const double* sw, int64_t ns, const double* tx, const double* ty, const double* tz,
            const double* tf, int64_t nt, int kernel, double kappa, double alpha, double* out,
            hipStream_t s);
+// the allocation-free direct sum: its scratch lives in a library-owned device
+// array of direct_noalloc_limit() bytes; a call needs direct_noalloc_bytes(ns, nt)
+int direct_noalloc(const double* sx, const double* sy, const double* sz, const double* sf,
+                   const double* sw, int64_t ns, const double* tx, const double* ty,
+                   const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
+                   double alpha, double* out, hipStream_t s);
+size_t direct_noalloc_bytes(int64_t ns, int64_t nt);
+size_t direct_noalloc_limit();
 
 }  // namespace tagi
