@@ -1,29 +1,48 @@
 #!/usr/bin/env python3
-"""Benchmark of the treecode Green-function convolution on one MI355X.
+"""Benchmark of the treecode Green-function convolutions on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload atom|cube]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload benzene|atom|cube]
+                    [--variants v1,v2,...] [--reps R] [--no-extras] [--no-cpu-baseline]
+    python bench.py --sweep [--workload benzene|atom] [--write-settings]
 
-A step is one pass of the whole path on the workload: tree build and batches,
-upward pass, interaction lists and schedule, far and near fields, combine, for
-every convolution the workload holds. The default workload is the single-atom
-adaptive mesh (Be-like Z = 4 in [-20, 20]^3, 1,007,616 Fejer points): a Yukawa
-convolution (kappa = sqrt(0.4)) of psi_1s + psi_2s and a Coulomb (Hartree)
-convolution of rho = 2 psi_1s^2 + 2 psi_2s^2, both singularity-subtracted, on one
-tree with N_L = 2000, each at the cheapest (theta, degree) found that holds it to
-1e-6 (Yukawa 0.75, 8; Coulomb 0.8, 8); the accuracy of theta = 0.8, degree 8,
-N_L = 500 is reported beside it.
+Default workload: the benzene mesh (C6H6 at the paper's coordinates in
+[-20, 20]^3, 4,143,104 Fejer points) with 21 orbitals, each convolved with its
+own Yukawa kernel (kappa_o = sqrt(-2 eps_o)) and singularity subtraction. A step
+is the whole path from scratch for all 21 orbitals: tree build and batches,
+upward pass, interaction lists and schedule, far and near fields, combine.
 Inputs are resident in HBM before timing.
 
-Printed: one JSON line with the throughput (batch-cluster kernel evaluations
-per second, far + near, over the whole step), the accuracy against the GPU
-direct sum on sampled targets, the roofline position of the dominant kernel
-(the interaction kernel, timed with HIP events on its own stream; its HBM
-traffic comes from the FETCH_SIZE / WRITE_SIZE counter profile committed under
-profiles/, reported only while the kernel sources match the profiled ones) and
-the CPU oracle's rate on a bounded sample. Unless --no-compare is given, it also
-holds two comparisons: Lagrange against Hermite interpolation on the atom at
-the accuracy targets 1e-6 and 1e-9, and the plain, batched, mixed-precision and
-learned-selector variants on the 21 benzene orbitals (with the GPU mesh build).
+Variants of the step, on the same GPU and held to the same bar (per orbital,
+relative L2 and relative max error <= 1e-6 at 10,000 seeded targets against the
+direct sum):
+  plain                  the per-orbital loop of Algorithm 2, FP64
+  batched_fp64           all orbitals in one launch sequence, FP64
+  batched_mixed          batched, far field in FP32 tiles
+  batched_fp64_learned   batched, degrees and acceptance by the learned selector
+  batched_mixed_learned  batched, learned selector and FP32 far-field tiles
+Each variant's time is the median of --reps steps after one warm-up step. The
+headline (`value`, `ms_per_step`) is the fastest variant that meets the bar,
+timed again over exactly --steps steps after --warmup steps. `value` counts its
+batch-cluster kernel evaluations (far + near, all orbitals) per second.
+
+`roofline` is the batched FP64 interaction kernel (one launch per step, blocks
+of 8 orbitals) against the FP64 vector peak, with algorithmic flops counted per
+evaluation (geometry once per orbital block, kernel value and accumulation per
+orbital); `roofline_mixed` the mixed-precision launch against the same 78.6
+TFLOP/s (non-packed FP32 issues at the FP64 vector rate; packed FP32 is not
+used); `roofline_headline` the headline variant's launches. HBM traffic comes
+from the FETCH_SIZE / WRITE_SIZE profile committed under profiles/ while the
+kernel sources match the profiled ones.
+
+Extras (unless --no-extras): the Be-like atom step (C2: Yukawa and Hartree
+convolutions on one tree), Lagrange against Hermite interpolation on the atom,
+the HIP-graph replay of the batched step, the autotuner's pick, the GPU mesh
+build, and the 10M-point uniform Coulomb case of Section 6.6.
+
+--sweep: the (theta, degree) table behind the settings of every variant: errors
+and time of one convolution per setting; --write-settings stores the cheapest
+setting meeting 1e-6 (both metrics, every orbital) per (workload, kernel,
+precision) in workloads/settings.json, which the benchmark reads.
 """
 from __future__ import annotations
 
@@ -31,6 +50,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import re
 import sys
 import time
@@ -42,40 +62,351 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Green-convolution time & interactions/s at 1e-6 rel err; batched/mixed vs plain"
-FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak
+VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak; non-packed FP32 issues at the same rate
+HBM_PEAK_GBS = 8000.0
+SETTINGS = os.path.join(ROOT, "workloads", "settings.json")
+BAR = 1e-6
 
-# Algorithmic FP64 flops per kernel evaluation (FMA = 2): squared distance (8
-# for particle sources; 3 for proxy sources, whose tensor grid gives d^2 with one
-# subtraction and one multiply-add per pair), reciprocal square root (seed plus
-# one Newton step, 7; 9 when the same step also gives d), exp as a power of two
-# whose reduced argument comes from the scaled decay constant in one multiply-add,
-# and a degree-9 polynomial (24), the products forming the kernel value, and two
-# multiply-adds (4). The far field of the Gaussian-subtracted
-# Coulomb kernel takes the Gaussian as the product of per-dimension factors: two
-# multiplies per evaluation, and 3 (n+1) exponentials per target and cluster
-# that are not counted.
-FLOPS = {
-    ("yukawa_ss", "far"): 3 + 9 + 24 + 1 + 4,
-    ("yukawa_ss", "near"): 8 + 9 + 24 + 1 + 4,
-    ("coulomb_ss", "far"): 3 + 7 + 2 + 4,
-    ("coulomb_ss", "near"): 8 + 7 + 24 + 1 + 2 + 2,
+# Algorithmic flops per kernel evaluation (FMA = 2), split into the part that is
+# formed once per (target, source) and shared by an orbital block (squared
+# distance, reciprocal square root, the Gaussian of the Coulomb-SS kernel) and the
+# part per orbital (exponential, kernel value, accumulation).
+#  - squared distance: 8 for particle sources (3 sub, 3 mul, 2 add), 3 for proxy
+#    sources (the tensor grid gives d^2 with one subtraction and one multiply-add);
+#  - reciprocal square root: seed plus one Newton step, 7; 9 when the same step
+#    also gives d;
+#  - exp: a power of two of the distance times the decay constant pre-scaled by
+#    log2 e (nearest integer 1 fma + 1 sub, reduced argument 1 fma, degree-9
+#    polynomial 9 fma, scaling 1) = 24, plus the product forming the kernel, 1;
+#  - accumulation: two multiply-adds for the subtracted kernels (4).
+# The Coulomb-SS far field takes its Gaussian as the product of per-dimension
+# factors (2 multiplies per evaluation; the 3 (n+1) factors per target and
+# cluster are not counted).
+FLOPS = {  # (kernel, part, precision): (shared, per orbital)
+    ("yukawa_ss", "far", "fp64"): (3 + 9, 24 + 1 + 4),
+    ("yukawa_ss", "near", "fp64"): (8 + 9, 24 + 1 + 4),
+    ("coulomb_ss", "far", "fp64"): (3 + 7 + 2 + 2, 2),
+    ("coulomb_ss", "near", "fp64"): (8 + 7 + 24 + 1 + 2, 2),
+    # FP32 far-field tiles: squared distance 3, hardware reciprocal square root 1,
+    # d = d^2 / d 1 (shared); per orbital: exponent 1, hardware exp2 1, kernel
+    # value 1, the FP64 subtracted charge q^ - f_i w^ (2, FP64) and one FP32
+    # multiply-add (2); Coulomb-SS: Gaussian products 2 and one multiply-add 2
+    # shared, one multiply-add per orbital
+    ("yukawa_ss", "far", "mixed"): (3 + 1 + 1, 1 + 1 + 1 + 2 + 2),
+    ("coulomb_ss", "far", "mixed"): (3 + 1 + 2 + 2, 2),
 }
+FLOPS[("yukawa_ss", "near", "mixed")] = FLOPS[("yukawa_ss", "near", "fp64")]
+FLOPS[("coulomb_ss", "near", "mixed")] = FLOPS[("coulomb_ss", "near", "fp64")]
 
-
-# Coulomb-SS pairs between boxes at least 6.12 alpha apart skip the Gaussian
-# term (its value is below 2^-54): a near evaluation is then squared distance (8),
-# reciprocal square root (7) and one multiply-add (2); a far one (blocks of up to
-# 4 orbitals, FP64) squared distance (3), reciprocal square root (7) and one
-# multiply-add (2)
+# Coulomb-SS pairs between boxes at least 6.12 alpha apart skip the Gaussian term
+# (below 2^-54): a near evaluation is then 8 + 7 + 2 flops, a far one (blocks of
+# up to 4 orbitals, FP64) 3 + 7 + 2
 COULOMB_NEAR_1R_FLOPS = 8 + 7 + 2
 COULOMB_FAR_1R_FLOPS = 3 + 7 + 2
 GAUSS_SKIP = 37.5  # (box gap / alpha)^2 above which the kernel skips the Gaussian
 
+# counter profiles and the sources they were taken from
+PROFILES = {"benzene": os.path.join(ROOT, "profiles", "k_interact_benzene_21.md"),
+            "atom": os.path.join(ROOT, "profiles", "k_interact_atom_mesh_Z4.md")}
+KERNEL_SOURCES = ["interact_impl.hpp", "devmath.hpp", "interact_yukawa_ss.hip",
+                  "interact_coulomb_ss.hip", "interact.hip", "lists.hip", "upward.hip",
+                  "learned.hip"]
+
+# settings used when workloads/settings.json has no entry (the values that file
+# holds from the last sweep are the ones the benchmark runs)
+DEFAULT_SETTINGS = {
+    "benzene": {"leaf_size": 2000,
+                "yukawa_ss": {"fp64": [0.7, 8], "mixed": [0.8, 10]}},
+    "atom": {"leaf_size": 2000,
+             "yukawa_ss": {"fp64": [0.75, 8]}, "coulomb_ss": {"fp64": [0.8, 8]}},
+}
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def load_settings():
+    s = json.loads(json.dumps(DEFAULT_SETTINGS))
+    if os.path.exists(SETTINGS):
+        with open(SETTINGS) as fh:
+            stored = json.load(fh)
+        for wl, v in stored.items():
+            if wl in s:
+                for k, vv in v.items():
+                    if isinstance(vv, dict):
+                        s[wl].setdefault(k, {}).update({p: list(x["setting"]) if isinstance(x, dict)
+                                                        else list(x) for p, x in vv.items()})
+                    elif k == "leaf_size":
+                        s[wl][k] = vv
+    return s
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2003_01833_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profile_values(workload: str, want_key: str):
+    """key -> value pairs of the committed counter profile of a workload, or {}
+    when it is missing, was taken on another setting, or the kernel sources
+    changed since."""
+    try:
+        with open(PROFILES[workload]) as fh:
+            kv = dict(re.findall(r"^- `(\w+)`: `([^`]*)`", fh.read(), re.M))
+    except (OSError, KeyError):
+        return {}
+    if kv.get("workload") != want_key or kv.get("source_sha256") != kernel_source_digest():
+        return {}
+    return kv
+
+
+def eval_flops(kernel, precision, far_inter, near_inter, n_orb, ob):
+    """Algorithmic flops of far_inter far and near_inter near evaluations per
+    orbital, for n_orb orbitals in blocks of ob."""
+    n_blocks = -(-n_orb // ob)
+    tot = 0.0
+    for part, cnt in (("far", far_inter), ("near", near_inter)):
+        shared, per = FLOPS[(kernel, part, precision)]
+        tot += cnt * (n_blocks * shared + n_orb * per)
+    return tot
+
+
+def cgroup_cores():
+    """CPU cores the process's cgroup quota allows (cpu.max), or None."""
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            quota, period = fh.read().split()[:2]
+        if quota != "max":
+            return max(1, int(int(quota) / int(period)))
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def host_cores():
+    """The cores this process may use: its CPU affinity, capped by the cgroup
+    quota when one is set."""
+    n = len(os.sched_getaffinity(0))
+    q = cgroup_cores()
+    return min(n, q) if q else n
+
+
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            m = re.search(r"^model name\s*:\s*(.+)$", fh.read(), re.M)
+            if m:
+                model = m.group(1).strip()
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0)),
+            "cgroup_quota_cores": cgroup_cores(), "cores_used": host_cores(), "cpu_model": model}
+
+
+# ---------------------------------------------------------------------------
+# workloads
+
+def benzene_case(tagi, torch, samples=10000):
+    from workloads.configs import DOMAIN, benzene_mesh, benzene_orbitals, sample_targets
+    _log("bench: building the benzene mesh and 21 orbitals")
+    t0 = time.perf_counter()
+    m = benzene_mesh()
+    cpu_mesh_ms = 1e3 * (time.perf_counter() - t0)
+    orb = benzene_orbitals(m["x"], m["y"], m["z"])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    n = m["x"].size
+    c = dict(name="benzene_mesh_21_orbitals", n=n, x=dev(m["x"]), y=dev(m["y"]), z=dev(m["z"]),
+             w=dev(m["w"]), F=dev(orb["psi"]), kappa=np.asarray(orb["kappa"]),
+             box=(*DOMAIN[0], *DOMAIN[1]), host=dict(m, psi=orb["psi"]),
+             cpu_mesh_ms=cpu_mesh_ms, kernel="yukawa_ss")
+    c["n_orb"] = c["F"].shape[0]
+    idx_h = sample_targets(n, samples, seed=4)
+    c["idx_h"] = idx_h
+    c["idx"] = torch.from_numpy(idx_h).cuda()
+    sub = lambda a: a[c["idx"]].contiguous()  # noqa: E731
+    _log(f"bench: direct sums at {samples} targets for {c['n_orb']} orbitals")
+    c["refs"] = [tagi.direct("yukawa_ss", c["x"], c["y"], c["z"], c["F"][o].contiguous(), c["w"],
+                             sub(c["x"]), sub(c["y"]), sub(c["z"]), sub(c["F"][o]),
+                             kappa=float(c["kappa"][o])) for o in range(c["n_orb"])]
+    torch.cuda.synchronize()
+    return c
+
+
+def errors(torch, case, U):
+    e = []
+    for o, ref in enumerate(case["refs"]):
+        u = U[o, case["idx"]]
+        e.append((float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
+                  float((u - ref).abs().max() / ref.abs().max())))
+    return {"rel_l2_max_over_orbitals": max(a for a, _ in e),
+            "rel_max_max_over_orbitals": max(b for _, b in e),
+            "rel_l2_per_orbital": [a for a, _ in e],
+            "rel_max_per_orbital": [b for _, b in e]}
+
+
+def meets_bar(err):
+    return err["rel_l2_max_over_orbitals"] <= BAR and err["rel_max_max_over_orbitals"] <= BAR
+
+
+# ---------------------------------------------------------------------------
+# variants of the benzene step: each runs the whole path from scratch and
+# returns (U, record) with the tree's phase times and evaluation counts
+
+class Benzene:
+    def __init__(self, tagi, torch, case, settings, selector=None, tol=None):
+        self.tagi, self.torch, self.c = tagi, torch, case
+        s = settings["benzene"]
+        self.leaf = s["leaf_size"]
+        self.fp64 = tuple(s["yukawa_ss"]["fp64"])
+        self.mixed = tuple(s["yukawa_ss"]["mixed"])
+        self.sel, self.tol = selector, tol
+        n, n_orb = case["n"], case["n_orb"]
+        self.U = torch.empty((n_orb, n), dtype=torch.float64, device="cuda")
+
+    def _tree(self):
+        t = self.tagi.Tree(self.c["x"], self.c["y"], self.c["z"], self.leaf, self.c["box"])
+        t.set_timing(True)
+        return t
+
+    def _finish(self, t, precision, inter, ob):
+        tm = t.timing()
+        t.close()
+        far, near = inter
+        n_orb = self.c["n_orb"]
+        return {"timing": tm, "far_inter": far, "near_inter": near,
+                "interactions": (far + near) * n_orb, "precision": precision, "ob": ob,
+                "flops": eval_flops("yukawa_ss", precision, far, near, n_orb, ob)}
+
+    def plain(self):
+        th, deg = self.fp64
+        t = self._tree()
+        c = self.c
+        for o in range(c["n_orb"]):
+            t.upward(c["F"][o].contiguous(), c["w"], deg)
+            t.convolve("yukawa_ss", float(c["kappa"][o]), th, deg, out=self.U[o:o + 1])
+        st = t.stats()
+        return self.U, self._finish(t, "fp64", (st["far_interactions"], st["near_interactions"]), 1)
+
+    def batched(self, precision):
+        th, deg = self.fp64 if precision == "fp64" else self.mixed
+        t = self._tree()
+        c = self.c
+        t.upward(c["F"], c["w"], deg)
+        t.convolve("yukawa_ss", c["kappa"], th, deg, precision=precision, out=self.U)
+        st = t.stats()
+        ob = 8 if precision == "fp64" else 4
+        return self.U, self._finish(t, precision, (st["far_interactions"], st["near_interactions"]),
+                                    ob)
+
+    def learned(self, precision):
+        t = self._tree()
+        c = self.c
+        # the learned path forms its own per-degree proxy charges; the upward pass
+        # only stages f and w (lowest degree)
+        t.upward(c["F"], c["w"], 1)
+        t.convolve_learned("yukawa_ss", c["kappa"], self.sel, self.tol, precision=precision,
+                           out=self.U)
+        ls = t.learned_stats()
+        ob = 8 if precision == "fp64" else 4
+        rec = self._finish(t, precision, (ls["far_interactions"], ls["near_interactions"]), ob)
+        rec["far_pairs_by_degree"] = ls["far_pairs_by_degree"]
+        return self.U, rec
+
+    def variants(self):
+        v = {"plain": self.plain,
+             "batched_fp64": lambda: self.batched("fp64"),
+             "batched_mixed": lambda: self.batched("mixed")}
+        if self.sel is not None:
+            v["batched_fp64_learned"] = lambda: self.learned("fp64")
+            v["batched_mixed_learned"] = lambda: self.learned("mixed")
+        return v
+
+
+def time_steps(torch, fn, n):
+    """n steps of fn, each bracketed by synchronisations; (last output, last
+    record, per-step ms)."""
+    ms = []
+    out = rec = None
+    for _ in range(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, rec = fn()
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    return out, rec, ms
+
+
+def roofline_of(rec, launches_key="interact_launches"):
+    tm = rec["timing"]
+    launches = max(int(tm[launches_key]), 1)
+    s = tm["interact_ms"] / 1e3
+    achieved = rec["flops"] / s / 1e12
+    return {"bound": "alu", "kernel": "k_interact", "achieved": achieved,
+            "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / VECTOR_PEAK_TFLOPS,
+            "traffic": None, "traffic_unit": "bytes per launch", "launches_per_step": launches,
+            "avg_launch_ms": tm["interact_ms"] / launches, "precision": rec["precision"],
+            "orbital_block": rec["ob"]}
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle on a bounded sample
+
+def cpu_baseline_benzene(case, seconds: float):
+    """The oracle's direct sum (all host cores) at the first k of the benchmark's
+    sampled targets for every orbital, k sized to about `seconds`; also checks the
+    GPU direct sums the errors are measured against at those targets."""
+    from oracle.direct import direct_sum
+    h = case["host"]
+    x, y, z, w, psi = h["x"], h["y"], h["z"], h["w"], h["psi"]
+    kap = case["kappa"]
+    n, n_orb = x.size, psi.shape[0]
+    threads = host_cores()
+    idx = case["idx_h"]
+
+    def positions(k):
+        # k of the sampled targets, spread evenly over the sample
+        return np.unique(np.linspace(0, idx.size - 1, k).round().astype(np.int64))
+
+    def run(k, thr):
+        pos = positions(k)
+        i = idx[pos]
+        t0 = time.perf_counter()
+        outs = [direct_sum("yukawa_ss", x, y, z, psi[o], w, x[i], y[i], z[i], psi[o][i],
+                           kappa=float(kap[o]), threads=thr) for o in range(n_orb)]
+        return time.perf_counter() - t0, outs, pos
+
+    dt, _, _ = run(threads, threads)
+    k = int(min(idx.size, max(threads, threads * seconds / max(dt, 1e-6))))
+    dt, outs, pos = run(k, threads)
+    k = pos.size
+    pairs = k * n * n_orb
+    agree = max(float(np.abs(case["refs"][o].cpu().numpy()[pos] - outs[o]).max() /
+                      np.abs(outs[o]).max()) for o in range(n_orb))
+    k1 = max(1, k // (10 * threads))
+    dt1, _, p1 = run(k1, 1)
+    k1 = p1.size
+    return {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"direct sum at {k} of the seeded targets x {n} sources x {n_orb} "
+                      f"orbitals, {dt:.1f} s",
+            "host": host_info(),
+            "extrapolated_full_direct_s": n * n * n_orb / (pairs / dt),
+            "per_core_value": k1 * n * n_orb / dt1,
+            "per_core_sample": f"{k1} targets x {n_orb} orbitals on 1 thread, {dt1:.1f} s",
+            "gpu_direct_vs_oracle_max_rel": agree}
+
+
+# ---------------------------------------------------------------------------
+# extras: the atom step, Hermite against Lagrange, graph replay, autotune, mesh,
+# the 10M-point uniform Coulomb case
 
 def coulomb_gauss_skipped(tagi, x, y, z, leaf, box, theta, degree, alpha=1.0):
     """(near, far) evaluations of a Coulomb-SS convolution that take the 1/d-only
-    path: (batch, cluster) pairs whose boxes lie at least 6.12 alpha apart, by the
-    kernel's own rule applied to the exported tree and lists."""
+    path, by the kernel's own rule applied to the exported tree and lists."""
     t = tagi.Tree(x, y, z, leaf, box)
     e = t.export()
     L = t.lists(theta, degree)
@@ -94,280 +425,83 @@ def coulomb_gauss_skipped(tagi, x, y, z, leaf, box, theta, degree, alpha=1.0):
     return near, far
 
 
-# counter profile of the interaction kernel and the sources it was taken from
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_interact_atom_mesh_Z4.md")
-KERNEL_SOURCES = ["interact_impl.hpp", "devmath.hpp", "interact_yukawa_ss.hip",
-                  "interact_coulomb_ss.hip", "interact.hip", "lists.hip"]
-
-
-def _log(msg):
-    print(msg, file=sys.stderr, flush=True)
-
-
-def kernel_source_digest() -> str:
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2003_01833_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-def workload_key(config: dict) -> str:
-    """One line naming the workload and every convolution's setting."""
-    convs = " ".join(f"{k} theta {v['theta']} degree {v['degree']}"
-                     for k, v in config["settings"].items())
-    return f"{config['workload']} {convs} leaf {config['leaf_size']}"
-
-
-def counter_traffic(config: dict):
-    """HBM bytes per interaction-kernel launch (FETCH_SIZE and WRITE_SIZE, each
-    scaled by its reading for a copy of known size) from the committed profile, or
-    None when the profile is missing, was taken on another workload, or the kernel
-    sources changed since."""
-    try:
-        with open(TRAFFIC_PROFILE) as fh:
-            kv = dict(re.findall(r"^- `(\w+)`: `([^`]*)`", fh.read(), re.M))
-    except OSError:
-        return None
-    want = workload_key(config)
-    if kv.get("workload") != want or kv.get("source_sha256") != kernel_source_digest():
-        return None
-    return float(kv["traffic_bytes_per_launch"])
-
-
-def make_workload(name: str):
-    from workloads.configs import DOMAIN, atom_mesh, uniform_cube
-    if name == "atom":
-        d = atom_mesh()
-        # each convolution at the cheapest (theta, degree) of the parameter sweep
-        # that meets 1e-6 relative L2 and max error on one tree (N_L = 2000); the
-        # workload's stated setting (theta 0.8, degree 8, N_L 500) is run once for
-        # its error
-        convs = [dict(kernel="yukawa_ss", f=d["psi"], kappa=float(d["kappa"]), theta=0.75,
-                      degree=8),
-                 dict(kernel="coulomb_ss", f=d["rho"], kappa=0.0, theta=0.8, degree=8)]
-        return dict(name="atom_mesh_Z4", x=d["x"], y=d["y"], z=d["z"], w=d["w"], convs=convs,
-                    leaf=2000, stated=(0.8, 8, 500), box=(*DOMAIN[0], *DOMAIN[1]))
-    x, y, z, f, w = uniform_cube(32768, seed=1)
-    return dict(name="uniform_cube_32768", x=x, y=y, z=z, w=w,
-                convs=[dict(kernel="yukawa_ss", f=f, kappa=1.0, theta=0.7, degree=6)],
-                leaf=500, box=None)
-
-
-def cpu_baseline(wl, seconds: float):
-    """The oracle's direct sum on sampled targets (all sources), both kernels."""
-    from oracle.direct import default_threads, direct_sum
-    from workloads.configs import sample_targets
-    threads = min(16, default_threads())
-    n = wl["x"].size
-
-    def run(k):
-        idx = sample_targets(n, k, seed=4)
-        t0 = time.perf_counter()
-        for c in wl["convs"]:
-            f = c["f"]
-            direct_sum(c["kernel"], wl["x"], wl["y"], wl["z"], f, wl["w"], wl["x"][idx],
-                       wl["y"][idx], wl["z"][idx], f[idx], kappa=c["kappa"] or 1.0,
-                       threads=threads)
-        return time.perf_counter() - t0
-
-    probe = max(threads, 16)
-    dt = run(probe)
-    k = int(min(n, max(probe, probe * seconds / max(dt, 1e-6))))
-    dt = run(k)
-    pairs = k * n * len(wl["convs"])
-    # one thread, for the per-core rate (a tenth of the time)
-    k1 = max(1, int(k * 0.1 / max(threads, 1)))
-    idx1 = sample_targets(n, k1, seed=5)
-    t0 = time.perf_counter()
-    for c in wl["convs"]:
-        f = c["f"]
-        direct_sum(c["kernel"], wl["x"], wl["y"], wl["z"], f, wl["w"], wl["x"][idx1],
-                   wl["y"][idx1], wl["z"][idx1], f[idx1], kappa=c["kappa"] or 1.0, threads=1)
-    dt1 = time.perf_counter() - t0
-    return {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
-            "sample": f"direct sum at {k} seeded targets x {n} sources for "
-                      f"{len(wl['convs'])} kernel(s), {dt:.1f} s",
-            # the full N^2 direct sums of one step at the sampled rate
-            "extrapolated_full_direct_s": n * n * len(wl["convs"]) / (pairs / dt),
-            "per_core_value": k1 * n * len(wl["convs"]) / dt1,
-            "per_core_sample": f"{k1} targets on 1 thread, {dt1:.1f} s"}
-
-
-def compare_batched(tagi, torch, fp64=(0.7, 8), mixed=(0.8, 10), leaf=2000, samples=10000,
-                    reps=1):
-    """The benzene workload (4,143,104 points, 21 orbitals, one kappa each): the
-    per-orbital FP64 loop and one batched FP64 launch sequence at the cheapest
-    FP64 (theta, degree) found that meets 1e-6, batched with the mixed-precision
-    far field at the cheapest such setting for it, and the learned selector.
-    Times exclude the tree build and include upward, lists (cached after the
-    first call) and the convolution; errors are per orbital against the GPU
-    direct sum at sampled targets."""
-    theta, degree = fp64
-    from workloads.configs import DOMAIN, benzene_mesh, benzene_orbitals, sample_targets
-    _log("compare: building the benzene mesh and 21 orbitals")
-    t0 = time.perf_counter()
-    m = benzene_mesh()
-    cpu_mesh_ms = 1e3 * (time.perf_counter() - t0)
-    orb = benzene_orbitals(m["x"], m["y"], m["z"])
-    n = m["x"].size
+def atom_step(tagi, torch, settings, steps=3, samples=2000):
+    """The Be-like atom (1,007,616 points): Yukawa-SS of psi_1s + psi_2s and
+    Coulomb-SS of rho on one tree per step, from scratch."""
+    from workloads.configs import DOMAIN, atom_mesh, sample_targets
+    d = atom_mesh()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
-    # the same mesh built on the GPU (adaptive refinement and the quadrature points)
-    from workloads.configs import benzene_atoms
-    atoms = [(tuple(R), Z) for R, Z in benzene_atoms()]
-    gpu_mesh = lambda: tagi.mesh(DOMAIN[0], DOMAIN[1], 7, 5e-4, 4, atoms=atoms,  # noqa: E731
-                                 test="root_density_vext")
-    gpu_mesh()
+    x, y, z, w = dev(d["x"]), dev(d["y"]), dev(d["z"]), dev(d["w"])
+    n = x.numel()
+    s = settings["atom"]
+    leaf, box = s["leaf_size"], (*DOMAIN[0], *DOMAIN[1])
+    fields = [dict(kernel="yukawa_ss", f=dev(d["psi"]), kappa=float(d["kappa"]),
+                   setting=tuple(s["yukawa_ss"]["fp64"])),
+              dict(kernel="coulomb_ss", f=dev(d["rho"]), kappa=1.0,
+                   setting=tuple(s["coulomb_ss"]["fp64"]))]
+    outs = [torch.empty((1, n), dtype=torch.float64, device="cuda") for _ in fields]
+
+    def step():
+        t = tagi.Tree(x, y, z, leaf, box)
+        t.set_timing(True)
+        sts = []
+        for c, out in zip(fields, outs):
+            th, deg = c["setting"]
+            t.upward(c["f"], w, deg)
+            t.convolve(c["kernel"], c["kappa"], th, deg, out=out)
+            sts.append(t.stats())
+        tm = t.timing()
+        t.close()
+        return tm, sts
+
+    step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gx, gy, gz, gw, glo, _ = gpu_mesh()
+    recs = [step() for _ in range(steps)]
     torch.cuda.synchronize()
-    mesh_info = {"cells": int(glo.shape[0]), "points": int(gx.numel()),
-                 "gpu_ms": 1e3 * (time.perf_counter() - t0),
-                 "cpu_input_generator_ms": cpu_mesh_ms,
-                 "same_points_as_cpu": bool(np.array_equal(gx.cpu().numpy(), m["x"]) and
-                                            np.allclose(gw.cpu().numpy(), m["w"], rtol=1e-15,
-                                                        atol=0))}
-    del gx, gy, gz, gw
-    x, y, z, w = dev(m["x"]), dev(m["y"]), dev(m["z"]), dev(m["w"])
-    F = dev(orb["psi"])
-    kap = orb["kappa"]
-    n_orb = F.shape[0]
-    t = tagi.Tree(x, y, z, leaf, (*DOMAIN[0], *DOMAIN[1]))
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    tm = {k: float(np.mean([r[0][k] for r in recs])) for k in
+          ("build_ms", "upward_ms", "lists_ms", "interact_ms", "combine_ms")}
+    sts = recs[-1][1]
+    inter = sum(st["far_interactions"] + st["near_interactions"] for st in sts)
+    flops = 0.0
+    for c, st in zip(fields, sts):
+        flops += eval_flops(c["kernel"], "fp64", st["far_interactions"], st["near_interactions"],
+                            1, 1)
+        if c["kernel"] == "coulomb_ss":
+            sn, sf = coulomb_gauss_skipped(tagi, x, y, z, leaf, box, *c["setting"])
+            flops -= sn * (sum(FLOPS[("coulomb_ss", "near", "fp64")]) - COULOMB_NEAR_1R_FLOPS)
+            flops -= sf * (sum(FLOPS[("coulomb_ss", "far", "fp64")]) - COULOMB_FAR_1R_FLOPS)
+    achieved = flops / (tm["interact_ms"] / 1e3) / 1e12
     idx = torch.from_numpy(sample_targets(n, samples, seed=4)).cuda()
-    sub = lambda a: a[idx].contiguous()  # noqa: E731
-    refs = [tagi.direct("yukawa_ss", x, y, z, F[o].contiguous(), w, sub(x), sub(y), sub(z),
-                        sub(F[o]), kappa=float(kap[o])) for o in range(n_orb)]
-
-    def errors(U):
-        e = []
-        for o in range(n_orb):
-            u = U[o, idx]
-            e.append((float(torch.linalg.norm(u - refs[o]) / torch.linalg.norm(refs[o])),
-                      float((u - refs[o]).abs().max() / refs[o].abs().max())))
-        return {"rel_l2_max_over_orbitals": max(a for a, _ in e),
-                "rel_max_max_over_orbitals": max(b for _, b in e),
-                "rel_l2_per_orbital": [a for a, _ in e],
-                "rel_max_per_orbital": [b for _, b in e]}
-
-    def timed(fn, warm=None):
-        # warm: a cheaper call that prepares the same plans and lists (default: fn)
-        (warm or fn)()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            out = fn()
-        torch.cuda.synchronize()
-        return out, 1e3 * (time.perf_counter() - t0) / reps
-
-    U_plain = torch.empty((n_orb, n), dtype=torch.float64, device="cuda")
-
-    def plain():
-        for o in range(n_orb):
-            t.upward(F[o].contiguous(), w, degree)
-            t.convolve("yukawa_ss", float(kap[o]), theta, degree, out=U_plain[o:o + 1])
-        return U_plain
-
-    res = {"workload": "benzene_mesh_21_orbitals", "n_points": n, "n_orb": n_orb,
-           "mesh_build": mesh_info,
-           "leaf_size": leaf, "fp64_setting": {"theta": theta, "degree": degree},
-           "mixed_setting": {"theta": mixed[0], "degree": mixed[1]}}
-    _log("compare: plain per-orbital loop")
-    def plain_warm():
-        # one orbital prepares the lists and the single-orbital schedule and plan
-        t.upward(F[0].contiguous(), w, degree)
-        t.convolve("yukawa_ss", float(kap[0]), theta, degree, out=U_plain[0:1])
-
-    U, ms = timed(plain, warm=plain_warm)
-    res["plain_fp64"] = {"ms": ms, **errors(U)}
-
-    def batched(precision, th, deg):
-        def run():
-            t.upward(F, w, deg)
-            return t.convolve("yukawa_ss", kap, th, deg, precision=precision)
-        return run
-
-    _log("compare: batched FP64")
-    U, ms = timed(batched("fp64", theta, degree))
-    st = t.stats()
-    res["batched_fp64"] = {"ms": ms, **errors(U),
-                           "interactions_per_orbital": st["far_interactions"] + st["near_interactions"]}
-    # the same step captured as a HIP graph (upward + convolve), replayed
-    Ug = torch.empty((n_orb, n), dtype=torch.float64, device="cuda")
-    g = t.graph(F, w, degree, "yukawa_ss", kap, theta, out=Ug)
-    # creating the graph ran the step once: the plans are ready
-    _, ms_g = timed(lambda: g.launch(), warm=lambda: None)
-    res["batched_fp64"]["graph_replay_ms"] = ms_g
-    res["batched_fp64"]["graph_equals_eager"] = bool(torch.equal(Ug, U))
-    g.close()
-    # autotuned leaf size and orbital block (timed on the first eight orbitals),
-    # then the batched FP64 step with the pick on all orbitals
-    _log("compare: autotuning N_L and the orbital block")
-    cand_leaf, cand_ob = (2000, 4000), (4, 8)
-    (leaf_t, ob_t), times = tagi.autotune(x, y, z, F[:8].contiguous(), w, "yukawa_ss", kap[:8],
-                                          theta, degree, leaf_sizes=cand_leaf, obs=cand_ob,
-                                          box=(*DOMAIN[0], *DOMAIN[1]))
-    tt = t if leaf_t == leaf else tagi.Tree(x, y, z, leaf_t, (*DOMAIN[0], *DOMAIN[1]))
-    tt.set_orbital_block(ob_t)
-
-    def tuned():
-        tt.upward(F, w, degree)
-        return tt.convolve("yukawa_ss", kap, theta, degree)
-    U, ms = timed(tuned)
-    res["batched_fp64_autotuned"] = {
-        "ms": ms, **errors(U), "leaf_size": leaf_t, "orbital_block": ob_t,
-        "tuning_ms_per_step_8_orbitals": {f"N_L {a} OB {b}": float(times[i, j])
-                                          for i, a in enumerate(cand_leaf)
-                                          for j, b in enumerate(cand_ob)}}
-    tt.set_orbital_block(0)
-    if tt is not t:
-        tt.close()
-    _log("compare: batched mixed")
-    U, ms = timed(batched("mixed", *mixed))
-    st_m = t.stats()
-    res["batched_mixed"] = {"ms": ms, **errors(U), "interactions_per_orbital":
-                            st_m["far_interactions"] + st_m["near_interactions"]}
-    weights = os.path.join(ROOT, "paper_2003_01833_amd", "selector_weights.npz")
-    if os.path.exists(weights):
-        from paper_2003_01833_amd.selector import Selector
-        sel = Selector.load(weights)
-        eta = float(sel.meta.get("eta", 0.01))
-        # per-orbital pair budget from the FP64 result's magnitude (in a Green
-        # iteration: the previous iterate's)
-        U64 = batched("fp64", theta, degree)()
-        tol = eta * 1e-6 * U64.abs().amax(dim=1).cpu().numpy()
-        for prec in ("fp64", "mixed"):
-            def learned(prec=prec):
-                # the learned path forms its own per-degree proxy charges; the
-                # upward pass only has to stage f and w (lowest degree)
-                t.upward(F, w, 1)
-                return t.convolve_learned("yukawa_ss", kap, sel, tol, precision=prec)
-            _log(f"compare: batched {prec} + learned selector")
-            t0 = time.perf_counter()
-            learned()
-            torch.cuda.synchronize()
-            first_ms = 1e3 * (time.perf_counter() - t0)
-            U, ms = timed(learned)
-            ls = t.learned_stats()
-            res[f"batched_{prec}_learned"] = {
-                "ms": ms, "first_call_ms_with_lists": first_ms, "eta": eta, **errors(U),
-                "interactions_per_orbital": ls["far_interactions"] + ls["near_interactions"],
-                "far_pairs_by_degree": ls["far_pairs_by_degree"]}
-    res["speedup_batched_vs_plain"] = res["plain_fp64"]["ms"] / res["batched_fp64"]["ms"]
-    res["speedup_mixed_vs_plain"] = res["plain_fp64"]["ms"] / res["batched_mixed"]["ms"]
-    res["speedup_autotuned_vs_plain"] = (res["plain_fp64"]["ms"] /
-                                         res["batched_fp64_autotuned"]["ms"])
-    if "batched_mixed_learned" in res:
-        res["speedup_mixed_learned_vs_plain"] = (res["plain_fp64"]["ms"] /
-                                                 res["batched_mixed_learned"]["ms"])
-    t.close()
-    return res
+    acc, refs = {}, {}
+    for c, out in zip(fields, outs):
+        f = c["f"]
+        ref = tagi.direct(c["kernel"], x, y, z, f, w, x[idx].contiguous(), y[idx].contiguous(),
+                          z[idx].contiguous(), f[idx].contiguous(), kappa=c["kappa"])
+        refs[c["kernel"]] = ref
+        u = out[0, idx]
+        acc[c["kernel"]] = {"rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
+                            "rel_max": float((u - ref).abs().max() / ref.abs().max())}
+    key = "atom_mesh_Z4 " + " ".join(f"{c['kernel']} theta {c['setting'][0]} degree "
+                                      f"{c['setting'][1]}" for c in fields) + f" leaf {leaf}"
+    kv = profile_values("atom", key)
+    res = {"workload": "atom_mesh_Z4", "n_points": n, "leaf_size": leaf, "ms_per_step": ms,
+           "interactions_per_step": inter, "interactions_per_s": inter / (ms / 1e3),
+           "direct_equivalent_pairs_per_s": n * n * len(fields) / (ms / 1e3),
+           "phases_ms": tm,
+           "settings": {c["kernel"]: list(c["setting"]) for c in fields},
+           "roofline": {"bound": "alu", "kernel": "k_interact", "achieved": achieved,
+                        "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / VECTOR_PEAK_TFLOPS,
+                        "traffic": float(kv["traffic_bytes_per_launch"]) if kv else None,
+                        "avg_launch_ms": tm["interact_ms"] / max(recs[-1][0]["interact_launches"], 1)},
+           "accuracy_vs_direct": acc}
+    return res, dict(x=x, y=y, z=z, w=w, fields=fields, refs=refs, idx=idx, leaf=leaf, box=box)
 
 
-# Cheapest settings of each interpolation form (N_L = 2000, the tree of the timed
-# step) reaching a maximum relative error of 1e-6 and of 1e-9 on the Be-like mesh,
-# from parameter sweeps (Lagrange degrees 8-14, Hermite degrees 4-7, theta
-# 0.5-0.9): (theta, degree).
+# Cheapest settings of each interpolation form (N_L = 2000) reaching a maximum
+# relative error of 1e-6 and of 1e-9 on the Be-like mesh: (theta, degree)
 HERMITE_COMPARE = {
     "yukawa_ss": {"1e-6": {"lagrange": (0.75, 8), "hermite": (0.8, 6)},
                   "1e-9": {"lagrange": (0.7, 12), "hermite": (0.5, 6)}},
@@ -376,61 +510,228 @@ HERMITE_COMPARE = {
 }
 
 
-def compare_hermite(tagi, torch, x, y, z, w, fields, refs, idx, leaf, box, reps=3):
-    """Lagrange against Hermite interpolation at two accuracy targets: the median
-    of `reps` convolutions after one warm-up, and the error at the sampled
-    targets against the GPU direct sum."""
-    _log("compare: Lagrange and Hermite treecodes on the Be-like mesh")
-    t = tagi.Tree(x, y, z, leaf, box)
+def compare_hermite(tagi, torch, a, reps=3):
+    """Lagrange against Hermite interpolation at two accuracy targets on the atom:
+    median of `reps` convolutions after one warm-up."""
+    t = tagi.Tree(a["x"], a["y"], a["z"], a["leaf"], a["box"])
     res = {}
-    for c in fields:
+    for c in a["fields"]:
         k = c["kernel"]
-        if k not in HERMITE_COMPARE:
-            continue
-        kap = c["kappa"] or 1.0
-        ref = refs[k]
+        ref = a["refs"][k]
         res[k] = {}
         for target, forms in HERMITE_COMPARE[k].items():
             res[k][target] = {}
             for form, (th, deg) in forms.items():
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                t.upward(c["f"], w, deg, interpolation=form)
-                torch.cuda.synchronize()
-                up_ms = 1e3 * (time.perf_counter() - t0)
-                u = t.convolve(k, kap, th, deg)
-                ts = []
-                for _ in range(reps):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    u = t.convolve(k, kap, th, deg)
-                    torch.cuda.synchronize()
-                    ts.append(1e3 * (time.perf_counter() - t0))
-                ui = u[0, idx]
-                st = t.stats()
+                t.upward(c["f"], a["w"], deg, interpolation=form)
+                u = t.convolve(k, c["kappa"], th, deg)
+                _, _, ts = time_steps(torch, lambda: (t.convolve(k, c["kappa"], th, deg), None),
+                                      reps)
+                u = t.convolve(k, c["kappa"], th, deg)
+                ui = u[0, a["idx"]]
                 res[k][target][form] = {
                     "theta": th, "degree": deg, "convolve_ms": float(np.median(ts)),
-                    "upward_ms": up_ms,
                     "rel_max": float((ui - ref).abs().max() / ref.abs().max()),
-                    "rel_l2": float(torch.linalg.norm(ui - ref) / torch.linalg.norm(ref)),
-                    "far_pairs": st["n_far_pairs"], "near_pairs": st["n_near_pairs"]}
+                    "rel_l2": float(torch.linalg.norm(ui - ref) / torch.linalg.norm(ref))}
             r = res[k][target]
             r["hermite_speedup"] = r["lagrange"]["convolve_ms"] / r["hermite"]["convolve_ms"]
     t.close()
     return res
 
 
+def anchor_10m(tagi, torch, samples=1000):
+    """Section 6.6: 10,000,000 points uniformly random in a cube, Coulomb kernel,
+    theta 0.7, degree 7; relative L2 error against the direct sum at seeded
+    targets (the paper reports 2.31e-6; its charges and N_L are not stated: here
+    f ~ U[-1, 1], w = 8/N on [-1, 1]^3, N_L = 2000)."""
+    from workloads.configs import sample_targets, uniform_cube
+    x, y, z, f, w = uniform_cube(10_000_000, seed=6)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    X, Y, Z, Fd, W = dev(x), dev(y), dev(z), dev(f), dev(w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = tagi.Tree(X, Y, Z, 2000)
+    t.upward(Fd, W, 7)
+    u = t.convolve("coulomb", 1.0, 0.7, 7)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0)
+    st = t.stats()
+    t.close()
+    idx = torch.from_numpy(sample_targets(x.size, samples, seed=7)).cuda()
+    ref = tagi.direct("coulomb", X, Y, Z, Fd, W, X[idx].contiguous(), Y[idx].contiguous(),
+                      Z[idx].contiguous(), Fd[idx].contiguous())
+    ui = u[0, idx]
+    return {"n": x.size, "theta": 0.7, "degree": 7, "leaf_size": 2000, "kernel": "coulomb",
+            "ms_including_tree": ms, "samples": samples,
+            "rel_l2": float(torch.linalg.norm(ui - ref) / torch.linalg.norm(ref)),
+            "rel_max": float((ui - ref).abs().max() / ref.abs().max()),
+            "paper_rel_l2": 2.31e-6,
+            "interactions": st["far_interactions"] + st["near_interactions"]}
+
+
+def extras(tagi, torch, settings, bz, case):
+    out = {}
+    _log("bench: extras: atom step")
+    out["atom_step"], a = atom_step(tagi, torch, settings)
+    _log("bench: extras: Hermite against Lagrange on the atom")
+    out["hermite_vs_lagrange"] = compare_hermite(tagi, torch, a)
+    del a
+    # the batched FP64 step captured as a HIP graph on a cached tree, replayed
+    _log("bench: extras: HIP graph replay of the batched step")
+    th, deg = bz.fp64
+    t = tagi.Tree(case["x"], case["y"], case["z"], bz.leaf, case["box"])
+    Ug = torch.empty_like(bz.U)
+    g = t.graph(case["F"], case["w"], deg, "yukawa_ss", case["kappa"], th, out=Ug)
+    _, _, ms_g = time_steps(torch, lambda: (g.launch(), None), 3)
+    t.upward(case["F"], case["w"], deg)
+    Ue = t.convolve("yukawa_ss", case["kappa"], th, deg)
+    out["graph_replay"] = {"ms_median": float(np.median(ms_g)),
+                           "equals_eager": bool(torch.equal(Ug, Ue))}
+    g.close()
+    t.close()
+    del Ug, Ue
+    # autotuner: leaf size, orbital block and schedule granularity on the first
+    # eight orbitals
+    _log("bench: extras: autotuner")
+    cand_leaf, cand_ob, cand_it = (1000, 2000, 4000), (4, 8), (8192, 16384, 32768)
+    (leaf_t, ob_t, it_t), times = tagi.autotune(case["x"], case["y"], case["z"],
+                                                case["F"][:8].contiguous(), case["w"], "yukawa_ss",
+                                                case["kappa"][:8], th, deg, leaf_sizes=cand_leaf,
+                                                obs=cand_ob, items=cand_it, box=case["box"])
+    out["autotune"] = {"leaf_size": leaf_t, "orbital_block": ob_t, "schedule_items": it_t,
+                       "ms_per_step_8_orbitals": {f"N_L {a} OB {b} items {c}": float(times[i, j, k])
+                                                  for i, a in enumerate(cand_leaf)
+                                                  for j, b in enumerate(cand_ob)
+                                                  for k, c in enumerate(cand_it)}}
+    # the benzene mesh built on the GPU
+    _log("bench: extras: GPU mesh build")
+    from workloads.configs import DOMAIN, benzene_atoms
+    atoms = [(tuple(R), Z) for R, Z in benzene_atoms()]
+    mk = lambda: tagi.mesh(DOMAIN[0], DOMAIN[1], 7, 5e-4, 4, atoms=atoms,  # noqa: E731
+                           test="root_density_vext")
+    mk()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gx, gy, gz, gw, glo, _ = mk()
+    torch.cuda.synchronize()
+    out["mesh_build"] = {"cells": int(glo.shape[0]), "points": int(gx.numel()),
+                         "gpu_ms": 1e3 * (time.perf_counter() - t0),
+                         "cpu_input_generator_ms": case["cpu_mesh_ms"],
+                         "same_points_as_cpu": bool(torch.equal(gx, case["x"]) and
+                                                    torch.allclose(gw, case["w"], rtol=1e-15,
+                                                                   atol=0))}
+    del gx, gy, gz, gw
+    _log("bench: extras: 10M uniform Coulomb (Section 6.6)")
+    out["uniform_10M_coulomb"] = anchor_10m(tagi, torch)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# parameter sweep
+
+def sweep(tagi, torch, workload, write):
+    settings = load_settings()
+    res = {}
+    if workload == "benzene":
+        case = benzene_case(tagi, torch)
+        leaf = settings["benzene"]["leaf_size"]
+        t = tagi.Tree(case["x"], case["y"], case["z"], leaf, case["box"])
+        grid = {"fp64": [(th, n) for n in (7, 8, 9, 10) for th in (0.6, 0.65, 0.7, 0.75, 0.8)],
+                "mixed": [(th, n) for n in (8, 9, 10, 11) for th in (0.65, 0.7, 0.75, 0.8, 0.85)]}
+        table = {}
+        for prec, pts in grid.items():
+            rows = []
+            for th, n in pts:
+                # one call per setting: its upward, interaction and combine time
+                # from HIP events (the list build of a new setting excluded)
+                t.set_timing(True)
+                t.upward(case["F"], case["w"], n)
+                U = t.convolve("yukawa_ss", case["kappa"], th, n, precision=prec)
+                tm = t.timing()
+                ms = tm["upward_ms"] + tm["interact_ms"] + tm["combine_ms"]
+                e = errors(torch, case, U)
+                rows.append({"theta": th, "degree": n, "convolve_ms": ms,
+                             "rel_l2": e["rel_l2_max_over_orbitals"],
+                             "rel_max": e["rel_max_max_over_orbitals"]})
+                _log(f"sweep benzene {prec} theta {th} degree {n}: {ms:.0f} ms, "
+                     f"rel_l2 {rows[-1]['rel_l2']:.2e} rel_max {rows[-1]['rel_max']:.2e}")
+            table[prec] = rows
+        t.close()
+        res["benzene"] = {"leaf_size": leaf, "yukawa_ss": table}
+    else:
+        from workloads.configs import DOMAIN, atom_mesh, sample_targets
+        d = atom_mesh()
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+        x, y, z, w = dev(d["x"]), dev(d["y"]), dev(d["z"]), dev(d["w"])
+        leaf = settings["atom"]["leaf_size"]
+        t = tagi.Tree(x, y, z, leaf, (*DOMAIN[0], *DOMAIN[1]))
+        idx = torch.from_numpy(sample_targets(x.numel(), 10000, seed=4)).cuda()
+        res["atom"] = {"leaf_size": leaf}
+        for kernel, f, kap in (("yukawa_ss", dev(d["psi"]), float(d["kappa"])),
+                               ("coulomb_ss", dev(d["rho"]), 1.0)):
+            ref = tagi.direct(kernel, x, y, z, f, w, x[idx].contiguous(), y[idx].contiguous(),
+                              z[idx].contiguous(), f[idx].contiguous(), kappa=kap)
+            rows = []
+            for n in range(6, 13):
+                for th in (0.6, 0.65, 0.7, 0.75, 0.8, 0.85, 0.9):
+                    t.set_timing(True)
+                    t.upward(f, w, n)
+                    u = t.convolve(kernel, kap, th, n)[0, idx]
+                    tm = t.timing()
+                    ms = tm["upward_ms"] + tm["interact_ms"] + tm["combine_ms"]
+                    rows.append({"theta": th, "degree": n, "convolve_ms": ms,
+                                 "rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
+                                 "rel_max": float((u - ref).abs().max() / ref.abs().max())})
+                    _log(f"sweep atom {kernel} theta {th} degree {n}: {ms:.1f} ms, "
+                         f"rel_l2 {rows[-1]['rel_l2']:.2e} rel_max {rows[-1]['rel_max']:.2e}")
+            res["atom"][kernel] = {"fp64": rows}
+        t.close()
+    # cheapest setting meeting the bar per (kernel, precision)
+    for wl, v in res.items():
+        for kernel, tabs in v.items():
+            if not isinstance(tabs, dict):
+                continue
+            for prec, rows in tabs.items():
+                ok = [r for r in rows if r["rel_l2"] <= BAR and r["rel_max"] <= BAR]
+                best = min(ok, key=lambda r: r["convolve_ms"]) if ok else None
+                tabs[prec] = {"setting": [best["theta"], best["degree"]] if best else None,
+                              "table": rows}
+    print(json.dumps({"sweep": res}), flush=True)
+    if write:
+        stored = {}
+        if os.path.exists(SETTINGS):
+            with open(SETTINGS) as fh:
+                stored = json.load(fh)
+        for wl, v in res.items():
+            entry = stored.setdefault(wl, {})
+            entry["leaf_size"] = v["leaf_size"]
+            for kernel, tabs in v.items():
+                if isinstance(tabs, dict):
+                    entry.setdefault(kernel, {}).update(
+                        {p: {"setting": x["setting"],
+                             "rule": "cheapest (theta, degree) of the sweep with rel L2 and rel max "
+                                     "<= 1e-6 at 10,000 seeded targets (every orbital)"}
+                         for p, x in tabs.items() if x["setting"]})
+        with open(SETTINGS, "w") as fh:
+            json.dump(stored, fh, indent=1, sort_keys=True)
+        _log(f"sweep: wrote {SETTINGS}")
+
+
+# ---------------------------------------------------------------------------
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="atom", choices=["atom", "cube"])
-    ap.add_argument("--samples", type=int, default=2000, help="targets for the accuracy check")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="benzene", choices=["benzene", "atom", "cube"])
+    ap.add_argument("--variants", default="plain,batched_fp64,batched_mixed,batched_fp64_learned,"
+                                          "batched_mixed_learned")
+    ap.add_argument("--reps", type=int, default=3, help="steps per variant (median)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true",
-                    help="skip the batched/mixed vs plain comparison on the benzene workload")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--write-settings", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB five times (the "
                          "reference for scaling HBM byte counters) and exit")
@@ -447,165 +748,179 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures a single GPU; runs on more than one GPU are not part of this "
+        print("bench.py measures one GPU: runs on more than one GPU are not part of this "
               "build (the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
     import torch
 
     import paper_2003_01833_amd as tagi
-    from workloads.configs import sample_targets
 
     torch.cuda.set_device(0)
-    _log(f"bench: building workload {args.workload}")
-    wl = make_workload(args.workload)
-    n = wl["x"].size
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
-    x, y, z, w = dev(wl["x"]), dev(wl["y"]), dev(wl["z"]), dev(wl["w"])
-    fields = [dict(c, f=dev(c["f"])) for c in wl["convs"]]
-    outs = [torch.empty((1, n), dtype=torch.float64, device="cuda") for _ in fields]
-    leaf = wl["leaf"]
-    torch.cuda.synchronize()
-
-    records = []
-
-    def step():
-        t = tagi.Tree(x, y, z, leaf, wl["box"])
-        t.set_timing(True)
-        stats = []
-        for c, out in zip(fields, outs):
-            t.upward(c["f"], w, c["degree"])
-            t.convolve(c["kernel"], c["kappa"] or 1.0, c["theta"], c["degree"], alpha=1.0,
-                       out=out)
-            stats.append(t.stats())
-        records.append((t.timing(), stats))
-        t.close()
-
-    for i in range(args.warmup):
-        step()
-        _log(f"bench: warmup step {i + 1}/{args.warmup} done")
-    records.clear()
+    if args.sweep:
+        sweep(tagi, torch, "benzene" if args.workload == "benzene" else "atom",
+              args.write_settings)
+        return
+    if args.workload != "benzene":
+        return small_workload(tagi, torch, args)
+    settings = load_settings()
+    case = benzene_case(tagi, torch)
+    sel = tol = None
+    weights = os.path.join(ROOT, "paper_2003_01833_amd", "selector_weights.npz")
+    wanted = [v for v in args.variants.split(",") if v]
+    need_fp64_scale = any(v.endswith("_learned") for v in wanted)
+    if need_fp64_scale and os.path.exists(weights):
+        from paper_2003_01833_amd.selector import Selector
+        sel = Selector.load(weights)
+    bz = Benzene(tagi, torch, case, settings, sel)
+    if sel is not None:
+        # per-orbital budget of one target's sum from the FP64 result's magnitude
+        # (in a Green iteration: the previous iterate's)
+        U64, _ = bz.batched("fp64")
+        bz.tol = sel.eta("yukawa_ss") * BAR * U64.abs().amax(dim=1).cpu().numpy()
+    runs = bz.variants()
+    results = {}
+    for name in wanted:
+        if name not in runs:
+            continue
+        _log(f"bench: variant {name}: warm-up + {args.reps} steps")
+        runs[name]()
+        U, rec, ms = time_steps(torch, runs[name], args.reps)
+        err = errors(torch, case, U)
+        results[name] = {"ms_median": float(np.median(ms)), "ms_steps": ms,
+                         "interactions_per_step": rec["interactions"],
+                         "interactions_per_s": rec["interactions"] / (np.median(ms) / 1e3),
+                         "phases_ms": {k: rec["timing"][k] for k in
+                                       ("build_ms", "upward_ms", "lists_ms", "interact_ms",
+                                        "combine_ms")},
+                         "meets_1e-6": meets_bar(err), **err, "_rec": rec}
+        if "far_pairs_by_degree" in rec:
+            results[name]["far_pairs_by_degree"] = rec["far_pairs_by_degree"]
+        _log(f"bench: variant {name}: {np.median(ms):.0f} ms, rel_max "
+             f"{err['rel_max_max_over_orbitals']:.2e}, rel_l2 {err['rel_l2_max_over_orbitals']:.2e}")
+    ok = [k for k, v in results.items() if v["meets_1e-6"]]
+    if not ok:
+        print("bench: no variant met the 1e-6 bar", file=sys.stderr)
+        sys.exit(1)
+    head = min(ok, key=lambda k: results[k]["ms_median"])
+    _log(f"bench: headline {head}: {args.warmup} warm-up + {args.steps} timed steps")
+    for _ in range(args.warmup):
+        runs[head]()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    step_ms = []
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        step()  # ends synchronised (phase timings are read, the tree is destroyed)
-        step_ms.append(1e3 * (time.perf_counter() - ts))
+    recs = []
+    for _ in range(args.steps):
+        U, rec = runs[head]()
+        recs.append(rec)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    _log(f"bench: {args.steps} timed steps in {elapsed:.3f} s")
     ms_per_step = 1e3 * elapsed / args.steps
+    head_err = errors(torch, case, U)
+    inter = recs[-1]["interactions"]
+    value = inter / (ms_per_step / 1e3)
 
-    sts = records[-1][1]
-    interactions = sum(st["far_interactions"] + st["near_interactions"] for st in sts)
-    value = interactions / (ms_per_step / 1e3)
-    # the N^2 pairs that the direct sums of one step would evaluate, per second
-    direct_equivalent = n * n * len(fields) / (ms_per_step / 1e3)
-    phases = {k: float(np.mean([r[0][k] for r in records])) for k in
-              ("build_ms", "upward_ms", "lists_ms", "interact_ms", "combine_ms")}
-    flops = sum(st["far_interactions"] * FLOPS[(c["kernel"], "far")] +
-                st["near_interactions"] * FLOPS[(c["kernel"], "near")]
-                for c, st in zip(fields, sts))
-    gauss_near = gauss_far = 0
-    for c in fields:
-        if c["kernel"] == "coulomb_ss":
-            sn, sf = coulomb_gauss_skipped(tagi, x, y, z, leaf, wl["box"], c["theta"], c["degree"])
-            gauss_near += sn
-            gauss_far += sf
-    flops -= gauss_near * (FLOPS[("coulomb_ss", "near")] - COULOMB_NEAR_1R_FLOPS)
-    flops -= gauss_far * (FLOPS[("coulomb_ss", "far")] - COULOMB_FAR_1R_FLOPS)
-    interact_s = phases["interact_ms"] / 1e3
-    achieved = flops / interact_s / 1e12
-    launches = records[-1][0]["interact_launches"]
-
-    # accuracy of the last step's outputs against the GPU direct sum at sampled targets
-    idx = torch.from_numpy(sample_targets(n, min(args.samples, n), seed=4)).cuda()
-    acc, refs = {}, {}
-    for c, out in zip(fields, outs):
-        f = c["f"]
-        ref = tagi.direct(c["kernel"], x, y, z, f, w, x[idx].contiguous(), y[idx].contiguous(),
-                          z[idx].contiguous(), f[idx].contiguous(), kappa=c["kappa"] or 1.0)
-        refs[c["kernel"]] = ref
-        u = out[0, idx]
-        acc[c["kernel"]] = {"rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
-                            "rel_max": float((u - ref).abs().max() / ref.abs().max())}
-
-    stated = None
-    if wl.get("stated"):
-        th_s, deg_s, leaf_s = wl["stated"]
-        t = tagi.Tree(x, y, z, leaf_s, wl["box"])
-        stated = {"theta": th_s, "degree": deg_s, "leaf_size": leaf_s}
-        for c in fields:
-            t.upward(c["f"], w, deg_s)
-            u = t.convolve(c["kernel"], c["kappa"] or 1.0, th_s, deg_s)[0, idx]
-            ref = refs[c["kernel"]]
-            stated[c["kernel"]] = {
-                "rel_l2": float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref)),
-                "rel_max": float((u - ref).abs().max() / ref.abs().max())}
-        t.close()
-
-    comparison = hermite = None
-    if not args.no_compare:
-        if args.workload == "atom":
-            hermite = compare_hermite(tagi, torch, x, y, z, w, fields, refs, idx, leaf, wl["box"])
-        comparison = compare_batched(tagi, torch)
+    plain_ms = results.get("plain", {}).get("ms_median")
+    comparison = {}
+    for k, v in results.items():
+        v = dict(v)
+        rec = v.pop("_rec")
+        v["roofline"] = roofline_of(rec)
+        if plain_ms:
+            v["speedup_vs_plain"] = plain_ms / v["ms_median"]
+        comparison[k] = v
+    settings_used = {"leaf_size": bz.leaf,
+                     "fp64": {"theta": bz.fp64[0], "degree": bz.fp64[1]},
+                     "mixed": {"theta": bz.mixed[0], "degree": bz.mixed[1]},
+                     "learned": {"eta": sel.eta("yukawa_ss") if sel else None,
+                                 "theta_max": 0.9, "fallback": [0.7, 8]}}
+    roof = comparison.get("batched_fp64", {}).get("roofline")
+    roof_mixed = comparison.get("batched_mixed", {}).get("roofline")
+    roof_head = roofline_of(recs[-1])
+    key = f"benzene_mesh_21_orbitals batched fp64 theta {bz.fp64[0]} degree {bz.fp64[1]} " \
+          f"leaf {bz.leaf}"
+    kv = profile_values("benzene", key)
+    if roof is not None and kv:
+        roof["traffic"] = float(kv["fp64_traffic_bytes_per_launch"])
+    upward = None
+    if "batched_fp64" in results:
+        rec = results["batched_fp64"]["_rec"]
+        up_ms = rec["timing"]["upward_ms"]
+        upward = {"ms_per_step": up_ms}
+        if kv and "upward_traffic_bytes" in kv:
+            b = float(kv["upward_traffic_bytes"])
+            upward.update({"hbm_bytes_counter": b, "gbs": b / (up_ms / 1e3) / 1e9,
+                           "frac_hbm": b / (up_ms / 1e3) / 1e9 / HBM_PEAK_GBS})
+        if kv and "upward_fp64_flops" in kv:
+            fl = float(kv["upward_fp64_flops"])
+            upward.update({"tflops_counter": fl / (up_ms / 1e3) / 1e12,
+                           "frac_fp64_counter": fl / (up_ms / 1e3) / 1e12 / VECTOR_PEAK_TFLOPS})
 
     cpu = None
     if not args.no_cpu_baseline:
         _log("bench: timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(wl, args.cpu_seconds)
+        cpu = cpu_baseline_benzene(case, args.cpu_seconds)
+    ext = None
+    if not args.no_extras:
+        ext = extras(tagi, torch, settings, bz, case)
 
     line = {
         "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": wl["name"], "n_points": n, "leaf_size": leaf,
-                   "settings": {c["kernel"]: {"theta": c["theta"], "degree": c["degree"],
-                                              "far_pairs": st["n_far_pairs"],
-                                              "near_pairs": st["n_near_pairs"]}
-                                for c, st in zip(fields, sts)},
-                   "n_leaves": sts[0]["n_leaves"], "interactions_per_step": interactions,
-                   "coulomb_evaluations_without_gaussian": {"near": gauss_near,
-                                                             "far": gauss_far}},
-        "roofline": {"bound": "alu", "kernel": "k_interact", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "traffic_unit": "bytes per launch",
-                     "launches_per_step": launches,
-                     "avg_launch_ms": phases["interact_ms"] / max(launches, 1)},
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32" if "mixed" in head else "f64", "data": "synthetic",
+        "config": {"workload": case["name"], "n_points": case["n"], "n_orb": case["n_orb"],
+                   "variant": head, "settings": settings_used,
+                   "interactions_per_step": inter,
+                   "accuracy_samples": int(case["idx_h"].size)},
+        "accuracy_vs_direct": {k: head_err[k] for k in ("rel_l2_max_over_orbitals",
+                                                          "rel_max_max_over_orbitals")},
+        "roofline": roof,
+        "roofline_mixed": roof_mixed,
+        "roofline_headline": roof_head,
+        "upward": upward,
         "cpu_baseline": cpu,
-        "direct_equivalent_pairs_per_s": direct_equivalent,
-        "phases_ms": phases,
-        "ms_per_step_median": float(np.median(step_ms)),
-        # a Green-iteration step on a fixed mesh reuses the tree and the lists:
-        # upward passes, interaction kernels and combine only
-        "ms_per_iteration_cached_tree": phases["upward_ms"] + phases["interact_ms"] + phases["combine_ms"],
-        "accuracy_vs_direct": acc,
-        "stated_setting_accuracy": stated,
-        "batched_mixed_vs_plain": comparison,
-        "hermite_vs_lagrange": hermite,
+        "direct_equivalent_pairs_per_s": case["n"] ** 2 * case["n_orb"] / (ms_per_step / 1e3),
+        "phases_ms": recs[-1]["timing"],
+        "variants": comparison,
+        "extras": ext,
     }
-    line["roofline"]["traffic"] = counter_traffic(line["config"])
-    # the upward pass (proxy charges), against both the FP64 and the HBM roofline.
-    # Per (source, approximable cluster) pair: barycentric basis values in three
-    # dimensions, 4 flops per node (difference, divide, sum, normalise), the
-    # (n+1)^2 products L_k1 L_k2, and one multiply-add per coefficient and charge
-    # set; bytes: the source's coordinates and charges read once per cluster it
-    # belongs to, and the proxy charges written once.
-    up_flops = up_bytes = 0.0
-    for c, st in zip(fields, sts):
-        p1 = c["degree"] + 1
-        sets = 2  # f w and w
-        up_flops += st["upward_points"] * (12 * p1 + p1 * p1 + 2 * sets * p1 ** 3)
-        up_bytes += st["upward_points"] * 8 * (3 + sets) + st["n_approx"] * 8 * sets * p1 ** 3
-    up_s = phases["upward_ms"] / 1e3
-    line["upward"] = {"ms_per_step": phases["upward_ms"],
-                      "tflops": up_flops / up_s / 1e12,
-                      "frac_fp64": up_flops / up_s / 1e12 / FP64_PEAK_TFLOPS,
-                      "gbs": up_bytes / up_s / 1e9, "frac_hbm": up_bytes / up_s / 1e9 / 8000.0}
     print(json.dumps(line), flush=True)
+
+
+def small_workload(tagi, torch, args):
+    """--workload atom | cube: the C2 atom step (or the uniform cube) alone."""
+    settings = load_settings()
+    if args.workload == "atom":
+        res, _ = atom_step(tagi, torch, settings, steps=args.steps)
+        print(json.dumps({"metric": METRIC, "value": res["interactions_per_s"],
+                          "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": 1, "ms_per_step": res["ms_per_step"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": res["workload"]}, "roofline": res["roofline"],
+                          "atom": res}), flush=True)
+        return
+    from workloads.configs import uniform_cube
+    x, y, z, f, w = uniform_cube(32768, seed=1)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    X, Y, Z, Fd, W = dev(x), dev(y), dev(z), dev(f), dev(w)
+    ms = []
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = tagi.treecode(X, Y, Z, Fd, W, "yukawa_ss", 1.0, 0.7, 6, 500)
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            ms.append(1e3 * (time.perf_counter() - t0))
+    ud = tagi.direct("yukawa_ss", X, Y, Z, Fd, W, kappa=1.0)
+    print(json.dumps({"metric": METRIC, "value": 32768 ** 2 / (np.mean(ms) / 1e3),
+                      "unit": "direct-equivalent pairs/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": float(np.mean(ms)),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "uniform_cube_32768"},
+                      "rel_l2": float(torch.linalg.norm(u[0] - ud) / torch.linalg.norm(ud))}),
+          flush=True)
 
 
 if __name__ == "__main__":
