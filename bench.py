@@ -61,10 +61,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from workloads.settings import SETTINGS, load_settings  # noqa: E402
+
 METRIC = "Green-convolution time & interactions/s at 1e-6 rel err; batched/mixed vs plain"
 VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak; non-packed FP32 issues at the same rate
 HBM_PEAK_GBS = 8000.0
-SETTINGS = os.path.join(ROOT, "workloads", "settings.json")
 BAR = 1e-6
 
 # Algorithmic flops per kernel evaluation (FMA = 2), split into the part that is
@@ -112,34 +113,8 @@ KERNEL_SOURCES = ["interact_impl.hpp", "devmath.hpp", "interact_yukawa_ss.hip",
                   "interact_coulomb_ss.hip", "interact.hip", "lists.hip", "upward.hip",
                   "learned.hip"]
 
-# settings used when workloads/settings.json has no entry (the values that file
-# holds from the last sweep are the ones the benchmark runs)
-DEFAULT_SETTINGS = {
-    "benzene": {"leaf_size": 2000,
-                "yukawa_ss": {"fp64": [0.7, 8], "mixed": [0.8, 10]}},
-    "atom": {"leaf_size": 2000,
-             "yukawa_ss": {"fp64": [0.75, 8]}, "coulomb_ss": {"fp64": [0.8, 8]}},
-}
-
-
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-def load_settings():
-    s = json.loads(json.dumps(DEFAULT_SETTINGS))
-    if os.path.exists(SETTINGS):
-        with open(SETTINGS) as fh:
-            stored = json.load(fh)
-        for wl, v in stored.items():
-            if wl in s:
-                for k, vv in v.items():
-                    if isinstance(vv, dict):
-                        s[wl].setdefault(k, {}).update({p: list(x["setting"]) if isinstance(x, dict)
-                                                        else list(x) for p, x in vv.items()})
-                    elif k == "leaf_size":
-                        s[wl][k] = vv
-    return s
 
 
 def kernel_source_digest() -> str:
@@ -300,8 +275,10 @@ class Benzene:
         t.convolve("yukawa_ss", c["kappa"], th, deg, precision=precision, out=self.U)
         st = t.stats()
         ob = 8 if precision == "fp64" else 4
-        return self.U, self._finish(t, precision, (st["far_interactions"], st["near_interactions"]),
-                                    ob)
+        rec = self._finish(t, precision, (st["far_interactions"], st["near_interactions"]), ob)
+        rec["upward_points"], rec["n_approx"], rec["degree"] = (st["upward_points"], st["n_approx"],
+                                                                deg)
+        return self.U, rec
 
     def learned(self, precision):
         t = self._tree()
@@ -501,7 +478,8 @@ def atom_step(tagi, torch, settings, steps=3, samples=2000):
 
 
 # Cheapest settings of each interpolation form (N_L = 2000) reaching a maximum
-# relative error of 1e-6 and of 1e-9 on the Be-like mesh: (theta, degree)
+# relative error of 1e-6 and of 1e-9 on the Be-like mesh: (theta, degree); the
+# Lagrange setting at 1e-6 is the stored atom setting (workloads/settings.json)
 HERMITE_COMPARE = {
     "yukawa_ss": {"1e-6": {"lagrange": (0.75, 8), "hermite": (0.8, 6)},
                   "1e-9": {"lagrange": (0.7, 12), "hermite": (0.5, 6)}},
@@ -510,7 +488,7 @@ HERMITE_COMPARE = {
 }
 
 
-def compare_hermite(tagi, torch, a, reps=3):
+def compare_hermite(tagi, torch, a, settings, reps=3):
     """Lagrange against Hermite interpolation at two accuracy targets on the atom:
     median of `reps` convolutions after one warm-up."""
     t = tagi.Tree(a["x"], a["y"], a["z"], a["leaf"], a["box"])
@@ -521,6 +499,9 @@ def compare_hermite(tagi, torch, a, reps=3):
         res[k] = {}
         for target, forms in HERMITE_COMPARE[k].items():
             res[k][target] = {}
+            forms = dict(forms)
+            if target == "1e-6":
+                forms["lagrange"] = tuple(settings["atom"][k]["fp64"])
             for form, (th, deg) in forms.items():
                 t.upward(c["f"], a["w"], deg, interpolation=form)
                 u = t.convolve(k, c["kappa"], th, deg)
@@ -573,7 +554,7 @@ def extras(tagi, torch, settings, bz, case):
     _log("bench: extras: atom step")
     out["atom_step"], a = atom_step(tagi, torch, settings)
     _log("bench: extras: Hermite against Lagrange on the atom")
-    out["hermite_vs_lagrange"] = compare_hermite(tagi, torch, a)
+    out["hermite_vs_lagrange"] = compare_hermite(tagi, torch, a, settings)
     del a
     # the batched FP64 step captured as a HIP graph on a cached tree, replayed
     _log("bench: extras: HIP graph replay of the batched step")
@@ -697,23 +678,33 @@ def sweep(tagi, torch, workload, write):
                               "table": rows}
     print(json.dumps({"sweep": res}), flush=True)
     if write:
-        stored = {}
-        if os.path.exists(SETTINGS):
-            with open(SETTINGS) as fh:
-                stored = json.load(fh)
-        for wl, v in res.items():
-            entry = stored.setdefault(wl, {})
-            entry["leaf_size"] = v["leaf_size"]
-            for kernel, tabs in v.items():
-                if isinstance(tabs, dict):
-                    entry.setdefault(kernel, {}).update(
-                        {p: {"setting": x["setting"],
-                             "rule": "cheapest (theta, degree) of the sweep with rel L2 and rel max "
-                                     "<= 1e-6 at 10,000 seeded targets (every orbital)"}
-                         for p, x in tabs.items() if x["setting"]})
-        with open(SETTINGS, "w") as fh:
-            json.dump(stored, fh, indent=1, sort_keys=True)
-        _log(f"sweep: wrote {SETTINGS}")
+        write_settings(res)
+
+
+def write_settings(res):
+    """Merges a sweep's result ({workload: {"leaf_size", kernel: {precision:
+    {"setting", "table"}}}}) into workloads/settings.json: the chosen setting,
+    the rule that chose it and the whole measured table, per kernel and
+    precision."""
+    stored = {}
+    if os.path.exists(SETTINGS):
+        with open(SETTINGS) as fh:
+            stored = json.load(fh)
+    for wl, v in res.items():
+        entry = stored.setdefault(wl, {})
+        entry["leaf_size"] = v["leaf_size"]
+        for kernel, tabs in v.items():
+            if isinstance(tabs, dict):
+                entry.setdefault(kernel, {}).update(
+                    {p: {"setting": x["setting"],
+                         "rule": "cheapest (theta, degree) of the sweep by convolve_ms (upward + "
+                                 "interaction + combine, HIP events) with rel L2 and rel max "
+                                 "<= 1e-6 at 10,000 seeded targets (every orbital)",
+                         "table": x["table"]}
+                     for p, x in tabs.items() if x["setting"]})
+    with open(SETTINGS, "w") as fh:
+        json.dump(stored, fh, indent=1, sort_keys=True)
+    _log(f"sweep: wrote {SETTINGS}")
 
 
 # ---------------------------------------------------------------------------
@@ -845,7 +836,21 @@ def main():
     if "batched_fp64" in results:
         rec = results["batched_fp64"]["_rec"]
         up_ms = rec["timing"]["upward_ms"]
-        upward = {"ms_per_step": up_ms}
+        # Algorithmic work of the proxy charges (Eq. particle-cluster-approx-
+        # rearranged) per (source, approximable cluster) pair: the barycentric basis
+        # in three dimensions (difference, divide, sum, normalise: 4 flops per
+        # node), the (n+1)^2 products L_k1 L_k2 and their product with each charge
+        # set, and one multiply-add per coefficient and set; bytes: the source's
+        # coordinates and charges read once per cluster it belongs to, the charges
+        # written once per cluster.
+        p1, sets = rec["degree"] + 1, case["n_orb"] + 1
+        up_flops = rec["upward_points"] * (12 * p1 + p1 * p1 * (1 + sets) + 2 * sets * p1 ** 3)
+        up_bytes = rec["upward_points"] * 8 * (3 + sets) + rec["n_approx"] * 8 * sets * p1 ** 3
+        upward = {"ms_per_step": up_ms, "degree": rec["degree"], "charge_sets": sets,
+                  "source_cluster_pairs": rec["upward_points"],
+                  "tflops": up_flops / (up_ms / 1e3) / 1e12,
+                  "frac_fp64": up_flops / (up_ms / 1e3) / 1e12 / VECTOR_PEAK_TFLOPS,
+                  "algorithmic_gbs": up_bytes / (up_ms / 1e3) / 1e9}
         if kv and "upward_traffic_bytes" in kv:
             b = float(kv["upward_traffic_bytes"])
             upward.update({"hbm_bytes_counter": b, "gbs": b / (up_ms / 1e3) / 1e9,

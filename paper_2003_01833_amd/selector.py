@@ -143,6 +143,16 @@ def slater_field(r: np.ndarray, seed: int, terms: int = 3):
     return f
 
 
+def centred_field(x, y, z, centres, seed: int):
+    """A Slater mixture (slater_field) about each centre, seed + 97 c for centre c,
+    summed: a multi-centre orbital-like function."""
+    f = np.zeros_like(x)
+    for c, (cx, cy, cz) in enumerate(centres):
+        r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)
+        f += slater_field(r, seed + 97 * c)
+    return f
+
+
 def make_samples(tagi, torch, seeds=(1, 2, 3, 4, 5), kappas_per_seed: int = 4,
                  pairs: int = 50000, theta_max: float = 0.9, leaf: int = 2000, mesh=None,
                  coulomb: bool = True, log=print):

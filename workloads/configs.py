@@ -63,6 +63,28 @@ def atom_mesh(Z: float = 4.0, tol_m: float = 3e-11, p: int = 7, uniform_levels: 
                 kappa=float(np.sqrt(0.4)), mesh=mesh, Z=Z)
 
 
+def diatomic_mesh(Z: float = 4.0, half_sep: float = 1.5, tol_m: float = 1e-10, p: int = 7,
+                  uniform_levels: int = 3, domain=DOMAIN):
+    """Two Be-like nuclei (charge Z) at (+-half_sep, 0, 0) in [-20, 20]^3, p = 7
+    Fejer cells, three uniform levels then refinement on the sum of their
+    hydrogenic 1s densities with tol_m, atoms moved onto cell vertices. A small
+    multi-centre mesh (about 1.3M points at the defaults) apart from the
+    single-atom and benzene workloads."""
+    centres = [(-half_sep, 0.0, 0.0), (half_sep, 0.0, 0.0)]
+
+    def rho(x, y, z):
+        out = np.zeros_like(x)
+        for cx, cy, cz in centres:
+            r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)
+            out += Z ** 3 / np.pi * np.exp(-2.0 * Z * r)
+        return out
+
+    mesh = refine_mesh(rho, domain[0], domain[1], p, tol_m, uniform_levels=uniform_levels,
+                       atoms=centres)
+    x, y, z, w = mesh.points()
+    return dict(x=x, y=y, z=z, w=w, mesh=mesh, centres=centres)
+
+
 BENZENE_C = [(-0.682781, 2.548170, 0.0), (0.682781, -2.548170, 0.0),
              (2.548230, -0.682767, 0.0), (-2.548230, 0.682767, 0.0),
              (1.86544, 1.86541, 0.0), (-1.86544, -1.86541, 0.0)]
