@@ -25,14 +25,17 @@ headline (`value`, `ms_per_step`) is the fastest variant that meets the bar,
 timed again over exactly --steps steps after --warmup steps. `value` counts its
 batch-cluster kernel evaluations (far + near, all orbitals) per second.
 
-`roofline` is the batched FP64 interaction kernel (one launch per step, blocks
-of 8 orbitals) against the FP64 vector peak, with algorithmic flops counted per
-evaluation (geometry once per orbital block, kernel value and accumulation per
-orbital); `roofline_mixed` the mixed-precision launch against the same 78.6
-TFLOP/s (non-packed FP32 issues at the FP64 vector rate; packed FP32 is not
-used); `roofline_headline` the headline variant's launches. HBM traffic comes
-from the FETCH_SIZE / WRITE_SIZE profile committed under profiles/ while the
-kernel sources match the profiled ones.
+`roofline` is the headline variant's interaction kernel against the vector
+peak (78.6 TFLOP/s: FP64, and non-packed FP32, which issues at the same rate;
+packed FP32 is not used), with algorithmic flops counted per evaluation
+(geometry once per orbital block, kernel value and accumulation per orbital)
+over the launches' own durations (HIP events on each launch's stream; the
+learned variant's per-degree launches overlap on several streams, so their
+summed durations exceed the phase's wall time). `roofline_fp64` and
+`roofline_mixed` are the fixed-MAC batched launches (one per step, blocks of 8
+and 4 orbitals). HBM traffic comes from the FETCH_SIZE / WRITE_SIZE profile
+committed under profiles/ while the kernel sources, settings and selector
+weights match the profiled ones.
 
 Extras (unless --no-extras): the Be-like atom step (C2: Yukawa and Hartree
 convolutions on one tree), Lagrange against Hermite interpolation on the atom,
@@ -137,6 +140,16 @@ def profile_values(workload: str, want_key: str):
     if kv.get("workload") != want_key or kv.get("source_sha256") != kernel_source_digest():
         return {}
     return kv
+
+
+def benzene_profile_key(bz, sel) -> str:
+    """The settings a benzene counter profile was taken at: both fixed-MAC
+    settings, the leaf size and the selector's budget factor and weights."""
+    w = os.path.join(ROOT, "paper_2003_01833_amd", "selector_weights.npz")
+    sw = hashlib.sha256(open(w, "rb").read()).hexdigest()[:12] if os.path.exists(w) else "none"
+    eta = sel.eta("yukawa_ss") if sel is not None else None
+    return (f"benzene_mesh_21_orbitals leaf {bz.leaf} fp64 theta {bz.fp64[0]} degree {bz.fp64[1]} "
+            f"mixed theta {bz.mixed[0]} degree {bz.mixed[1]} learned eta {eta} selector {sw}")
 
 
 def eval_flops(kernel, precision, far_inter, near_inter, n_orb, ob):
@@ -319,15 +332,17 @@ def time_steps(torch, fn, n):
 
 
 def roofline_of(rec, launches_key="interact_launches"):
+    """Algorithmic flops of a step's interaction launches over their summed
+    durations (each launch timed on its own stream)."""
     tm = rec["timing"]
     launches = max(int(tm[launches_key]), 1)
-    s = tm["interact_ms"] / 1e3
-    achieved = rec["flops"] / s / 1e12
+    kms = tm.get("interact_kernel_ms") or tm["interact_ms"]
+    achieved = rec["flops"] / (kms / 1e3) / 1e12
     return {"bound": "alu", "kernel": "k_interact", "achieved": achieved,
             "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / VECTOR_PEAK_TFLOPS,
             "traffic": None, "traffic_unit": "bytes per launch", "launches_per_step": launches,
-            "avg_launch_ms": tm["interact_ms"] / launches, "precision": rec["precision"],
-            "orbital_block": rec["ob"]}
+            "avg_launch_ms": kms / launches, "interact_phase_ms": tm["interact_ms"],
+            "precision": rec["precision"], "orbital_block": rec["ob"]}
 
 
 # ---------------------------------------------------------------------------
@@ -827,11 +842,13 @@ def main():
     roof = comparison.get("batched_fp64", {}).get("roofline")
     roof_mixed = comparison.get("batched_mixed", {}).get("roofline")
     roof_head = roofline_of(recs[-1])
-    key = f"benzene_mesh_21_orbitals batched fp64 theta {bz.fp64[0]} degree {bz.fp64[1]} " \
-          f"leaf {bz.leaf}"
-    kv = profile_values("benzene", key)
-    if roof is not None and kv:
-        roof["traffic"] = float(kv["fp64_traffic_bytes_per_launch"])
+    kv = profile_values("benzene", benzene_profile_key(bz, sel))
+    traffic_keys = {"batched_fp64": "fp64_traffic_bytes_per_launch",
+                    "batched_mixed": "mixed_traffic_bytes_per_launch",
+                    "batched_mixed_learned": "learned_mixed_traffic_bytes_per_launch"}
+    for name, r in (("batched_fp64", roof), ("batched_mixed", roof_mixed), (head, roof_head)):
+        if r is not None and kv and traffic_keys.get(name) in kv:
+            r["traffic"] = float(kv[traffic_keys[name]])
     upward = None
     if "batched_fp64" in results:
         rec = results["batched_fp64"]["_rec"]
@@ -879,9 +896,9 @@ def main():
                    "accuracy_samples": int(case["idx_h"].size)},
         "accuracy_vs_direct": {k: head_err[k] for k in ("rel_l2_max_over_orbitals",
                                                           "rel_max_max_over_orbitals")},
-        "roofline": roof,
+        "roofline": dict(roof_head, variant=head),
+        "roofline_fp64": roof,
         "roofline_mixed": roof_mixed,
-        "roofline_headline": roof_head,
         "upward": upward,
         "cpu_baseline": cpu,
         "direct_equivalent_pairs_per_s": case["n"] ** 2 * case["n_orb"] / (ms_per_step / 1e3),

@@ -537,6 +537,11 @@ typedef struct {
   double interact_ms;     /* batch-cluster interaction kernel (far + near fields) */
   double combine_ms;      /* partial-sum reduction, subtraction term, unpermute */
   int64_t interact_launches;
+  double interact_kernel_ms; /* sum of the interaction launches' own durations (events on
+                                each launch's stream around it alone): interact_ms when
+                                they run one after another, more when they overlap (the
+                                learned selection runs its per-degree launches side by
+                                side on several streams) */
 } tagi_timing;
 
 /* Enables (1) or disables (0) phase timing on the tree; enabling resets the sums. */

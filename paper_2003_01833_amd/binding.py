@@ -66,7 +66,8 @@ class Points(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_double), ("upward_ms", ctypes.c_double),
                 ("lists_ms", ctypes.c_double), ("interact_ms", ctypes.c_double),
-                ("combine_ms", ctypes.c_double), ("interact_launches", ctypes.c_int64)]
+                ("combine_ms", ctypes.c_double), ("interact_launches", ctypes.c_int64),
+                ("interact_kernel_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -591,7 +591,7 @@ int tagi_tree_set_timing(tagi_tree* t, int enable) {
 int tagi_tree_timing(tagi_tree* t, tagi_timing* o) {
   g_err[0] = 0;
   REQUIRE(t && o, "tagi_tree_timing: null argument");
-  for (int ph = 0; ph < 4; ++ph) {
+  for (int ph = 0; ph < 5; ++ph) {
     for (auto& e : t->events[ph]) {
       TAGI_HIP(hipEventSynchronize(e.second));
       float ms = 0.f;
@@ -606,6 +606,7 @@ int tagi_tree_timing(tagi_tree* t, tagi_timing* o) {
   o->interact_ms = t->phase_ms[kPhaseInteract];
   o->combine_ms = t->phase_ms[kPhaseCombine];
   o->interact_launches = t->interact_launches;
+  o->interact_kernel_ms = t->phase_ms[kLaunchInteract];
   return TAGI_OK;
 }
 

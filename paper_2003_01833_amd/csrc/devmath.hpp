@@ -50,6 +50,15 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
   return __builtin_fma(y, 0.5 * e, y);
 }
 
+// 2/sqrt(x) for finite x > 0: the same Newton step written as
+// 2 y' = y (3 - x y^2) with h = x y, three operations instead of four; callers
+// that sum many such terms apply the factor 1/2 once to the sums (exact).
+__device__ __forceinline__ double rsqrt_pos_x2(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = x * y;
+  return y * __builtin_fma(-h, y, 3.0);
+}
+
 // 1/sqrt(x) and sqrt(x) for finite x > 0 from the same Newton step: with
 // h = x y, sqrt(x) = x y' = h + h e / 2 (same error bound).
 __device__ __forceinline__ void rsqrt_sqrt(double x, double& rinv, double& r) {
@@ -58,6 +67,16 @@ __device__ __forceinline__ void rsqrt_sqrt(double x, double& rinv, double& r) {
   const double e2 = 0.5 * __builtin_fma(-h, y, 1.0);
   rinv = __builtin_fma(y, e2, y);
   r = __builtin_fma(h, e2, h);
+}
+
+// 2/sqrt(x) and 2 sqrt(x) from the step of rsqrt_pos_x2: e = 3 - h y,
+// 2 y' = y e, 2 sqrt(x) = h e.
+__device__ __forceinline__ void rsqrt_sqrt_x2(double x, double& rinv2, double& r2) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = x * y;
+  const double e = __builtin_fma(-h, y, 3.0);
+  rinv2 = y * e;
+  r2 = h * e;
 }
 
 }  // namespace tagi

@@ -203,6 +203,7 @@ int convolve(tagi_tree* t, tagi_tree* bt, const double* tfs, int kernel, const d
   A.tn = bt->n;
   if (bt->n_items > 0) {
     phase_begin(t, kPhaseInteract, s);
+    phase_begin(t, kLaunchInteract, s);
     ++t->interact_launches;
     if (t->px.herm) {
       switch (kernel) {
@@ -219,6 +220,7 @@ int convolve(tagi_tree* t, tagi_tree* bt, const double* tfs, int kernel, const d
         default: launch_interact_ob<TAGI_COULOMB>(ob, t, mix, A, orb, s); break;
       }
     }
+    phase_end(t, kLaunchInteract, s);
     phase_end(t, kPhaseInteract, s);
     TAGI_HIP(hipGetLastError());
   }

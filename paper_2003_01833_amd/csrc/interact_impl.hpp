@@ -48,13 +48,18 @@ struct Chunk {
 };
 
 // 1/d and, for the Yukawa kernels, d from the squared distance r2; with MASK,
-// both are 0 for a coincident pair (r2 = 0), which then adds nothing.
-template <int KER, bool MASK>
+// both are 0 for a coincident pair (r2 = 0), which then adds nothing. With X2
+// both come out doubled (2/d, 2d; one operation fewer per pair): callers then
+// pass the Yukawa decay constants halved and halve their sums once at the end.
+template <int KER, bool MASK, bool X2 = false>
 __device__ __forceinline__ void inv_dist(double r2, double& rinv, double& r) {
   if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
-    rsqrt_sqrt(r2, rinv, r);
+    if constexpr (X2)
+      rsqrt_sqrt_x2(r2, rinv, r);
+    else
+      rsqrt_sqrt(r2, rinv, r);
   } else {
-    rinv = rsqrt_pos(r2);
+    rinv = X2 ? rsqrt_pos_x2(r2) : rsqrt_pos(r2);
     r = 0.0;
   }
   if constexpr (MASK) {
@@ -97,7 +102,8 @@ constexpr int kRowStep = 24 / (OB + 1) > 2 ? 24 / (OB + 1) : 2;
 
 // Far pairs of one cluster: proxy points s_k on the tensor grid px x py x pz
 // (NP1 = degree + 1 points per dimension; NP1 == 0 means a run-time degree).
-template <int KER, int OB, int NP1>
+// X2 as for inv_dist: the sums come out doubled.
+template <int KER, int OB, int NP1, bool X2 = false>
 __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int np1_rt,
                                             const double* __restrict__ px,
                                             const double* __restrict__ wk,
@@ -109,7 +115,9 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
   if constexpr (KER == TAGI_COULOMB_SS && NP1 > 0) {
     // The Gaussian of K2 separates over the tensor grid,
     //   exp(-d^2/a^2) = exp(-dx^2/a^2) exp(-dy^2/a^2) exp(-dz^2/a^2),
-    // so the cluster needs 3 (n+1) exponentials per target instead of (n+1)^3.
+    // so the cluster needs 3 (n+1) exponentials per target instead of (n+1)^3;
+    // along a grid row (fixed x and y) the sum of exp(-dz^2/a^2) w^_k / d is
+    // formed first and multiplied by the row's exp(-dx^2/a^2) exp(-dy^2/a^2) once.
     double dz[NP1], gz[NP1], gy[NP1];
 #pragma unroll
     for (int k3 = 0; k3 < NP1; ++k3) {
@@ -130,19 +138,20 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
       for (int k2 = 0; k2 < NP1; ++k2) {
         const double dy = yi - py[k2];
         const double dxy = __builtin_fma(dy, dy, dx2);
-        const double gxy = gx * gy[k2];
+        double row = 0.0;
 #pragma unroll
         for (int h = 0; h < NP1; h += kRowStep<OB>) {
 #pragma unroll
           for (int k3 = h; k3 < (h + kRowStep<OB> < NP1 ? h + kRowStep<OB> : NP1); ++k3) {
             const double r2 = __builtin_fma(dz[k3], dz[k3], dxy);
-            const double rinv = rsqrt_pos(r2);
-            a2[0] = __builtin_fma(gxy * gz[k3] * rinv, wk[k + k3], a2[0]);
+            const double rinv = X2 ? rsqrt_pos_x2(r2) : rsqrt_pos(r2);
+            row = __builtin_fma(gz[k3] * wk[k + k3], rinv, row);
 #pragma unroll
             for (int o = 0; o < OB; ++o) a1[o] = __builtin_fma(rinv, qk[o][k + k3], a1[o]);
           }
           if constexpr (kRowStep<OB> < NP1) __builtin_amdgcn_sched_barrier(0);
         }
+        a2[0] = __builtin_fma(gx * gy[k2], row, a2[0]);
         k += NP1;
       }
     }
@@ -166,7 +175,7 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
 #pragma unroll
             for (int o = 0; o < OB; ++o) c[o] = qk[o][k + k3];
             double rinv, r;
-            inv_dist<KER, false>(r2, rinv, r);
+            inv_dist<KER, false, X2>(r2, rinv, r);
             Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k + k3], kl2, al2, a1, a2);
           }
           if constexpr (kRowStep<OB> < NP1) __builtin_amdgcn_sched_barrier(0);
@@ -180,7 +189,7 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
 #pragma unroll
           for (int o = 0; o < OB; ++o) c[o] = qk[o][k];
           double rinv, r;
-          inv_dist<KER, false>(r2, rinv, r);
+          inv_dist<KER, false, X2>(r2, rinv, r);
           Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k], kl2, al2, a1, a2);
         }
       }
@@ -200,7 +209,7 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
 // G c_k is summed in FP32: summing f_i G w^_k separately in FP32 would carry an
 // error of the size of the analytic term 4 pi f_i / k^2, which can exceed u_i by
 // orders of magnitude where f is peaked.
-template <int KER, int OB, int NP1>
+template <int KER, int OB, int NP1, bool X2 = false>
 __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int np1_rt,
                                               const float* __restrict__ px,
                                               const float* __restrict__ wk,
@@ -211,6 +220,7 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
   const int np1 = NP1 ? NP1 : np1_rt;
   const float* py = px + np1;
   const float* pz = py + np1;
+  const double vzero = 0.0 * (double)ox;  // 0 in a vector register (ox is finite)
   float b1[OB], b2[OB];
 #pragma unroll
   for (int o = 0; o < OB; ++o) b1[o] = b2[o] = 0.0f;
@@ -250,8 +260,8 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
     }
 #pragma unroll
     for (int o = 0; o < OB; ++o) {
-      a1[o] += (double)b1[o];
-      a2[o] += (double)b2[o];
+      a1[o] += (X2 ? 2.0 : 1.0) * (double)b1[o];
+      a2[o] += (X2 ? 2.0 : 1.0) * (double)b2[o];
     }
     return;
   }
@@ -269,13 +279,21 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float m = wk[k + k3];
         if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
+          // The charges of a proxy point arrive in scalar registers and one
+          // instruction may read only one of them: for blocks of up to 4
+          // orbitals the shared w^_k is copied to a vector register once (added
+          // to a lane-varying zero), so that each orbital's subtracted charge
+          // q^_k - f_i w^_k takes one multiply-add instead of two vector moves
+          // and one. (For 8 orbitals the copy makes the loop spill scalar
+          // registers; the compiler's moves cost less there.)
+          const double wv = KER == TAGI_YUKAWA_SS && OB <= 4 ? wk64[k + k3] + vzero : wk64[k + k3];
           const float r = r2 * rinv;
 #pragma unroll
           for (int o = 0; o < OB; ++o) {
             const float g = __builtin_amdgcn_exp2f(nkl2[o] * r) * rinv;
             if constexpr (KER == TAGI_YUKAWA_SS) {
-              const float c = (float)__builtin_fma(-fi[o], wk64[k + k3], qk64[o][k + k3]);
-              b1[o] = __builtin_fmaf(g, c, b1[o]);
+              const double c64 = __builtin_fma(-fi[o], wv, qk64[o][k + k3]);
+              b1[o] = __builtin_fmaf(g, (float)c64, b1[o]);
             } else {
               b1[o] = __builtin_fmaf(g, qk[o][k + k3], b1[o]);
             }
@@ -292,15 +310,15 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
   }
 #pragma unroll
   for (int o = 0; o < OB; ++o) {
-    a1[o] += (double)b1[o];
-    a2[o] += (double)b2[o];
+    a1[o] += (X2 ? 2.0 : 1.0) * (double)b1[o];
+    a2[o] += (X2 ? 2.0 : 1.0) * (double)b2[o];
   }
 }
 
 // Near pairs with the particles [j0, j1): coincident points are masked out
 // (MASK), or, where the caller has shown that no source coincides with a target
-// of the wave, summed without the test.
-template <int KER, int OB, bool MASK = true>
+// of the wave, summed without the test. X2 as for inv_dist.
+template <int KER, int OB, bool MASK = true, bool X2 = false>
 __device__ __forceinline__ void near_range(double xi, double yi, double zi, int j0, int j1,
                                            const double* __restrict__ xs,
                                            const double* __restrict__ ys,
@@ -322,7 +340,7 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
       const double dz = zi - zs[j + u];
       const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
       double rinv, r;
-      inv_dist<KER, MASK>(r2, rinv, r);
+      inv_dist<KER, MASK, X2>(r2, rinv, r);
       double c[OB];
 #pragma unroll
       for (int o = 0; o < OB; ++o) c[o] = qr[o][j + u];
@@ -335,7 +353,7 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
     const double dz = zi - zs[j];
     const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
     double rinv, r;
-    inv_dist<KER, MASK>(r2, rinv, r);
+    inv_dist<KER, MASK, X2>(r2, rinv, r);
     double c[OB];
 #pragma unroll
     for (int o = 0; o < OB; ++o) c[o] = qr[o][j];
@@ -571,13 +589,19 @@ void k_interact(InteractArgs A, OrbArg orb) {
   const int i = tb + lane < te ? tb + lane : tb;
   const double xi = A.txs[i], yi = A.tys[i], zi = A.tzs[i];
   const int o0 = item.z * OB;
-  double nkap[OB], kl2[OB];  // -k and -k log2(e) per orbital
+  // The FP64 and mixed forms sum doubled terms (inv_dist's X2: 2/d and 2d, one
+  // operation fewer per pair) and halve the sums at the end; the Yukawa decay
+  // constants they use with 2d are halved to match (kl2x). The Hermite form
+  // takes powers of 1/d and keeps the plain terms.
+  constexpr bool X2 = MODE != kModeHermite;
+  double nkap[OB], kl2[OB], kl2x[OB];  // -k, -k log2(e) and its X2 form per orbital
   int orb_row[OB];
 #pragma unroll
   for (int o = 0; o < OB; ++o) {
     orb_row[o] = min(o0 + o, A.n_orb - 1);
     nkap[o] = -orb.kappa[orb_row[o]];
     kl2[o] = nkap[o] * kLog2e;
+    kl2x[o] = X2 ? 0.5 * kl2[o] : kl2[o];
   }
   const double nia2 = -A.ia2;
   const double al2 = nia2 * kLog2e;
@@ -613,7 +637,7 @@ void k_interact(InteractArgs A, OrbArg orb) {
         const float ox = (float)(xi - A.geom[C * 4 + 0]);
         const float oy = (float)(yi - A.geom[C * 4 + 1]);
         const float oz = (float)(zi - A.geom[C * 4 + 2]);
-        far_cluster32<KER, OB, NP1>(ox, oy, oz, np1, A.pnodes32 + (int64_t)slot * 3 * np1,
+        far_cluster32<KER, OB, NP1, X2>(ox, oy, oz, np1, A.pnodes32 + (int64_t)slot * 3 * np1,
                                     A.what32 + (int64_t)slot * K, qk, nkl2,
                                     (float)al2, A.what + (int64_t)slot * K, qk64,
                                     fi, a1, a2);
@@ -631,11 +655,12 @@ void k_interact(InteractArgs A, OrbArg orb) {
             // only the 1/d part where the Gaussian is negligible (not for blocks of
             // 8 orbitals: the second far loop makes their near loop spill)
             if (gauss_negligible(A, B, C))
-              far_cluster<TAGI_COULOMB, OB, NP1>(xi, yi, zi, np1, pn, wk, qk, kl2, al2, a1, a2);
+              far_cluster<TAGI_COULOMB, OB, NP1, X2>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2, a1,
+                                                     a2);
             else
-              far_cluster<KER, OB, NP1>(xi, yi, zi, np1, pn, wk, qk, kl2, al2, a1, a2);
+              far_cluster<KER, OB, NP1, X2>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2, a1, a2);
           } else {
-            far_cluster<KER, OB, NP1>(xi, yi, zi, np1, pn, wk, qk, kl2, al2, a1, a2);
+            far_cluster<KER, OB, NP1, X2>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2, a1, a2);
           }
         }
       }
@@ -650,8 +675,8 @@ void k_interact(InteractArgs A, OrbArg orb) {
         // only the 1/d part where the Gaussian is negligible (such a cluster
         // cannot hold a target either)
         if (gauss_negligible(A, B, C)) {
-          near_range<TAGI_COULOMB, OB, false>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys,
-                                              A.zs, A.ws, qr, kl2, al2, a1, a2);
+          near_range<TAGI_COULOMB, OB, false, X2>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys,
+                                                  A.zs, A.ws, qr, kl2x, al2, a1, a2);
           continue;
         }
       }
@@ -665,18 +690,19 @@ void k_interact(InteractArgs A, OrbArg orb) {
                  zi <= bx[5];
       }
       if (__builtin_amdgcn_ballot_w64(inside))
-        near_range<KER, OB, true>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws, qr,
-                                  kl2, al2, a1, a2);
+        near_range<KER, OB, true, X2>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws,
+                                      qr, kl2x, al2, a1, a2);
       else
-        near_range<KER, OB, false>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws,
-                                   qr, kl2, al2, a1, a2);
+        near_range<KER, OB, false, X2>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws,
+                                       qr, kl2x, al2, a1, a2);
     }
   }
   double* out = A.partial + (int64_t)it * OB * 2 * kWave;
+  constexpr double kScale = X2 ? 0.5 : 1.0;
 #pragma unroll
   for (int o = 0; o < OB; ++o) {
-    out[(o * 2 + 0) * kWave + lane] = a1[o];
-    out[(o * 2 + 1) * kWave + lane] = KER == TAGI_COULOMB_SS ? a2[0] : a2[o];
+    out[(o * 2 + 0) * kWave + lane] = kScale * a1[o];
+    out[(o * 2 + 1) * kWave + lane] = kScale * (KER == TAGI_COULOMB_SS ? a2[0] : a2[o]);
   }
 }
 

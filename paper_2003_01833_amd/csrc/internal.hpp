@@ -256,8 +256,9 @@ struct tagi_tree {
   // phase timing (HIP events on the calls' stream)
   bool timing = false;
   double build_ms = 0.0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events[4];  // upward, lists, interact, combine
-  double phase_ms[4] = {0, 0, 0, 0};
+  // upward, lists, interact, combine, and each interaction launch on its own stream
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events[5];
+  double phase_ms[5] = {0, 0, 0, 0, 0};
   int64_t interact_launches = 0;
 };
 
@@ -288,7 +289,13 @@ inline bool lists_current(const tagi_tree* t, double theta, int degree) {
   return lists_current(t, t, theta, degree);
 }
 
-enum Phase { kPhaseUpward = 0, kPhaseLists = 1, kPhaseInteract = 2, kPhaseCombine = 3 };
+enum Phase {
+  kPhaseUpward = 0,
+  kPhaseLists = 1,
+  kPhaseInteract = 2,
+  kPhaseCombine = 3,
+  kLaunchInteract = 4  // one interaction launch, on the stream it runs on
+};
 
 inline void phase_begin(tagi_tree* t, int ph, hipStream_t s) {
   if (!t->timing) return;

@@ -639,12 +639,14 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
     }
     A.ia2 = kernel == TAGI_COULOMB_SS ? 1.0 / (alpha * alpha) : 0.0;
     ++t->interact_launches;
+    phase_begin(t, kLaunchInteract, ls);
     switch (kernel) {
       case TAGI_YUKAWA_SS: launch_interact_ob<TAGI_YUKAWA_SS>(ob, t, mix, A, orb, ls); break;
       case TAGI_COULOMB_SS: launch_interact_ob<TAGI_COULOMB_SS>(ob, t, mix, A, orb, ls); break;
       case TAGI_YUKAWA: launch_interact_ob<TAGI_YUKAWA>(ob, t, mix, A, orb, ls); break;
       default: launch_interact_ob<TAGI_COULOMB>(ob, t, mix, A, orb, ls); break;
     }
+    phase_end(t, kLaunchInteract, ls);
     TAGI_HIP(hipGetLastError());
   }
   for (int k = 0; k < LearnedState::kStreams; ++k) {
