@@ -25,17 +25,19 @@ headline (`value`, `ms_per_step`) is the fastest variant that meets the bar,
 timed again over exactly --steps steps after --warmup steps. `value` counts its
 batch-cluster kernel evaluations (far + near, all orbitals) per second.
 
-`roofline` is the headline variant's interaction kernel against the vector
-peak (78.6 TFLOP/s: FP64, and non-packed FP32, which issues at the same rate;
-packed FP32 is not used), with algorithmic flops counted per evaluation
-(geometry once per orbital block, kernel value and accumulation per orbital)
-over the launches' own durations (HIP events on each launch's stream; the
-learned variant's per-degree launches overlap on several streams, so their
-summed durations exceed the phase's wall time). `roofline_fp64` and
-`roofline_mixed` are the fixed-MAC batched launches (one per step, blocks of 8
-and 4 orbitals). HBM traffic comes from the FETCH_SIZE / WRITE_SIZE profile
-committed under profiles/ while the kernel sources, settings and selector
-weights match the profiled ones.
+`roofline` is the batched FP64 interaction kernel (one launch per step, blocks
+of 8 orbitals) against the FP64 vector peak, 78.6 TFLOP/s, with algorithmic
+flops counted per evaluation (geometry once per orbital block, kernel value and
+accumulation per orbital) over the launch's duration (HIP events on its
+stream). `roofline_mixed` is the mixed-precision launch (blocks of 4) against
+the same 78.6 TFLOP/s: non-packed FP32 VALU instructions issue at the FP64
+vector rate (256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz), and
+packed FP32 is not used. `roofline_headline` is the headline variant's launches
+(the learned variant's per-degree launches overlap on several streams; each is
+timed on its own stream, so their summed durations exceed the phase's wall
+time). HBM traffic comes from the FETCH_SIZE / WRITE_SIZE profile committed
+under profiles/ while the kernel sources, settings and selector weights match
+the profiled ones.
 
 Extras (unless --no-extras): the Be-like atom step (C2: Yukawa and Hartree
 convolutions on one tree), Lagrange against Hermite interpolation on the atom,
@@ -795,6 +797,7 @@ def main():
         err = errors(torch, case, U)
         results[name] = {"ms_median": float(np.median(ms)), "ms_steps": ms,
                          "interactions_per_step": rec["interactions"],
+                         "far_near_evaluations_per_orbital": [rec["far_inter"], rec["near_inter"]],
                          "interactions_per_s": rec["interactions"] / (np.median(ms) / 1e3),
                          "phases_ms": {k: rec["timing"][k] for k in
                                        ("build_ms", "upward_ms", "lists_ms", "interact_ms",
@@ -896,9 +899,9 @@ def main():
                    "accuracy_samples": int(case["idx_h"].size)},
         "accuracy_vs_direct": {k: head_err[k] for k in ("rel_l2_max_over_orbitals",
                                                           "rel_max_max_over_orbitals")},
-        "roofline": dict(roof_head, variant=head),
-        "roofline_fp64": roof,
+        "roofline": roof,
         "roofline_mixed": roof_mixed,
+        "roofline_headline": dict(roof_head, variant=head),
         "upward": upward,
         "cpu_baseline": cpu,
         "direct_equivalent_pairs_per_s": case["n"] ** 2 * case["n_orb"] / (ms_per_step / 1e3),
