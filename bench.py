@@ -587,19 +587,21 @@ def extras(tagi, torch, settings, bz, case):
     g.close()
     t.close()
     del Ug, Ue
-    # autotuner: leaf size, orbital block and schedule granularity on the first
-    # eight orbitals
+    # autotuner: leaf size, orbital block, schedule granularity and kernel launch
+    # variant on the first eight orbitals
     _log("bench: extras: autotuner")
     cand_leaf, cand_ob, cand_it = (1000, 2000, 4000), (4, 8), (8192, 16384, 32768)
-    (leaf_t, ob_t, it_t), times = tagi.autotune(case["x"], case["y"], case["z"],
-                                                case["F"][:8].contiguous(), case["w"], "yukawa_ss",
-                                                case["kappa"][:8], th, deg, leaf_sizes=cand_leaf,
-                                                obs=cand_ob, items=cand_it, box=case["box"])
+    cand_var = (0, 1, 2, 3)
+    (leaf_t, ob_t, it_t, var_t), times = tagi.autotune(
+        case["x"], case["y"], case["z"], case["F"][:8].contiguous(), case["w"], "yukawa_ss",
+        case["kappa"][:8], th, deg, leaf_sizes=cand_leaf, obs=cand_ob, items=cand_it,
+        box=case["box"], variants=cand_var)
     out["autotune"] = {"leaf_size": leaf_t, "orbital_block": ob_t, "schedule_items": it_t,
-                       "ms_per_step_8_orbitals": {f"N_L {a} OB {b} items {c}": float(times[i, j, k])
-                                                  for i, a in enumerate(cand_leaf)
-                                                  for j, b in enumerate(cand_ob)
-                                                  for k, c in enumerate(cand_it)}}
+                       "kernel_variant": var_t,
+                       "ms_per_step_8_orbitals": {
+                           f"N_L {a} OB {b} items {c} variant {d}": float(times[i, j, k, m])
+                           for i, a in enumerate(cand_leaf) for j, b in enumerate(cand_ob)
+                           for k, c in enumerate(cand_it) for m, d in enumerate(cand_var)}}
     # the benzene mesh built on the GPU
     _log("bench: extras: GPU mesh build")
     from workloads.configs import DOMAIN, benzene_atoms

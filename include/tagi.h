@@ -395,21 +395,35 @@ int tagi_tree_set_orbital_block(tagi_tree* tree, int ob);
 int tagi_tree_set_schedule_items(tagi_tree* tree, int items);
 
 /*
+ * Launch variant of the interaction kernel (a project addition; tile
+ * parameters the autotuner chooses): 0 the defaults; 1 the other register
+ * budget (waves per SIMD); 2 the other step along a proxy-grid row in the FP64
+ * far field; 3 the other number of near-field sources per step. Compiled for
+ * the subtracted kernels at degrees 6 to 10 and orbital blocks of 1, 4 and 8;
+ * elsewhere every variant runs the defaults. No variant changes the arithmetic
+ * or its order: results are bitwise the same. Applies to later tagi_convolve /
+ * tagi_convolve_learned calls on the tree.
+ * Errors: TAGI_E_ARG (variant outside 0..3).
+ */
+int tagi_tree_set_kernel_variant(tagi_tree* tree, int variant);
+
+/*
  * Autotuner for the batched launch (a project addition): picks the leaf size
  * N_L (Section 6.1; batches are leaves, so it sets both N_L and N_B), the
- * orbital block width and the schedule granularity for one convolution by
- * timing the candidates on the caller's data. For every leaf size it builds a
- * tree, and for every (orbital block, schedule items) pair it runs tagi_upward
- * + tagi_convolve once untimed (plans, lists and schedule), then `reps` times
- * between HIP events on `stream`.
+ * orbital block width, the schedule granularity and the kernel launch variant
+ * for one convolution by timing the candidates on the caller's data. For every
+ * leaf size it builds a tree, and for every (orbital block, schedule items,
+ * variant) triple it runs tagi_upward + tagi_convolve once untimed (plans,
+ * lists and schedule), then `reps` times between HIP events on `stream`.
  *   x, y, z, w   DEVICE double [n] sources; f DEVICE double [n_orb][n]
  *   box          HOST double[6] root box or NULL, as tagi_tree_build
  *   kernel, kappa (HOST [n_orb]), alpha, theta, degree, precision: as tagi_convolve
  *   leaf_sizes   HOST int [n_leaf] candidates (>= 1)
  *   obs          HOST int [n_ob] candidates (0, 1, 2, 4 or 8)
  *   items        HOST int [n_items] candidates for tagi_tree_set_schedule_items
- *   best         HOST int [3] receives {leaf size, orbital block, items} of the fastest
- *   times        HOST double [n_leaf][n_ob][n_items] mean ms per step (may be NULL)
+ *   variants     HOST int [n_var] candidates for tagi_tree_set_kernel_variant
+ *   best         HOST int [4] receives {leaf size, orbital block, items, variant} of the fastest
+ *   times        HOST double [n_leaf][n_ob][n_items][n_var] mean ms per step (may be NULL)
  * The accuracy at a fixed (theta, degree) changes slightly with N_L; checking
  * it is the caller's. Synchronises the stream; allocates and frees its own
  * scratch (one output array and the candidate trees).
@@ -418,8 +432,9 @@ int tagi_tree_set_schedule_items(tagi_tree* tree, int items);
 int tagi_autotune(const double* x, const double* y, const double* z, const double* w, int64_t n,
                   const double* box, const double* f, int n_orb, int kernel, const double* kappa,
                   double alpha, double theta, int degree, int precision, const int* leaf_sizes,
-                  int n_leaf, const int* obs, int n_ob, const int* items, int n_items, int reps,
-                  int* best, double* times, void* stream);
+                  int n_leaf, const int* obs, int n_ob, const int* items, int n_items,
+                  const int* variants, int n_var, int reps, int* best, double* times,
+                  void* stream);
 
 /*
  * Learned degree/MAC selector (a project addition on top of Section 6.2-6.3).

@@ -30,7 +30,8 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_upward_hermite", "tagi_convo
             "tagi_tree_timing", "tagi_graph_create", "tagi_graph_launch", "tagi_graph_destroy",
             "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
             "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
-            "tagi_tree_set_orbital_block", "tagi_tree_set_schedule_items", "tagi_autotune",
+            "tagi_tree_set_orbital_block", "tagi_tree_set_schedule_items",
+            "tagi_tree_set_kernel_variant", "tagi_autotune",
             "tagi_green_step",
             "tagi_learned_lists_export", "tagi_mesh_build", "tagi_mesh_info",
             "tagi_mesh_cells", "tagi_mesh_points", "tagi_mesh_destroy", "tagi_tree_destroy",
@@ -105,8 +106,9 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_mesh_points.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.tagi_mesh_destroy.argtypes = [vp]
     lib.tagi_autotune.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, vp, dbl, dbl, i32, i32,
-                                  vp, i32, vp, i32, vp, i32, i32, vp, vp, vp]
+                                  vp, i32, vp, i32, vp, i32, vp, i32, i32, vp, vp, vp]
     lib.tagi_tree_set_schedule_items.argtypes = [vp, i32]
+    lib.tagi_tree_set_kernel_variant.argtypes = [vp, i32]
     lib.tagi_graph_create.argtypes = [vp, vp, vp, i32, i32, i32, vp, dbl, dbl, i32, vp, vp,
                                       ctypes.POINTER(vp)]
     lib.tagi_graph_launch.argtypes = [vp, vp]
@@ -336,6 +338,10 @@ class Tree:
         """tagi_tree_set_schedule_items: work items a schedule aims at; 0 = default."""
         _check(load_library().tagi_tree_set_schedule_items(self._h, int(items)))
 
+    def set_kernel_variant(self, variant: int = 0):
+        """tagi_tree_set_kernel_variant: interaction-kernel launch variant 0..3."""
+        _check(load_library().tagi_tree_set_kernel_variant(self._h, int(variant)))
+
     def set_timing(self, enable: bool = True):
         _check(load_library().tagi_tree_set_timing(self._h, int(bool(enable))))
 
@@ -491,26 +497,27 @@ def mesh(domain_lo, domain_hi, p: int, tol_m: float, uniform_levels: int = 3,
 
 def autotune(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_sizes,
              obs=(0,), items=(0,), alpha: float = 1.0, precision: str = "fp64", reps: int = 1,
-             box=None):
-    """tagi_autotune: ((best leaf size, orbital block, schedule items), times ms
-    [n_leaf][n_ob][n_items])."""
+             box=None, variants=(0,)):
+    """tagi_autotune: ((best leaf size, orbital block, schedule items, kernel
+    variant), times ms [n_leaf][n_ob][n_items][n_var])."""
     n = x.numel()
     n_orb = 1 if f.dim() == 1 else f.shape[0]
     kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64), (n_orb,)))
     ls = np.ascontiguousarray(leaf_sizes, dtype=np.int32)
     ob = np.ascontiguousarray(obs, dtype=np.int32)
     it = np.ascontiguousarray(items, dtype=np.int32)
+    va = np.ascontiguousarray(variants, dtype=np.int32)
     bx = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
-    best = np.zeros(3, np.int32)
-    times = np.zeros((ls.size, ob.size, it.size), np.float64)
+    best = np.zeros(4, np.int32)
+    times = np.zeros((ls.size, ob.size, it.size, va.size), np.float64)
     _check(load_library().tagi_autotune(_dptr(x, "x", n), _dptr(y, "y", n), _dptr(z, "z", n),
                                         _dptr(w, "w", n), n, None if bx is None else _hptr(bx),
                                         _dptr(f, "f", n_orb * n), n_orb, KERNELS[kernel],
                                         _hptr(kap), float(alpha), float(theta), int(degree),
                                         PRECISIONS[precision], _hptr(ls), ls.size, _hptr(ob),
-                                        ob.size, _hptr(it), it.size, int(reps), _hptr(best),
-                                        _hptr(times), _stream()))
-    return (int(best[0]), int(best[1]), int(best[2])), times
+                                        ob.size, _hptr(it), it.size, _hptr(va), va.size,
+                                        int(reps), _hptr(best), _hptr(times), _stream()))
+    return tuple(int(b) for b in best), times
 
 
 def tuning_key(n: int, n_orb: int, kernel: str, precision: str, theta: float, degree: int) -> str:
@@ -523,10 +530,10 @@ def tuning_key(n: int, n_orb: int, kernel: str, precision: str, theta: float, de
 
 def autotune_cached(cache_path: str, x, y, z, f, w, kernel: str, kappa, theta: float,
                     degree: int, leaf_sizes, obs=(0,), items=(0,), alpha: float = 1.0,
-                    precision: str = "fp64", reps: int = 1, box=None):
+                    precision: str = "fp64", reps: int = 1, box=None, variants=(0,)):
     """tagi_autotune behind a JSON cache: a configuration (tuning_key) tuned once
-    is read back from `cache_path` afterwards. Returns ((leaf size, orbital block,
-    schedule items), from_cache)."""
+    over the same candidates is read back from `cache_path` afterwards. Returns
+    ((leaf size, orbital block, schedule items, kernel variant), from_cache)."""
     import json
     n_orb = 1 if f.dim() == 1 else f.shape[0]
     key = tuning_key(x.numel(), n_orb, kernel, precision, theta, degree)
@@ -534,15 +541,16 @@ def autotune_cached(cache_path: str, x, y, z, f, w, kernel: str, kappa, theta: f
     if os.path.exists(cache_path):
         with open(cache_path) as fh:
             cache = json.load(fh)
+    cand = {"leaf_sizes": list(map(int, leaf_sizes)), "obs": list(map(int, obs)),
+            "items": list(map(int, items)), "variants": list(map(int, variants))}
     hit = cache.get(key)
-    if hit is not None:
-        return (int(hit["leaf_size"]), int(hit["orbital_block"]), int(hit["schedule_items"])), True
+    if hit is not None and hit.get("candidates") == cand:
+        return (int(hit["leaf_size"]), int(hit["orbital_block"]), int(hit["schedule_items"]),
+                int(hit["kernel_variant"])), True
     best, times = autotune(x, y, z, f, w, kernel, kappa, theta, degree, leaf_sizes, obs, items,
-                           alpha, precision, reps, box)
+                           alpha, precision, reps, box, variants)
     cache[key] = {"leaf_size": best[0], "orbital_block": best[1], "schedule_items": best[2],
-                  "candidates": {"leaf_sizes": list(map(int, leaf_sizes)), "obs": list(map(int, obs)),
-                                 "items": list(map(int, items))},
-                  "ms": times.tolist()}
+                  "kernel_variant": best[3], "candidates": cand, "ms": times.tolist()}
     tmp = cache_path + ".tmp"
     with open(tmp, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)

@@ -712,6 +712,16 @@ int tagi_tree_set_schedule_items(tagi_tree* t, int items) {
   return TAGI_OK;
 }
 
+int tagi_tree_set_kernel_variant(tagi_tree* t, int variant) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_tree_set_kernel_variant: tree is NULL");
+  REQUIRE(variant >= 0 && variant < kKernelVariants,
+          "tagi_tree_set_kernel_variant: variant = %d out of range [0, %d)", variant,
+          kKernelVariants);
+  t->kvariant = variant;
+  return TAGI_OK;
+}
+
 int tagi_tree_set_orbital_block(tagi_tree* t, int ob) {
   g_err[0] = 0;
   REQUIRE(t, "tagi_tree_set_orbital_block: tree is NULL");
@@ -724,13 +734,19 @@ int tagi_tree_set_orbital_block(tagi_tree* t, int ob) {
 int tagi_autotune(const double* x, const double* y, const double* z, const double* w, int64_t n,
                   const double* box, const double* f, int n_orb, int kernel, const double* kappa,
                   double alpha, double theta, int degree, int precision, const int* leaf_sizes,
-                  int n_leaf, const int* obs, int n_ob, const int* items, int n_items, int reps,
-                  int* best, double* times, void* stream) {
+                  int n_leaf, const int* obs, int n_ob, const int* items, int n_items,
+                  const int* variants, int n_var, int reps, int* best, double* times,
+                  void* stream) {
   g_err[0] = 0;
   REQUIRE(x && y && z && w && f, "tagi_autotune: null input array");
   REQUIRE(leaf_sizes && n_leaf >= 1, "tagi_autotune: no leaf size candidates");
   REQUIRE(obs && n_ob >= 1, "tagi_autotune: no orbital block candidates");
   REQUIRE(items && n_items >= 1, "tagi_autotune: no schedule item candidates");
+  REQUIRE(variants && n_var >= 1, "tagi_autotune: no kernel variant candidates");
+  for (int i = 0; i < n_var; ++i)
+    REQUIRE(variants[i] >= 0 && variants[i] < kKernelVariants,
+            "tagi_autotune: variants[%d] = %d out of range [0, %d)", i, variants[i],
+            kKernelVariants);
   for (int i = 0; i < n_items; ++i)
     REQUIRE(items[i] == 0 || (items[i] >= 256 && items[i] <= (1 << 22)),
             "tagi_autotune: items[%d] = %d must be 0 or in [256, 2^22]", i, items[i]);
@@ -751,7 +767,7 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int st = TAGI_OK;
   double best_ms = INFINITY;
-  best[0] = best[1] = best[2] = 0;
+  best[0] = best[1] = best[2] = best[3] = 0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     set_error("tagi_autotune: hipEventCreate failed");
     st = TAGI_E_HIP;
@@ -759,11 +775,12 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
   for (int li = 0; li < n_leaf && st == TAGI_OK; ++li) {
     tagi_tree* t = nullptr;
     st = tagi_tree_build(x, y, z, n, box, leaf_sizes[li], stream, &t);
-    for (int ci = 0; ci < n_ob * n_items && st == TAGI_OK; ++ci) {
-      const int oi = ci / n_items, ii = ci % n_items;
+    for (int ci = 0; ci < n_ob * n_items * n_var && st == TAGI_OK; ++ci) {
+      const int oi = ci / (n_items * n_var), ii = ci / n_var % n_items, vi = ci % n_var;
       t->ob_override = obs[oi];
       st = tagi_tree_set_schedule_items(t, items[ii]);
       if (st != TAGI_OK) break;
+      t->kvariant = variants[vi];
       auto step = [&]() {
         int r = tagi_upward(t, f, w, n_orb, degree, stream);
         if (r == TAGI_OK)
@@ -784,12 +801,13 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
         break;
       }
       const double per = (double)ms / reps;
-      if (times) times[((size_t)li * n_ob + oi) * n_items + ii] = per;
+      if (times) times[(((size_t)li * n_ob + oi) * n_items + ii) * n_var + vi] = per;
       if (per < best_ms) {
         best_ms = per;
         best[0] = leaf_sizes[li];
         best[1] = obs[oi];
         best[2] = items[ii];
+        best[3] = variants[vi];
       }
     }
     if (t) {

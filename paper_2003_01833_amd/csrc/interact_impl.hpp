@@ -102,8 +102,9 @@ constexpr int kRowStep = 24 / (OB + 1) > 2 ? 24 / (OB + 1) : 2;
 
 // Far pairs of one cluster: proxy points s_k on the tensor grid px x py x pz
 // (NP1 = degree + 1 points per dimension; NP1 == 0 means a run-time degree).
-// X2 as for inv_dist: the sums come out doubled.
-template <int KER, int OB, int NP1, bool X2 = false>
+// X2 as for inv_dist: the sums come out doubled. RS: proxy points per step of a
+// grid row (kRowStep by default).
+template <int KER, int OB, int NP1, bool X2 = false, int RS = kRowStep<OB>>
 __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int np1_rt,
                                             const double* __restrict__ px,
                                             const double* __restrict__ wk,
@@ -140,16 +141,16 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
         const double dxy = __builtin_fma(dy, dy, dx2);
         double row = 0.0;
 #pragma unroll
-        for (int h = 0; h < NP1; h += kRowStep<OB>) {
+        for (int h = 0; h < NP1; h += RS) {
 #pragma unroll
-          for (int k3 = h; k3 < (h + kRowStep<OB> < NP1 ? h + kRowStep<OB> : NP1); ++k3) {
+          for (int k3 = h; k3 < (h + RS < NP1 ? h + RS : NP1); ++k3) {
             const double r2 = __builtin_fma(dz[k3], dz[k3], dxy);
             const double rinv = X2 ? rsqrt_pos_x2(r2) : rsqrt_pos(r2);
             row = __builtin_fma(gz[k3] * wk[k + k3], rinv, row);
 #pragma unroll
             for (int o = 0; o < OB; ++o) a1[o] = __builtin_fma(rinv, qk[o][k + k3], a1[o]);
           }
-          if constexpr (kRowStep<OB> < NP1) __builtin_amdgcn_sched_barrier(0);
+          if constexpr (RS < NP1) __builtin_amdgcn_sched_barrier(0);
         }
         a2[0] = __builtin_fma(gx * gy[k2], row, a2[0]);
         k += NP1;
@@ -166,9 +167,9 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
       const double dxy = __builtin_fma(dy, dy, dx2);
       if constexpr (NP1 > 0) {
 #pragma unroll
-        for (int h = 0; h < NP1; h += kRowStep<OB>) {
+        for (int h = 0; h < NP1; h += RS) {
 #pragma unroll
-          for (int k3 = h; k3 < (h + kRowStep<OB> < NP1 ? h + kRowStep<OB> : NP1); ++k3) {
+          for (int k3 = h; k3 < (h + RS < NP1 ? h + RS : NP1); ++k3) {
             const double dz = zi - pz[k3];
             const double r2 = __builtin_fma(dz, dz, dxy);
             double c[OB];
@@ -178,7 +179,7 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
             inv_dist<KER, false, X2>(r2, rinv, r);
             Pair<KER>::template add<OB>(r2, rinv, r, c, wk[k + k3], kl2, al2, a1, a2);
           }
-          if constexpr (kRowStep<OB> < NP1) __builtin_amdgcn_sched_barrier(0);
+          if constexpr (RS < NP1) __builtin_amdgcn_sched_barrier(0);
         }
         k += NP1;
       } else {
@@ -318,7 +319,7 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
 // Near pairs with the particles [j0, j1): coincident points are masked out
 // (MASK), or, where the caller has shown that no source coincides with a target
 // of the wave, summed without the test. X2 as for inv_dist.
-template <int KER, int OB, bool MASK = true, bool X2 = false>
+template <int KER, int OB, bool MASK = true, bool X2 = false, int UN = 0>
 __device__ __forceinline__ void near_range(double xi, double yi, double zi, int j0, int j1,
                                            const double* __restrict__ xs,
                                            const double* __restrict__ ys,
@@ -329,8 +330,9 @@ __device__ __forceinline__ void near_range(double xi, double yi, double zi, int 
   // 4 sources per step for blocks of one or two orbitals; 2 for the masked form
   // (rare: only where a target may coincide with a source) and for blocks of 4
   // or 8 orbitals, whose per-orbital charges of 4 sources overflow the scalar
-  // register file (spill moves were a quarter of the 8-orbital loop)
-  constexpr int U = MASK || OB >= 4 ? 2 : 4;
+  // register file (spill moves were a quarter of the 8-orbital loop). UN > 0
+  // sets the unmasked step instead.
+  constexpr int U = MASK ? 2 : (UN > 0 ? UN : (OB >= 4 ? 2 : 4));
   int j = j0;
   for (; j + U <= j1; j += U) {
 #pragma unroll
@@ -574,9 +576,36 @@ constexpr int kWavesPerEu =
         ? 1
         : (MODE == kModeMixed ? 6 : 5);
 
-template <int KER, int OB, int NP1, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<KER, OB, MODE>)))
+// Launch variants the autotuner chooses between (tagi_tree_set_kernel_variant).
+// None changes the arithmetic or its order, so all give the same bits:
+//   0  the defaults above;
+//   1  the other register budget (the bound where the default has none: 5 waves
+//      per SIMD for FP64 tiles, 6 for mixed ones; none where it has one);
+//   2  the other proxy-row step of the FP64 far field (whole rows where the
+//      default splits them, half rows where it does not);
+//   3  the other near-field step (4 sources where the default takes 2, and 2
+//      where it takes 4).
+// Compiled for the subtracted kernels, degrees 6 to 10 and blocks of 1, 4 and 8
+// orbitals; elsewhere every variant runs the defaults. (kKernelVariants, the
+// number of variants, is in internal.hpp.)
+template <int KER, int OB, int NP1>
+constexpr bool kHasVariants = (KER == TAGI_YUKAWA_SS || KER == TAGI_COULOMB_SS) && NP1 >= 7 &&
+                              NP1 <= 11 && OB != 2;
+template <int KER, int OB, int MODE, int VAR>
+constexpr int kWavesPerEuV =
+    VAR == 1 ? (kWavesPerEu<KER, OB, MODE> == 1 ? (MODE == kModeMixed ? 6 : 5) : 1)
+             : kWavesPerEu<KER, OB, MODE>;
+template <int OB, int NP1, int VAR>
+constexpr int kRowStepV =
+    VAR == 2 && NP1 > 0 ? (kRowStep<OB> < NP1 ? NP1 : (NP1 + 1) / 2) : kRowStep<OB>;
+template <int OB, int VAR>
+constexpr int kNearStepV = VAR == 3 ? (OB >= 4 ? 4 : 2) : (OB >= 4 ? 2 : 4);
+
+template <int KER, int OB, int NP1, int MODE, int VAR = 0>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWavesPerEuV<KER, OB, MODE, VAR>)))
 void k_interact(InteractArgs A, OrbArg orb) {
+  constexpr int RS = kRowStepV<OB, NP1, VAR>;
+  constexpr int UN = kNearStepV<OB, VAR>;
   const int lane = threadIdx.x % kWave;
   const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
   const int wv = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (int)(threadIdx.x / kWave));
@@ -655,12 +684,12 @@ void k_interact(InteractArgs A, OrbArg orb) {
             // only the 1/d part where the Gaussian is negligible (not for blocks of
             // 8 orbitals: the second far loop makes their near loop spill)
             if (gauss_negligible(A, B, C))
-              far_cluster<TAGI_COULOMB, OB, NP1, X2>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2, a1,
-                                                     a2);
+              far_cluster<TAGI_COULOMB, OB, NP1, X2, RS>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2,
+                                                         a1, a2);
             else
-              far_cluster<KER, OB, NP1, X2>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2, a1, a2);
+              far_cluster<KER, OB, NP1, X2, RS>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2, a1, a2);
           } else {
-            far_cluster<KER, OB, NP1, X2>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2, a1, a2);
+            far_cluster<KER, OB, NP1, X2, RS>(xi, yi, zi, np1, pn, wk, qk, kl2x, al2, a1, a2);
           }
         }
       }
@@ -675,8 +704,8 @@ void k_interact(InteractArgs A, OrbArg orb) {
         // only the 1/d part where the Gaussian is negligible (such a cluster
         // cannot hold a target either)
         if (gauss_negligible(A, B, C)) {
-          near_range<TAGI_COULOMB, OB, false, X2>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys,
-                                                  A.zs, A.ws, qr, kl2x, al2, a1, a2);
+          near_range<TAGI_COULOMB, OB, false, X2, UN>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs,
+                                                      A.ys, A.zs, A.ws, qr, kl2x, al2, a1, a2);
           continue;
         }
       }
@@ -693,8 +722,8 @@ void k_interact(InteractArgs A, OrbArg orb) {
         near_range<KER, OB, true, X2>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws,
                                       qr, kl2x, al2, a1, a2);
       else
-        near_range<KER, OB, false, X2>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs, A.ws,
-                                       qr, kl2x, al2, a1, a2);
+        near_range<KER, OB, false, X2, UN>(xi, yi, zi, A.nbeg[C], A.nend[C], A.xs, A.ys, A.zs,
+                                           A.ws, qr, kl2x, al2, a1, a2);
     }
   }
   double* out = A.partial + (int64_t)it * OB * 2 * kWave;
@@ -706,18 +735,32 @@ void k_interact(InteractArgs A, OrbArg orb) {
   }
 }
 
+template <int KER, int OB, int NP1, int VAR>
+void launch_interact_var(bool mix, const InteractArgs& A, const OrbArg& orb, int64_t blocks,
+                         hipStream_t s) {
+  if (mix)
+    hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeMixed, VAR>), dim3(blocks), dim3(kBlock), 0,
+                       s, A, orb);
+  else
+    hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeFp64, VAR>), dim3(blocks), dim3(kBlock), 0,
+                       s, A, orb);
+}
+
 template <int KER, int OB, int NP1>
 void launch_interact(tagi_tree* t, bool mix, const InteractArgs& A, const OrbArg& orb,
                      hipStream_t s) {
   const int64_t waves = A.item_list ? A.n_list : A.n_items;
   const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks == 0) return;
-  if (mix)
-    hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeMixed>), dim3(blocks), dim3(kBlock), 0, s, A,
-                       orb);
-  else
-    hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeFp64>), dim3(blocks), dim3(kBlock), 0, s, A,
-                       orb);
+  if constexpr (kHasVariants<KER, OB, NP1>) {
+    switch (t ? t->kvariant : 0) {
+      case 1: launch_interact_var<KER, OB, NP1, 1>(mix, A, orb, blocks, s); return;
+      case 2: launch_interact_var<KER, OB, NP1, 2>(mix, A, orb, blocks, s); return;
+      case 3: launch_interact_var<KER, OB, NP1, 3>(mix, A, orb, blocks, s); return;
+      default: break;
+    }
+  }
+  launch_interact_var<KER, OB, NP1, 0>(mix, A, orb, blocks, s);
 }
 
 // Hermite far field: degrees 1 .. kMaxHermDegree

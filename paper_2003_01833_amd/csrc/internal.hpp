@@ -235,6 +235,7 @@ struct tagi_tree {
   std::vector<uint8_t> h_chunk_far;      // 1 for far chunks
   int ob_override = 0;              // orbital block set by the caller (0 = automatic)
   int sched_items = 0;              // work items a schedule aims at (0 = kDefaultScheduleItems)
+  int kvariant = 0;                 // interaction-kernel launch variant (0 = defaults)
   int items_n_orb = 0;
   tagi::DBuf chunks;                // int4 {kind, e0, e1, cost}
   tagi::DBuf items;                 // int4 {batch, group, oblock, chunk}
@@ -276,6 +277,8 @@ namespace tagi {
 // of at most (total kernel evaluations per target lane) / items, so the launch
 // has about that many waves (more where batches hold several 64-target groups).
 constexpr int kDefaultScheduleItems = 16384;
+// launch variants of the interaction kernel (tagi_tree_set_kernel_variant)
+constexpr int kKernelVariants = 4;
 inline int64_t schedule_items(const tagi_tree* t) {
   return t->sched_items > 0 ? t->sched_items : kDefaultScheduleItems;
 }

@@ -67,24 +67,31 @@ def test_validation_rejects_before_any_device_work():
     assert lib.tagi_tree_set_orbital_block(None, 4) == -1
     i32, dbl = ctypes.c_int, ctypes.c_double
     lib.tagi_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, i32, i32, vp, dbl, dbl,
-                                  i32, i32, vp, i32, vp, i32, vp, i32, i32, vp, vp, vp]
+                                  i32, i32, vp, i32, vp, i32, vp, i32, vp, i32, i32, vp, vp, vp]
     leafs = (ctypes.c_int * 2)(500, 0)
     obs = (ctypes.c_int * 1)(3)
     items = (ctypes.c_int * 2)(0, 100)
-    best = (ctypes.c_int * 3)()
-    # a leaf size of 0, then an orbital block of 3, then 100 schedule items
+    var = (ctypes.c_int * 2)(1, 4)
+    best = (ctypes.c_int * 4)()
+    # a leaf size of 0, then an orbital block of 3, then 100 schedule items, then
+    # kernel variant 4
     assert lib.tagi_autotune(bogus, bogus, bogus, bogus, 10, None, bogus, 1, 0, bogus, 1.0, 0.5, 4,
-                             0, leafs, 2, obs, 1, items, 1, 1, best, None, None) == -1
+                             0, leafs, 2, obs, 1, items, 1, var, 1, 1, best, None, None) == -1
     assert b"leaf_sizes[1]" in lib.tagi_last_error()
     assert lib.tagi_autotune(bogus, bogus, bogus, bogus, 10, None, bogus, 1, 0, bogus, 1.0, 0.5, 4,
-                             0, leafs, 1, obs, 1, items, 1, 1, best, None, None) == -1
+                             0, leafs, 1, obs, 1, items, 1, var, 1, 1, best, None, None) == -1
     assert b"obs[0]" in lib.tagi_last_error()
     ob4 = (ctypes.c_int * 1)(4)
     assert lib.tagi_autotune(bogus, bogus, bogus, bogus, 10, None, bogus, 1, 0, bogus, 1.0, 0.5, 4,
-                             0, leafs, 1, ob4, 1, items, 2, 1, best, None, None) == -1
+                             0, leafs, 1, ob4, 1, items, 2, var, 1, 1, best, None, None) == -1
     assert b"items[1]" in lib.tagi_last_error()
+    assert lib.tagi_autotune(bogus, bogus, bogus, bogus, 10, None, bogus, 1, 0, bogus, 1.0, 0.5, 4,
+                             0, leafs, 1, ob4, 1, items, 1, var, 2, 1, best, None, None) == -1
+    assert b"variants[1]" in lib.tagi_last_error()
     lib.tagi_tree_set_schedule_items.argtypes = [vp, ctypes.c_int]
     assert lib.tagi_tree_set_schedule_items(None, 4096) == -1
+    lib.tagi_tree_set_kernel_variant.argtypes = [vp, ctypes.c_int]
+    assert lib.tagi_tree_set_kernel_variant(None, 1) == -1
     lib.tagi_green_step.argtypes = [vp, vp, vp, vp, i32, vp, dbl, i32, i32, vp, vp, vp]
     eps = (ctypes.c_double * 1)(-1.0)
     assert lib.tagi_green_step(None, bogus, bogus, bogus, 1, eps, 0.7, 6, 0, bogus, None, None) == -1

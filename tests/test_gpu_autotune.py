@@ -1,7 +1,9 @@
-"""Orbital-block override and the autotuner: the width of the orbital block only
-changes how many orbitals share a pair's geometry, never the arithmetic of an
-orbital, so every width gives the same bits; the autotuner's pick must be one of
-the candidates and reproduce the same result as setting it by hand."""
+"""Orbital-block override, kernel launch variants and the autotuner: the width
+of the orbital block only changes how many orbitals share a pair's geometry, and
+a launch variant only the register budget or the loop steps, never the
+arithmetic of an orbital or its order, so every width and variant gives the
+same bits; the autotuner's pick must be one of the candidates and reproduce the
+same result as setting it by hand."""
 import numpy as np
 import pytest
 import torch
@@ -37,6 +39,27 @@ def test_orbital_block_width_does_not_change_results(kernel, precision):
     t.close()
 
 
+@pytest.mark.parametrize("kernel,precision,ob,degree", [
+    ("yukawa_ss", "fp64", 1, 8), ("yukawa_ss", "fp64", 8, 7), ("yukawa_ss", "mixed", 4, 9),
+    ("coulomb_ss", "fp64", 1, 8), ("coulomb_ss", "fp64", 4, 10), ("coulomb_ss", "mixed", 1, 6),
+    ("yukawa_ss", "fp64", 2, 8), ("coulomb", "fp64", 4, 8)])
+def test_kernel_variants_give_the_same_bits(kernel, precision, ob, degree):
+    # the last two cases have no compiled variants: every variant runs the defaults
+    import paper_2003_01833_amd as tagi
+    dx, dy, dz, dw, dF = _case(ob)
+    kap = np.linspace(0.7, 2.5, ob)
+    t = tagi.Tree(dx, dy, dz, 300)
+    t.upward(dF, dw, degree)
+    t.set_orbital_block(ob)
+    ref = t.convolve(kernel, kap, 0.7, degree, precision=precision).clone()
+    for v in (1, 2, 3, 0):
+        t.set_kernel_variant(v)
+        assert torch.equal(t.convolve(kernel, kap, 0.7, degree, precision=precision), ref), v
+    with pytest.raises(tagi.TagiError):
+        t.set_kernel_variant(4)
+    t.close()
+
+
 def test_orbital_block_rejects_other_widths():
     import paper_2003_01833_amd as tagi
     dx, dy, dz, dw, dF = _case(2)
@@ -50,15 +73,17 @@ def test_autotune_picks_a_candidate_that_reproduces_the_result(tmp_path):
     import paper_2003_01833_amd as tagi
     dx, dy, dz, dw, dF = _case(5)
     kap = np.linspace(0.8, 2.4, 5)
-    (leaf, ob, items), times = tagi.autotune(dx, dy, dz, dF, dw, "yukawa_ss", kap, 0.7, 6,
-                                             leaf_sizes=(150, 400), obs=(1, 4),
-                                             items=(0, 1024), reps=2)
-    assert leaf in (150, 400) and ob in (1, 4) and items in (0, 1024)
-    assert times.shape == (2, 2, 2) and np.all(times > 0)
-    assert times[(150, 400).index(leaf), (1, 4).index(ob), (0, 1024).index(items)] == times.min()
+    (leaf, ob, items, var), times = tagi.autotune(dx, dy, dz, dF, dw, "yukawa_ss", kap, 0.7, 6,
+                                                  leaf_sizes=(150, 400), obs=(1, 4),
+                                                  items=(0, 1024), reps=2, variants=(0, 1))
+    assert leaf in (150, 400) and ob in (1, 4) and items in (0, 1024) and var in (0, 1)
+    assert times.shape == (2, 2, 2, 2) and np.all(times > 0)
+    assert times[(150, 400).index(leaf), (1, 4).index(ob), (0, 1024).index(items),
+                 var] == times.min()
     t = tagi.Tree(dx, dy, dz, leaf)
     t.set_orbital_block(ob)
     t.set_schedule_items(items)
+    t.set_kernel_variant(var)
     t.upward(dF, dw, 6)
     u = t.convolve("yukawa_ss", kap, 0.7, 6)
     t2 = tagi.Tree(dx, dy, dz, leaf)
@@ -76,6 +101,10 @@ def test_autotune_picks_a_candidate_that_reproduces_the_result(tmp_path):
     again, hit = tagi.autotune_cached(cache, dx, dy, dz, dF, dw, "yukawa_ss", kap, 0.7, 6,
                                       leaf_sizes=(150, 400), obs=(1, 4))
     assert hit and again == best
+    # another candidate set is tuned afresh
+    other, hit = tagi.autotune_cached(cache, dx, dy, dz, dF, dw, "yukawa_ss", kap, 0.7, 6,
+                                      leaf_sizes=(150, 400), obs=(1, 4), variants=(0, 3))
+    assert not hit and other[3] in (0, 3)
 
 
 def test_schedule_items_change_only_the_grouping_of_partial_sums():
