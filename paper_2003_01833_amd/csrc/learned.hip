@@ -71,58 +71,76 @@ struct LearnArgs {
   int32_t* overflow;   // traversal stack overflow
 };
 
-// network forward for one lane; hA, hB are this block's [64][64] LDS buffers
-// (unit-major, lane-minor), P the parameters in LDS
-__device__ void mlp_forward(const float* P, const float* x, float* hA, float* hB, int lane,
-                            float* out) {
-  const float* W0 = P;
-  const float* b0 = W0 + kH * kIn;
-  const float* W1 = b0 + kH;
-  const float* b1 = W1 + kH * kH;
-  const float* W2 = b1 + kH;
-  const float* b2 = W2 + kH * kH;
-  const float* W3 = b2 + kH;
-  const float* b3 = W3 + kOut * kH;
-  for (int o = 0; o < kH; ++o) {
-    float s = b0[o];
+// Offsets of the layers in the parameter vector: W0 [64][5], b0 [64], W1 [64][64],
+// b1 [64], W2 [64][64], b2 [64], W3 [9][64], b3 [9] (row-major, out x in).
+constexpr int kOffW0 = 0, kOffB0 = kOffW0 + kH * kIn, kOffW1 = kOffB0 + kH;
+constexpr int kOffB1 = kOffW1 + kH * kH, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kOut * kH;
+constexpr int kW3Stride = kH + 1;  // LDS row stride of W3: the 9 rows fall in distinct banks
+
+// The network for one orbital with the wave's 64 lanes as the 64 hidden units:
+// lane j holds row j of W0, W1 and W2 in registers (w0, w1, w2, and the biases
+// bj), each layer's input is read from LDS as a broadcast, and each unit's sum
+// runs over its inputs in order, so every output has the bits of the plain
+// per-unit loop. x: the orbital's normalised features (LDS); hx: three [64] LDS
+// buffers; w3: W3 in LDS with row stride kW3Stride; b3: the output biases;
+// out: the 9 outputs, written to LDS by lanes 0..8.
+__device__ void mlp_units(const float* w0, const float* w1, const float* w2, const float* bj,
+                          const float* x, float* hx, const float* w3, const float* b3, int lane,
+                          float* out) {
+  float s = bj[0];
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) s = __builtin_fmaf(W0[o * kIn + i], x[i], s);
-    hA[o * kWave + lane] = tanhf(s);
-  }
-  for (int o = 0; o < kH; ++o) {
-    float s = b1[o];
-#pragma unroll 16
-    for (int i = 0; i < kH; ++i) s = __builtin_fmaf(W1[o * kH + i], hA[i * kWave + lane], s);
-    hB[o * kWave + lane] = tanhf(s);
-  }
-  for (int o = 0; o < kH; ++o) {
-    float s = b2[o];
-#pragma unroll 16
-    for (int i = 0; i < kH; ++i) s = __builtin_fmaf(W2[o * kH + i], hB[i * kWave + lane], s);
-    hA[o * kWave + lane] = tanhf(s);
-  }
+  for (int i = 0; i < kIn; ++i) s = __builtin_fmaf(w0[i], x[i], s);
+  hx[lane] = tanhf(s);
+  __syncthreads();
+  s = bj[1];
 #pragma unroll
-  for (int k = 0; k < kOut; ++k) {
-    float s = b3[k];
-#pragma unroll 16
-    for (int i = 0; i < kH; ++i) s = __builtin_fmaf(W3[k * kH + i], hA[i * kWave + lane], s);
-    out[k] = s;
+  for (int i = 0; i < kH; ++i) s = __builtin_fmaf(w1[i], hx[i], s);
+  hx[kH + lane] = tanhf(s);
+  __syncthreads();
+  s = bj[2];
+#pragma unroll
+  for (int i = 0; i < kH; ++i) s = __builtin_fmaf(w2[i], hx[kH + i], s);
+  hx[2 * kH + lane] = tanhf(s);
+  __syncthreads();
+  if (lane < kOut) {
+    s = b3[lane];
+    for (int i = 0; i < kH; ++i) s = __builtin_fmaf(w3[lane * kW3Stride + i], hx[2 * kH + i], s);
+    out[lane] = s;
   }
+  __syncthreads();
 }
 
 constexpr int kStack = 512;  // traversal stack entries
 
 // One wave per batch: the ComputePotential traversal is wave-uniform; at a
-// candidate pair lane o evaluates the network for orbital o. Every visited
-// pair's outcome goes to the batch's log in traversal order as (C << 4) | slot
-// (slot 0..8: far at degree 4 + slot, 9: near); entries beyond `cap` are counted
-// but not written.
+// candidate pair lane o forms the features of orbital o, then the wave evaluates
+// the network for each orbital in turn (lanes = hidden units), and lane o picks
+// its orbital's degree. Every visited pair's outcome goes to the batch's log in
+// traversal order as (C << 4) | slot (slot 0..8: far at degree 4 + slot, 9:
+// near); entries beyond `cap` are counted but not written.
 __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
-  __shared__ float sP[kNParam];
-  __shared__ float hbuf[2][kH * kWave];
+  __shared__ float sW3[kOut * kW3Stride + kOut];
+  __shared__ float sx[kMaxOrb * kIn];      // normalised features per orbital
+  __shared__ float spred[kMaxOrb * kOut];  // network outputs per orbital
+  __shared__ float hx[3 * kH];             // layer outputs (broadcast buffers)
   __shared__ int stk[kStack];
-  for (int i = threadIdx.x; i < kNParam; i += blockDim.x) sP[i] = L.params[i];
   const int lane = threadIdx.x;
+  for (int i = lane; i < kOut * kH; i += blockDim.x)
+    sW3[(i / kH) * kW3Stride + i % kH] = L.params[kOffW3 + i];
+  if (lane < kOut) sW3[kOut * kW3Stride + lane] = L.params[kOffB3 + lane];
+  // this lane's hidden unit: its rows of W0, W1, W2 and its biases
+  float w0[kIn], w1[kH], w2[kH], bj[3];
+#pragma unroll
+  for (int i = 0; i < kIn; ++i) w0[i] = L.params[kOffW0 + lane * kIn + i];
+#pragma unroll
+  for (int i = 0; i < kH; ++i) {
+    w1[i] = L.params[kOffW1 + lane * kH + i];
+    w2[i] = L.params[kOffW2 + lane * kH + i];
+  }
+  bj[0] = L.params[kOffB0 + lane];
+  bj[1] = L.params[kOffB1 + lane];
+  bj[2] = L.params[kOffB2 + lane];
   const int b = blockIdx.x;
   const int B = L.leaf_node[b];
   const double rB = L.geom[B * 4 + 3];
@@ -160,6 +178,7 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
     } else {
       bool fb = false;
       int d_o = 0;  // this lane's orbital: lowest acceptable degree, -1 if none
+      float l1_o = 1.0f;
       // weight of the subtracted charges: 1 (Yukawa-SS), the Gaussian at the
       // least batch-cluster distance (Coulomb-SS), 0 (plain kernels)
       float gsub = L.sub_kind == 1 ? 1.0f : 0.0f;
@@ -180,29 +199,34 @@ __global__ __launch_bounds__(64) void k_lists_learned(LearnArgs L) {
                                    gsub * L.fmax[(int64_t)o * L.n_leaves + b] * L.l1w[C],
                                1e-30f);
         raw[4] = logf(l1);
-        float x[kIn];
         for (int k = 0; k < kIn; ++k) {
           if (!(raw[k] >= L.lo[k] && raw[k] <= L.hi[k])) fb = true;
-          x[k] = (raw[k] - L.shift[k]) * L.scale[k];
+          sx[o * kIn + k] = (raw[k] - L.shift[k]) * L.scale[k];
         }
-        if (!fb) {
-          float pred[kOut];
-          mlp_forward(sP, x, hbuf[0], hbuf[1], lane, pred);
+        l1_o = l1;
+      }
+      const bool fallback = __builtin_amdgcn_ballot_w64(fb) != 0;
+      if (!fallback) {
+        __syncthreads();  // the features are in LDS
+        for (int o = 0; o < L.n_orb; ++o)
+          mlp_units(w0, w1, w2, bj, sx + o * kIn, hx, sW3, sW3 + kOut * kW3Stride, lane,
+                    spred + o * kOut);
+        if (lane < L.n_orb) {
+          const int o = lane;
           // the network predicts the error relative to the magnitude scale
           // l1 exp(-c d) / d of the pair, d = R - r_B
           const float dd = (float)fmax(R - rB, 1e-12);
-          const float scl = log10f(l1) - 0.43429448f * L.kap[o] * dd - log10f(dd);
+          const float scl = log10f(l1_o) - 0.43429448f * L.kap[o] * dd - log10f(dd);
           d_o = -1;
           for (int d = kDegMin; d <= kDegMax; ++d) {
             if ((d + 1) * (d + 1) * (d + 1) >= cnt) break;
-            if (pred[d - kDegMin] + scl <= pair_log_tol) {
+            if (spred[o * kOut + d - kDegMin] + scl <= pair_log_tol) {
               d_o = d;
               break;
             }
           }
         }
       }
-      const bool fallback = __builtin_amdgcn_ballot_w64(fb) != 0;
       const bool ok = __builtin_amdgcn_ballot_w64(d_o < 0) == 0;
       int dmax = d_o;
       for (int off = kWave / 2; off > 0; off >>= 1) dmax = max(dmax, __shfl_xor(dmax, off));
