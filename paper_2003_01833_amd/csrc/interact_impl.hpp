@@ -735,12 +735,18 @@ void k_interact(InteractArgs A, OrbArg orb) {
   }
 }
 
+// The mixed Coulomb-SS far field for 8 orbitals at 12 or more proxy points per
+// dimension keeps far more values live than the scalar register file holds
+// (over a thousand spilled scalars); it takes the run-time-degree loop instead.
+template <int KER, int OB, int NP1>
+constexpr int kMixedNP1 = KER == TAGI_COULOMB_SS && OB == 8 && NP1 >= 12 ? 0 : NP1;
+
 template <int KER, int OB, int NP1, int VAR>
 void launch_interact_var(bool mix, const InteractArgs& A, const OrbArg& orb, int64_t blocks,
                          hipStream_t s) {
   if (mix)
-    hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeMixed, VAR>), dim3(blocks), dim3(kBlock), 0,
-                       s, A, orb);
+    hipLaunchKernelGGL((k_interact<KER, OB, kMixedNP1<KER, OB, NP1>, kModeMixed, VAR>),
+                       dim3(blocks), dim3(kBlock), 0, s, A, orb);
   else
     hipLaunchKernelGGL((k_interact<KER, OB, NP1, kModeFp64, VAR>), dim3(blocks), dim3(kBlock), 0,
                        s, A, orb);
@@ -804,6 +810,8 @@ void launch_interact_np(tagi_tree* t, bool mix, const InteractArgs& A, const Orb
     case 9: launch_interact<KER, OB, 9>(t, mix, A, orb, s); break;
     case 10: launch_interact<KER, OB, 10>(t, mix, A, orb, s); break;
     case 11: launch_interact<KER, OB, 11>(t, mix, A, orb, s); break;
+    case 12: launch_interact<KER, OB, 12>(t, mix, A, orb, s); break;
+    case 13: launch_interact<KER, OB, 13>(t, mix, A, orb, s); break;
     default: launch_interact<KER, OB, 0>(t, mix, A, orb, s); break;
   }
 }

@@ -212,8 +212,8 @@ def test_coulomb_ss_narrow_gaussian_matches_oracle(ragged_tree):
 @pytest.mark.parametrize("kernel,n_orb,degree,theta", [
     ("coulomb_ss", 9, 8, 0.8),   # orbital blocks of 8 and a ragged last block; separable Gaussian
     ("yukawa_ss", 5, 9, 0.8),    # blocks of 4 and 1; proxy rows taken in steps
-    ("coulomb_ss", 2, 11, 0.9),  # a degree without a compiled loop (run-time trip counts)
-    ("yukawa", 3, 4, 0.6),
+    ("coulomb_ss", 2, 11, 0.9),  # 12 proxy points per dimension
+    ("yukawa", 3, 3, 0.6),       # a degree without a compiled loop (run-time trip counts)
 ])
 def test_treecode_orbital_blocks_and_degrees(ragged_tree, kernel, n_orb, degree, theta):
     c = ragged_tree
@@ -230,6 +230,33 @@ def test_treecode_orbital_blocks_and_degrees(ragged_tree, kernel, n_orb, degree,
     for o in range(n_orb):
         S = _scale(kernel, c["x"], c["y"], c["z"], F[o], c["w"], kap[o])
         assert np.all(np.abs(u[o] - ref[o]) <= 1e-12 * S), (o, np.max(np.abs(u[o] - ref[o]) / S))
+
+
+@pytest.mark.parametrize("kernel,ob", [("coulomb_ss", 8), ("yukawa_ss", 4)])
+def test_degree_12_matches_oracle(kernel, ob):
+    # degree 12 (13 proxy points per dimension, the highest compiled loop; the
+    # learned selector's top degree) in blocks of `ob` orbitals over 3 orbitals
+    # (a ragged block): FP64 to the 1e-12 S_i bar, and the mixed far field (whose
+    # Coulomb-SS blocks of 8 take the run-time loop at this width) within 1e-6
+    tagi = _tag()
+    x, y, z, _, w = uniform_cube(20000, seed=31)
+    g = SplitMix64(91)
+    F = np.stack([g.uniform(x.size, -1, 1) for _ in range(3)])
+    kap = np.array([0.5, 0.9, 1.3])
+    t = tagi.Tree(*_dev(x, y, z), leaf_size=400)
+    dF, dw = _dev(F, w)
+    t.upward(dF, dw, 12)
+    t.set_orbital_block(ob)
+    u = t.convolve(kernel, kap, 0.9, 12).cpu().numpy()
+    assert t.stats()["n_far_pairs"] > 0
+    um = t.convolve(kernel, kap, 0.9, 12, precision="mixed").cpu().numpy()
+    t.close()
+    ref = bltc.treecode(x, y, z, F, w, kernel, kap, 0.9, 12, 400)
+    for o in range(3):
+        S = _scale(kernel, x, y, z, F[o], w, kap[o])
+        assert np.all(np.abs(u[o] - ref[o]) <= 1e-12 * S), (o, np.max(np.abs(u[o] - ref[o]) / S))
+        assert np.linalg.norm(um[o] - ref[o]) / np.linalg.norm(ref[o]) < 1e-6
+        assert np.abs(um[o] - ref[o]).max() / np.abs(ref[o]).max() < 1e-6
 
 
 def test_theta_zero_equals_direct_and_is_repeatable(ragged_tree):
