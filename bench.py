@@ -289,7 +289,7 @@ class Benzene:
         t.upward(c["F"], c["w"], deg)
         t.convolve("yukawa_ss", c["kappa"], th, deg, precision=precision, out=self.U)
         st = t.stats()
-        ob = 8 if precision == "fp64" else 4
+        ob = 8 if precision == "fp64" else 4  # the automatic block (21 orbitals)
         rec = self._finish(t, precision, (st["far_interactions"], st["near_interactions"]), ob)
         rec["upward_points"], rec["n_approx"], rec["degree"] = (st["upward_points"], st["n_approx"],
                                                                 deg)
@@ -304,7 +304,7 @@ class Benzene:
         t.convolve_learned("yukawa_ss", c["kappa"], self.sel, self.tol, precision=precision,
                            out=self.U)
         ls = t.learned_stats()
-        ob = 8 if precision == "fp64" else 4
+        ob = 8  # the automatic block of the learned launches (21 orbitals)
         rec = self._finish(t, precision, (ls["far_interactions"], ls["near_interactions"]), ob)
         rec["far_pairs_by_degree"] = ls["far_pairs_by_degree"]
         return self.U, rec
@@ -590,8 +590,8 @@ def extras(tagi, torch, settings, bz, case):
     # autotuner: leaf size, orbital block, schedule granularity and kernel launch
     # variant on the first eight orbitals
     _log("bench: extras: autotuner")
-    cand_leaf, cand_ob, cand_it = (1000, 2000, 4000), (4, 8), (8192, 16384, 32768)
-    cand_var = (0, 1, 2, 3)
+    cand_leaf, cand_ob, cand_it = (1000, 2000, 4000), (4, 8), (16384,)
+    cand_var = (0, 1, 3)
     (leaf_t, ob_t, it_t, var_t), times = tagi.autotune(
         case["x"], case["y"], case["z"], case["F"][:8].contiguous(), case["w"], "yukawa_ss",
         case["kappa"][:8], th, deg, leaf_sizes=cand_leaf, obs=cand_ob, items=cand_it,

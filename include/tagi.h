@@ -374,7 +374,8 @@ int tagi_green_step(tagi_tree* tree, const double* psi, const double* veff, cons
  * once for `ob` orbitals. ob = 1, 2, 4 or 8 fixes the width for every later
  * tagi_convolve / tagi_convolve_learned on the tree (the schedule is rebuilt on
  * the next call); ob = 0 restores the automatic choice: the largest power of
- * two not above n_orb, capped at 4 for Yukawa kernels in mixed precision and at
+ * two not above n_orb, capped at 4 for Yukawa kernels in mixed precision
+ * under tagi_convolve (tagi_convolve_learned takes 8 there too) and at
  * 8 otherwise. Results do not depend on ob.
  * Errors: TAGI_E_ARG.
  */

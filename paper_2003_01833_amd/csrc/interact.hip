@@ -277,18 +277,24 @@ int gather_values(const tagi_tree* t, const double* f, int n_orb, double* out, h
   return TAGI_OK;
 }
 
-int orbital_block_of(const tagi_tree* t, int kernel, int precision) {
-  const int ob = t->ob_override ? t->ob_override : orbital_block(kernel, t->n_orb, precision);
+int orbital_block_of(const tagi_tree* t, int kernel, int precision, bool learned) {
+  const int ob =
+      t->ob_override ? t->ob_override : orbital_block(kernel, t->n_orb, precision, learned);
   // the Hermite far field reads 8 charges per proxy point and set: at most 4 orbitals
   return t->px.herm ? std::min(ob, 4) : ob;
 }
 
-int orbital_block(int kernel, int n_orb, int precision) {
+int orbital_block(int kernel, int n_orb, int precision, bool learned) {
   // The widest block that the orbitals fill: a pair's geometry is then shared by
   // more orbitals. Measured on 21 orbitals (benzene): FP64 Yukawa tiles are 9%
-  // faster at 8 than at 4; mixed ones, whose FP32 registers spill at 8, are
-  // fastest at 4.
-  const int cap = (precision == TAGI_MIXED && (kernel == TAGI_YUKAWA_SS || kernel == TAGI_YUKAWA)) ? 4 : 8;
+  // faster at 8 than at 4. The fixed-MAC mixed launch is 6% faster at 4 (at 8
+  // its FP32 tiles hold 4 waves per SIMD instead of 6); the learned lists' mixed
+  // launches are 3% faster at 8, where their separate FP64 near launch gains
+  // from sharing a pair's geometry over more orbitals.
+  const int cap = (precision == TAGI_MIXED && !learned &&
+                   (kernel == TAGI_YUKAWA_SS || kernel == TAGI_YUKAWA))
+                      ? 4
+                      : 8;
   int ob = 1;
   while (ob * 2 <= n_orb && ob * 2 <= cap) ob *= 2;
   return ob;

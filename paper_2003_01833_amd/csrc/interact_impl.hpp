@@ -210,7 +210,13 @@ __device__ __forceinline__ void far_cluster(double xi, double yi, double zi, int
 // G c_k is summed in FP32: summing f_i G w^_k separately in FP32 would carry an
 // error of the size of the analytic term 4 pi f_i / k^2, which can exceed u_i by
 // orders of magnitude where f is peaked.
-template <int KER, int OB, int NP1, bool X2 = false>
+// Proxy points per step of a grid row in the FP32 far field: whole rows for up
+// to 4 orbitals; 2 for 8, whose 9 scalar-loaded doubles per point would
+// otherwise overflow the scalar register file.
+template <int OB>
+constexpr int kRowStep32 = OB >= 8 ? 2 : 16;
+
+template <int KER, int OB, int NP1, bool X2 = false, int RS = kRowStep32<OB>>
 __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int np1_rt,
                                               const float* __restrict__ px,
                                               const float* __restrict__ wk,
@@ -266,6 +272,37 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
     }
     return;
   }
+  // one proxy point k = k0 + k3 of the row whose squared (x, y) offset is dxy
+  auto point = [&](int k0, int k3, float dxy) {
+    const float dz = oz - pz[k3];
+    const float r2 = __builtin_fmaf(dz, dz, dxy);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float m = wk[k0 + k3];
+    if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
+      // The charges of a proxy point arrive in scalar registers and one
+      // instruction may read only one of them: the shared w^_k is copied to a
+      // vector register once (added to a lane-varying zero), so that each
+      // orbital's subtracted charge q^_k - f_i w^_k takes one multiply-add
+      // instead of two vector moves and one.
+      const double wv = KER == TAGI_YUKAWA_SS ? wk64[k0 + k3] + vzero : 0.0;
+      const float r = r2 * rinv;
+#pragma unroll
+      for (int o = 0; o < OB; ++o) {
+        const float g = __builtin_amdgcn_exp2f(nkl2[o] * r) * rinv;
+        if constexpr (KER == TAGI_YUKAWA_SS) {
+          const double c64 = __builtin_fma(-fi[o], wv, qk64[o][k0 + k3]);
+          b1[o] = __builtin_fmaf(g, (float)c64, b1[o]);
+        } else {
+          b1[o] = __builtin_fmaf(g, qk[o][k0 + k3], b1[o]);
+        }
+      }
+    } else {
+      if constexpr (KER == TAGI_COULOMB_SS)
+        b2[0] = __builtin_fmaf(__builtin_amdgcn_exp2f(r2 * nial2) * rinv, m, b2[0]);
+#pragma unroll
+      for (int o = 0; o < OB; ++o) b1[o] = __builtin_fmaf(rinv, qk[o][k0 + k3], b1[o]);
+    }
+  };
   int k = 0;
   for (int k1 = 0; k1 < np1; ++k1) {
     const float dx = ox - px[k1];
@@ -273,38 +310,17 @@ __device__ __forceinline__ void far_cluster32(float ox, float oy, float oz, int 
     for (int k2 = 0; k2 < np1; ++k2) {
       const float dy = oy - py[k2];
       const float dxy = __builtin_fmaf(dy, dy, dx2);
-#pragma unroll(NP1 > 0 ? NP1 : 1)
-      for (int k3 = 0; k3 < np1; ++k3) {
-        const float dz = oz - pz[k3];
-        const float r2 = __builtin_fmaf(dz, dz, dxy);
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float m = wk[k + k3];
-        if constexpr (KER == TAGI_YUKAWA_SS || KER == TAGI_YUKAWA) {
-          // The charges of a proxy point arrive in scalar registers and one
-          // instruction may read only one of them: for blocks of up to 4
-          // orbitals the shared w^_k is copied to a vector register once (added
-          // to a lane-varying zero), so that each orbital's subtracted charge
-          // q^_k - f_i w^_k takes one multiply-add instead of two vector moves
-          // and one. (For 8 orbitals the copy makes the loop spill scalar
-          // registers; the compiler's moves cost less there.)
-          const double wv = KER == TAGI_YUKAWA_SS && OB <= 4 ? wk64[k + k3] + vzero : wk64[k + k3];
-          const float r = r2 * rinv;
+      if constexpr (NP1 > 0) {
+        // a row in steps of RS points, a scheduling barrier between steps, so
+        // that the step's scalar-loaded charges fit the scalar register file
 #pragma unroll
-          for (int o = 0; o < OB; ++o) {
-            const float g = __builtin_amdgcn_exp2f(nkl2[o] * r) * rinv;
-            if constexpr (KER == TAGI_YUKAWA_SS) {
-              const double c64 = __builtin_fma(-fi[o], wv, qk64[o][k + k3]);
-              b1[o] = __builtin_fmaf(g, (float)c64, b1[o]);
-            } else {
-              b1[o] = __builtin_fmaf(g, qk[o][k + k3], b1[o]);
-            }
-          }
-        } else {
-          if constexpr (KER == TAGI_COULOMB_SS)
-            b2[0] = __builtin_fmaf(__builtin_amdgcn_exp2f(r2 * nial2) * rinv, m, b2[0]);
+        for (int h = 0; h < NP1; h += RS) {
 #pragma unroll
-          for (int o = 0; o < OB; ++o) b1[o] = __builtin_fmaf(rinv, qk[o][k + k3], b1[o]);
+          for (int k3 = h; k3 < (h + RS < NP1 ? h + RS : NP1); ++k3) point(k, k3, dxy);
+          if constexpr (RS < NP1) __builtin_amdgcn_sched_barrier(0);
         }
+      } else {
+        for (int k3 = 0; k3 < np1; ++k3) point(k, k3, dxy);
       }
       k += np1;
     }

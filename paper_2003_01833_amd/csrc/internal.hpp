@@ -351,9 +351,10 @@ struct WaveRun {
 // longest runs first within each XCD's range of the launch over `list`
 int order_runs_per_xcd(std::vector<int32_t>& list, const std::vector<WaveRun>& runs);
 double far_weight(int kernel, int precision, bool herm);
-int orbital_block(int kernel, int n_orb, int precision);
+int orbital_block(int kernel, int n_orb, int precision, bool learned = false);
 // the tree's orbital block for a kernel: its override if set, else the default
-int orbital_block_of(const tagi_tree* t, int kernel, int precision);
+// (`learned`: for tagi_convolve_learned's launches)
+int orbital_block_of(const tagi_tree* t, int kernel, int precision, bool learned = false);
 // The far and near sums of the batches of `bt` (lists and schedule prepared in
 // it) against the source tree `src`, the combine and the scatter to the caller's
 // target order; tfs = target values in bt's order, [n_orb][bt->n] (bt == src:

@@ -309,7 +309,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
   for (int o = 0; o < n_orb; ++o) key.push_back(tol[o]);
   for (int k = 0; k < 4 * kIn; ++k) key.push_back(norm[k]);
   for (int k = 0; k < kNParam; ++k) key.push_back(params[k]);
-  const int ob = orbital_block_of(t, kernel, precision);
+  const int ob = orbital_block_of(t, kernel, precision, true);
   if (key != S.key) {
     phase_begin(t, kPhaseLists, s);
     S.key.clear();
