@@ -97,9 +97,11 @@ def benzene_atoms():
     return [(np.array(c), 6.0) for c in BENZENE_C] + [(np.array(h), 1.0) for h in BENZENE_H]
 
 
-def benzene_mesh(tol_m: float = 5e-4, p: int = 7, uniform_levels: int = 4, domain=DOMAIN):
-    atoms = benzene_atoms()
-
+def molecule_mesh(atoms, tol_m: float = 5e-4, p: int = 7, uniform_levels: int = 4,
+                  domain=DOMAIN):
+    """Fejer mesh for the nuclei `atoms` ([(R, Z)]) in the domain: refinement on
+    sqrt(rho0) v_ext (rho0 the sum of the atoms' hydrogenic 1s densities, v_ext
+    their Coulomb potential) with tol_m, nuclei moved onto cell vertices."""
     def test_fn(x, y, z):
         rho0 = np.zeros_like(x)
         vext = np.zeros_like(x)
@@ -115,8 +117,30 @@ def benzene_mesh(tol_m: float = 5e-4, p: int = 7, uniform_levels: int = 4, domai
     return dict(x=x, y=y, z=z, w=w, mesh=mesh, atoms=atoms)
 
 
-def benzene_orbitals(x, y, z, n_orb: int = 21, seed: int = 3):
-    atoms = benzene_atoms()
+def benzene_mesh(tol_m: float = 5e-4, p: int = 7, uniform_levels: int = 4, domain=DOMAIN):
+    return molecule_mesh(benzene_atoms(), tol_m, p, uniform_levels, domain)
+
+
+def random_molecule(seed: int, n_heavy: int = 3, n_light: int = 3, spread: float = 3.0,
+                    min_sep: float = 1.8):
+    """n_heavy nuclei of charge 6 and n_light of charge 1 at SplitMix64(seed)
+    positions, uniform in [-spread, spread]^3 and at least min_sep apart (draws
+    closer to an earlier nucleus are redrawn)."""
+    g = SplitMix64(seed)
+    atoms = []
+    for Z in [6.0] * n_heavy + [1.0] * n_light:
+        while True:
+            R = g.uniform(3, -spread, spread)
+            if all(np.linalg.norm(R - Q) >= min_sep for Q, _ in atoms):
+                break
+        atoms.append((R, Z))
+    return atoms
+
+
+def molecule_orbitals(atoms, x, y, z, n_orb: int, seed: int):
+    """n_orb orbital-like functions on the points: each a sum over the nuclei of
+    c exp(-zeta d) with c ~ U[-1, 1] and zeta ~ U[0.5, 6] from SplitMix64(seed),
+    and decay rates kappa_o = sqrt(-2 eps_o) with eps log-spaced in [-10, -0.2]."""
     g = SplitMix64(seed)
     coef = np.empty((n_orb, len(atoms)))
     zeta = np.empty((n_orb, len(atoms)))
@@ -132,6 +156,10 @@ def benzene_orbitals(x, y, z, n_orb: int = 21, seed: int = 3):
     eps = -10.0 * 0.02 ** (np.arange(n_orb) / max(n_orb - 1, 1))
     kappa = np.sqrt(-2.0 * eps)
     return dict(psi=psi, kappa=kappa, eps=eps, coef=coef, zeta=zeta)
+
+
+def benzene_orbitals(x, y, z, n_orb: int = 21, seed: int = 3):
+    return molecule_orbitals(benzene_atoms(), x, y, z, n_orb, seed)
 
 
 def sample_targets(n_total: int, k: int, seed: int = 4) -> np.ndarray:
