@@ -122,3 +122,34 @@ def test_largest_orbital_count():
     kap = np.linspace(0.5, 4.0, 64)
     for kernel in ("coulomb_ss", "yukawa_ss"):
         _check(x, y, z, F, w, kernel, kap, 0.7, 4, 100)
+
+
+def test_timing_reports_each_interaction_launch():
+    # the fixed MAC runs one interaction launch per convolution: its own
+    # duration (events on its stream around it alone) lies within the phase's;
+    # the learned lists run one launch per degree in use plus one for the near
+    # pairs, each timed on its own stream
+    import os
+
+    import paper_2003_01833_amd as tagi
+    from paper_2003_01833_amd.selector import Selector
+    x, y, z, f, w = uniform_cube(40000, seed=44)
+    dx, dy, dz, df, dw = (torch.from_numpy(a).cuda() for a in (x, y, z, f, w))
+    t = tagi.Tree(dx, dy, dz, 500)
+    t.upward(df, dw, 6)
+    t.convolve("yukawa_ss", 1.2, 0.7, 6)
+    t.set_timing(True)
+    t.convolve("yukawa_ss", 1.2, 0.7, 6)
+    tm = t.timing()
+    assert tm["interact_launches"] == 1
+    assert 0.0 < tm["interact_kernel_ms"] <= tm["interact_ms"] * (1 + 1e-6) + 1e-3
+    sel = Selector.load(os.path.join(os.path.dirname(tagi.__file__), "selector_weights.npz"))
+    t.upward(df, dw, 1)
+    t.set_timing(True)
+    t.convolve_learned("yukawa_ss", 1.2, sel, [1e-7])
+    tm = t.timing()
+    st = t.learned_stats()
+    degrees = [d for d, c in st["far_pairs_by_degree"].items() if c > 0]
+    assert tm["interact_launches"] == len(degrees) + (st["near_interactions"] > 0)
+    assert tm["interact_kernel_ms"] > 0.0 and tm["interact_ms"] > 0.0
+    t.close()
