@@ -192,7 +192,7 @@ int convolve(tagi_tree* t, tagi_tree* bt, const double* tfs, int kernel, const d
   A.ia2 = ia2;
   A.partial = bt->partial.as<double>();
   A.item_list = bt->item_order.as<int32_t>();
-  A.n_list = bt->n_items;
+  A.n_list = (int64_t)bt->h_order.size();
   A.bbeg = bt->nd_begin.as<int32_t>();
   A.bend = bt->nd_end.as<int32_t>();
   A.bbox = bt->nd_box.as<double>();

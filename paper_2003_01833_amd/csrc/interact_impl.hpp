@@ -524,6 +524,7 @@ struct InteractArgs {
   double ia2;
   double* partial;
   const int32_t* item_list;  // optional: this launch processes items item_list[0 .. n_list)
+                             // (entries -1 are empty slots)
   int64_t n_list;
   // target side: batch-tree node ranges and boxes, targets [tn] and values [n_orb][tn]
   const int32_t *bbeg, *bend;
@@ -627,6 +628,7 @@ void k_interact(InteractArgs A, OrbArg orb) {
   const int wv = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (int)(threadIdx.x / kWave));
   if (A.item_list ? wv >= A.n_list : wv >= A.n_items) return;
   const int it = A.item_list ? __builtin_amdgcn_readfirstlane(A.item_list[wv]) : wv;
+  if (it < 0) return;  // an empty slot of a cost-balanced launch order
   const int4 item = A.items[it];
   const int B = A.leaf_node[item.x];
   const int tb = A.bbeg[B] + item.y * kWave;

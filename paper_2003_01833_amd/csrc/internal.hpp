@@ -224,9 +224,9 @@ struct tagi_tree {
   // schedule: chunks of (kind, begin, end) per batch, items, group table
   int64_t n_items = 0;
   int items_orb_block = 0;
-  double items_far_w = -1.0;             // far weight the launch order was sorted for
+  double items_far_w = -1.0;             // far weight the launch order was made for
   std::vector<int32_t> h_order_base;     // chunk-major launch order
-  std::vector<int32_t> h_order;          // the order last uploaded
+  std::vector<int32_t> h_order;          // the order last uploaded (-1: an empty slot)
   struct Run {
     int32_t start, len, chunk;           // waves [start, start+len) of h_order_base
   };
@@ -239,7 +239,7 @@ struct tagi_tree {
   int items_n_orb = 0;
   tagi::DBuf chunks;                // int4 {kind, e0, e1, cost}
   tagi::DBuf items;                 // int4 {batch, group, oblock, chunk}
-  tagi::DBuf item_order;            // int32 [n_items] launch order: per batch and orbital
+  tagi::DBuf item_order;            // int32 launch order (h_order): per batch and orbital
                                     // block, chunk-major (the groups of a chunk adjacent)
   tagi::DBuf group_first_item;      // int32 per (batch, group)
   tagi::DBuf batch_group_base;      // int32 [n_leaves] first (batch, group) index
@@ -348,8 +348,11 @@ struct WaveRun {
   int32_t start, len;
   double cost;
 };
-// longest runs first within each XCD's range of the launch over `list`
-int order_runs_per_xcd(std::vector<int32_t>& list, const std::vector<WaveRun>& runs);
+// the launch order cut into one contiguous piece of equal cost per XCD, each
+// padded with empty slots (-1) to a common length; `longest_first` also sorts
+// the runs of each piece by descending cost
+int balance_runs_per_xcd(std::vector<int32_t>& list, const std::vector<WaveRun>& runs,
+                         bool longest_first);
 double far_weight(int kernel, int precision, bool herm);
 int orbital_block(int kernel, int n_orb, int precision, bool learned = false);
 // the tree's orbital block for a kernel: its override if set, else the default

@@ -552,7 +552,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
       if (per[k].empty()) continue;
       // one launch per list: its chunks are all of one kind, so their costs
       // compare directly
-      TAGI_TRY(order_runs_per_xcd(per[k], per_runs[k]));
+      TAGI_TRY(balance_runs_per_xcd(per[k], per_runs[k], true));
       S.list_begin.push_back((int64_t)S.h_lists.size());
       S.list_degree.push_back(k < kNDeg ? kDegMin + k : 0);
       S.h_lists.insert(S.h_lists.end(), per[k].begin(), per[k].end());

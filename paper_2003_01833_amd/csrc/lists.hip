@@ -376,47 +376,89 @@ int ensure_schedule(const tagi_tree* src, tagi_tree* t, int orb_block, hipStream
   return TAGI_OK;
 }
 
-// Longest first within each XCD's range of one launch over list.size() waves
-// (xcd_range): runs of waves that read the same sources (start, len, cost; in
-// list order, covering the list) are stably sorted by descending cost inside each
-// range, so every XCD ends on short items, the waves of a run stay side by side
-// (a run cut by a range boundary is split) and equal-cost runs keep their order.
-int order_runs_per_xcd(std::vector<int32_t>& list, const std::vector<WaveRun>& runs) {
+// Cost-balanced XCD pieces. Workgroups go to the XCDs round-robin, so each XCD
+// runs an equal count of the launch's waves: the range xcd_range gives it. With
+// the order cut into equal counts, an XCD whose range holds the costly chunks
+// (the dense parts of a mesh come together in tree order) finishes last while
+// the others idle. Here the order (runs of waves in list order, each with its
+// cost per wave) is cut into kXcds contiguous pieces of equal total cost, the
+// pieces keep their waves in order (or sort their runs longest first), and each
+// is padded with empty slots (-1, a wave that returns at once) to the length of
+// the longest, rounded up to whole workgroups, so that piece x is exactly XCD
+// x's range. A run cut by a piece boundary is split.
+int balance_runs_per_xcd(std::vector<int32_t>& list, const std::vector<WaveRun>& runs,
+                         bool longest_first) {
   struct Piece {
     int32_t a, b;
     double cost;
   };
   const std::vector<int32_t> base = list;
-  const int64_t n = (int64_t)list.size();
-  const int nb = (int)((n + ik::kWavesPerBlock - 1) / ik::kWavesPerBlock);
-  std::vector<Piece> pieces;
-  size_t r = 0;  // first run not wholly before the range
-  for (int x = 0; x < ik::kXcds; ++x) {
-    int b0, b1;
-    ik::xcd_range(x, nb, b0, b1);
-    const int32_t i0 = (int32_t)std::min<int64_t>(n, (int64_t)b0 * ik::kWavesPerBlock);
-    const int32_t i1 = (int32_t)std::min<int64_t>(n, (int64_t)b1 * ik::kWavesPerBlock);
-    pieces.clear();
-    while (r < runs.size() && runs[r].start + runs[r].len <= i0) ++r;
-    for (size_t k = r; k < runs.size() && runs[k].start < i1; ++k)
-      pieces.push_back({std::max(runs[k].start, i0), std::min(runs[k].start + runs[k].len, i1),
-                        runs[k].cost});
-    std::stable_sort(pieces.begin(), pieces.end(),
-                     [](const Piece& p, const Piece& q) { return p.cost > q.cost; });
-    int32_t pos = i0;
-    for (const Piece& p : pieces)
-      for (int32_t i = p.a; i < p.b; ++i) list[pos++] = base[i];
-    if (pos != i1) {
-      set_error("internal: launch order range %d has %d of %d waves", x, pos - i0, i1 - i0);
-      return TAGI_E_STATE;
+  const int64_t n = (int64_t)base.size();
+  if (n == 0) return TAGI_OK;
+  double total = 0.0;
+  int64_t covered = 0;
+  for (const WaveRun& u : runs) {
+    total += u.cost * u.len;
+    covered += u.len;
+  }
+  if (covered != n) {
+    set_error("internal: %lld run waves for a launch order of %lld", (long long)covered,
+              (long long)n);
+    return TAGI_E_STATE;
+  }
+  std::vector<WaveRun> unit;
+  const std::vector<WaveRun>* rs = &runs;
+  if (!(total > 0.0)) {  // no costs: every wave counts 1
+    unit = runs;
+    for (WaveRun& u : unit) u.cost = 1.0;
+    total = (double)n;
+    rs = &unit;
+  }
+  std::vector<std::vector<Piece>> parts(ik::kXcds);
+  int x = 0;
+  double acc = 0.0;  // cost assigned to pieces 0..x
+  for (const WaveRun& u : *rs) {
+    int32_t a = u.start;
+    const int32_t e = u.start + u.len;
+    while (a < e) {
+      // waves of this run that still fit in piece x's share (all, for the last)
+      int32_t take = e - a;
+      if (x < ik::kXcds - 1 && u.cost > 0.0) {
+        const double room = total * (x + 1) / ik::kXcds - acc;
+        const int64_t fit = (int64_t)std::ceil(room / u.cost);
+        take = (int32_t)std::max<int64_t>(0, std::min<int64_t>(take, fit));
+      }
+      if (take > 0) {
+        parts[x].push_back({a, a + take, u.cost});
+        acc += u.cost * take;
+        a += take;
+      }
+      if (a < e && x < ik::kXcds - 1) ++x;
     }
+  }
+  int64_t len = 0;
+  for (const auto& p : parts) {
+    int64_t m = 0;
+    for (const Piece& q : p) m += q.b - q.a;
+    len = std::max(len, m);
+  }
+  len = (len + ik::kWavesPerBlock - 1) / ik::kWavesPerBlock * ik::kWavesPerBlock;
+  list.assign((size_t)(len * ik::kXcds), -1);
+  for (int k = 0; k < ik::kXcds; ++k) {
+    if (longest_first)
+      std::stable_sort(parts[k].begin(), parts[k].end(),
+                       [](const Piece& p, const Piece& q) { return p.cost > q.cost; });
+    int64_t pos = k * len;
+    for (const Piece& q : parts[k])
+      for (int32_t i = q.a; i < q.b; ++i) list[(size_t)pos++] = base[(size_t)i];
   }
   return TAGI_OK;
 }
 
-// Launch order of the schedule for far evaluations that cost far_w near ones
-// (order_runs_per_xcd over the chunk runs); far_w = 0 keeps the chunk-major
-// order. Results do not depend on the order.
+// Launch order of the schedule for far evaluations that cost far_w near ones:
+// the chunk-major order cut into cost-balanced XCD pieces, each sorted longest
+// first (balance_runs_per_xcd over the chunk runs); far_w = 0 keeps the
+// chunk-major order cut into equal counts. Results do not depend on the order.
 int order_schedule(tagi_tree* t, double far_w, hipStream_t s) {
   if (t->n_items == 0 || t->items_far_w == far_w) return TAGI_OK;
   t->h_order = t->h_order_base;
@@ -427,8 +469,9 @@ int order_schedule(tagi_tree* t, double far_w, hipStream_t s) {
       runs[k] = {u.start, u.len,
                  t->h_chunk_cost[u.chunk] * (t->h_chunk_far[u.chunk] ? far_w : 1.0)};
     }
-    TAGI_TRY(order_runs_per_xcd(t->h_order, runs));
+    TAGI_TRY(balance_runs_per_xcd(t->h_order, runs, true));
   }
+  TAGI_TRY(t->item_order.ensure(std::max<size_t>(t->h_order.size(), 1) * 4));
   TAGI_HIP(hipMemcpyAsync(t->item_order.p, t->h_order.data(), t->h_order.size() * 4,
                           hipMemcpyHostToDevice, s));
   TAGI_HIP(hipStreamSynchronize(s));  // the host order is reused by the next call
@@ -439,8 +482,10 @@ int order_schedule(tagi_tree* t, double far_w, hipStream_t s) {
 // Far evaluation cost relative to a near one, from the instruction counts of the
 // interaction loops: FP64 Yukawa far 23 vs near 28; Coulomb-SS far 10.5 (the
 // Gaussian factors per dimension) vs 27; a Hermite point about 65. Mixed
-// precision keeps the chunk-major order (0): ordered by cost, its launches were
-// 7% slower on 8 benzene orbitals, where the FP64 ones gained 3-6%.
+// precision keeps the chunk-major order in equal counts (0): on the 21 benzene
+// orbitals it ran 5% faster than the order cut into pieces of equal modelled
+// cost (far weight 0.5), and sorting by cost had made it 7% slower, where the
+// FP64 launches gain from both.
 double far_weight(int kernel, int precision, bool herm) {
   const bool yuk = kernel == TAGI_YUKAWA_SS || kernel == TAGI_YUKAWA;
   if (herm) return 2.3;
