@@ -758,8 +758,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: runs on more than one GPU are not part of this "
-              "build (the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the treecode runs on one GPU per process, and "
+              "sharding the batches over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -58,7 +58,7 @@ enum tagi_status {
   TAGI_E_STATE = -2,       /* call out of order (convolve before upward, degree mismatch) */
   TAGI_E_OOM = -3,         /* device allocation failed */
   TAGI_E_HIP = -4,         /* a HIP runtime call failed; message in tagi_last_error() */
-  TAGI_E_UNSUPPORTED = -5  /* valid request this build does not implement */
+  TAGI_E_UNSUPPORTED = -5  /* valid request the library does not implement */
 };
 
 enum tagi_kernel {
