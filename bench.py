@@ -41,8 +41,9 @@ the profiled ones.
 
 Extras (unless --no-extras): the Be-like atom step (C2: Yukawa and Hartree
 convolutions on one tree), Lagrange against Hermite interpolation on the atom,
-the HIP-graph replay of the batched step, the autotuner's pick, the GPU mesh
-build, and the 10M-point uniform Coulomb case of Section 6.6.
+the HIP-graph replay of the batched step, one block Green-iteration step over
+the 21 orbitals, the autotuner's pick, the GPU mesh build, and the 10M-point
+uniform Coulomb case of Section 6.6.
 
 --sweep: the (theta, degree) table behind the settings of every variant: errors
 and time of one convolution per setting; --write-settings stores the cheapest
@@ -566,6 +567,66 @@ def anchor_10m(tagi, torch, samples=1000):
             "interactions": st["far_interactions"] + st["near_interactions"]}
 
 
+def green_step(tagi, torch, bz, case, reps=2):
+    """One block Green-iteration step (the body of Algorithm 2 for all 21
+    orbitals at once) on a cached tree: V_eff psi with V_eff the nuclei's
+    Coulomb potential, the batched convolution, the eigenvalue update,
+    Gram-Schmidt with the quadrature weights and the residual. Two forms: the
+    fixed MAC at the mixed setting, and the learned lists in mixed precision
+    with the budget tol_o = eta 1e-6 max|conv(V psi_o)| (the maximum from one
+    fixed-MAC convolution). Median of `reps` steps after one that builds the
+    lists; the treecode phases' share from HIP events."""
+    from workloads.configs import benzene_atoms
+    x, y, z = case["x"], case["y"], case["z"]
+    v = torch.zeros_like(x)
+    for R, Z in benzene_atoms():
+        v -= Z / torch.sqrt((x - R[0]) ** 2 + (y - R[1]) ** 2 + (z - R[2]) ** 2)
+    eps = -0.5 * np.asarray(case["kappa"]) ** 2
+    th, deg = bz.mixed
+    t = tagi.Tree(x, y, z, bz.leaf, case["box"])
+    out = torch.empty_like(bz.U)
+    rec = {"orbitals": int(case["n_orb"]), "precision": "mixed"}
+
+    def timed(step):
+        step()  # builds the lists and the schedule
+        ms, tree_ms, last = [], [], None
+        for _ in range(reps):
+            t.set_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            last = step()
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+            tm = t.timing()
+            tree_ms.append(tm["upward_ms"] + tm["lists_ms"] + tm["interact_ms"] + tm["combine_ms"])
+        step_ms, conv_ms = float(np.median(ms)), float(np.median(tree_ms))
+        return {"ms_median": step_ms, "treecode_ms": conv_ms, "other_ms": step_ms - conv_ms}, last
+
+    fixed, (p_fix, e_fix, _) = timed(lambda: t.green_step(case["F"], v, case["w"], eps, th, deg,
+                                                          precision="mixed", out=out))
+    rec["fixed_mac"] = {"theta": th, "degree": deg, **fixed}
+    p_fix = p_fix.clone()
+    if bz.sel is not None:
+        t.upward(case["F"] * v, case["w"], deg)
+        umax = t.convolve("yukawa_ss", case["kappa"], th, deg, precision="mixed", out=out)
+        tol = bz.sel.eta("yukawa_ss") * BAR * umax.abs().amax(dim=1).cpu().numpy()
+        learned, (p_l, e_l, _) = timed(lambda: t.green_step_learned(
+            case["F"], v, case["w"], eps, bz.sel, tol, precision="mixed", out=out))
+        ls = t.learned_stats()
+        rec["learned"] = {"eta": bz.sel.eta("yukawa_ss"), **learned,
+                          "far_near_evaluations_per_orbital": [ls["far_interactions"],
+                                                               ls["near_interactions"]],
+                          # per orbital, after Gram-Schmidt: differences between the two
+                          # convolutions grow by the block's conditioning
+                          "psi_rel_max_vs_fixed": [float(a) for a in (
+                              (p_l - p_fix).abs().amax(dim=1) / p_fix.abs().amax(dim=1)).cpu()],
+                          "eps_rel_max_vs_fixed": float(np.max(np.abs(e_l - e_fix) /
+                                                               np.abs(e_fix)))}
+    t.close()
+    del v, out, p_fix
+    return rec
+
+
 def extras(tagi, torch, settings, bz, case):
     out = {}
     _log("bench: extras: atom step")
@@ -587,6 +648,8 @@ def extras(tagi, torch, settings, bz, case):
     g.close()
     t.close()
     del Ug, Ue
+    _log("bench: extras: Green-iteration step")
+    out["green_step"] = green_step(tagi, torch, bz, case)
     # autotuner: leaf size, orbital block, schedule granularity and kernel launch
     # variant on the first eight orbitals
     _log("bench: extras: autotuner")

@@ -369,6 +369,25 @@ int tagi_green_step(tagi_tree* tree, const double* psi, const double* veff, cons
                     double* psi_out, double* resid, void* stream);
 
 /*
+ * tagi_green_step with the learned selector as its convolution (the project's
+ * learned degree/MAC lists, as tagi_convolve_learned with TAGI_YUKAWA_SS and
+ * kappa_o = sqrt(-2 eps_o)) in place of the fixed (theta, degree): steps 2-4
+ * are the same. params, norm, theta_max, theta_fb, degree_fb as for
+ * tagi_convolve_learned; tol HOST [n_orb] the absolute error budget of one
+ * target's subtracted Yukawa sum of f_o = V_eff psi_o (psi'_o's error is
+ * 1/(2 pi) of it). The lists are rebuilt whenever kappa or tol change, i.e.
+ * on nearly every step of an iteration. Runs an upward pass on the tree (its
+ * previous upward state is replaced). Synchronises the stream; bitwise
+ * repeatable.
+ * Errors: as tagi_green_step and tagi_convolve_learned.
+ */
+int tagi_green_step_learned(tagi_tree* tree, const double* psi, const double* veff,
+                            const double* w, int n_orb, double* eps, const float* params,
+                            const float* norm, const double* tol, double theta_max,
+                            double theta_fb, int degree_fb, int precision, double* psi_out,
+                            double* resid, void* stream);
+
+/*
  * Orbital block of the batched launch (a project addition on the per-orbital
  * loop of Algorithm 2): the interaction kernel evaluates the geometry of a pair
  * once for `ob` orbitals. ob = 1, 2, 4 or 8 fixes the width for every later
@@ -509,7 +528,8 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
  *   params  HOST float [tagi_selector_param_count()]
  *   norm    HOST float [20] = shift[5], scale[5], lo[5], hi[5]
  *   0 < theta_fb, theta_max < 1; 4 <= degree_fb <= 12; tol[o] > 0.
- * Lists and per-degree plans are cached per argument set (rebuilding them
+ * Lists and per-degree plans are cached per argument set and are rebuilt
+ * after every upward pass, whose charges give the features (rebuilding them
  * synchronises the stream); proxy charges are recomputed on every call.
  * Errors: TAGI_E_ARG, TAGI_E_STATE (no upward), TAGI_E_OOM, TAGI_E_HIP,
  * TAGI_E_UNSUPPORTED (lists beyond 2^31 entries, a tree deeper than the

@@ -32,7 +32,7 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_upward_hermite", "tagi_convo
             "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
             "tagi_tree_set_orbital_block", "tagi_tree_set_schedule_items",
             "tagi_tree_set_kernel_variant", "tagi_autotune",
-            "tagi_green_step",
+            "tagi_green_step", "tagi_green_step_learned",
             "tagi_learned_lists_export", "tagi_mesh_build", "tagi_mesh_info",
             "tagi_mesh_cells", "tagi_mesh_points", "tagi_mesh_destroy", "tagi_tree_destroy",
             "tagi_last_error"]
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_tree_set_timing.argtypes = [vp, i32]
     lib.tagi_tree_set_orbital_block.argtypes = [vp, i32]
     lib.tagi_green_step.argtypes = [vp, vp, vp, vp, i32, vp, dbl, i32, i32, vp, vp, vp]
+    lib.tagi_green_step_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, dbl, dbl, i32,
+                                            i32, vp, vp, vp]
     lib.tagi_learned_lists_export.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.tagi_mesh_build.argtypes = [vp, vp, i32, dbl, i32, i32, vp, i32, i32, dbl, vp,
                                     ctypes.POINTER(vp)]
@@ -327,6 +329,31 @@ class Tree:
                                               _dptr(out, "out", n_orb * self.n), _hptr(res),
                                               _stream()))
         self.n_orb, self.degree = n_orb, int(degree)
+        self.interpolation = "lagrange"
+        return out, e, res
+
+    def green_step_learned(self, psi: torch.Tensor, veff: torch.Tensor, w: torch.Tensor, eps,
+                           selector, tol, theta_max: float = 0.9, theta_fb: float = 0.7,
+                           degree_fb: int = 8, precision: str = "fp64",
+                           out: torch.Tensor | None = None):
+        """tagi_green_step_learned: the Green step with the learned lists of
+        `selector` (its Yukawa-SS network); tol per orbital on the convolution
+        of V_eff psi. Returns (psi' (n_orb, n), eps' numpy, residual numpy)."""
+        n_orb = 1 if psi.dim() == 1 else psi.shape[0]
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (n_orb,))).copy()
+        tl = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (n_orb,)))
+        net = selector.net("yukawa_ss")
+        prm = np.ascontiguousarray(net.params, dtype=np.float32)
+        nrm = np.ascontiguousarray(net.norm, dtype=np.float32)
+        res = np.zeros(n_orb, np.float64)
+        if out is None:
+            out = torch.empty((n_orb, self.n), dtype=torch.float64, device="cuda")
+        _check(load_library().tagi_green_step_learned(
+            self._h, _dptr(psi, "psi", n_orb * self.n), _dptr(veff, "veff", self.n),
+            _dptr(w, "w", self.n), n_orb, _hptr(e), _hptr(prm), _hptr(nrm), _hptr(tl),
+            float(theta_max), float(theta_fb), int(degree_fb), PRECISIONS[precision],
+            _dptr(out, "out", n_orb * self.n), _hptr(res), _stream()))
+        self.n_orb, self.degree = n_orb, 1
         self.interpolation = "lagrange"
         return out, e, res
 

@@ -163,6 +163,7 @@ int tagi_upward(tagi_tree* t, const double* f, const double* w, int n_orb, int d
           kMaxOrb);
   REQUIRE(degree >= 1 && degree <= kMaxDegree, "tagi_upward: degree = %d out of range [1, %d]",
           degree, kMaxDegree);
+  ++t->charges_gen;
   return upward(t, f, w, n_orb, degree, (hipStream_t)stream);
 }
 
@@ -175,6 +176,7 @@ int tagi_upward_hermite(tagi_tree* t, const double* f, const double* w, int n_or
           n_orb, kMaxOrb);
   REQUIRE(degree >= 1 && degree <= kMaxHermDegree,
           "tagi_upward_hermite: degree = %d out of range [1, %d]", degree, kMaxHermDegree);
+  ++t->charges_gen;
   return upward(t, f, w, n_orb, degree, (hipStream_t)stream, true);
 }
 
@@ -374,6 +376,7 @@ int tagi_upward_export(const tagi_tree* t, int32_t* cluster, double* nodes, doub
 struct tagi_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  tagi_tree* tree = nullptr;  // every replay runs an upward pass on it
 };
 
 extern "C" {
@@ -402,6 +405,7 @@ int tagi_graph_create(tagi_tree* t, const double* f, const double* w, int n_orb,
   t->timing = false;  // no event records inside the capture
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
+    ++t->charges_gen;
     st = upward(t, f, w, n_orb, degree, cs);
     if (st == TAGI_OK) st = convolve(t, kernel, kappa, alpha, precision, out, cs);
     hipGraph_t gr = nullptr;
@@ -431,6 +435,7 @@ int tagi_graph_create(tagi_tree* t, const double* f, const double* w, int n_orb,
     std::memcpy(g_err, keep, sizeof(keep));
     return st;
   }
+  g->tree = t;
   *graph = g;
   return TAGI_OK;
 }
@@ -463,6 +468,7 @@ int tagi_convolve_learned(tagi_tree* t, int kernel, const double* kappa, double 
   }
   for (int k = 0; k < selector_param_count(); ++k)
     REQUIRE(std::isfinite(params[k]), "tagi_convolve_learned: params[%d] not finite", k);
+  learned_follow_charges(t);
   return convolve_learned(t, kernel, kappa, alpha, params, norm, tol, theta_max, theta_fb,
                           degree_fb, precision, out, (hipStream_t)stream);
 }
@@ -556,6 +562,7 @@ int tagi_graph_launch(tagi_graph* g, void* stream) {
   g_err[0] = 0;
   REQUIRE(g && g->exec, "tagi_graph_launch: graph is NULL");
   TAGI_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  ++g->tree->charges_gen;
   return TAGI_OK;
 }
 
@@ -629,6 +636,35 @@ int tagi_green_step(tagi_tree* t, const double* psi, const double* veff, const d
           "tagi_green_step: unknown precision %d", precision);
   return green_step(t, psi, veff, w, n_orb, eps, theta, degree, precision, psi_out, resid,
                     (hipStream_t)stream);
+}
+
+int tagi_green_step_learned(tagi_tree* t, const double* psi, const double* veff, const double* w,
+                            int n_orb, double* eps, const float* params, const float* norm,
+                            const double* tol, double theta_max, double theta_fb, int degree_fb,
+                            int precision, double* psi_out, double* resid, void* stream) {
+  g_err[0] = 0;
+  REQUIRE(t, "tagi_green_step_learned: tree is NULL");
+  REQUIRE(psi && veff && w && psi_out && eps && params && norm && tol,
+          "tagi_green_step_learned: null argument");
+  REQUIRE(psi_out != psi, "tagi_green_step_learned: psi_out must not alias psi");
+  REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb,
+          "tagi_green_step_learned: n_orb = %d out of range [1, %d]", n_orb, kMaxOrb);
+  for (int o = 0; o < n_orb; ++o) {
+    REQUIRE(std::isfinite(eps[o]) && eps[o] < 0.0,
+            "tagi_green_step_learned: eps[%d] = %g must be finite and < 0", o, eps[o]);
+    REQUIRE(std::isfinite(tol[o]) && tol[o] > 0.0,
+            "tagi_green_step_learned: tol[%d] = %g must be finite and > 0", o, tol[o]);
+  }
+  REQUIRE(theta_max > 0.0 && theta_max < 1.0, "tagi_green_step_learned: theta_max out of (0, 1)");
+  REQUIRE(theta_fb > 0.0 && theta_fb < 1.0, "tagi_green_step_learned: theta_fb out of (0, 1)");
+  REQUIRE(degree_fb >= 4 && degree_fb <= 12,
+          "tagi_green_step_learned: degree_fb out of [4, 12]");
+  REQUIRE(precision == TAGI_FP64 || precision == TAGI_MIXED,
+          "tagi_green_step_learned: unknown precision %d", precision);
+  for (int k = 0; k < selector_param_count(); ++k)
+    REQUIRE(std::isfinite(params[k]), "tagi_green_step_learned: params[%d] not finite", k);
+  return green_step_learned(t, psi, veff, w, n_orb, eps, params, norm, tol, theta_max, theta_fb,
+                            degree_fb, precision, psi_out, resid, (hipStream_t)stream);
 }
 
 int tagi_mesh_build(const double* lo3, const double* hi3, int p, double tol_m,

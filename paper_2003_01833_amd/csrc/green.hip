@@ -139,36 +139,32 @@ int gather_sums(const DBuf& part, int m, std::vector<double>& out, hipStream_t s
   return TAGI_OK;
 }
 
-}  // namespace
-
-int green_step(tagi_tree* t, const double* psi, const double* veff, const double* w, int n_orb,
-               double* eps, double theta, int degree, int precision, double* psi_out,
-               double* resid, hipStream_t s) {
+// f_o = V psi_o into the tree's Green buffers; kappa_o = sqrt(-2 eps_o)
+int green_prepare(tagi_tree* t, const double* psi, const double* veff, int n_orb,
+                  const double* eps, std::vector<double>& kappa, hipStream_t s) {
   const int64_t n = t->n;
-  const int grid = (int)((n + 255) / 256);
   TAGI_TRY(t->green_f.ensure((size_t)n_orb * n * sizeof(double)));
   TAGI_TRY(t->green_phi.ensure((size_t)n_orb * n * sizeof(double)));
   TAGI_TRY(t->green_part.ensure((size_t)2 * kMaxOrb * kRedBlocks * sizeof(double)));
-  double* f = t->green_f.as<double>();
-  double* phi = t->green_phi.as<double>();
-  double* part = t->green_part.as<double>();
-  hipLaunchKernelGGL(k_vpsi, dim3(grid), dim3(256), 0, s, veff, psi, n, n_orb, f);
+  hipLaunchKernelGGL(k_vpsi, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, veff, psi, n,
+                     n_orb, t->green_f.as<double>());
   TAGI_HIP(hipGetLastError());
-  // psi'_o = G(eps_o) psi_o through the batched treecode
-  std::vector<double> kappa(n_orb);
+  kappa.resize(n_orb);
   for (int o = 0; o < n_orb; ++o) kappa[o] = std::sqrt(-2.0 * eps[o]);
-  TAGI_TRY(upward(t, f, w, n_orb, degree, s));
-  const int ob = orbital_block_of(t, TAGI_YUKAWA_SS, precision);
-  if (!lists_current(t, theta, degree) ||
-      !(t->items_orb_block == ob && t->items_n_orb == n_orb && t->n_items > 0)) {
-    phase_begin(t, kPhaseLists, s);
-    int st = ensure_lists(t, theta, degree, s);
-    if (st == TAGI_OK) st = ensure_schedule(t, ob, s);
-    phase_end(t, kPhaseLists, s);
-    if (st != TAGI_OK) return st;
-  }
-  TAGI_TRY(order_schedule(t, far_weight(TAGI_YUKAWA_SS, precision, false), s));
-  TAGI_TRY(convolve(t, TAGI_YUKAWA_SS, kappa.data(), 1.0, precision, phi, s));
+  // the convolution's upward pass replaces the tree's charges
+  ++t->charges_gen;
+  return TAGI_OK;
+}
+
+// everything after the convolution phi_o = conv(f_o): psi' = -phi / (2 pi), the
+// eigenvalue update, Gram-Schmidt, normalization and the residual
+int green_finish(tagi_tree* t, const double* psi, const double* w, int n_orb, double* eps,
+                 double* psi_out, double* resid, hipStream_t s) {
+  const int64_t n = t->n;
+  const int grid = (int)((n + 255) / 256);
+  const double* f = t->green_f.as<double>();
+  const double* phi = t->green_phi.as<double>();
+  double* part = t->green_part.as<double>();
   // scale, and the eigenvalue update from psi' before orthogonalization
   hipLaunchKernelGGL(k_update_sums, dim3(kRedBlocks, n_orb), dim3(kRedThreads), 0, s, w, f, psi,
                      phi, n, psi_out, part);
@@ -225,6 +221,45 @@ int green_step(tagi_tree* t, const double* psi, const double* veff, const double
   }
   for (int o = 0; o < n_orb; ++o) eps[o] = eps_new[o];
   return TAGI_OK;
+}
+
+}  // namespace
+
+int green_step(tagi_tree* t, const double* psi, const double* veff, const double* w, int n_orb,
+               double* eps, double theta, int degree, int precision, double* psi_out,
+               double* resid, hipStream_t s) {
+  std::vector<double> kappa;
+  TAGI_TRY(green_prepare(t, psi, veff, n_orb, eps, kappa, s));
+  // psi'_o = G(eps_o) psi_o through the batched treecode
+  TAGI_TRY(upward(t, t->green_f.as<double>(), w, n_orb, degree, s));
+  const int ob = orbital_block_of(t, TAGI_YUKAWA_SS, precision);
+  if (!lists_current(t, theta, degree) ||
+      !(t->items_orb_block == ob && t->items_n_orb == n_orb && t->n_items > 0)) {
+    phase_begin(t, kPhaseLists, s);
+    int st = ensure_lists(t, theta, degree, s);
+    if (st == TAGI_OK) st = ensure_schedule(t, ob, s);
+    phase_end(t, kPhaseLists, s);
+    if (st != TAGI_OK) return st;
+  }
+  TAGI_TRY(order_schedule(t, far_weight(TAGI_YUKAWA_SS, precision, false), s));
+  TAGI_TRY(convolve(t, TAGI_YUKAWA_SS, kappa.data(), 1.0, precision, t->green_phi.as<double>(),
+                    s));
+  return green_finish(t, psi, w, n_orb, eps, psi_out, resid, s);
+}
+
+int green_step_learned(tagi_tree* t, const double* psi, const double* veff, const double* w,
+                       int n_orb, double* eps, const float* params, const float* norm,
+                       const double* tol, double theta_max, double theta_fb, int degree_fb,
+                       int precision, double* psi_out, double* resid, hipStream_t s) {
+  std::vector<double> kappa;
+  TAGI_TRY(green_prepare(t, psi, veff, n_orb, eps, kappa, s));
+  // the learned path forms its own per-degree proxy charges: the upward pass
+  // stages f and w (lowest degree), and the lists follow the new charges
+  TAGI_TRY(upward(t, t->green_f.as<double>(), w, n_orb, 1, s));
+  learned_follow_charges(t);
+  TAGI_TRY(convolve_learned(t, TAGI_YUKAWA_SS, kappa.data(), 1.0, params, norm, tol, theta_max,
+                            theta_fb, degree_fb, precision, t->green_phi.as<double>(), s));
+  return green_finish(t, psi, w, n_orb, eps, psi_out, resid, s);
 }
 
 }  // namespace tagi

@@ -211,6 +211,11 @@ struct tagi_tree {
   tagi::ProxySet px;                // degree `degree`, every cluster with (n+1)^3 < N_S
   tagi::ProxySet lx[tagi::kMaxDegree + 1];  // learned path: per degree, clusters in use
   tagi::LearnedState learned;
+  // charges generation: bumped before every upward pass (tagi_upward, its Hermite
+  // form, graph capture, the Green step, selector sampling); the learned lists
+  // take their features from the charges, so they are rebuilt when it moves
+  uint64_t charges_gen = 0;
+  uint64_t learned_gen = 0;         // charges generation the learned lists were built from
 
   // cached interaction lists and compute schedule
   double list_theta = -1.0;
@@ -373,6 +378,14 @@ int gather_values(const tagi_tree* t, const double* f, int n_orb, double* out, h
 int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha,
                      const float* params, const float* norm, const double* tol, double theta_max,
                      double theta_fb, int degree_fb, int precision, double* out, hipStream_t s);
+// the learned lists' features come from the charges: forget the cached lists
+// once an upward pass has run since they were built
+inline void learned_follow_charges(tagi_tree* t) {
+  if (t->learned_gen != t->charges_gen) {
+    t->learned.key.clear();
+    t->learned_gen = t->charges_gen;
+  }
+}
 int mesh_build(const double* lo, const double* hi, int p, double tol, int uniform_levels,
                int max_level, const double* atoms, int n_atoms, int kind, double max_aspect,
                hipStream_t s, tagi_mesh** out);
@@ -380,6 +393,10 @@ int mesh_points(const tagi_mesh* m, double* x, double* y, double* z, double* w, 
 int green_step(tagi_tree* t, const double* psi, const double* veff, const double* w, int n_orb,
                double* eps, double theta, int degree, int precision, double* psi_out,
                double* resid, hipStream_t s);
+int green_step_learned(tagi_tree* t, const double* psi, const double* veff, const double* w,
+                       int n_orb, double* eps, const float* params, const float* norm,
+                       const double* tol, double theta_max, double theta_fb, int degree_fb,
+                       int precision, double* psi_out, double* resid, hipStream_t s);
 int selector_param_count();
 // l1 norms of one charge set of a proxy set (set < n_orb: orbital, set == n_orb:
 // the weights' charges), written to out[node] for every slot's node

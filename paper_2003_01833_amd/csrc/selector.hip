@@ -415,6 +415,7 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, int kernel,
   if (coul) kappa = 0.0;  // the decay rate of 1/r
   // candidate pairs: the far pairs of the lists at (theta_max, degree 4)
   const int d0 = 4;
+  ++t->charges_gen;
   TAGI_TRY(upward(t, f, w, 1, d0, s));
   TAGI_TRY(ensure_lists(t, theta_max, d0, s));
   const int nl = (int)t->leaves.size();
@@ -511,6 +512,7 @@ int selector_samples(tagi_tree* t, const double* f, const double* w, int kernel,
   TAGI_HIP(hipGetLastError());
   std::vector<float> e(np);
   for (int d = 4; d <= 12; ++d) {
+    ++t->charges_gen;
     TAGI_TRY(upward(t, f, w, 1, d, s));
     A = args_of(t);
     A.ia2 = ia2;

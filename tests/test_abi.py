@@ -95,4 +95,10 @@ def test_validation_rejects_before_any_device_work():
     lib.tagi_green_step.argtypes = [vp, vp, vp, vp, i32, vp, dbl, i32, i32, vp, vp, vp]
     eps = (ctypes.c_double * 1)(-1.0)
     assert lib.tagi_green_step(None, bogus, bogus, bogus, 1, eps, 0.7, 6, 0, bogus, None, None) == -1
+    lib.tagi_green_step_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, dbl, dbl, i32,
+                                            i32, vp, vp, vp]
+    tol = (ctypes.c_double * 1)(1e-6)
+    assert lib.tagi_green_step_learned(None, bogus, bogus, bogus, 1, eps, bogus, bogus, tol, 0.9,
+                                       0.7, 8, 0, bogus, None, None) == -1
+    assert b"tree is NULL" in lib.tagi_last_error()
     assert lib.tagi_tree_destroy(None) == 0

@@ -1,16 +1,25 @@
 """The block Green-iteration step on the GPU (tagi_green_step) against the oracle's
 step with the oracle treecode as its convolution, its repeatability, and Green
 Iteration driven by it on the Be-like mesh converging to the hydrogenic
-eigenvalues -Z^2/2 and -Z^2/8 for V = -Z/r."""
+eigenvalues -Z^2/2 and -Z^2/8 for V = -Z/r. The step with the learned lists
+(tagi_green_step_learned) against the oracle's step whose convolution is the
+oracle's learned traversal and list sum with the same network, and with a
+network whose features all fall outside its range against the fixed MAC."""
+import os
+
 import numpy as np
 import pytest
 import torch
 
 from oracle import bltc
 from oracle.green import green_step
+from oracle.learned import learned_lists, lists_treecode
 from workloads.configs import DOMAIN, atom_mesh, uniform_cube
 
 pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2003_01833_amd", "selector_weights.npz")
 
 
 def _dev(*arrs):
@@ -47,6 +56,84 @@ def test_green_step_matches_oracle_step():
     t.close()
 
 
+def _fallback_selector():
+    # features always outside the (empty) training range: every pair that passes
+    # theta_max falls back to the fixed MAC at (theta_fb, degree_fb)
+    import paper_2003_01833_amd as tagi
+    from paper_2003_01833_amd.selector import Selector
+    p = np.zeros(tagi.binding.selector_param_count(), np.float32)
+    norm = np.concatenate([np.zeros(5), np.ones(5), np.full(5, 1.0), np.full(5, -1.0)])
+    return Selector.single(p, norm.astype(np.float32))
+
+
+def test_learned_green_step_with_fallback_matches_fixed_mac_step():
+    import paper_2003_01833_amd as tagi
+    x, y, z, w, V, psi, eps = _small_case()
+    ref_tree = bltc.build_tree(x, y, z, 200)
+    conv = lambda f, k: bltc.treecode(x, y, z, f, w, "yukawa_ss", k, 0.7, 6, 200,  # noqa: E731
+                                      tree=ref_tree)[0]
+    p_ref, e_ref, r_ref = green_step(w, psi, V, eps, conv)
+    dx, dy, dz, dw, dV, dpsi = _dev(x, y, z, w, V, psi)
+    t = tagi.Tree(dx, dy, dz, 200)
+    p, e, r = t.green_step_learned(dpsi, dV, dw, eps, _fallback_selector(), [1e-6] * 3,
+                                   theta_max=0.8, theta_fb=0.7, degree_fb=6)
+    p = p.cpu().numpy()
+    np.testing.assert_allclose(e, e_ref, rtol=1e-10)
+    np.testing.assert_allclose(r, r_ref, rtol=1e-8)
+    for o in range(3):
+        assert np.abs(p[o] - p_ref[o]).max() <= 1e-10 * np.abs(p_ref[o]).max(), o
+    assert set(t.learned_stats()["far_pairs_by_degree"]) == {6}
+    t.close()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector weights")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_green_step_matches_oracle_step(precision):
+    # 25,600-point Be-like mesh, V = -4/r, two Slater-type wavefunctions; the
+    # budget leaves no decision of the oracle's FP64 network within 2e-4 of its
+    # threshold, so the GPU's FP32 network takes the same ones
+    import paper_2003_01833_amd as tagi
+    from paper_2003_01833_amd.selector import Selector
+    sel = Selector.load(WEIGHTS)
+    d = atom_mesh(tol_m=1e-4, p=3, uniform_levels=2)
+    x, y, z, w = d["x"], d["y"], d["z"], d["w"]
+    r = np.sqrt(x * x + y * y + z * z)
+    V = -4.0 / r
+    psi = np.stack([np.exp(-3.5 * r), (1 - r) * np.exp(-1.2 * r)])
+    eps = np.array([-7.0, -1.5])
+    kap = np.sqrt(-2 * eps)
+    F = V[None] * psi
+    tol = 1e-8 * 4 * np.pi / kap ** 2 * np.abs(F).max(axis=1)
+    ref_tree = bltc.build_tree(x, y, z, 150)
+    pm = ref_tree.perm
+    net = sel.net("yukawa_ss")
+    far, near, ties = learned_lists(ref_tree, x[pm], y[pm], z[pm], F[:, pm], w[pm], "yukawa_ss",
+                                    kap, net.params, net.norm, np.log10(tol), 0.9, 0.7, 8)
+    assert ties == []
+    inv = np.empty_like(pm)
+    inv[pm] = np.arange(pm.size)
+
+    def conv(f, k):
+        return lists_treecode(ref_tree, x[pm], y[pm], z[pm], f[None, pm], w[pm], "yukawa_ss",
+                              [k], far, near)[0][inv]
+    p_ref, e_ref, r_ref = green_step(w, psi, V, eps, conv)
+    dx, dy, dz, dw, dV, dpsi = _dev(x, y, z, w, V, psi)
+    t = tagi.Tree(dx, dy, dz, 150)
+    p, e, res = t.green_step_learned(dpsi, dV, dw, eps, sel, tol, precision=precision)
+    p = p.cpu().numpy()
+    assert len(t.learned_stats()["far_pairs_by_degree"]) >= 3
+    # FP64: the same sums up to rounding order; mixed: the far field in FP32
+    bar = 1e-10 if precision == "fp64" else 1e-5
+    np.testing.assert_allclose(e, e_ref, rtol=bar)
+    np.testing.assert_allclose(res, r_ref, rtol=100 * bar)
+    for o in range(2):
+        assert np.abs(p[o] - p_ref[o]).max() <= bar * np.abs(p_ref[o]).max(), o
+    # bitwise repeatable (the lists are rebuilt for the step's new charges)
+    p2, e2, _ = t.green_step_learned(dpsi, dV, dw, eps, sel, tol, precision=precision)
+    assert np.array_equal(p2.cpu().numpy(), p) and np.array_equal(e2, e)
+    t.close()
+
+
 def test_green_step_rejects_bad_arguments():
     import paper_2003_01833_amd as tagi
     x, y, z, w, V, psi, eps = _small_case()
@@ -56,6 +143,13 @@ def test_green_step_rejects_bad_arguments():
         t.green_step(dpsi, dV, dw, np.array([-1.0, 0.5, -1.0]), 0.7, 6)  # eps must be < 0
     with pytest.raises(tagi.TagiError):
         t.green_step(dpsi, dV, dw, eps, 0.7, 6, out=dpsi)  # aliasing
+    sel = _fallback_selector()
+    with pytest.raises(tagi.TagiError):
+        t.green_step_learned(dpsi, dV, dw, eps, sel, [1e-6, 0.0, 1e-6])  # tol must be > 0
+    with pytest.raises(tagi.TagiError):
+        t.green_step_learned(dpsi, dV, dw, eps, sel, 1e-6, out=dpsi)  # aliasing
+    with pytest.raises(tagi.TagiError):
+        t.green_step_learned(dpsi, dV, dw, eps, sel, 1e-6, degree_fb=3)
     t.close()
 
 

@@ -115,3 +115,37 @@ def test_learned_precisions_share_lists_and_agree():
     err = ((u32 - u64).abs().amax(dim=1) / u64.abs().amax(dim=1)).cpu().numpy()
     assert err.max() < 1e-4, err
     t.close()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector weights")
+def test_learned_lists_follow_new_charges():
+    # the lists take their features from the charges: after an upward pass with
+    # other values and the same kappa and tol, the result must be that of a
+    # fresh tree on the new values, not of the lists cached for the old ones
+    import paper_2003_01833_amd as tagi
+    from paper_2003_01833_amd.selector import Selector
+    sel = Selector.load(WEIGHTS)
+    d = atom_mesh(tol_m=1e-5, p=5, uniform_levels=2)
+    x, y, z, w = d["x"], d["y"], d["z"], d["w"]
+    r = np.sqrt(x * x + y * y + z * z)
+    F1 = np.stack([_slater(r, 51), _slater(r, 52)])
+    F2 = np.stack([_slater(r, 53), 40.0 * _slater(r, 54)])
+    kap = np.array([0.8, 2.0])
+    tol = np.array([1e-9, 1e-9])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()  # noqa: E731
+    dx, dy, dz, dw = dev(x), dev(y), dev(z), dev(w)
+    t = tagi.Tree(dx, dy, dz, 300)
+    t.upward(dev(F1), dw, 1)
+    t.convolve_learned("yukawa_ss", kap, sel, tol)
+    s1 = t.learned_stats()
+    t.upward(dev(F2), dw, 1)
+    u = t.convolve_learned("yukawa_ss", kap, sel, tol).clone()
+    s2 = t.learned_stats()
+    fresh = tagi.Tree(dx, dy, dz, 300)
+    fresh.upward(dev(F2), dw, 1)
+    ref = fresh.convolve_learned("yukawa_ss", kap, sel, tol)
+    assert s1 != fresh.learned_stats()  # the two charge sets select different lists
+    assert s2 == fresh.learned_stats()
+    assert torch.equal(u, ref)
+    t.close()
+    fresh.close()
