@@ -52,11 +52,26 @@ extern "C" {
 
 typedef struct tagi_tree tagi_tree;
 
+/*
+ * Device memory. The library allocates its own device buffers (trees, proxy
+ * charges, lists, schedules, partial sums; stream-ordered scratch inside a
+ * call) and keeps a tree's buffers until tagi_tree_destroy. The environment
+ * variable TAGI_WORKSPACE_LIMIT (bytes, optionally with a K, M or G suffix for
+ * 2^10, 2^20, 2^30; unset or 0 means no limit), read at every allocation,
+ * caps the bytes the library holds at once over all trees: an allocation
+ * beyond it fails with TAGI_E_OOM before anything is launched that needs it,
+ * and a failed call leaves each tree usable (its caches are rebuilt on the
+ * next call). Caller-owned arrays and tagi_direct_noalloc's array do not count.
+ * tagi_workspace_held: HOST *bytes = the device bytes the library holds now
+ * (all trees and meshes of the process). Errors: TAGI_E_ARG.
+ */
+int tagi_workspace_held(int64_t* bytes);
+
 enum tagi_status {
   TAGI_OK = 0,
   TAGI_E_ARG = -1,         /* invalid argument (null pointer, size, range) */
   TAGI_E_STATE = -2,       /* call out of order (convolve before upward, degree mismatch) */
-  TAGI_E_OOM = -3,         /* device allocation failed */
+  TAGI_E_OOM = -3,         /* device allocation failed, or beyond TAGI_WORKSPACE_LIMIT */
   TAGI_E_HIP = -4,         /* a HIP runtime call failed; message in tagi_last_error() */
   TAGI_E_UNSUPPORTED = -5  /* valid request the library does not implement */
 };

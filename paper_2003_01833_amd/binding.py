@@ -35,7 +35,7 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_upward_hermite", "tagi_convo
             "tagi_green_step", "tagi_green_step_learned",
             "tagi_learned_lists_export", "tagi_mesh_build", "tagi_mesh_info",
             "tagi_mesh_cells", "tagi_mesh_points", "tagi_mesh_destroy", "tagi_tree_destroy",
-            "tagi_last_error"]
+            "tagi_workspace_held", "tagi_last_error"]
 
 
 class TagiError(RuntimeError):
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_selector_train.argtypes = [vp, vp, vp, vp, i64, vp, i32, i32, ctypes.c_float, vp, vp]
     lib.tagi_convolve_learned.argtypes = [vp, i32, vp, dbl, vp, vp, vp, dbl, dbl, i32, i32, vp, vp]
     lib.tagi_learned_stats.argtypes = [vp, vp]
+    lib.tagi_workspace_held.argtypes = [vp]
     lib.tagi_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "tagi_last_error":
@@ -433,6 +434,14 @@ def _fptr(t: torch.Tensor, name: str, n: int | None = None):
 
 def selector_param_count() -> int:
     return int(load_library().tagi_selector_param_count())
+
+
+def workspace_held() -> int:
+    """tagi_workspace_held: device bytes the library holds now (TAGI_WORKSPACE_LIMIT
+    in the environment caps it)."""
+    v = ctypes.c_int64(0)
+    _check(load_library().tagi_workspace_held(ctypes.byref(v)))
+    return int(v.value)
 
 
 def selector_grad(params: torch.Tensor, X: torch.Tensor, Y: torch.Tensor, M: torch.Tensor):

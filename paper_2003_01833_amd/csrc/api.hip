@@ -2,10 +2,12 @@
 // dispatch to the tree, upward, list and interaction stages.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -24,17 +26,48 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
+namespace {
+std::atomic<size_t> g_held{0};
+
+// TAGI_WORKSPACE_LIMIT in bytes (a K, M or G suffix multiplies by 2^10, 2^20,
+// 2^30); 0 when unset, empty or not a number
+size_t workspace_limit() {
+  const char* v = std::getenv("TAGI_WORKSPACE_LIMIT");
+  if (!v || !*v) return 0;
+  char* end = nullptr;
+  const unsigned long long n = std::strtoull(v, &end, 10);
+  if (end == v) return 0;
+  int shift = 0;
+  if (*end == 'K' || *end == 'k') shift = 10;
+  if (*end == 'M' || *end == 'm') shift = 20;
+  if (*end == 'G' || *end == 'g') shift = 30;
+  return (size_t)n << shift;
+}
+}  // namespace
+
+int workspace_take(size_t bytes) {
+  const size_t lim = workspace_limit();
+  const size_t held = g_held.fetch_add(bytes) + bytes;
+  if (lim && held > lim) {
+    g_held.fetch_sub(bytes);
+    set_error("device workspace limit (TAGI_WORKSPACE_LIMIT = %zu bytes): %zu held, %zu more "
+              "requested", lim, held - bytes, bytes);
+    return TAGI_E_OOM;
+  }
+  return TAGI_OK;
+}
+
+void workspace_give(size_t bytes) { g_held.fetch_sub(bytes); }
+
 int DBuf::ensure(size_t bytes) {
   if (bytes <= cap && p) return TAGI_OK;
-  if (p) {
-    (void)hipFree(p);
-    p = nullptr;
-    cap = 0;
-  }
+  release();
   if (bytes == 0) bytes = 8;
+  TAGI_TRY(workspace_take(bytes));
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     p = nullptr;
+    workspace_give(bytes);
     set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? TAGI_E_OOM : TAGI_E_HIP;
@@ -44,7 +77,10 @@ int DBuf::ensure(size_t bytes) {
 }
 
 void DBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    (void)hipFree(p);
+    workspace_give(cap);
+  }
   p = nullptr;
   cap = 0;
 }
@@ -102,6 +138,7 @@ static int convolve_targets(tagi_tree* t, const tagi_points* tp, int kernel, con
     nodes.insert(nodes.end(), t->px.nodes.begin(), t->px.nodes.end());
     st = prepare_proxies(t, t->px, nodes, degree, t->n_orb, s, t->px.herm);
     if (st == TAGI_OK) st = compute_proxies(t, t->px, s);
+    if (st != TAGI_OK) t->degree = 0;  // the proxy plan is incomplete: upward again
   }
   const int ob = orbital_block_of(t, kernel, precision);
   if (st == TAGI_OK) st = ensure_schedule(t, bt, ob, s);
@@ -116,6 +153,13 @@ static int convolve_targets(tagi_tree* t, const tagi_points* tp, int kernel, con
 extern "C" {
 
 const char* tagi_last_error(void) { return g_err; }
+
+int tagi_workspace_held(int64_t* bytes) {
+  g_err[0] = 0;
+  REQUIRE(bytes, "tagi_workspace_held: bytes is NULL");
+  *bytes = (int64_t)g_held.load();
+  return TAGI_OK;
+}
 
 int tagi_tree_build(const double* x, const double* y, const double* z, int64_t n,
                     const double* box, int leaf_size, void* stream, tagi_tree** out) {
@@ -602,7 +646,11 @@ int tagi_tree_timing(tagi_tree* t, tagi_timing* o) {
     for (auto& e : t->events[ph]) {
       TAGI_HIP(hipEventSynchronize(e.second));
       float ms = 0.f;
-      TAGI_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+      // a phase that ended in an error has no end event: it adds nothing
+      if (hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
       t->phase_ms[ph] += ms;
     }
   }

@@ -35,9 +35,36 @@ void set_error(const char* fmt, ...);
 // ---------------------------------------------------------------------------
 // grow-only device buffer
 
+// device memory the library holds: every DBuf and StreamScratch allocation is
+// counted, and refused with TAGI_E_OOM beyond the TAGI_WORKSPACE_LIMIT
+// environment variable (bytes, K/M/G suffixes; unset or 0: no limit), read at
+// each allocation
+int workspace_take(size_t bytes);   // TAGI_OK, or TAGI_E_OOM with the message set
+void workspace_give(size_t bytes);
+
+// one owned device allocation (freed when the holder goes away, early error
+// returns included)
 struct DBuf {
   void* p = nullptr;
   size_t cap = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), cap(o.cap) {
+    o.p = nullptr;
+    o.cap = 0;
+  }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      cap = o.cap;
+      o.p = nullptr;
+      o.cap = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { release(); }
   int ensure(size_t bytes);   // reallocates (contents lost) when too small
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
@@ -54,17 +81,23 @@ class StreamScratch {
   StreamScratch& operator=(const StreamScratch&) = delete;
   ~StreamScratch() {
     for (void* p : ptrs_) (void)hipFreeAsync(p, s_);
+    workspace_give(held_);
   }
   template <class T>
   int alloc(T** out, size_t count) {
+    const size_t bytes = count * sizeof(T) + (count == 0 ? 8 : 0);
+    const int st = workspace_take(bytes);
+    if (st != TAGI_OK) return st;
     void* p = nullptr;
-    const hipError_t e = hipMallocAsync(&p, count * sizeof(T) + (count == 0 ? 8 : 0), s_);
+    const hipError_t e = hipMallocAsync(&p, bytes, s_);
     if (e != hipSuccess) {
-      set_error("hipMallocAsync(%zu bytes) failed: %s", count * sizeof(T), hipGetErrorString(e));
+      workspace_give(bytes);
+      set_error("hipMallocAsync(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
       (void)hipGetLastError();
       return e == hipErrorOutOfMemory ? TAGI_E_OOM : TAGI_E_HIP;
     }
     ptrs_.push_back(p);
+    held_ += bytes;
     *out = static_cast<T*>(p);
     return TAGI_OK;
   }
@@ -72,6 +105,7 @@ class StreamScratch {
  private:
   hipStream_t s_;
   std::vector<void*> ptrs_;
+  size_t held_ = 0;
 };
 
 // ---------------------------------------------------------------------------

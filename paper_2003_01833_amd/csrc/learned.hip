@@ -514,6 +514,7 @@ int convolve_learned(tagi_tree* t, int kernel, const double* kappa, double alpha
   }
   if (S.ob != ob) {
     // items (batch, group, orbital block, chunk); launch lists per degree and near
+    S.ob = 0;  // invalid until every buffer below is in place
     const int n_ob = (n_orb + ob - 1) / ob;
     S.h_items.clear();
     S.h_group_first.clear();

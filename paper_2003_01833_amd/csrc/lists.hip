@@ -461,6 +461,7 @@ int balance_runs_per_xcd(std::vector<int32_t>& list, const std::vector<WaveRun>&
 // chunk-major order cut into equal counts. Results do not depend on the order.
 int order_schedule(tagi_tree* t, double far_w, hipStream_t s) {
   if (t->n_items == 0 || t->items_far_w == far_w) return TAGI_OK;
+  t->items_far_w = -1.0;  // invalid until the order is on the device
   t->h_order = t->h_order_base;
   if (far_w != 0.0) {
     std::vector<WaveRun> runs(t->h_runs.size());

@@ -535,6 +535,7 @@ int upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree
   t->degree = 0;  // invalid until complete
   phase_begin(t, kPhaseUpward, s);
   if (!(t->px.degree == degree && t->px.n_orb == n_orb && t->px.herm == herm)) {
+    t->px.degree = t->px.n_orb = 0;  // invalid until the plan is complete
     TAGI_TRY(t->ws.ensure(n * sizeof(double)));
     TAGI_TRY(t->fs.ensure((size_t)n_orb * n * sizeof(double)));
     TAGI_TRY(t->qs.ensure((size_t)n_orb * n * sizeof(double)));

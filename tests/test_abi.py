@@ -102,3 +102,13 @@ def test_validation_rejects_before_any_device_work():
                                        0.7, 8, 0, bogus, None, None) == -1
     assert b"tree is NULL" in lib.tagi_last_error()
     assert lib.tagi_tree_destroy(None) == 0
+
+
+def test_workspace_held_reports_nothing_before_device_work():
+    lib = _lib()
+    lib.tagi_workspace_held.argtypes = [ctypes.c_void_p]
+    lib.tagi_last_error.restype = ctypes.c_char_p
+    held = ctypes.c_int64(-1)
+    assert lib.tagi_workspace_held(ctypes.byref(held)) == 0 and held.value == 0
+    assert lib.tagi_workspace_held(None) == -1
+    assert b"bytes is NULL" in lib.tagi_last_error()
