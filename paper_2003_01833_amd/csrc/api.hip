@@ -164,6 +164,7 @@ int tagi_workspace_held(int64_t* bytes) {
 int tagi_tree_build(const double* x, const double* y, const double* z, int64_t n,
                     const double* box, int leaf_size, void* stream, tagi_tree** out) {
   g_err[0] = 0;
+  CallRange range_("tagi_tree_build");
   REQUIRE(out, "tagi_tree_build: out is NULL");
   *out = nullptr;
   REQUIRE(x && y && z, "tagi_tree_build: null coordinate array");
@@ -201,6 +202,7 @@ int tagi_tree_build(const double* x, const double* y, const double* z, int64_t n
 int tagi_upward(tagi_tree* t, const double* f, const double* w, int n_orb, int degree,
                 void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_upward");
   REQUIRE(t, "tagi_upward: tree is NULL");
   REQUIRE(f && w, "tagi_upward: null f or w");
   REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb, "tagi_upward: n_orb = %d out of range [1, %d]", n_orb,
@@ -214,6 +216,7 @@ int tagi_upward(tagi_tree* t, const double* f, const double* w, int n_orb, int d
 int tagi_upward_hermite(tagi_tree* t, const double* f, const double* w, int n_orb, int degree,
                         void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_upward_hermite");
   REQUIRE(t, "tagi_upward_hermite: tree is NULL");
   REQUIRE(f && w, "tagi_upward_hermite: null f or w");
   REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb, "tagi_upward_hermite: n_orb = %d out of range [1, %d]",
@@ -228,6 +231,7 @@ int tagi_convolve(tagi_tree* t, const tagi_points* targets, int kernel, const do
                   double alpha, double theta, int degree, int precision, double* out,
                   void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_convolve");
   REQUIRE(t, "tagi_convolve: tree is NULL");
   REQUIRE(out || (targets && targets->n == 0), "tagi_convolve: out is NULL");
   REQUIRE(valid_kernel(kernel), "tagi_convolve: unknown kernel %d", kernel);
@@ -284,6 +288,7 @@ int tagi_direct(const double* sx, const double* sy, const double* sz, const doub
                 const double* tz, const double* tf, int64_t nt, int kernel, double kappa,
                 double alpha, double* out, void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_direct");
   REQUIRE(valid_kernel(kernel), "tagi_direct: unknown kernel %d", kernel);
   REQUIRE(sx && sy && sz && sf && sw, "tagi_direct: null source array");
   REQUIRE(tx && ty && tz && out, "tagi_direct: null target or output array");
@@ -429,6 +434,7 @@ int tagi_graph_create(tagi_tree* t, const double* f, const double* w, int n_orb,
                       int kernel, const double* kappa, double alpha, double theta, int precision,
                       double* out, void* stream, tagi_graph** graph) {
   g_err[0] = 0;
+  CallRange range_("tagi_graph_create");
   REQUIRE(graph, "tagi_graph_create: graph is NULL");
   *graph = nullptr;
   hipStream_t s = (hipStream_t)stream;
@@ -489,6 +495,7 @@ int tagi_convolve_learned(tagi_tree* t, int kernel, const double* kappa, double 
                           double theta_max, double theta_fb, int degree_fb, int precision,
                           double* out, void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_convolve_learned");
   REQUIRE(t && params && norm && out && tol, "tagi_convolve_learned: null argument");
   REQUIRE(valid_kernel(kernel), "tagi_convolve_learned: unknown kernel %d", kernel);
   REQUIRE(kappa || !is_yukawa(kernel), "tagi_convolve_learned: kappa is NULL for a Yukawa kernel");
@@ -566,6 +573,7 @@ int tagi_selector_samples(tagi_tree* t, const double* f, const double* w, int ke
                           float* features, float* errors, int32_t* pair_ids, int64_t* n,
                           void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_selector_samples");
   REQUIRE(t && f && w && features && errors && n, "tagi_selector_samples: null argument");
   REQUIRE(kernel == TAGI_YUKAWA_SS || kernel == TAGI_COULOMB_SS,
           "tagi_selector_samples: kernel must be TAGI_YUKAWA_SS or TAGI_COULOMB_SS");
@@ -583,6 +591,7 @@ int tagi_selector_samples(tagi_tree* t, const double* f, const double* w, int ke
 int tagi_selector_grad(const float* params, const float* X, const float* Y, const float* M,
                        int64_t m, float* grads, float* loss, void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_selector_grad");
   REQUIRE(params && X && Y && M && grads, "tagi_selector_grad: null argument");
   REQUIRE(m >= 1 && m < (int64_t)INT32_MAX, "tagi_selector_grad: bad m");
   return selector_grad(params, X, Y, M, m, grads, loss, (hipStream_t)stream);
@@ -592,6 +601,7 @@ int tagi_selector_train(float* params, const float* X, const float* Y, const flo
                         const int32_t* order, int epochs, int batch, float lr, float* loss_hist,
                         void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_selector_train");
   REQUIRE(params && X && Y && M && order, "tagi_selector_train: null argument");
   REQUIRE(m >= 1 && m < (int64_t)INT32_MAX, "tagi_selector_train: bad m");
   REQUIRE(batch >= 1 && epochs >= 0 && lr > 0.0f, "tagi_selector_train: bad batch/epochs/lr");
@@ -604,6 +614,7 @@ int tagi_selector_train(float* params, const float* X, const float* Y, const flo
 
 int tagi_graph_launch(tagi_graph* g, void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_graph_launch");
   REQUIRE(g && g->exec, "tagi_graph_launch: graph is NULL");
   TAGI_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
   ++g->tree->charges_gen;
@@ -669,6 +680,7 @@ int tagi_green_step(tagi_tree* t, const double* psi, const double* veff, const d
                     int n_orb, double* eps, double theta, int degree, int precision,
                     double* psi_out, double* resid, void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_green_step");
   REQUIRE(t, "tagi_green_step: tree is NULL");
   REQUIRE(psi && veff && w && psi_out && eps, "tagi_green_step: null argument");
   REQUIRE(psi_out != psi, "tagi_green_step: psi_out must not alias psi");
@@ -691,6 +703,7 @@ int tagi_green_step_learned(tagi_tree* t, const double* psi, const double* veff,
                             const double* tol, double theta_max, double theta_fb, int degree_fb,
                             int precision, double* psi_out, double* resid, void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_green_step_learned");
   REQUIRE(t, "tagi_green_step_learned: tree is NULL");
   REQUIRE(psi && veff && w && psi_out && eps && params && norm && tol,
           "tagi_green_step_learned: null argument");
@@ -719,6 +732,7 @@ int tagi_mesh_build(const double* lo3, const double* hi3, int p, double tol_m,
                     int uniform_levels, int max_level, const double* atoms, int n_atoms,
                     int test_fn, double max_aspect, void* stream, tagi_mesh** out) {
   g_err[0] = 0;
+  CallRange range_("tagi_mesh_build");
   REQUIRE(out, "tagi_mesh_build: out is NULL");
   *out = nullptr;
   REQUIRE(lo3 && hi3, "tagi_mesh_build: null domain");
@@ -774,6 +788,7 @@ int tagi_mesh_cells(const tagi_mesh* m, double* lo, double* hi) {
 int tagi_mesh_points(const tagi_mesh* m, double* x, double* y, double* z, double* w,
                      void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_mesh_points");
   REQUIRE(m && x && y && z && w, "tagi_mesh_points: null argument");
   return mesh_points(m, x, y, z, w, (hipStream_t)stream);
 }
@@ -822,6 +837,7 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
                   const int* variants, int n_var, int reps, int* best, double* times,
                   void* stream) {
   g_err[0] = 0;
+  CallRange range_("tagi_autotune");
   REQUIRE(x && y && z && w && f, "tagi_autotune: null input array");
   REQUIRE(leaf_sizes && n_leaf >= 1, "tagi_autotune: no leaf size candidates");
   REQUIRE(obs && n_ob >= 1, "tagi_autotune: no orbital block candidates");

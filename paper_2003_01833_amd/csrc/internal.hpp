@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <string>
@@ -337,6 +338,15 @@ enum Phase {
   kPhaseInteract = 2,
   kPhaseCombine = 3,
   kLaunchInteract = 4  // one interaction launch, on the stream it runs on
+};
+
+// a roctx range over one API call on the calling thread (host time of the
+// call; rocprofv3 --marker-trace lists it beside the kernels it launched)
+struct CallRange {
+  explicit CallRange(const char* name) { roctxRangePush(name); }
+  ~CallRange() { roctxRangePop(); }
+  CallRange(const CallRange&) = delete;
+  CallRange& operator=(const CallRange&) = delete;
 };
 
 inline void phase_begin(tagi_tree* t, int ph, hipStream_t s) {
