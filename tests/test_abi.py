@@ -112,3 +112,21 @@ def test_workspace_held_reports_nothing_before_device_work():
     assert lib.tagi_workspace_held(ctypes.byref(held)) == 0 and held.value == 0
     assert lib.tagi_workspace_held(None) == -1
     assert b"bytes is NULL" in lib.tagi_last_error()
+
+
+@pytest.mark.parametrize("value,limit", [("1", 1), ("3K", 3 << 10), ("2m", 2 << 20)])
+def test_workspace_limit_refuses_the_first_allocation(monkeypatch, value, limit):
+    # a tree needs far more than these limits: its first buffer is refused before
+    # any device allocation is attempted, with the limit read back in the message
+    lib = _lib()
+    vp = ctypes.c_void_p
+    lib.tagi_tree_build.argtypes = [vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int, vp,
+                                    ctypes.POINTER(vp)]
+    lib.tagi_last_error.restype = ctypes.c_char_p
+    monkeypatch.setenv("TAGI_WORKSPACE_LIMIT", value)
+    n = 1 << 20
+    bogus = ctypes.c_void_p(0x1000)  # never dereferenced: the limit stops the call first
+    tree = vp()
+    assert lib.tagi_tree_build(bogus, bogus, bogus, n, None, 64, None, ctypes.byref(tree)) == -3
+    msg = lib.tagi_last_error().decode()
+    assert "TAGI_WORKSPACE_LIMIT = %d bytes" % limit in msg and not tree.value
