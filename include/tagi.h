@@ -472,6 +472,27 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
                   void* stream);
 
 /*
+ * tagi_autotune for the learned lists (a project addition): the same
+ * candidates, best[4] and times layout, with each step an upward pass (lowest
+ * degree) and tagi_convolve_learned(kernel, kappa, alpha, params, norm, tol,
+ * theta_max, theta_fb, degree_fb, precision) as documented there. Every step
+ * stages its charges again, so the learned lists are rebuilt in each timed
+ * step, as in a Green iteration. Results do not depend on the orbital block
+ * or the launch variant; the schedule items regroup partial sums and the leaf
+ * size changes the tree. Synchronises the stream; allocates and frees its own
+ * scratch.
+ * Errors: as tagi_autotune and tagi_convolve_learned.
+ */
+int tagi_autotune_learned(const double* x, const double* y, const double* z, const double* w,
+                          int64_t n, const double* box, const double* f, int n_orb, int kernel,
+                          const double* kappa, double alpha, const float* params,
+                          const float* norm, const double* tol, double theta_max,
+                          double theta_fb, int degree_fb, int precision, const int* leaf_sizes,
+                          int n_leaf, const int* obs, int n_ob, const int* items, int n_items,
+                          const int* variants, int n_var, int reps, int* best, double* times,
+                          void* stream);
+
+/*
  * Learned degree/MAC selector (a project addition on top of Section 6.2-6.3).
  *
  * Network: 5 inputs -> 3 hidden tanh layers of 64 -> 9 linear outputs, FP32.

@@ -31,7 +31,7 @@ EXPORTED = ["tagi_tree_build", "tagi_upward", "tagi_upward_hermite", "tagi_convo
             "tagi_selector_param_count", "tagi_selector_samples", "tagi_selector_grad",
             "tagi_selector_train", "tagi_convolve_learned", "tagi_learned_stats",
             "tagi_tree_set_orbital_block", "tagi_tree_set_schedule_items",
-            "tagi_tree_set_kernel_variant", "tagi_autotune",
+            "tagi_tree_set_kernel_variant", "tagi_autotune", "tagi_autotune_learned",
             "tagi_green_step", "tagi_green_step_learned",
             "tagi_learned_lists_export", "tagi_mesh_build", "tagi_mesh_info",
             "tagi_mesh_cells", "tagi_mesh_points", "tagi_mesh_destroy", "tagi_tree_destroy",
@@ -109,6 +109,9 @@ def load_library(path: str = LIB_PATH):
     lib.tagi_mesh_destroy.argtypes = [vp]
     lib.tagi_autotune.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, vp, dbl, dbl, i32, i32,
                                   vp, i32, vp, i32, vp, i32, vp, i32, i32, vp, vp, vp]
+    lib.tagi_autotune_learned.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, vp, dbl, vp, vp,
+                                          vp, dbl, dbl, i32, i32, vp, i32, vp, i32, vp, i32, vp,
+                                          i32, i32, vp, vp, vp]
     lib.tagi_tree_set_schedule_items.argtypes = [vp, i32]
     lib.tagi_tree_set_kernel_variant.argtypes = [vp, i32]
     lib.tagi_graph_create.argtypes = [vp, vp, vp, i32, i32, i32, vp, dbl, dbl, i32, vp, vp,
@@ -553,6 +556,37 @@ def autotune(x, y, z, f, w, kernel: str, kappa, theta: float, degree: int, leaf_
                                         PRECISIONS[precision], _hptr(ls), ls.size, _hptr(ob),
                                         ob.size, _hptr(it), it.size, _hptr(va), va.size,
                                         int(reps), _hptr(best), _hptr(times), _stream()))
+    return tuple(int(b) for b in best), times
+
+
+def autotune_learned(x, y, z, f, w, kernel: str, kappa, selector, tol, leaf_sizes, obs=(0,),
+                     items=(0,), variants=(0,), theta_max: float = 0.9, theta_fb: float = 0.7,
+                     degree_fb: int = 8, alpha: float = 1.0, precision: str = "mixed",
+                     reps: int = 1, box=None):
+    """tagi_autotune_learned: ((best leaf size, orbital block, schedule items,
+    kernel variant), times ms [n_leaf][n_ob][n_items][n_var]) for the learned
+    lists of `selector` with the per-orbital budget `tol`."""
+    n = x.numel()
+    n_orb = 1 if f.dim() == 1 else f.shape[0]
+    kap = np.ascontiguousarray(np.broadcast_to(np.asarray(kappa, dtype=np.float64), (n_orb,)))
+    tl = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (n_orb,)))
+    net = selector.net(kernel)
+    prm = np.ascontiguousarray(net.params, dtype=np.float32)
+    nrm = np.ascontiguousarray(net.norm, dtype=np.float32)
+    ls = np.ascontiguousarray(leaf_sizes, dtype=np.int32)
+    ob = np.ascontiguousarray(obs, dtype=np.int32)
+    it = np.ascontiguousarray(items, dtype=np.int32)
+    va = np.ascontiguousarray(variants, dtype=np.int32)
+    bx = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
+    best = np.zeros(4, np.int32)
+    times = np.zeros((ls.size, ob.size, it.size, va.size), np.float64)
+    _check(load_library().tagi_autotune_learned(
+        _dptr(x, "x", n), _dptr(y, "y", n), _dptr(z, "z", n), _dptr(w, "w", n), n,
+        None if bx is None else _hptr(bx), _dptr(f, "f", n_orb * n), n_orb, KERNELS[kernel],
+        _hptr(kap), float(alpha), _hptr(prm), _hptr(nrm), _hptr(tl), float(theta_max),
+        float(theta_fb), int(degree_fb), PRECISIONS[precision], _hptr(ls), ls.size, _hptr(ob),
+        ob.size, _hptr(it), it.size, _hptr(va), va.size, int(reps), _hptr(best), _hptr(times),
+        _stream()))
     return tuple(int(b) for b in best), times
 
 

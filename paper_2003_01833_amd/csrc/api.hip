@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 
 #include "internal.hpp"
@@ -830,36 +831,45 @@ int tagi_tree_set_orbital_block(tagi_tree* t, int ob) {
   return TAGI_OK;
 }
 
-int tagi_autotune(const double* x, const double* y, const double* z, const double* w, int64_t n,
-                  const double* box, const double* f, int n_orb, int kernel, const double* kappa,
-                  double alpha, double theta, int degree, int precision, const int* leaf_sizes,
-                  int n_leaf, const int* obs, int n_ob, const int* items, int n_items,
-                  const int* variants, int n_var, int reps, int* best, double* times,
-                  void* stream) {
-  g_err[0] = 0;
-  CallRange range_("tagi_autotune");
-  REQUIRE(x && y && z && w && f, "tagi_autotune: null input array");
-  REQUIRE(leaf_sizes && n_leaf >= 1, "tagi_autotune: no leaf size candidates");
-  REQUIRE(obs && n_ob >= 1, "tagi_autotune: no orbital block candidates");
-  REQUIRE(items && n_items >= 1, "tagi_autotune: no schedule item candidates");
-  REQUIRE(variants && n_var >= 1, "tagi_autotune: no kernel variant candidates");
+}  // extern "C"
+
+// Candidate arguments shared by the autotuners, checked before any work.
+static int autotune_check(const char* who, const double* x, const double* y, const double* z,
+                          const double* w, const double* f, int64_t n, int n_orb,
+                          const int* leaf_sizes, int n_leaf, const int* obs, int n_ob,
+                          const int* items, int n_items, const int* variants, int n_var,
+                          int reps, const int* best) {
+  REQUIRE(x && y && z && w && f, "%s: null input array", who);
+  REQUIRE(leaf_sizes && n_leaf >= 1, "%s: no leaf size candidates", who);
+  REQUIRE(obs && n_ob >= 1, "%s: no orbital block candidates", who);
+  REQUIRE(items && n_items >= 1, "%s: no schedule item candidates", who);
+  REQUIRE(variants && n_var >= 1, "%s: no kernel variant candidates", who);
   for (int i = 0; i < n_var; ++i)
     REQUIRE(variants[i] >= 0 && variants[i] < kKernelVariants,
-            "tagi_autotune: variants[%d] = %d out of range [0, %d)", i, variants[i],
-            kKernelVariants);
+            "%s: variants[%d] = %d out of range [0, %d)", who, i, variants[i], kKernelVariants);
   for (int i = 0; i < n_items; ++i)
     REQUIRE(items[i] == 0 || (items[i] >= 256 && items[i] <= (1 << 22)),
-            "tagi_autotune: items[%d] = %d must be 0 or in [256, 2^22]", i, items[i]);
-  REQUIRE(best, "tagi_autotune: best is NULL");
-  REQUIRE(reps >= 1 && reps <= 1000, "tagi_autotune: reps = %d out of range [1, 1000]", reps);
-  REQUIRE(n >= 1 && n < (int64_t)INT32_MAX, "tagi_autotune: n = %lld out of range", (long long)n);
-  REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb, "tagi_autotune: n_orb = %d out of range", n_orb);
+            "%s: items[%d] = %d must be 0 or in [256, 2^22]", who, i, items[i]);
+  REQUIRE(best, "%s: best is NULL", who);
+  REQUIRE(reps >= 1 && reps <= 1000, "%s: reps = %d out of range [1, 1000]", who, reps);
+  REQUIRE(n >= 1 && n < (int64_t)INT32_MAX, "%s: n = %lld out of range", who, (long long)n);
+  REQUIRE(n_orb >= 1 && n_orb <= kMaxOrb, "%s: n_orb = %d out of range", who, n_orb);
   for (int i = 0; i < n_leaf; ++i)
-    REQUIRE(leaf_sizes[i] >= 1, "tagi_autotune: leaf_sizes[%d] = %d must be >= 1", i,
-            leaf_sizes[i]);
+    REQUIRE(leaf_sizes[i] >= 1, "%s: leaf_sizes[%d] = %d must be >= 1", who, i, leaf_sizes[i]);
   for (int i = 0; i < n_ob; ++i)
     REQUIRE(obs[i] == 0 || obs[i] == 1 || obs[i] == 2 || obs[i] == 4 || obs[i] == 8,
-            "tagi_autotune: obs[%d] = %d must be 0, 1, 2, 4 or 8", i, obs[i]);
+            "%s: obs[%d] = %d must be 0, 1, 2, 4 or 8", who, i, obs[i]);
+  return TAGI_OK;
+}
+
+// The timing loop shared by the autotuners: for every leaf size a tree, and on
+// it for every (orbital block, schedule items, launch variant) one untimed
+// step and `reps` timed ones of `step` (which writes its result to `out`).
+static int autotune_loop(const char* who, const double* x, const double* y, const double* z,
+                         int64_t n, const double* box, int n_orb, const int* leaf_sizes,
+                         int n_leaf, const int* obs, int n_ob, const int* items, int n_items,
+                         const int* variants, int n_var, int reps, int* best, double* times,
+                         void* stream, const std::function<int(tagi_tree*, double*)>& step) {
   hipStream_t s = (hipStream_t)stream;
   StreamScratch scratch(s);
   double* out = nullptr;
@@ -869,7 +879,7 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
   double best_ms = INFINITY;
   best[0] = best[1] = best[2] = best[3] = 0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    set_error("tagi_autotune: hipEventCreate failed");
+    set_error("%s: hipEventCreate failed", who);
     st = TAGI_E_HIP;
   }
   for (int li = 0; li < n_leaf && st == TAGI_OK; ++li) {
@@ -881,22 +891,15 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
       st = tagi_tree_set_schedule_items(t, items[ii]);
       if (st != TAGI_OK) break;
       t->kvariant = variants[vi];
-      auto step = [&]() {
-        int r = tagi_upward(t, f, w, n_orb, degree, stream);
-        if (r == TAGI_OK)
-          r = tagi_convolve(t, nullptr, kernel, kappa, alpha, theta, degree, precision, out,
-                            stream);
-        return r;
-      };
-      st = step();
+      st = step(t, out);
       if (st != TAGI_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) st = TAGI_E_HIP;
-      for (int r = 0; r < reps && st == TAGI_OK; ++r) st = step();
+      for (int r = 0; r < reps && st == TAGI_OK; ++r) st = step(t, out);
       if (st != TAGI_OK) break;
       float ms = 0.0f;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        set_error("tagi_autotune: event timing failed");
+        set_error("%s: event timing failed", who);
         st = TAGI_E_HIP;
         break;
       }
@@ -921,6 +924,56 @@ int tagi_autotune(const double* x, const double* y, const double* z, const doubl
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(s);
   return st;
+}
+
+extern "C" {
+
+int tagi_autotune(const double* x, const double* y, const double* z, const double* w, int64_t n,
+                  const double* box, const double* f, int n_orb, int kernel, const double* kappa,
+                  double alpha, double theta, int degree, int precision, const int* leaf_sizes,
+                  int n_leaf, const int* obs, int n_ob, const int* items, int n_items,
+                  const int* variants, int n_var, int reps, int* best, double* times,
+                  void* stream) {
+  g_err[0] = 0;
+  CallRange range_("tagi_autotune");
+  TAGI_TRY(autotune_check("tagi_autotune", x, y, z, w, f, n, n_orb, leaf_sizes, n_leaf, obs,
+                          n_ob, items, n_items, variants, n_var, reps, best));
+  return autotune_loop("tagi_autotune", x, y, z, n, box, n_orb, leaf_sizes, n_leaf, obs, n_ob,
+                       items, n_items, variants, n_var, reps, best, times, stream,
+                       [&](tagi_tree* t, double* out) {
+                         int r = tagi_upward(t, f, w, n_orb, degree, stream);
+                         if (r == TAGI_OK)
+                           r = tagi_convolve(t, nullptr, kernel, kappa, alpha, theta, degree,
+                                             precision, out, stream);
+                         return r;
+                       });
+}
+
+int tagi_autotune_learned(const double* x, const double* y, const double* z, const double* w,
+                          int64_t n, const double* box, const double* f, int n_orb, int kernel,
+                          const double* kappa, double alpha, const float* params,
+                          const float* norm, const double* tol, double theta_max,
+                          double theta_fb, int degree_fb, int precision, const int* leaf_sizes,
+                          int n_leaf, const int* obs, int n_ob, const int* items, int n_items,
+                          const int* variants, int n_var, int reps, int* best, double* times,
+                          void* stream) {
+  g_err[0] = 0;
+  CallRange range_("tagi_autotune_learned");
+  REQUIRE(params && norm && tol, "tagi_autotune_learned: null selector argument");
+  TAGI_TRY(autotune_check("tagi_autotune_learned", x, y, z, w, f, n, n_orb, leaf_sizes, n_leaf,
+                          obs, n_ob, items, n_items, variants, n_var, reps, best));
+  // each step stages new charges, so the learned lists are rebuilt every time,
+  // as in a Green iteration whose kappa and charges change from step to step
+  return autotune_loop("tagi_autotune_learned", x, y, z, n, box, n_orb, leaf_sizes, n_leaf, obs,
+                       n_ob, items, n_items, variants, n_var, reps, best, times, stream,
+                       [&](tagi_tree* t, double* out) {
+                         int r = tagi_upward(t, f, w, n_orb, 1, stream);
+                         if (r == TAGI_OK)
+                           r = tagi_convolve_learned(t, kernel, kappa, alpha, params, norm, tol,
+                                                     theta_max, theta_fb, degree_fb, precision,
+                                                     out, stream);
+                         return r;
+                       });
 }
 
 int tagi_tree_destroy(tagi_tree* t) {

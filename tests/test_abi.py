@@ -88,6 +88,19 @@ def test_validation_rejects_before_any_device_work():
     assert lib.tagi_autotune(bogus, bogus, bogus, bogus, 10, None, bogus, 1, 0, bogus, 1.0, 0.5, 4,
                              0, leafs, 1, ob4, 1, items, 1, var, 2, 1, best, None, None) == -1
     assert b"variants[1]" in lib.tagi_last_error()
+    lib.tagi_autotune_learned.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int,
+                                          ctypes.c_int, vp, ctypes.c_double, vp, vp, vp,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp,
+                                          ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    assert lib.tagi_autotune_learned(bogus, bogus, bogus, bogus, 10, None, bogus, 1, 0, bogus,
+                                     1.0, None, bogus, bogus, 0.9, 0.7, 8, 1, leafs, 1, ob4, 1,
+                                     items, 1, var, 1, 1, best, None, None) == -1
+    assert b"null selector argument" in lib.tagi_last_error()
+    assert lib.tagi_autotune_learned(bogus, bogus, bogus, bogus, 10, None, bogus, 1, 0, bogus,
+                                     1.0, bogus, bogus, bogus, 0.9, 0.7, 8, 1, leafs, 1, ob4, 1,
+                                     items, 1, var, 2, 1, best, None, None) == -1
+    assert b"tagi_autotune_learned: variants[1]" in lib.tagi_last_error()
     lib.tagi_tree_set_schedule_items.argtypes = [vp, ctypes.c_int]
     assert lib.tagi_tree_set_schedule_items(None, 4096) == -1
     lib.tagi_tree_set_kernel_variant.argtypes = [vp, ctypes.c_int]

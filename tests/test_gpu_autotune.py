@@ -3,7 +3,10 @@ of the orbital block only changes how many orbitals share a pair's geometry, and
 a launch variant only the register budget or the loop steps, never the
 arithmetic of an orbital or its order, so every width and variant gives the
 same bits; the autotuner's pick must be one of the candidates and reproduce the
-same result as setting it by hand."""
+same result as setting it by hand; the same for the autotuner of the learned
+lists."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -121,3 +124,36 @@ def test_schedule_items_change_only_the_grouping_of_partial_sums():
     with pytest.raises(tagi.TagiError):
         t.set_schedule_items(100)
     t.close()
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2003_01833_amd", "selector_weights.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained selector weights")
+def test_learned_autotune_picks_a_candidate_that_reproduces_the_result():
+    import paper_2003_01833_amd as tagi
+    from paper_2003_01833_amd.selector import Selector
+    sel = Selector.load(WEIGHTS)
+    dx, dy, dz, dw, dF = _case(5)
+    kap = np.linspace(0.8, 2.4, 5)
+    tol = 1e-8 * 4 * np.pi / kap ** 2
+    (leaf, ob, items, var), times = tagi.autotune_learned(
+        dx, dy, dz, dF, dw, "yukawa_ss", kap, sel, tol, leaf_sizes=(150, 400), obs=(4, 8),
+        items=(0,), variants=(0, 1), reps=2)
+    assert leaf in (150, 400) and ob in (4, 8) and items == 0 and var in (0, 1)
+    assert times.shape == (2, 2, 1, 2) and np.all(times > 0)
+    assert times[(150, 400).index(leaf), (4, 8).index(ob), 0, var] == times.min()
+    # the pick on a tree by hand against the defaults on the same leaf size: the
+    # orbital block and the launch variant leave the bits alone
+    t = tagi.Tree(dx, dy, dz, leaf)
+    t.set_orbital_block(ob)
+    t.set_kernel_variant(var)
+    t.upward(dF, dw, 1)
+    u = t.convolve_learned("yukawa_ss", kap, sel, tol, precision="mixed").clone()
+    t2 = tagi.Tree(dx, dy, dz, leaf)
+    t2.upward(dF, dw, 1)
+    u2 = t2.convolve_learned("yukawa_ss", kap, sel, tol, precision="mixed")
+    assert torch.equal(u, u2)
+    t.close()
+    t2.close()
